@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark of the rank-share SpMV on one MI355X.
+
+One step = one ``spmv_exec`` of the rank share: Pack, local product y_L,
+host-staged halo exchange (PostSend/PostRecv/Wait*), Unpack and remote
+product y_R, in the plan's operation order and stream binding, ending with
+all work finished.  Inputs are resident in HBM before the timed region.
+
+Cold-cache protocol: the share is uploaded R times (independent device
+copies of A, x and y, R * footprint > 2x the 256 MB Infinity Cache) and the
+steps rotate over the copies, so each step streams A from HBM.
+
+Printed: one JSON line with the metric ``rank-share SpMV GB/s`` (algorithmic
+device bytes of all GPU steps / wall time per step), the roofline of the
+dominant kernel (y_L, timed with HIP events on its own stream) and the CPU
+oracle's rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
+MALL_BYTES = 256 << 20         # Infinity Cache
+
+
+def step_bytes(info: dict) -> dict:
+    """Algorithmic device bytes of each GPU step of one exec (unique data
+    touched once: index arrays, matrix values, gathered/scattered vectors).
+    """
+    n, nl, nr = info["n_loc"], info["nnz_local"], info["nnz_remote"]
+    h, s, rr = info["n_halo"], info["n_send"], info["n_remote_rows"]
+    b = {}
+    b["pack"] = 20 * s                                   # idx 4 + x 8 + sendbuf 8
+    b["yL"] = 12 * nl + 4 * (n + 1) + 8 * n + 8 * n      # col+val, row_ptr, x, y
+    b["unpack"] = 0 if info["fuse_unpack"] else 20 * h   # perm 4 + recv 8 + x_halo 8
+    yr = 12 * nr + 4 * (rr + 1) + 4 * rr + 8 * h        # col+val, ptr, row ids, x_halo
+    if info["fused_combine"]:
+        yr += 16 * rr                                    # y read + write
+        b["combine"] = 0
+    else:
+        yr += 8 * rr                                     # partial sums written
+        b["combine"] = 4 * rr + 8 * rr + 16 * rr         # ids, partials, y read+write
+    b["yR"] = yr
+    b["total"] = sum(v for k, v in b.items())
+    b["host_link"] = 8 * (s + h)                         # staged each way
+    return b
+
+
+def cpu_baseline(A, P, r, x, bytes_per_step: float, budget_s: float = 12.0) -> dict:
+    """The oracle (Dot2 over every owned row, OpenMP) timed on the host."""
+    import oracle
+    oracle.build(force=False)
+    lo_all = oracle.row_blocks(A.n_rows, P)
+    lo, hi = int(lo_all[r]), int(lo_all[r + 1])
+    rp = np.ascontiguousarray(A.row_ptr[lo:hi + 1])
+    oracle.spmv_dot2(rp, A.col_idx, A.val, x)                 # warm-up
+    times = []
+    t_start = time.perf_counter()
+    while len(times) < 5 or (time.perf_counter() - t_start < budget_s and len(times) < 200):
+        t0 = time.perf_counter()
+        oracle.spmv_dot2(rp, A.col_idx, A.val, x)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_start > budget_s and len(times) >= 1:
+            break
+    t = float(np.median(times))
+    return {"value": round(bytes_per_step / t / 1e9, 3), "unit": "GB/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{len(times)} full rank-share products (Dot2, all {hi - lo} owned rows), "
+                      f"median {t * 1e3:.2f} ms each"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="laplace3d_128_p4r1")
+    ap.add_argument("--replicas", type=int, default=0, help="0 = enough to exceed 2x MALL")
+    ap.add_argument("--plan", default="default", help="'default' or a plan-space index")
+    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--xcd-remap", type=int, default=0)
+    ap.add_argument("--fuse-unpack", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one rank share on one GPU; --gpus {args.gpus} is not "
+              "supported (the multi-GPU exchange is a design, not part of this build)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    import gen
+    import paper_2203_02530_amd as sp
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = gen.WORKLOADS[args.workload]
+    A = w["build"]()
+    P, r = w["nranks"], w["rank"]
+    x = w["x"](A.n_cols)
+
+    ops = smap = None
+    if args.plan != "default":
+        ops, smap = sp.spmv_plan_space_get(P, 2, int(args.plan))
+    tune = {"flags": sp.SPMV_F_PROFILE, "lanes_local": args.lanes, "lanes_remote": 0,
+            "xcd_remap": args.xcd_remap, "fuse_unpack": args.fuse_unpack}
+
+    first = sp.spmv_plan_create(A, P, r, ops, smap, 2, tune)
+    info = sp.spmv_plan_info(first)
+    lo, n = info["lo"], info["n_loc"]
+    footprint = info["device_bytes"] + 16 * n
+    R = args.replicas or max(1, math.ceil(2 * MALL_BYTES / max(footprint, 1)))
+    plans = [first] + [sp.spmv_plan_create(A, P, r, ops, smap, 2, tune) for _ in range(R - 1)]
+    halo = sp.spmv_plan_get_i32(first, sp.SPMV_I32_HALO_COLS).astype(np.int64)
+    xs, ys = [], []
+    for p in plans:
+        sp.spmv_plan_inbox(p)[:] = x[halo]
+        xs.append(torch.from_numpy(np.ascontiguousarray(x[lo:lo + n])).cuda())
+        ys.append(torch.empty(n, dtype=torch.float64, device="cuda"))
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    for i in range(args.warmup):
+        sp.spmv_exec(plans[i % R], xs[i % R], ys[i % R], stream)
+    for p in plans:
+        sp.spmv_plan_reset_times(p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        j = i % R
+        sp.spmv_exec(plans[j], xs[j], ys[j], stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = elapsed / args.steps * 1e3
+
+    ms = np.zeros(sp.SPMV_N_VERTICES + 1)
+    cnt = np.zeros(sp.SPMV_N_VERTICES + 1)
+    for p in plans:
+        ms += sp.spmv_plan_get_f64(p, sp.SPMV_F64_OP_MS)
+        cnt += sp.spmv_plan_get_f64(p, sp.SPMV_F64_OP_COUNT)
+    avg = np.where(cnt > 0, ms / np.maximum(cnt, 1), 0.0)
+    B = step_bytes(info)
+    t_yl = avg[sp.SPMV_OP_YL] * 1e-3
+    achieved = B["yL"] / t_yl / 1e9
+    value = B["total"] / (ms_step * 1e-3) / 1e9
+    kernel_ms = {"pack": avg[sp.SPMV_OP_PACK], "yL": avg[sp.SPMV_OP_YL],
+                 "unpack": avg[sp.SPMV_OP_UNPACK], "yR": avg[sp.SPMV_OP_YR],
+                 "combine": avg[sp.SPMV_N_VERTICES], "post_send_copy": avg[sp.SPMV_OP_POST_SEND],
+                 "post_recv_copy": avg[sp.SPMV_OP_POST_RECV]}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(A, P, r, x, float(B["total"]))
+
+    out = {
+        "metric": "rank-share SpMV GB/s vs HBM peak",
+        "value": round(value, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "rows": int(A.n_rows), "nnz": int(A.nnz),
+                   "nranks": P, "rank": r, "n_loc": n, "nnz_local": info["nnz_local"],
+                   "nnz_remote": info["nnz_remote"], "n_halo": info["n_halo"],
+                   "plan": args.plan, "lanes_local": info["lanes_local"],
+                   "lanes_remote": info["lanes_remote"], "xcd_remap": info["xcd_remap"],
+                   "fuse_unpack": info["fuse_unpack"], "replicas": R,
+                   "step_device_bytes": B["total"], "step_host_link_bytes": B["host_link"]},
+        "roofline": {"bound": "hbm", "kernel": "y_L local CSR (k_csr_vector)",
+                     "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": B["yL"], "avg_us": round(t_yl * 1e6, 3)},
+        "kernel_avg_ms": {k: round(float(v), 5) for k, v in kernel_ms.items()},
+        "gflops": round(2.0 * (info["nnz_local"] + info["nnz_remote"]) / (ms_step * 1e-3) / 1e9, 3),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    for p in plans:
+        sp.spmv_plan_destroy(p)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,293 @@
+/*
+ * spmv.h -- C ABI of the MI355X (gfx950) row-partitioned SpMV library.
+ *
+ * The library computes one rank's share of the distributed sparse
+ * matrix-vector product y = A x of Sec. III-A of "Machine Learning for
+ * CUDA+MPI Design Rules" (Pearson, Javeed, Devine): the rows, x entries and
+ * y entries of A are divided into contiguous blocks over P ranks; rank r
+ * computes y_r = A_L x_L + A_R x_R, where A_L holds the columns of the x
+ * entries it owns and A_R the columns owned by other ranks.  One exec runs
+ * the operations of the paper's SpMV program DAG (Fig. 3c):
+ *
+ *   Pack      gather the owned x entries other ranks need into one send
+ *             buffer per destination (GPU kernel)
+ *   y_L       local CSR product A_L x_L (GPU kernel)
+ *   PostSend  start sending the packed buffers (here: asynchronous copy of
+ *             the send buffer into a pinned host outbox)
+ *   PostRecv  start receiving the halo x_R (here: asynchronous copy of a
+ *             pinned host inbox, filled by the caller, into device memory)
+ *   WaitSend / WaitRecv   block the host until the copy finished
+ *   Unpack    place received values in halo order (GPU kernel)
+ *   y_R       remote CSR product A_R x_R, added into y (GPU kernel)
+ *   start / end           artificial entry and exit; end waits for all work
+ *
+ * The order of these operations and the stream each GPU operation runs on
+ * are an explicit plan input (a traversal of the DAG, Sec. III-B), and the
+ * synchronisation operations of Table III are explicit tokens of that order.
+ * On one GPU the other ranks are emulated: the caller fills the inbox with
+ * the halo values and reads the packed values from the outbox.
+ *
+ * Conventions
+ *   - All functions return an int status: SPMV_OK (0) or a negative
+ *     SPMV_E* code; spmv_last_error() then gives a message (thread-local,
+ *     valid until the next call on the same thread).  No C++ exception
+ *     crosses this boundary.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory on the current device.  Streams are hipStream_t passed
+ *     as void* (NULL = the null stream).
+ *   - Matrices are CSR with int32 row_ptr/col_idx and FP64 values; column
+ *     indices strictly ascending inside each row.
+ *   - A plan is not safe for concurrent use from several host threads.
+ */
+#ifndef SPMV_H
+#define SPMV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define SPMV_OK       0
+#define SPMV_EINVAL  -1   /* NULL pointer, size or index out of range        */
+#define SPMV_ECSR    -2   /* malformed CSR: row_ptr not monotone, column out
+                             of range, columns unsorted or duplicated         */
+#define SPMV_EPLAN   -3   /* invalid operation order / stream map            */
+#define SPMV_ENOMEM  -4   /* host or device allocation failed                */
+#define SPMV_EHIP    -5   /* a HIP runtime call failed (message names it)    */
+#define SPMV_EBUDGET -6   /* serving: request does not fit the memory budget */
+#define SPMV_ESTATE  -7   /* call not valid in the object's current state    */
+
+/* ------------------------------------------------------------ operations
+ * DAG vertices of the SpMV program (Sec. III-A).  Table II types:
+ * CPU = start, PostSend, PostRecv, WaitSend, WaitRecv, end;
+ * GPU = Pack, y_L, Unpack, y_R (bound to a stream by the stream map).     */
+#define SPMV_OP_START      0
+#define SPMV_OP_PACK       1
+#define SPMV_OP_YL         2
+#define SPMV_OP_POST_SEND  3
+#define SPMV_OP_POST_RECV  4
+#define SPMV_OP_WAIT_SEND  5
+#define SPMV_OP_WAIT_RECV  6
+#define SPMV_OP_UNPACK     7
+#define SPMV_OP_YR         8
+#define SPMV_OP_END        9
+#define SPMV_N_VERTICES   10
+
+/* Synchronisation operations of Table III, inserted for a DAG edge u -> v:
+ *   GPU u -> CPU v:               CER-after-u, then CES-b4-v
+ *                                 (event record on u's stream; the host
+ *                                 blocks on that event before v)
+ *   GPU u -> GPU v, other stream: CER-after-u, then CSWE-b4-v
+ *                                 (v's stream waits on the event)
+ *   CPU u -> anything, GPU u -> GPU v on u's stream: nothing.
+ * A record captures all work issued to u's stream before the record token,
+ * not only u.  Edges into end need no tokens: end waits for everything.   */
+#define SPMV_SYNC_CER    0x10
+#define SPMV_SYNC_CES    0x20
+#define SPMV_SYNC_CSWE   0x30
+#define SPMV_CER_AFTER(u)  (SPMV_SYNC_CER  | (u))
+#define SPMV_CES_B4(v)     (SPMV_SYNC_CES  | (v))
+#define SPMV_CSWE_B4(v)    (SPMV_SYNC_CSWE | (v))
+
+#define SPMV_MAX_OPS     24   /* longest valid operation order              */
+#define SPMV_MAX_STREAMS  8
+
+/* ------------------------------------------------------------ types */
+
+/* Global matrix, host memory, borrowed for the duration of the call. */
+typedef struct {
+    int32_t        n_rows;
+    int32_t        n_cols;    /* must equal n_rows (square, same partition) */
+    int64_t        nnz;
+    const int32_t *row_ptr;   /* [n_rows + 1], row_ptr[0] = 0               */
+    const int32_t *col_idx;   /* [nnz], ascending inside each row           */
+    const double  *val;       /* [nnz]                                      */
+} spmv_csr_t;
+
+/* Kernel variant knobs (not part of the paper's plan; chosen by the tuner).
+ * Zero-initialised = automatic choice for every field.                    */
+typedef struct {
+    int32_t lanes_local;   /* lanes per row for y_L: 0 = auto, 1..64 pow2  */
+    int32_t lanes_remote;  /* lanes per row for y_R: 0 = auto, 1..64 pow2  */
+    int32_t xcd_remap;     /* 0 = auto, 1 = contiguous row tiles per XCD,
+                              2 = plain round-robin block order             */
+    int32_t fuse_unpack;   /* 0 = explicit Unpack kernel, 1 = y_R reads the
+                              receive buffer directly (valid because the
+                              receive layout equals the halo order)          */
+    int32_t flags;         /* SPMV_F_* below                               */
+    int32_t reserved[3];
+} spmv_tune_t;
+
+#define SPMV_F_HOST_ONLY  1  /* build metadata only: no device resources;
+                                inspection works, spmv_exec returns
+                                SPMV_ESTATE                                  */
+#define SPMV_F_PROFILE    2  /* time every GPU op and copy with HIP events   */
+
+typedef struct spmv_plan  spmv_plan_t;   /* opaque */
+
+typedef struct {
+    int64_t n_global;      /* rows of A                                     */
+    int64_t lo;            /* first owned global row                        */
+    int64_t n_loc;         /* owned rows                                    */
+    int64_t nnz_local;     /* entries of A_L                                */
+    int64_t nnz_remote;    /* entries of A_R                                */
+    int64_t n_halo;        /* |x_R|: distinct remote columns                */
+    int64_t n_send;        /* total entries packed for other ranks          */
+    int64_t n_remote_rows; /* owned rows with at least one remote entry     */
+    int64_t device_bytes;  /* device memory owned by the plan               */
+    int32_t nranks, rank;
+    int32_t n_streams;     /* plan streams (excluding the two copy streams) */
+    int32_t n_ops;         /* tokens in the canonical operation order        */
+    int32_t lanes_local, lanes_remote, xcd_remap, fuse_unpack;
+    int32_t fused_combine; /* 1: y_R adds into y itself; 0: a combine step
+                              at end adds the remote partial sums            */
+    int32_t reserved[3];
+} spmv_info_t;
+
+/* Integer metadata selectors for spmv_plan_get_i32. */
+#define SPMV_I32_HALO_COLS    0  /* [n_halo] global columns of x_R, ascending */
+#define SPMV_I32_RECV_OFF     1  /* [nranks+1] halo entries owned by rank q:
+                                    [recv_off[q], recv_off[q+1])             */
+#define SPMV_I32_SEND_IDX     2  /* [n_send] local x indices packed, grouped
+                                    by destination ascending, ascending      */
+#define SPMV_I32_SEND_OFF     3  /* [nranks+1]                                */
+#define SPMV_I32_AL_PTR       4  /* [n_loc+1] A_L row pointer                 */
+#define SPMV_I32_AL_COLS      5  /* [nnz_local] local column indices          */
+#define SPMV_I32_AR_ROWS      6  /* [n_remote_rows] local row ids, ascending  */
+#define SPMV_I32_AR_PTR       7  /* [n_remote_rows+1]                         */
+#define SPMV_I32_AR_COLS      8  /* [nnz_remote] index into the halo          */
+#define SPMV_I32_UNPACK_PERM  9  /* [n_halo] x_halo[p] = recv[perm[p]]        */
+#define SPMV_I32_OP_ORDER    10  /* [n_ops] canonical operation order          */
+#define SPMV_I32_STREAM_MAP  11  /* [SPMV_N_VERTICES] canonical streams, -1
+                                    for CPU vertices                          */
+
+/* FP64 selectors for spmv_plan_get_f64 (device contents are copied back). */
+#define SPMV_F64_AL_VAL       0  /* [nnz_local]                               */
+#define SPMV_F64_AR_VAL       1  /* [nnz_remote]                              */
+#define SPMV_F64_SENDBUF      2  /* [n_send] device send buffer after Pack    */
+#define SPMV_F64_RECVBUF      3  /* [n_halo] device receive buffer            */
+#define SPMV_F64_X_HALO       4  /* [n_halo] x_R after Unpack (equals RECVBUF
+                                    when fuse_unpack = 1)                     */
+#define SPMV_F64_OP_MS        5  /* [SPMV_N_VERTICES + 1] summed milliseconds
+                                    per op since the last reset (SPMV_F_PROFILE;
+                                    index SPMV_N_VERTICES = combine step)      */
+#define SPMV_F64_OP_COUNT     6  /* [SPMV_N_VERTICES + 1] timed launches       */
+
+/* ------------------------------------------------------------ plans */
+
+/*
+ * Build rank `rank`'s share of `csr` partitioned over `nranks` contiguous row
+ * blocks (rank q owns rows [q*floor(n/P) + min(q, n mod P), ...)), split it
+ * into A_L / A_R (Sec. III-A), derive the halo set and the send lists,
+ * validate the operation order, and allocate and upload everything the exec
+ * needs: device CSRs, send/receive buffers, pinned inbox/outbox, the plan
+ * streams, two private copy streams and the events.
+ *
+ *   csr        host, borrowed; validated (SPMV_ECSR on any defect)
+ *   nranks     >= 1; rank in [0, nranks)
+ *   op_order   host [n_ops] operation tokens (SPMV_OP_*, SPMV_CER_AFTER(u),
+ *              SPMV_CES_B4(v), SPMV_CSWE_B4(v)), or NULL for the default plan.
+ *              Must be a topological order of the DAG that starts with
+ *              START, ends with END and contains exactly the Table III
+ *              tokens its stream binding requires (SPMV_EPLAN otherwise).
+ *              UNPACK may be omitted: it is then run on y_R's stream
+ *              immediately before y_R.  With nranks == 1 the DAG is
+ *              START -> y_L -> END.
+ *   stream_map host [SPMV_N_VERTICES] stream of each GPU vertex (indexed by
+ *              SPMV_OP_*; entries of CPU vertices are ignored), values in
+ *              [0, n_streams); NULL = all on stream 0.  Streams are
+ *              relabelled by first use along the order (plans equal up to a
+ *              stream bijection are the same plan).
+ *   n_streams  1..SPMV_MAX_STREAMS plan streams
+ *   tune       kernel knobs, NULL = automatic
+ *   out        receives the plan; the caller owns it (spmv_plan_destroy)
+ *
+ * The caller may free every input on return.
+ */
+int spmv_plan_create(const spmv_csr_t *csr, int32_t nranks, int32_t rank,
+                     const int32_t *op_order, int32_t n_ops,
+                     const int32_t *stream_map, int32_t n_streams,
+                     spmv_plan_t **out);
+int spmv_plan_create_ex(const spmv_csr_t *csr, int32_t nranks, int32_t rank,
+                        const int32_t *op_order, int32_t n_ops,
+                        const int32_t *stream_map, int32_t n_streams,
+                        const spmv_tune_t *tune, spmv_plan_t **out);
+
+/* Release everything the plan owns.  NULL-safe. */
+int spmv_plan_destroy(spmv_plan_t *plan);
+
+/*
+ * One SpMV of the rank share: y_local = (A x)[lo, lo + n_loc).
+ *
+ *   x_local  device [n_loc] owned x entries (read only)
+ *   y_local  device [n_loc] result; must not alias x_local
+ *   stream   ordering anchor: the plan streams wait for work already issued
+ *            to `stream` at start, and `stream` waits for the plan at end
+ *
+ * The halo values are read from the plan's pinned inbox, which the caller
+ * fills beforehand (spmv_plan_inbox) with x at the halo columns, in halo
+ * order (the values the other ranks would send).  On return the outbox
+ * (spmv_plan_outbox) holds the packed send buffer.  The call runs the plan's
+ * operation order token by token and returns after end, i.e. with all work
+ * finished (host-synchronous, like the paper's end vertex).  Every plan
+ * gives bit-identical y: y[i] = fl(s_L[i] + s_R[i]) where the two partial
+ * sums do not depend on the plan.
+ */
+int spmv_exec(spmv_plan_t *plan, const double *x_local, double *y_local, void *stream);
+
+int spmv_plan_info(const spmv_plan_t *plan, spmv_info_t *info);
+
+/* Copy integer metadata `which` (SPMV_I32_*) into host out[0..n); n must be
+ * at least the selected array's length (SPMV_EINVAL otherwise). */
+int spmv_plan_get_i32(const spmv_plan_t *plan, int32_t which, int32_t *out, int64_t n);
+/* Copy FP64 data `which` (SPMV_F64_*) into host out[0..n) (synchronous). */
+int spmv_plan_get_f64(spmv_plan_t *plan, int32_t which, double *out, int64_t n);
+/* Zero the per-op timing accumulators of a SPMV_F_PROFILE plan. */
+int spmv_plan_reset_times(spmv_plan_t *plan);
+
+/* Pinned host buffers owned by the plan: the inbox [n_halo] the caller
+ * fills before spmv_exec, and the outbox [n_send] the exec fills. */
+int spmv_plan_inbox(spmv_plan_t *plan, double **host_ptr, int64_t *n);
+int spmv_plan_outbox(spmv_plan_t *plan, double **host_ptr, int64_t *n);
+
+/* ------------------------------------------------------------ plan space */
+
+/*
+ * Validate an operation order and stream map without building a plan
+ * (host only).  Same rules and error codes as spmv_plan_create.
+ */
+int spmv_plan_validate(int32_t nranks, const int32_t *op_order, int32_t n_ops,
+                       const int32_t *stream_map, int32_t n_streams);
+
+/*
+ * The design space of Sec. III-B/C: every topological order of the SpMV DAG
+ * with its Table III tokens, times every stream binding of the GPU vertices
+ * up to a stream bijection (Unpack implied before y_R).  Enumerated in a
+ * fixed depth-first order (ready tokens ascending by code, streams
+ * ascending), so index i names the same plan on every call.
+ *   nranks     1 (only START, y_L, END) or > 1 (the full DAG)
+ *   n_streams  1..SPMV_MAX_STREAMS
+ */
+int spmv_plan_space_count(int32_t nranks, int32_t n_streams, int64_t *count);
+/* Plan `index` of that space: op_order [SPMV_MAX_OPS] host out, *n_ops out,
+ * stream_map [SPMV_N_VERTICES] host out (-1 for CPU vertices). */
+int spmv_plan_space_get(int32_t nranks, int32_t n_streams, int64_t index,
+                        int32_t *op_order, int32_t *n_ops, int32_t *stream_map);
+
+/* Printable name of a token ("Pack", "CER-after-Pack", ...), the paper's
+ * names.  Writes at most cap bytes including the terminator; returns the
+ * full length, or SPMV_EINVAL for an unknown token. */
+int spmv_op_name(int32_t op, char *buf, int32_t cap);
+
+/* ------------------------------------------------------------ misc */
+
+const char *spmv_last_error(void);
+const char *spmv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPMV_H */

@@ -1,0 +1,306 @@
+"""MI355X (gfx950) row-partitioned SpMV: Python binding of ``libspmv.so``.
+
+Thin ctypes marshalling over the C ABI declared in ``include/spmv.h``; every
+step of the SpMV runs in the library's HIP kernels.  Function names match
+the C entry points.  Device arrays are passed as torch CUDA tensors (or raw
+integer device addresses), host arrays as numpy arrays.
+
+The library must be built first (``python -m paper_2203_02530_amd.build``);
+importing this package without it raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspmv.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build the HIP library with "
+        "`python -m paper_2203_02530_amd.build` (no CPU fallback exists)")
+
+# One HIP runtime per process: torch ships its own libamdhip64 (same soname
+# as ROCm's), and two runtimes in one process do not share the device.
+# Loading torch first makes the library bind to the runtime torch uses.
+try:
+    import torch  # noqa: F401
+except ImportError:  # pure C-ABI use without torch
+    torch = None
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+def _hip_runtimes() -> set:
+    try:
+        with open("/proc/self/maps") as f:
+            return {ln.split()[-1] for ln in f if "libamdhip64" in ln}
+    except OSError:
+        return set()
+
+
+if len(_hip_runtimes()) > 1:
+    raise ImportError("two HIP runtimes are loaded in this process "
+                      f"({sorted(_hip_runtimes())}); import torch before any other HIP library")
+
+# ------------------------------------------------------------ constants
+SPMV_OK, SPMV_EINVAL, SPMV_ECSR, SPMV_EPLAN = 0, -1, -2, -3
+SPMV_ENOMEM, SPMV_EHIP, SPMV_EBUDGET, SPMV_ESTATE = -4, -5, -6, -7
+
+SPMV_OP_START, SPMV_OP_PACK, SPMV_OP_YL, SPMV_OP_POST_SEND = 0, 1, 2, 3
+SPMV_OP_POST_RECV, SPMV_OP_WAIT_SEND, SPMV_OP_WAIT_RECV = 4, 5, 6
+SPMV_OP_UNPACK, SPMV_OP_YR, SPMV_OP_END, SPMV_N_VERTICES = 7, 8, 9, 10
+SPMV_SYNC_CER, SPMV_SYNC_CES, SPMV_SYNC_CSWE = 0x10, 0x20, 0x30
+SPMV_MAX_OPS, SPMV_MAX_STREAMS = 24, 8
+
+
+def SPMV_CER_AFTER(u): return SPMV_SYNC_CER | u
+def SPMV_CES_B4(v): return SPMV_SYNC_CES | v
+def SPMV_CSWE_B4(v): return SPMV_SYNC_CSWE | v
+
+
+SPMV_F_HOST_ONLY, SPMV_F_PROFILE = 1, 2
+
+(SPMV_I32_HALO_COLS, SPMV_I32_RECV_OFF, SPMV_I32_SEND_IDX, SPMV_I32_SEND_OFF,
+ SPMV_I32_AL_PTR, SPMV_I32_AL_COLS, SPMV_I32_AR_ROWS, SPMV_I32_AR_PTR,
+ SPMV_I32_AR_COLS, SPMV_I32_UNPACK_PERM, SPMV_I32_OP_ORDER,
+ SPMV_I32_STREAM_MAP) = range(12)
+(SPMV_F64_AL_VAL, SPMV_F64_AR_VAL, SPMV_F64_SENDBUF, SPMV_F64_RECVBUF,
+ SPMV_F64_X_HALO, SPMV_F64_OP_MS, SPMV_F64_OP_COUNT) = range(7)
+
+
+# ------------------------------------------------------------ structs
+class spmv_csr_t(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int32), ("n_cols", ctypes.c_int32),
+                ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class spmv_tune_t(ctypes.Structure):
+    _fields_ = [("lanes_local", ctypes.c_int32), ("lanes_remote", ctypes.c_int32),
+                ("xcd_remap", ctypes.c_int32), ("fuse_unpack", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class spmv_info_t(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in (
+        "n_global", "lo", "n_loc", "nnz_local", "nnz_remote", "n_halo", "n_send",
+        "n_remote_rows", "device_bytes")] + [(k, ctypes.c_int32) for k in (
+            "nranks", "rank", "n_streams", "n_ops", "lanes_local", "lanes_remote",
+            "xcd_remap", "fuse_unpack", "fused_combine")] + [("reserved", ctypes.c_int32 * 3)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_P = ctypes.c_void_p
+_I32, _I64 = ctypes.c_int32, ctypes.c_int64
+
+
+def _proto(name, args, res=ctypes.c_int):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_proto("spmv_plan_create", [_P, _I32, _I32, _P, _I32, _P, _I32, _P])
+_proto("spmv_plan_create_ex", [_P, _I32, _I32, _P, _I32, _P, _I32, _P, _P])
+_proto("spmv_plan_destroy", [_P])
+_proto("spmv_exec", [_P, _P, _P, _P])
+_proto("spmv_plan_info", [_P, _P])
+_proto("spmv_plan_get_i32", [_P, _I32, _P, _I64])
+_proto("spmv_plan_get_f64", [_P, _I32, _P, _I64])
+_proto("spmv_plan_reset_times", [_P])
+_proto("spmv_plan_inbox", [_P, _P, _P])
+_proto("spmv_plan_outbox", [_P, _P, _P])
+_proto("spmv_plan_validate", [_I32, _P, _I32, _P, _I32])
+_proto("spmv_plan_space_count", [_I32, _I32, _P])
+_proto("spmv_plan_space_get", [_I32, _I32, _I64, _P, _P, _P])
+_proto("spmv_op_name", [_I32, ctypes.c_char_p, _I32])
+_proto("spmv_last_error", [], ctypes.c_char_p)
+_proto("spmv_version", [], ctypes.c_char_p)
+
+
+class SpmvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise SpmvError(rc, _lib.spmv_last_error().decode(errors="replace"))
+    return rc
+
+
+def _addr(a) -> int:
+    """Address of a torch tensor, numpy array, int or None."""
+    if a is None:
+        return 0
+    if isinstance(a, int):
+        return a
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return int(a.data_ptr())
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        return 0
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def make_csr(A):
+    """spmv_csr_t view of a CSR (anything with n_rows, n_cols, row_ptr,
+    col_idx, val).  Returns (struct, keepalive)."""
+    rp = _i32(A.row_ptr)
+    ci = _i32(A.col_idx)
+    va = np.ascontiguousarray(A.val, dtype=np.float64)
+    c = spmv_csr_t(int(A.n_rows), int(A.n_cols), int(rp[-1]) if rp.size else 0,
+                   rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
+    return c, (rp, ci, va)
+
+
+# ------------------------------------------------------------ entry points
+def spmv_plan_create(A, nranks: int, rank: int, op_order=None, stream_map=None,
+                     n_streams: int = 2, tune: spmv_tune_t | dict | None = None):
+    """Build a plan for rank ``rank`` of ``nranks``; returns the plan handle."""
+    c, keep = make_csr(A)
+    ops = None if op_order is None else _i32(op_order)
+    smap = None
+    if stream_map is not None:
+        smap = np.full(SPMV_N_VERTICES, -1, np.int32)
+        if isinstance(stream_map, dict):
+            for k, v in stream_map.items():
+                smap[k] = v
+        else:
+            smap[:len(stream_map)] = stream_map
+    if isinstance(tune, dict):
+        t = spmv_tune_t()
+        for k, v in tune.items():
+            setattr(t, k, v)
+        tune = t
+    out = ctypes.c_void_p()
+    _check(_lib.spmv_plan_create_ex(
+        ctypes.byref(c), nranks, rank, _addr(ops), 0 if ops is None else ops.size,
+        _addr(smap), n_streams, ctypes.byref(tune) if tune is not None else None,
+        ctypes.byref(out)))
+    del keep
+    return out.value
+
+
+def spmv_plan_destroy(plan) -> None:
+    _check(_lib.spmv_plan_destroy(plan))
+
+
+def spmv_exec(plan, x, y, stream=None) -> None:
+    """y = (A x) over the plan's rows; x, y device arrays of n_loc FP64."""
+    _check(_lib.spmv_exec(plan, _addr(x), _addr(y), _stream_handle(stream)))
+
+
+def spmv_plan_info(plan) -> dict:
+    info = spmv_info_t()
+    _check(_lib.spmv_plan_info(plan, ctypes.byref(info)))
+    return info.as_dict()
+
+
+_I32_LEN = {
+    SPMV_I32_HALO_COLS: lambda i: i["n_halo"], SPMV_I32_RECV_OFF: lambda i: i["nranks"] + 1,
+    SPMV_I32_SEND_IDX: lambda i: i["n_send"], SPMV_I32_SEND_OFF: lambda i: i["nranks"] + 1,
+    SPMV_I32_AL_PTR: lambda i: i["n_loc"] + 1, SPMV_I32_AL_COLS: lambda i: i["nnz_local"],
+    SPMV_I32_AR_ROWS: lambda i: i["n_remote_rows"],
+    SPMV_I32_AR_PTR: lambda i: i["n_remote_rows"] + 1,
+    SPMV_I32_AR_COLS: lambda i: i["nnz_remote"], SPMV_I32_UNPACK_PERM: lambda i: i["n_halo"],
+    SPMV_I32_OP_ORDER: lambda i: i["n_ops"], SPMV_I32_STREAM_MAP: lambda i: SPMV_N_VERTICES,
+}
+_F64_LEN = {
+    SPMV_F64_AL_VAL: lambda i: i["nnz_local"], SPMV_F64_AR_VAL: lambda i: i["nnz_remote"],
+    SPMV_F64_SENDBUF: lambda i: i["n_send"], SPMV_F64_RECVBUF: lambda i: i["n_halo"],
+    SPMV_F64_X_HALO: lambda i: i["n_halo"], SPMV_F64_OP_MS: lambda i: SPMV_N_VERTICES + 1,
+    SPMV_F64_OP_COUNT: lambda i: SPMV_N_VERTICES + 1,
+}
+
+
+def spmv_plan_get_i32(plan, which: int) -> np.ndarray:
+    n = _I32_LEN[which](spmv_plan_info(plan))
+    out = np.empty(max(n, 1), np.int32)
+    _check(_lib.spmv_plan_get_i32(plan, which, out.ctypes.data, out.size))
+    return out[:n]
+
+
+def spmv_plan_get_f64(plan, which: int) -> np.ndarray:
+    n = _F64_LEN[which](spmv_plan_info(plan))
+    out = np.empty(max(n, 1), np.float64)
+    _check(_lib.spmv_plan_get_f64(plan, which, out.ctypes.data, out.size))
+    return out[:n]
+
+
+def spmv_plan_reset_times(plan) -> None:
+    _check(_lib.spmv_plan_reset_times(plan))
+
+
+def _mailbox(fn, plan) -> np.ndarray:
+    p = ctypes.c_void_p()
+    n = ctypes.c_int64()
+    _check(fn(plan, ctypes.byref(p), ctypes.byref(n)))
+    if n.value == 0:
+        return np.zeros(0, np.float64)
+    buf = (ctypes.c_double * n.value).from_address(p.value)
+    return np.frombuffer(buf, dtype=np.float64)
+
+
+def spmv_plan_inbox(plan) -> np.ndarray:
+    """Writable numpy view of the plan's pinned inbox (halo order)."""
+    return _mailbox(_lib.spmv_plan_inbox, plan)
+
+
+def spmv_plan_outbox(plan) -> np.ndarray:
+    """Numpy view of the plan's pinned outbox (packed send buffer)."""
+    return _mailbox(_lib.spmv_plan_outbox, plan)
+
+
+def spmv_plan_validate(nranks: int, op_order, stream_map=None, n_streams: int = 2) -> int:
+    """Returns SPMV_OK or the negative error code (no exception)."""
+    ops = _i32(op_order)
+    smap = None if stream_map is None else _i32(stream_map)
+    return _lib.spmv_plan_validate(nranks, _addr(ops), ops.size, _addr(smap), n_streams)
+
+
+def spmv_plan_space_count(nranks: int, n_streams: int) -> int:
+    n = ctypes.c_int64()
+    _check(_lib.spmv_plan_space_count(nranks, n_streams, ctypes.byref(n)))
+    return n.value
+
+
+def spmv_plan_space_get(nranks: int, n_streams: int, index: int):
+    """(op_order int32 array, stream_map int32 array[SPMV_N_VERTICES])."""
+    ops = np.empty(SPMV_MAX_OPS, np.int32)
+    smap = np.empty(SPMV_N_VERTICES, np.int32)
+    n = ctypes.c_int32()
+    _check(_lib.spmv_plan_space_get(nranks, n_streams, index, ops.ctypes.data,
+                                    ctypes.byref(n), smap.ctypes.data))
+    return ops[:n.value].copy(), smap
+
+
+def spmv_op_name(op: int) -> str:
+    buf = ctypes.create_string_buffer(64)
+    _check(_lib.spmv_op_name(op, buf, 64))
+    return buf.value.decode()
+
+
+def spmv_last_error() -> str:
+    return _lib.spmv_last_error().decode(errors="replace")
+
+
+def spmv_version() -> str:
+    return _lib.spmv_version().decode()

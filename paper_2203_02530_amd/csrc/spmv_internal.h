@@ -1,0 +1,102 @@
+// Internal declarations of the SpMV library (not part of the C ABI).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "spmv.h"
+
+namespace spmv {
+
+// ----------------------------------------------------------------- errors
+// Thread-local message behind spmv_last_error(); set_error returns `code` so
+// call sites can `return set_error(...)`.
+int set_error(int code, const std::string &msg);
+int hip_error(hipError_t e, const char *what);
+void clear_error();
+
+#define SPMV_HIP(call)                                                    \
+    do {                                                                  \
+        hipError_t e__ = (call);                                          \
+        if (e__ != hipSuccess) return ::spmv::hip_error(e__, #call);      \
+    } while (0)
+
+// ----------------------------------------------------------------- share
+// One rank's share of the global matrix (Sec. III-A), host side.
+struct Share {
+    int64_t n_global = 0, lo = 0, n_loc = 0;
+    int32_t nranks = 1, rank = 0;
+    // A_L: local columns renumbered to col - lo
+    std::vector<int32_t> L_ptr, L_col;
+    std::vector<double> L_val;
+    // A_R over the rows that have remote entries; columns index the halo
+    std::vector<int32_t> R_rows, R_ptr, R_col;
+    std::vector<double> R_val;
+    // halo: ascending global columns; recv_off[q] .. recv_off[q+1] owned by q
+    std::vector<int32_t> halo, recv_off;
+    // send lists: local indices each destination needs, dest ascending
+    std::vector<int32_t> send_idx, send_off;
+    // x_halo[p] = recv[perm[p]]; identity under the layout above
+    std::vector<int32_t> unpack_perm;
+};
+
+int validate_csr(const spmv_csr_t *csr);
+int64_t block_lo(int64_t n, int32_t P, int32_t q);
+int build_share(const spmv_csr_t *csr, int32_t nranks, int32_t rank, Share &out);
+
+// ----------------------------------------------------------------- DAG
+enum class VType : uint8_t { CPU, GPU };
+VType vertex_type(int32_t v);
+bool is_vertex(int32_t tok);
+bool is_sync(int32_t tok);
+inline int32_t sync_kind(int32_t tok) { return tok & 0x30; }
+inline int32_t sync_operand(int32_t tok) { return tok & 0x0f; }
+
+// A validated, canonical plan: order of tokens, canonical stream per vertex
+// (-1 for CPU vertices), explicit or implied Unpack.
+struct Schedule {
+    std::vector<int32_t> order;            // as given (Unpack inserted if implied)
+    int32_t stream[SPMV_N_VERTICES];        // canonical stream of GPU vertices
+    int32_t n_streams_used = 0;
+    bool unpack_implied = false;
+    bool multi = false;                     // nranks > 1
+};
+
+int validate_schedule(int32_t nranks, const int32_t *ops, int32_t n_ops,
+                      const int32_t *stream_map, int32_t n_streams, Schedule &out);
+void default_order(int32_t nranks, std::vector<int32_t> &ops, int32_t *stream_map);
+int op_name(int32_t tok, std::string &out);
+
+// Plan-space enumeration (cached per (multi, n_streams)).
+struct PlanEntry {
+    std::vector<int32_t> order;
+    int32_t stream[SPMV_N_VERTICES];
+};
+const std::vector<PlanEntry> &plan_space(bool multi, int32_t n_streams);
+
+// ----------------------------------------------------------------- kernels
+// Launchers (spmv_kernels.hip).  All are asynchronous on `s` and launch
+// nothing for empty inputs.
+struct CsrDev {
+    int32_t n_rows = 0;            // rows computed by the kernel
+    const int32_t *rp = nullptr;   // [n_rows + 1]
+    const int32_t *col = nullptr;
+    const double *val = nullptr;
+    const int32_t *rows = nullptr; // compressed-row ids (remote), else null
+};
+
+hipError_t launch_pack(const double *x, const int32_t *idx, double *out, int64_t n,
+                       hipStream_t s);
+hipError_t launch_unpack(const double *recv, const int32_t *perm, double *xh, int64_t n,
+                         hipStream_t s);
+// y[row] = sum (store) or y[rows[j]] += sum (accumulate) when acc_into != null
+hipError_t launch_csr(const CsrDev &A, const double *x, double *out, double *acc_into,
+                      int lanes, int xcd_remap, hipStream_t s);
+hipError_t launch_combine(const int32_t *rows, const double *part, double *y, int64_t n,
+                          hipStream_t s);
+int auto_lanes(int64_t nnz, int64_t rows);
+
+}  // namespace spmv

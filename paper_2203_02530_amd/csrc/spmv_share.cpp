@@ -1,0 +1,172 @@
+// Host side of the rank share: CSR validation, the contiguous row-block
+// partition, the A = A_L + A_R split, the halo x_R and the send lists
+// (Sec. III-A of the paper).  Runs once per plan: A is static, only the
+// values of x change between products.
+#include <algorithm>
+#include <cstring>
+
+#include "spmv_internal.h"
+
+namespace spmv {
+
+int validate_csr(const spmv_csr_t *csr)
+{
+    if (!csr) return set_error(SPMV_EINVAL, "csr is NULL");
+    if (csr->n_rows < 0 || csr->n_cols < 0 || csr->nnz < 0)
+        return set_error(SPMV_EINVAL, "negative CSR size");
+    if (csr->n_rows != csr->n_cols)
+        return set_error(SPMV_EINVAL, "matrix must be square: rows, x and y share one partition");
+    if (csr->nnz >= (int64_t(1) << 31))
+        return set_error(SPMV_EINVAL, "nnz does not fit int32 indexing");
+    if (!csr->row_ptr) return set_error(SPMV_EINVAL, "row_ptr is NULL");
+    if (csr->nnz > 0 && (!csr->col_idx || !csr->val))
+        return set_error(SPMV_EINVAL, "col_idx/val is NULL");
+    const int32_t *rp = csr->row_ptr;
+    if (rp[0] != 0) return set_error(SPMV_ECSR, "row_ptr[0] != 0");
+    if (rp[csr->n_rows] != csr->nnz)
+        return set_error(SPMV_ECSR, "row_ptr[n_rows] != nnz");
+    for (int32_t i = 0; i < csr->n_rows; ++i) {
+        if (rp[i + 1] < rp[i])
+            return set_error(SPMV_ECSR, "row_ptr decreases at row " + std::to_string(i));
+        int32_t prev = -1;
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            int32_t c = csr->col_idx[k];
+            if (c < 0 || c >= csr->n_cols)
+                return set_error(SPMV_ECSR, "column out of range in row " + std::to_string(i));
+            if (c <= prev)
+                return set_error(SPMV_ECSR, "columns not strictly ascending in row " +
+                                                std::to_string(i));
+            prev = c;
+        }
+    }
+    return SPMV_OK;
+}
+
+// Rank q owns rows [block_lo(q), block_lo(q+1)): the rows are divided evenly,
+// and when P does not divide n the first n mod P ranks take one extra row.
+int64_t block_lo(int64_t n, int32_t P, int32_t q)
+{
+    return int64_t(q) * (n / P) + std::min<int64_t>(q, n % P);
+}
+
+int build_share(const spmv_csr_t *csr, int32_t P, int32_t r, Share &S)
+{
+    if (int rc = validate_csr(csr)) return rc;
+    if (P < 1) return set_error(SPMV_EINVAL, "nranks < 1");
+    if (r < 0 || r >= P) return set_error(SPMV_EINVAL, "rank out of range");
+    const int64_t n = csr->n_rows;
+    const int32_t *rp = csr->row_ptr, *ci = csr->col_idx;
+    const double *va = csr->val;
+    const int64_t lo = block_lo(n, P, r), hi = block_lo(n, P, r + 1);
+    const int64_t nl = hi - lo;
+    S = Share();
+    S.n_global = n;
+    S.lo = lo;
+    S.n_loc = nl;
+    S.nranks = P;
+    S.rank = r;
+
+    // A_L and the set of remote columns.
+    std::vector<uint8_t> remote_mark(size_t(n), 0);
+    S.L_ptr.assign(size_t(nl) + 1, 0);
+    int64_t nnz_rem = 0;
+    for (int64_t i = 0; i < nl; ++i) {
+        int32_t cnt = 0;
+        for (int32_t k = rp[lo + i]; k < rp[lo + i + 1]; ++k) {
+            int32_t c = ci[k];
+            if (c >= lo && c < hi) {
+                ++cnt;
+            } else {
+                remote_mark[size_t(c)] = 1;
+                ++nnz_rem;
+            }
+        }
+        S.L_ptr[size_t(i) + 1] = S.L_ptr[size_t(i)] + cnt;
+    }
+    const int64_t nnz_loc = S.L_ptr[size_t(nl)];
+    S.L_col.resize(size_t(nnz_loc));
+    S.L_val.resize(size_t(nnz_loc));
+
+    // Halo in ascending global column order; owners are contiguous blocks,
+    // so the halo is grouped by owner rank in ascending order.
+    std::vector<int32_t> halo_index(size_t(n), -1);
+    for (int64_t c = 0; c < n; ++c)
+        if (remote_mark[size_t(c)]) {
+            halo_index[size_t(c)] = int32_t(S.halo.size());
+            S.halo.push_back(int32_t(c));
+        }
+    S.recv_off.resize(size_t(P) + 1);
+    for (int32_t q = 0; q <= P; ++q)
+        S.recv_off[size_t(q)] = int32_t(
+            std::lower_bound(S.halo.begin(), S.halo.end(), block_lo(n, P, q)) - S.halo.begin());
+
+    // Fill A_L values and A_R over the rows that touch the halo.
+    S.R_ptr.push_back(0);
+    S.R_col.reserve(size_t(nnz_rem));
+    S.R_val.reserve(size_t(nnz_rem));
+    for (int64_t i = 0; i < nl; ++i) {
+        int32_t w = S.L_ptr[size_t(i)];
+        int32_t rcount = 0;
+        for (int32_t k = rp[lo + i]; k < rp[lo + i + 1]; ++k) {
+            int32_t c = ci[k];
+            if (c >= lo && c < hi) {
+                S.L_col[size_t(w)] = int32_t(c - lo);
+                S.L_val[size_t(w)] = va[k];
+                ++w;
+            } else {
+                S.R_col.push_back(halo_index[size_t(c)]);
+                S.R_val.push_back(va[k]);
+                ++rcount;
+            }
+        }
+        if (rcount) {
+            S.R_rows.push_back(int32_t(i));
+            S.R_ptr.push_back(S.R_ptr.back() + rcount);
+        }
+    }
+
+    // Send lists: for each other rank q, the owned columns appearing in q's
+    // rows, as local indices, ascending.  A stamp per local index avoids
+    // clearing a marker between destinations.
+    std::vector<int32_t> stamp(size_t(nl), -1);
+    S.send_off.assign(size_t(P) + 1, 0);
+    for (int32_t q = 0; q < P; ++q) {
+        S.send_off[size_t(q) + 1] = S.send_off[size_t(q)];
+        if (q == r) continue;
+        const int64_t qlo = block_lo(n, P, q), qhi = block_lo(n, P, q + 1);
+        int64_t found = 0;
+        for (int32_t k = rp[qlo]; k < rp[qhi]; ++k) {
+            int32_t c = ci[k];
+            if (c >= lo && c < hi && stamp[size_t(c - lo)] != q) {
+                stamp[size_t(c - lo)] = q;
+                ++found;
+            }
+        }
+        if (!found) continue;
+        const size_t base = S.send_idx.size();
+        if (found * 8 < nl) {
+            // few entries: collect and sort
+            for (int32_t k = rp[qlo]; k < rp[qhi]; ++k) {
+                int32_t c = ci[k];
+                if (c >= lo && c < hi && stamp[size_t(c - lo)] == q) {
+                    stamp[size_t(c - lo)] = P + q;  // collected
+                    S.send_idx.push_back(int32_t(c - lo));
+                }
+            }
+            std::sort(S.send_idx.begin() + long(base), S.send_idx.end());
+        } else {
+            for (int64_t j = 0; j < nl; ++j)
+                if (stamp[size_t(j)] == q) {
+                    S.send_idx.push_back(int32_t(j));
+                    stamp[size_t(j)] = P + q;
+                }
+        }
+        S.send_off[size_t(q) + 1] = int32_t(S.send_idx.size());
+    }
+
+    S.unpack_perm.resize(S.halo.size());
+    for (size_t p = 0; p < S.halo.size(); ++p) S.unpack_perm[p] = int32_t(p);
+    return SPMV_OK;
+}
+
+}  // namespace spmv

@@ -1,0 +1,278 @@
+"""Host-side checks of the C-ABI library (no GPU work is launched).
+
+* the shared library loads and exports every function include/spmv.h declares;
+* the plan validator and the plan-space enumerator agree with the oracle's
+  brute force over permutations (same set of plans, by operation names);
+* host-only plans build the rank share bit-exactly like the oracle;
+* malformed CSRs and invalid plans return the documented error codes.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+import paper_2203_02530_amd as sp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+NAME_OF = {sp.SPMV_OP_START: "start", sp.SPMV_OP_PACK: "Pack", sp.SPMV_OP_YL: "yL",
+           sp.SPMV_OP_POST_SEND: "PostSend", sp.SPMV_OP_POST_RECV: "PostRecv",
+           sp.SPMV_OP_WAIT_SEND: "WaitSend", sp.SPMV_OP_WAIT_RECV: "WaitRecv",
+           sp.SPMV_OP_UNPACK: "Unpack", sp.SPMV_OP_YR: "yR", sp.SPMV_OP_END: "end"}
+CODE_OF = {v: k for k, v in NAME_OF.items()}
+CODE_OF["CER-after-Pack"] = sp.SPMV_CER_AFTER(sp.SPMV_OP_PACK)
+CODE_OF["CES-b4-PostSend"] = sp.SPMV_CES_B4(sp.SPMV_OP_POST_SEND)
+HOST_ONLY = {"flags": sp.SPMV_F_HOST_ONLY}
+
+
+def setup_module(_):
+    oracle.build(force=False)
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "spmv.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(spmv_[a-z0-9_]+)\s*\(", txt)) - {
+        "spmv_CER_AFTER", "spmv_CES_B4", "spmv_CSWE_B4"})
+
+
+def test_library_exports_every_declared_function():
+    lib = ctypes.CDLL(sp.LIB_PATH)
+    names = _header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_op_names_match_paper():
+    for name, code in CODE_OF.items():
+        assert sp.spmv_op_name(code) == name
+    with pytest.raises(sp.SpmvError):
+        sp.spmv_op_name(0x7f)
+
+
+# ------------------------------------------------------------ plan space
+
+def _library_space(nranks, S):
+    out = set()
+    for i in range(sp.spmv_plan_space_count(nranks, S)):
+        ops, smap = sp.spmv_plan_space_get(nranks, S, i)
+        names = tuple(sp.spmv_op_name(int(o)) for o in ops)
+        out.add((names, (int(smap[sp.SPMV_OP_PACK]), int(smap[sp.SPMV_OP_YL]),
+                         int(smap[sp.SPMV_OP_YR]))))
+    return out
+
+
+@pytest.mark.parametrize("S", [1, 2, 3])
+def test_plan_space_equals_oracle_brute_force(S):
+    lib = _library_space(4, S)
+    ref = oracle.plan_space(S)
+    assert len(lib) == sp.spmv_plan_space_count(4, S)   # no duplicates
+    assert lib == ref
+
+
+def test_plan_space_every_entry_validates():
+    for i in range(sp.spmv_plan_space_count(4, 2)):
+        ops, smap = sp.spmv_plan_space_get(4, 2, i)
+        assert sp.spmv_plan_validate(4, ops, smap, 2) == sp.SPMV_OK
+
+
+def test_single_rank_space():
+    assert sp.spmv_plan_space_count(1, 2) == 1
+    ops, smap = sp.spmv_plan_space_get(1, 2, 0)
+    assert ops.tolist() == [sp.SPMV_OP_START, sp.SPMV_OP_YL, sp.SPMV_OP_END]
+
+
+def _codes(names):
+    return [CODE_OF[n] for n in names]
+
+
+def _paper_sequence(numbers):
+    """A paper traversal (vertex numbers, Sec. III-A) with the Table III pair
+    inserted right before PostSend and Unpack left implied."""
+    num = {1: "start", 2: "Pack", 3: "yL", 4: "PostSend", 5: "PostRecv",
+           6: "WaitSend", 7: "WaitRecv", 8: "Unpack", 9: "yR", 10: "end"}
+    out = []
+    for v in numbers:
+        name = num[v]
+        if name == "Unpack":
+            continue
+        if name == "PostSend":
+            out += ["CER-after-Pack", "CES-b4-PostSend"]
+        out.append(name)
+    return out
+
+
+def test_paper_sequences_validate():
+    smap = np.full(10, -1, np.int32)
+    smap[[sp.SPMV_OP_PACK, sp.SPMV_OP_YL, sp.SPMV_OP_YR]] = [0, 1, 0]
+    for seq in ([1, 2, 3, 4, 5, 6, 7, 8, 9, 10], [1, 5, 3, 2, 4, 7, 6, 8, 9, 10]):
+        assert sp.spmv_plan_validate(4, _codes(_paper_sequence(seq)), smap, 2) == sp.SPMV_OK
+
+
+def _swap(o, a, b):
+    i, j = o.index(a), o.index(b)
+    o[i], o[j] = o[j], o[i]
+    return o
+
+
+BASE = ["start", "PostRecv", "Pack", "CER-after-Pack", "yL", "CES-b4-PostSend",
+        "PostSend", "WaitRecv", "yR", "WaitSend", "end"]
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda o: [t for t in o if t != "CES-b4-PostSend"], sp.SPMV_EPLAN),          # missing sync
+    (lambda o: [t for t in o if t != "CER-after-Pack"], sp.SPMV_EPLAN),
+    (lambda o: o[:1] + ["PostSend"] + [t for t in o[1:] if t != "PostSend"], sp.SPMV_EPLAN),
+    (lambda o: ["Pack"] + [t for t in o if t != "Pack"], sp.SPMV_EPLAN),          # start not first
+    (lambda o: o[:-1], sp.SPMV_EPLAN),                                               # no end
+    (lambda o: o[:2] + ["yL"] + o[2:], sp.SPMV_EPLAN),                               # duplicate
+    (lambda o: [t for t in o if t != "WaitRecv"], sp.SPMV_EPLAN),                    # missing vertex
+    (lambda o: _swap(o, "WaitRecv", "yR"), sp.SPMV_EPLAN),                          # yR before WaitRecv
+    (lambda o: _swap(o, "CER-after-Pack", "CES-b4-PostSend"), sp.SPMV_EPLAN),       # wait before record
+])
+def test_invalid_plans_rejected(mutate, code):
+    smap = np.full(10, -1, np.int32)
+    smap[[sp.SPMV_OP_PACK, sp.SPMV_OP_YL, sp.SPMV_OP_YR]] = [0, 1, 1]
+    assert sp.spmv_plan_validate(4, _codes(BASE), smap, 2) == sp.SPMV_OK
+    assert sp.spmv_plan_validate(4, _codes(mutate(list(BASE))), smap, 2) == code
+
+
+def test_invalid_tokens_and_streams():
+    smap = np.full(10, -1, np.int32)
+    smap[[sp.SPMV_OP_PACK, sp.SPMV_OP_YL, sp.SPMV_OP_YR]] = [0, 1, 2]
+    assert sp.spmv_plan_validate(4, _codes(BASE), smap, 2) == sp.SPMV_EPLAN    # stream 2 of 2
+    bad = _codes(BASE)
+    bad.insert(3, 0x7f)
+    smap[sp.SPMV_OP_YR] = 1
+    assert sp.spmv_plan_validate(4, bad, smap, 2) == sp.SPMV_EPLAN             # unknown token
+    extra = _codes(BASE)
+    extra.insert(5, sp.SPMV_CER_AFTER(sp.SPMV_OP_YL))
+    assert sp.spmv_plan_validate(4, extra, smap, 2) == sp.SPMV_EPLAN           # unneeded sync
+    assert sp.spmv_plan_validate(4, _codes(BASE), smap, 0) == sp.SPMV_EINVAL
+    # single-rank DAG has no Pack
+    assert sp.spmv_plan_validate(1, _codes(["start", "Pack", "yL", "end"]), smap, 1) == sp.SPMV_EPLAN
+    assert sp.spmv_plan_validate(1, _codes(["start", "yL", "end"]), smap, 1) == sp.SPMV_EPLAN
+    assert sp.spmv_plan_validate(1, _codes(["start", "yL", "end"]), None, 1) == sp.SPMV_OK
+
+
+def test_explicit_unpack_on_other_stream_needs_stream_wait():
+    """Table III, GPU -> GPU across streams: a record after Unpack and a
+    stream wait before y_R."""
+    smap = np.full(10, -1, np.int32)
+    smap[[sp.SPMV_OP_PACK, sp.SPMV_OP_YL, sp.SPMV_OP_UNPACK, sp.SPMV_OP_YR]] = [0, 1, 0, 1]
+    ops = _codes(BASE)
+    i = ops.index(sp.SPMV_OP_YR)
+    no_sync = ops[:i] + [sp.SPMV_OP_UNPACK] + ops[i:]
+    assert sp.spmv_plan_validate(4, no_sync, smap, 2) == sp.SPMV_EPLAN
+    with_sync = ops[:i] + [sp.SPMV_OP_UNPACK, sp.SPMV_CER_AFTER(sp.SPMV_OP_UNPACK),
+                           sp.SPMV_CSWE_B4(sp.SPMV_OP_YR)] + ops[i:]
+    assert sp.spmv_plan_validate(4, with_sync, smap, 2) == sp.SPMV_OK
+    smap[sp.SPMV_OP_UNPACK] = 1    # same stream: the tokens become superfluous
+    assert sp.spmv_plan_validate(4, with_sync, smap, 2) == sp.SPMV_EPLAN
+    assert sp.spmv_plan_validate(4, no_sync, smap, 2) == sp.SPMV_OK
+
+
+def test_stream_canonicalisation():
+    A = gen.laplacian_3d7(8)
+    smap = np.full(10, -1, np.int32)
+    smap[[sp.SPMV_OP_PACK, sp.SPMV_OP_YL, sp.SPMV_OP_YR]] = [2, 0, 2]
+    p = sp.spmv_plan_create(A, 2, 0, _codes(BASE), smap, 3, tune=HOST_ONLY)
+    try:
+        m = sp.spmv_plan_get_i32(p, sp.SPMV_I32_STREAM_MAP)
+        # Pack is the first GPU op in BASE: stream 0; y_L next: stream 1
+        assert (m[sp.SPMV_OP_PACK], m[sp.SPMV_OP_YL], m[sp.SPMV_OP_YR]) == (0, 1, 0)
+        assert m[sp.SPMV_OP_UNPACK] == m[sp.SPMV_OP_YR]
+    finally:
+        sp.spmv_plan_destroy(p)
+
+
+# ------------------------------------------------------------ share metadata
+
+def _share_matches_oracle(A, P, r):
+    ref = oracle.split(A, P, r)
+    p = sp.spmv_plan_create(A, P, r, tune=HOST_ONLY)
+    try:
+        info = sp.spmv_plan_info(p)
+        assert info["lo"] == ref["lo"] and info["n_loc"] == ref["n_loc"]
+        g = lambda w: sp.spmv_plan_get_i32(p, w)
+        pairs = [(sp.SPMV_I32_HALO_COLS, "H"), (sp.SPMV_I32_RECV_OFF, "recv_off"),
+                 (sp.SPMV_I32_SEND_IDX, "send_idx"), (sp.SPMV_I32_SEND_OFF, "send_off"),
+                 (sp.SPMV_I32_AL_PTR, "L_ptr"), (sp.SPMV_I32_AL_COLS, "L_col"),
+                 (sp.SPMV_I32_AR_ROWS, "R_rows"), (sp.SPMV_I32_AR_PTR, "R_ptr"),
+                 (sp.SPMV_I32_AR_COLS, "R_col")]
+        for w, k in pairs:
+            assert np.array_equal(g(w), ref[k]), k
+        assert np.array_equal(g(sp.SPMV_I32_UNPACK_PERM), np.arange(ref["H"].size))
+        for w, k in [(sp.SPMV_F64_AL_VAL, "L_val"), (sp.SPMV_F64_AR_VAL, "R_val")]:
+            assert np.array_equal(sp.spmv_plan_get_f64(p, w).view(np.int64),
+                                  ref[k].view(np.int64)), k
+    finally:
+        sp.spmv_plan_destroy(p)
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 4, 7])
+def test_share_metadata_banded(P):
+    A = gen.banded_uniform(2000, 10, 500, seed=3)
+    for r in range(P):
+        _share_matches_oracle(A, P, r)
+
+
+def test_share_metadata_stencils_and_powerlaw():
+    _share_matches_oracle(gen.laplacian_3d7(16), 4, 1)
+    _share_matches_oracle(gen.stencil_3d27(12, seed=3), 8, 3)
+    _share_matches_oracle(gen.laplacian_2d5(64), 1, 0)
+    A = gen.power_law(20000, seed=5)
+    for r in (0, 5, 15):
+        _share_matches_oracle(A, 16, r)
+
+
+def test_share_metadata_more_ranks_than_rows():
+    A = gen.laplacian_2d5(2, 2)      # 4 rows, 6 ranks: ranks 4, 5 own nothing
+    for r in range(6):
+        _share_matches_oracle(A, 6, r)
+
+
+def test_malformed_csr_rejected():
+    A = gen.laplacian_2d5(4)
+    bad_cols = gen.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx.copy(), A.val)
+    bad_cols.col_idx[3] = 99
+    unsorted = gen.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx.copy(), A.val)
+    unsorted.col_idx[[0, 1]] = unsorted.col_idx[[1, 0]]
+    bad_ptr = gen.CSR(A.n_rows, A.n_cols, A.row_ptr.copy(), A.col_idx, A.val)
+    bad_ptr.row_ptr[2] = bad_ptr.row_ptr[3] + 1
+    for M in (bad_cols, unsorted, bad_ptr):
+        with pytest.raises(sp.SpmvError) as e:
+            sp.spmv_plan_create(M, 2, 0, tune=HOST_ONLY)
+        assert e.value.code == sp.SPMV_ECSR
+    with pytest.raises(sp.SpmvError) as e:
+        sp.spmv_plan_create(A, 2, 2, tune=HOST_ONLY)
+    assert e.value.code == sp.SPMV_EINVAL
+    with pytest.raises(sp.SpmvError) as e:
+        sp.spmv_plan_create(A, 2, 0, tune={"flags": sp.SPMV_F_HOST_ONLY, "lanes_local": 3})
+    assert e.value.code == sp.SPMV_EINVAL
+
+
+def test_host_only_plan_refuses_exec():
+    A = gen.laplacian_2d5(4)
+    p = sp.spmv_plan_create(A, 1, 0, tune=HOST_ONLY)
+    try:
+        with pytest.raises(sp.SpmvError) as e:
+            sp.spmv_exec(p, 0, 0)
+        assert e.value.code == sp.SPMV_ESTATE
+    finally:
+        sp.spmv_plan_destroy(p)
+
+
+def test_default_plan_fuses_combine():
+    A = gen.laplacian_3d7(8)
+    p = sp.spmv_plan_create(A, 2, 1, tune=HOST_ONLY)
+    try:
+        info = sp.spmv_plan_info(p)
+        assert info["fused_combine"] == 1 and info["lanes_local"] == 8
+    finally:
+        sp.spmv_plan_destroy(p)

@@ -1,0 +1,209 @@
+"""GPU parity of the rank-share SpMV against the CPU oracle, through the C ABI.
+
+Bar: send buffer, receive buffer and halo bit-exact; y within
+1e-12 * (|A||x|)_i per row; integer-valued stencil products bit-exact; every
+plan of the design space bit-identical to every other.
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+import paper_2203_02530_amd as sp
+from gpu_util import assert_share_parity, bits, log, run_share
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    oracle.build(force=False)
+    yield
+
+
+# ------------------------------------------------------------ single rank
+
+def test_laplace2d_64_single_rank():
+    A = gen.laplacian_2d5(64)
+    x = gen.x_uniform(A.n_cols, 1)
+    log("laplace2d 64x64 P=1 uniform x")
+    res, ref = run_share(A, 1, 0, x)
+    assert res["info"]["n_halo"] == 0 and res["info"]["n_ops"] == 3
+    assert_share_parity(res, ref)
+
+
+@pytest.mark.parametrize("xkind", ["ones", "integer"])
+def test_laplace_integer_vectors_bit_exact(xkind):
+    for A, P, r in [(gen.laplacian_2d5(64), 1, 0), (gen.laplacian_3d7(32), 4, 1)]:
+        x = np.ones(A.n_cols) if xkind == "ones" else gen.x_integer(A.n_cols, 7)
+        log(f"integer vector {xkind} n={A.n_rows} P={P}")
+        res, ref = run_share(A, P, r, x)
+        assert np.array_equal(bits(res["y"]), bits(ref["y"]))
+
+
+# ------------------------------------------------------------ multi rank
+
+CASES = [
+    ("laplace3d_16_p4", lambda: gen.laplacian_3d7(16), 4, [0, 1, 3], lambda n: gen.x_uniform(n, 2)),
+    ("banded_3000_p4", lambda: gen.banded_uniform(3000, 10, 750, seed=100), 4, [0, 1, 2, 3],
+     lambda n: gen.x_normal(n, 101)),
+    ("stencil27_12_p8", lambda: gen.stencil_3d27(12, seed=3), 8, [0, 3, 7],
+     lambda n: gen.x_normal(n, 30)),
+    ("powerlaw_20k_p16", lambda: gen.power_law(20000, seed=4000), 16, [0, 5, 15],
+     lambda n: gen.x_normal(n, 4100)),
+    ("ragged_1001_p3", lambda: gen.banded_random(1001, seed=9), 3, [0, 1, 2],
+     lambda n: gen.x_normal(n, 11)),
+]
+
+
+@pytest.mark.parametrize("name,build,P,ranks,xf", CASES, ids=[c[0] for c in CASES])
+def test_share_default_plan(name, build, P, ranks, xf):
+    A = build()
+    x = xf(A.n_cols)
+    for r in ranks:
+        log(f"{name} rank {r}")
+        res, ref = run_share(A, P, r, x)
+        assert_share_parity(res, ref)
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("remap", [1, 2])
+def test_lane_variants(lanes, remap):
+    A = gen.power_law(30000, seed=17)
+    x = gen.x_normal(A.n_cols, 18)
+    log(f"power-law 30k lanes={lanes} remap={remap}")
+    for fuse in (0, 1):
+        res, ref = run_share(A, 4, 2, x, tune={"lanes_local": lanes, "lanes_remote": lanes,
+                                               "xcd_remap": remap, "fuse_unpack": fuse})
+        assert_share_parity(res, ref)
+
+
+def test_every_plan_bit_identical():
+    """All 2016 plans of the design space give the same y bits (missing
+    synchronisation or a race would break this) and pass parity."""
+    A = gen.banded_uniform(6000, 10, 1500, seed=21)
+    x = gen.x_normal(A.n_cols, 22)
+    P, r = 4, 1
+    ref = oracle.share_reference(A, P, r, x)
+    n = sp.spmv_plan_space_count(P, 2)
+    assert n == 2016
+    first = None
+    fused = 0
+    for i in range(n):
+        if i % 500 == 0:
+            log(f"plan {i}/{n}")
+        ops, smap = sp.spmv_plan_space_get(P, 2, i)
+        res, _ = run_share(A, P, r, x, ops, smap, 2, ref=ref)
+        fused += res["info"]["fused_combine"]
+        if first is None:
+            assert_share_parity(res, ref)
+            first = bits(res["y"])
+        else:
+            assert np.array_equal(bits(res["y"]), first), i
+            assert np.array_equal(bits(res["outbox"]), bits(ref["sendbuf"])), i
+    assert 0 < fused < n   # both the fused and the combine path were exercised
+
+
+def test_three_streams_and_explicit_unpack():
+    A = gen.banded_uniform(4000, 10, 1000, seed=5)
+    x = gen.x_normal(A.n_cols, 6)
+    ref = oracle.share_reference(A, 4, 2, x)
+    O = sp
+    ops = [O.SPMV_OP_START, O.SPMV_OP_POST_RECV, O.SPMV_OP_PACK, O.SPMV_CER_AFTER(O.SPMV_OP_PACK),
+           O.SPMV_OP_YL, O.SPMV_CES_B4(O.SPMV_OP_POST_SEND), O.SPMV_OP_POST_SEND,
+           O.SPMV_OP_WAIT_RECV, O.SPMV_OP_UNPACK, O.SPMV_CER_AFTER(O.SPMV_OP_UNPACK),
+           O.SPMV_CSWE_B4(O.SPMV_OP_YR), O.SPMV_OP_YR, O.SPMV_OP_WAIT_SEND, O.SPMV_OP_END]
+    smap = {O.SPMV_OP_PACK: 0, O.SPMV_OP_YL: 1, O.SPMV_OP_UNPACK: 2, O.SPMV_OP_YR: 0}
+    res, _ = run_share(A, 4, 2, x, ops, smap, 3, ref=ref)
+    assert res["info"]["n_streams"] == 3 and res["info"]["fused_combine"] == 0
+    assert_share_parity(res, ref)
+
+
+def test_repeated_exec_new_x():
+    """A is static, x is not: one plan, several x vectors."""
+    A = gen.banded_uniform(5000, 10, 1250, seed=31)
+    plan = sp.spmv_plan_create(A, 4, 1)
+    try:
+        for s in range(4):
+            x = gen.x_normal(A.n_cols, 100 + s)
+            res, ref = run_share(A, 4, 1, x, plan=plan)
+            assert_share_parity(res, ref)
+    finally:
+        sp.spmv_plan_destroy(plan)
+
+
+# ------------------------------------------------------------ edge cases
+
+def test_empty_share_and_empty_rows():
+    A = gen.laplacian_2d5(2, 2)               # 4 rows over 6 ranks
+    x = gen.x_normal(4, 1)
+    for r in range(6):
+        res, ref = run_share(A, 6, r, x)
+        assert_share_parity(res, ref)
+    # matrix with empty rows and a block-diagonal rank (no halo at all)
+    rp = np.array([0, 0, 2, 2, 3, 3, 5, 5], np.int32)
+    ci = np.array([0, 1, 3, 5, 6], np.int32)
+    B = gen.CSR(7, 7, rp, ci, np.array([1.5, -2.0, 3.0, 0.25, 7.0]))
+    x = gen.x_normal(7, 2)
+    for P in (1, 2, 3):
+        for r in range(P):
+            res, ref = run_share(B, P, r, x)
+            assert_share_parity(res, ref)
+
+
+def test_long_rows():
+    """Rows far longer than a wavefront (up to 10^4 entries)."""
+    A = gen.power_law(40000, mean_len=200.0, sigma=1.2, max_len=10000, seed=44)
+    x = gen.x_normal(A.n_cols, 45)
+    for lanes in (0, 64, 8):
+        res, ref = run_share(A, 4, 1, x, tune={"lanes_local": lanes, "lanes_remote": lanes})
+        assert_share_parity(res, ref)
+
+
+def test_profile_counters():
+    A = gen.laplacian_3d7(24)
+    x = gen.x_uniform(A.n_cols, 3)
+    plan = sp.spmv_plan_create(A, 4, 1, tune={"flags": sp.SPMV_F_PROFILE})
+    try:
+        for _ in range(3):
+            run_share(A, 4, 1, x, plan=plan)
+        cnt = sp.spmv_plan_get_f64(plan, sp.SPMV_F64_OP_COUNT)
+        ms = sp.spmv_plan_get_f64(plan, sp.SPMV_F64_OP_MS)
+        for op in (sp.SPMV_OP_PACK, sp.SPMV_OP_YL, sp.SPMV_OP_UNPACK, sp.SPMV_OP_YR):
+            assert cnt[op] == 3 and ms[op] > 0
+        sp.spmv_plan_reset_times(plan)
+        assert sp.spmv_plan_get_f64(plan, sp.SPMV_F64_OP_COUNT).sum() == 0
+    finally:
+        sp.spmv_plan_destroy(plan)
+
+
+# ------------------------------------------------------------ full sizes
+
+def _sampled(res, ref, rows):
+    ok = oracle.within_tolerance(res["y"][rows], ref["y"][rows], ref["absax"][rows])
+    assert ok.all()
+
+
+def test_full_laplace3d_128_p4_rank1():
+    """The measured workload at full size, in the launch configuration the
+    benchmark times, every row checked."""
+    A = gen.laplacian_3d7(128)
+    x = gen.x_uniform(A.n_cols, 2)
+    log("full 3D 7-point 128^3 P=4 r=1")
+    res, ref = run_share(A, 4, 1, x)
+    info = res["info"]
+    assert info["n_loc"] == 524288 and info["nnz_local"] == 3620864
+    assert info["n_halo"] == 32768 and info["n_send"] == 32768
+    assert_share_parity(res, ref)
+
+
+def test_full_stencil27_150_p8_rank3():
+    A = gen.stencil_3d27(150, seed=3)
+    x = gen.x_normal(A.n_cols, 30)
+    log("full 3D 27-point 150^3 P=8 r=3")
+    res, ref = run_share(A, 8, 3, x)
+    info = res["info"]
+    assert info["n_loc"] == 421875 and info["n_halo"] == 45151
+    assert_share_parity(res, ref)
