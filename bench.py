@@ -56,6 +56,25 @@ def step_bytes(info: dict) -> dict:
     return b
 
 
+def time_op(sp, torch, plans, op, xs, ys, launches: int) -> float:
+    """Average duration (us) of one GPU op of the plan: HIP events bracket
+    `launches` back-to-back launches on one stream, rotating over the cold
+    replicas, so launch gaps are hidden behind the queued kernels."""
+    stream = torch.cuda.Stream()
+    R = len(plans)
+    with torch.cuda.stream(stream):
+        for i in range(2 * R):
+            sp.spmv_op_launch(plans[i % R], op, xs[i % R], ys[i % R], stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(launches):
+            sp.spmv_op_launch(plans[i % R], op, xs[i % R], ys[i % R], stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / launches
+
+
 def cpu_baseline(A, P, r, x, bytes_per_step: float, budget_s: float = 12.0) -> dict:
     """The oracle (Dot2 over every owned row, OpenMP) timed on the host."""
     import oracle
@@ -88,6 +107,7 @@ def main() -> int:
     ap.add_argument("--replicas", type=int, default=0, help="0 = enough to exceed 2x MALL")
     ap.add_argument("--plan", default="default", help="'default' or a plan-space index")
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=0)
     ap.add_argument("--fuse-unpack", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -114,6 +134,7 @@ def main() -> int:
     if args.plan != "default":
         ops, smap = sp.spmv_plan_space_get(P, 2, int(args.plan))
     tune = {"flags": sp.SPMV_F_PROFILE, "lanes_local": args.lanes, "lanes_remote": 0,
+            "rows_local": args.rows,
             "xcd_remap": args.xcd_remap, "fuse_unpack": args.fuse_unpack}
 
     first = sp.spmv_plan_create(A, P, r, ops, smap, 2, tune)
@@ -149,15 +170,22 @@ def main() -> int:
     for p in plans:
         ms += sp.spmv_plan_get_f64(p, sp.SPMV_F64_OP_MS)
         cnt += sp.spmv_plan_get_f64(p, sp.SPMV_F64_OP_COUNT)
-    avg = np.where(cnt > 0, ms / np.maximum(cnt, 1), 0.0)
+    in_plan = np.where(cnt > 0, ms / np.maximum(cnt, 1), 0.0) * 1e3
     B = step_bytes(info)
-    t_yl = avg[sp.SPMV_OP_YL] * 1e-3
-    achieved = B["yL"] / t_yl / 1e9
     value = B["total"] / (ms_step * 1e-3) / 1e9
-    kernel_ms = {"pack": avg[sp.SPMV_OP_PACK], "yL": avg[sp.SPMV_OP_YL],
-                 "unpack": avg[sp.SPMV_OP_UNPACK], "yR": avg[sp.SPMV_OP_YR],
-                 "combine": avg[sp.SPMV_N_VERTICES], "post_send_copy": avg[sp.SPMV_OP_POST_SEND],
-                 "post_recv_copy": avg[sp.SPMV_OP_POST_RECV]}
+
+    # Kernel durations: back-to-back launches of each GPU op, events on the
+    # launching stream.  y_L is the dominant kernel (95% of the device bytes).
+    launches = max(10 * R, 200)
+    kern_us = {name: time_op(sp, torch, plans, op, xs, ys, launches)
+               for name, op in (("yL", sp.SPMV_OP_YL), ("pack", sp.SPMV_OP_PACK),
+                                ("unpack", sp.SPMV_OP_UNPACK), ("yR", sp.SPMV_OP_YR))}
+    achieved = B["yL"] / (kern_us["yL"] * 1e-6) / 1e9
+    in_plan_us = {"pack": in_plan[sp.SPMV_OP_PACK], "yL": in_plan[sp.SPMV_OP_YL],
+                  "unpack": in_plan[sp.SPMV_OP_UNPACK], "yR": in_plan[sp.SPMV_OP_YR],
+                  "combine": in_plan[sp.SPMV_N_VERTICES],
+                  "post_send_copy": in_plan[sp.SPMV_OP_POST_SEND],
+                  "post_recv_copy": in_plan[sp.SPMV_OP_POST_RECV]}
 
     cpu = None
     if not args.no_cpu:
@@ -180,14 +208,19 @@ def main() -> int:
                    "nranks": P, "rank": r, "n_loc": n, "nnz_local": info["nnz_local"],
                    "nnz_remote": info["nnz_remote"], "n_halo": info["n_halo"],
                    "plan": args.plan, "lanes_local": info["lanes_local"],
-                   "lanes_remote": info["lanes_remote"], "xcd_remap": info["xcd_remap"],
+                   "rows_local": info["rows_local"], "lanes_remote": info["lanes_remote"],
+                   "rows_remote": info["rows_remote"], "xcd_remap": info["xcd_remap"],
                    "fuse_unpack": info["fuse_unpack"], "replicas": R,
                    "step_device_bytes": B["total"], "step_host_link_bytes": B["host_link"]},
         "roofline": {"bound": "hbm", "kernel": "y_L local CSR (k_csr_vector)",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "bytes_per_launch": B["yL"], "avg_us": round(t_yl * 1e6, 3)},
-        "kernel_avg_ms": {k: round(float(v), 5) for k, v in kernel_ms.items()},
+                     "bytes_per_launch": B["yL"], "avg_us": round(kern_us["yL"], 3),
+                     "launches": launches},
+        "kernel_us": {k: round(float(v), 3) for k, v in kern_us.items()},
+        "kernel_gbs": {k: round(B[k] / (kern_us[k] * 1e-6) / 1e9, 1) for k in kern_us
+                       if kern_us[k] > 0 and B[k] > 0},
+        "in_plan_event_us": {k: round(float(v), 3) for k, v in in_plan_us.items()},
         "gflops": round(2.0 * (info["nnz_local"] + info["nnz_remote"]) / (ms_step * 1e-3) / 1e9, 3),
         "cpu_baseline": cpu,
     }

@@ -111,13 +111,17 @@ typedef struct {
 typedef struct {
     int32_t lanes_local;   /* lanes per row for y_L: 0 = auto, 1..64 pow2  */
     int32_t lanes_remote;  /* lanes per row for y_R: 0 = auto, 1..64 pow2  */
+    int32_t rows_local;    /* rows per lane group per block for y_L (all
+                              their loads in flight together): 0 = auto,
+                              1, 2, 4 or 8                                   */
+    int32_t rows_remote;   /* same for y_R                                  */
     int32_t xcd_remap;     /* 0 = auto, 1 = contiguous row tiles per XCD,
                               2 = plain round-robin block order             */
     int32_t fuse_unpack;   /* 0 = explicit Unpack kernel, 1 = y_R reads the
                               receive buffer directly (valid because the
                               receive layout equals the halo order)          */
     int32_t flags;         /* SPMV_F_* below                               */
-    int32_t reserved[3];
+    int32_t reserved;
 } spmv_tune_t;
 
 #define SPMV_F_HOST_ONLY  1  /* build metadata only: no device resources;
@@ -140,10 +144,11 @@ typedef struct {
     int32_t nranks, rank;
     int32_t n_streams;     /* plan streams (excluding the two copy streams) */
     int32_t n_ops;         /* tokens in the canonical operation order        */
-    int32_t lanes_local, lanes_remote, xcd_remap, fuse_unpack;
+    int32_t lanes_local, lanes_remote, rows_local, rows_remote;
+    int32_t xcd_remap, fuse_unpack;
     int32_t fused_combine; /* 1: y_R adds into y itself; 0: a combine step
                               at end adds the remote partial sums            */
-    int32_t reserved[3];
+    int32_t reserved;
 } spmv_info_t;
 
 /* Integer metadata selectors for spmv_plan_get_i32. */
@@ -237,6 +242,20 @@ int spmv_plan_destroy(spmv_plan_t *plan);
  */
 int spmv_exec(spmv_plan_t *plan, const double *x_local, double *y_local, void *stream);
 
+/*
+ * Launch one GPU operation of the plan on `stream`, asynchronously: no
+ * synchronisation token, no copy, no host wait.  For callers that compose
+ * their own schedule (or capture one in a graph) and for kernel timing.
+ *   SPMV_OP_PACK    send buffer <- x_local[send_idx]
+ *   SPMV_OP_YL      y_local = A_L x_local
+ *   SPMV_OP_UNPACK  x_halo <- receive buffer (permuted)
+ *   SPMV_OP_YR      y_local[rows of A_R] += A_R x_halo; the caller orders it
+ *                   after y_L on the same stream (or after a join)
+ * x_local / y_local as in spmv_exec (only the ones the op touches are read).
+ */
+int spmv_op_launch(spmv_plan_t *plan, int32_t op, const double *x_local, double *y_local,
+                   void *stream);
+
 int spmv_plan_info(const spmv_plan_t *plan, spmv_info_t *info);
 
 /* Copy integer metadata `which` (SPMV_I32_*) into host out[0..n); n must be
@@ -280,6 +299,19 @@ int spmv_plan_space_get(int32_t nranks, int32_t n_streams, int64_t index,
  * names.  Writes at most cap bytes including the terminator; returns the
  * full length, or SPMV_EINVAL for an unknown token. */
 int spmv_op_name(int32_t op, char *buf, int32_t cap);
+
+/* ------------------------------------------------------------ measurement */
+
+/*
+ * HBM probe: the achievable-bandwidth yardstick for the SpMV kernels.
+ *   mode 0  read every byte of src once (16-byte loads) and write one partial
+ *           sum per block to dst (device, >= `blocks` doubles)
+ *   mode 1  copy `bytes` from src to dst (device, non-overlapping)
+ * bytes: a multiple of 16; blocks: grid size, 0 = 2048.  Asynchronous on
+ * `stream`; the caller times it (e.g. with events around repeated calls).
+ */
+int spmv_hbm_probe(int32_t mode, const void *src, void *dst, int64_t bytes, int32_t blocks,
+                   void *stream);
 
 /* ------------------------------------------------------------ misc */
 

@@ -5,7 +5,7 @@ step of the SpMV runs in the library's HIP kernels.  Function names match
 the C entry points.  Device arrays are passed as torch CUDA tensors (or raw
 integer device addresses), host arrays as numpy arrays.
 
-The library must be built first (``python -m paper_2203_02530_amd.build``);
+The library must be built first (``python paper_2203_02530_amd/build.py``);
 importing this package without it raises ImportError.
 """
 from __future__ import annotations
@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libspmv.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"{LIB_PATH} is missing: build the HIP library with "
-        "`python -m paper_2203_02530_amd.build` (no CPU fallback exists)")
+        "`python paper_2203_02530_amd/build.py` (no CPU fallback exists)")
 
 # One HIP runtime per process: torch ships its own libamdhip64 (same soname
 # as ROCm's), and two runtimes in one process do not share the device.
@@ -80,9 +80,9 @@ class spmv_csr_t(ctypes.Structure):
 
 
 class spmv_tune_t(ctypes.Structure):
-    _fields_ = [("lanes_local", ctypes.c_int32), ("lanes_remote", ctypes.c_int32),
-                ("xcd_remap", ctypes.c_int32), ("fuse_unpack", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+    _fields_ = [(k, ctypes.c_int32) for k in (
+        "lanes_local", "lanes_remote", "rows_local", "rows_remote", "xcd_remap",
+        "fuse_unpack", "flags", "reserved")]
 
 
 class spmv_info_t(ctypes.Structure):
@@ -90,7 +90,8 @@ class spmv_info_t(ctypes.Structure):
         "n_global", "lo", "n_loc", "nnz_local", "nnz_remote", "n_halo", "n_send",
         "n_remote_rows", "device_bytes")] + [(k, ctypes.c_int32) for k in (
             "nranks", "rank", "n_streams", "n_ops", "lanes_local", "lanes_remote",
-            "xcd_remap", "fuse_unpack", "fused_combine")] + [("reserved", ctypes.c_int32 * 3)]
+            "rows_local", "rows_remote", "xcd_remap", "fuse_unpack", "fused_combine",
+            "reserved")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -112,6 +113,7 @@ _proto("spmv_plan_create_ex", [_P, _I32, _I32, _P, _I32, _P, _I32, _P, _P])
 _proto("spmv_plan_destroy", [_P])
 _proto("spmv_exec", [_P, _P, _P, _P])
 _proto("spmv_plan_info", [_P, _P])
+_proto("spmv_op_launch", [_P, _I32, _P, _P, _P])
 _proto("spmv_plan_get_i32", [_P, _I32, _P, _I64])
 _proto("spmv_plan_get_f64", [_P, _I32, _P, _I64])
 _proto("spmv_plan_reset_times", [_P])
@@ -121,6 +123,7 @@ _proto("spmv_plan_validate", [_I32, _P, _I32, _P, _I32])
 _proto("spmv_plan_space_count", [_I32, _I32, _P])
 _proto("spmv_plan_space_get", [_I32, _I32, _I64, _P, _P, _P])
 _proto("spmv_op_name", [_I32, ctypes.c_char_p, _I32])
+_proto("spmv_hbm_probe", [_I32, _P, _P, _I64, _I32, _P])
 _proto("spmv_last_error", [], ctypes.c_char_p)
 _proto("spmv_version", [], ctypes.c_char_p)
 
@@ -206,6 +209,11 @@ def spmv_plan_destroy(plan) -> None:
 def spmv_exec(plan, x, y, stream=None) -> None:
     """y = (A x) over the plan's rows; x, y device arrays of n_loc FP64."""
     _check(_lib.spmv_exec(plan, _addr(x), _addr(y), _stream_handle(stream)))
+
+
+def spmv_op_launch(plan, op: int, x=None, y=None, stream=None) -> None:
+    """Launch one GPU op of the plan asynchronously on ``stream``."""
+    _check(_lib.spmv_op_launch(plan, op, _addr(x), _addr(y), _stream_handle(stream)))
 
 
 def spmv_plan_info(plan) -> dict:
@@ -296,6 +304,12 @@ def spmv_op_name(op: int) -> str:
     buf = ctypes.create_string_buffer(64)
     _check(_lib.spmv_op_name(op, buf, 64))
     return buf.value.decode()
+
+
+def spmv_hbm_probe(mode: int, src, dst, nbytes: int, blocks: int = 0, stream=None) -> None:
+    """Launch the read (mode 0) or copy (mode 1) bandwidth probe."""
+    _check(_lib.spmv_hbm_probe(mode, _addr(src), _addr(dst), nbytes, blocks,
+                               _stream_handle(stream)))
 
 
 def spmv_last_error() -> str:

@@ -1,6 +1,6 @@
 """Build libspmv.so in-tree for gfx950 with hipcc.
 
-``python -m paper_2203_02530_amd.build`` compiles every source under
+``python paper_2203_02530_amd/build.py`` compiles every source under
 ``csrc/`` to an object in ``_build/`` (in parallel) and links the shared
 library next to this file.
 """

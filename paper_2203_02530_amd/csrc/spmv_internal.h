@@ -94,9 +94,10 @@ hipError_t launch_unpack(const double *recv, const int32_t *perm, double *xh, in
                          hipStream_t s);
 // y[row] = sum (store) or y[rows[j]] += sum (accumulate) when acc_into != null
 hipError_t launch_csr(const CsrDev &A, const double *x, double *out, double *acc_into,
-                      int lanes, int xcd_remap, hipStream_t s);
+                      int lanes, int rows, int xcd_remap, hipStream_t s);
 hipError_t launch_combine(const int32_t *rows, const double *part, double *y, int64_t n,
                           hipStream_t s);
 int auto_lanes(int64_t nnz, int64_t rows);
+int auto_rows(int lanes, int64_t rows);
 
 }  // namespace spmv

@@ -4,51 +4,40 @@
 //
 // SpMV in FP64 moves >= 12 bytes (value + column) per 2 flops, far below the
 // MI355X ridge point, so these kernels are written for HBM streaming, not for
-// the matrix cores: every load of the A stream is coalesced across the
-// wavefront, the row pointers of a block are staged once in LDS, each row is
-// reduced inside its group of lanes with cross-lane moves, and block tiles
-// can be laid out so that each XCD (with its private L2) walks a contiguous
-// range of rows and reuses the x entries its neighbours touch.
+// the matrix cores:
+//   - every load of the A stream is coalesced across the wavefront (the lanes
+//     of a group walk consecutive entries of one row, consecutive groups take
+//     consecutive rows) and marked non-temporal, leaving L2 to x;
+//   - the row pointers of a block are staged once in LDS;
+//   - each lane group handles ROWS rows at once, issuing all their column and
+//     value loads before the first wait, so a wave keeps ROWS times more bytes
+//     in flight than a one-row-per-group kernel (the kernel is latency-bound
+//     otherwise: one block's work is a short chain of dependent loads);
+//   - rows are reduced inside their group with DPP row moves (quad_perm,
+//     row_half_mirror, row_mirror) and the gfx950 permlane16/32 swaps, in a
+//     fixed butterfly order, so results depend only on the lane values;
+//   - block tiles can be laid out so that each XCD (with its private L2) walks
+//     a contiguous range of rows and reuses the x entries neighbours touch.
+#include "spmv_device.h"
 #include "spmv_internal.h"
 
 namespace spmv {
 namespace {
 
 constexpr int kBlock = 256;   // 4 wave64 per block
-constexpr int kXcds = 8;      // MI355X: 8 XCDs, workgroups dispatched round-robin
-
-// Block b of nb is dispatched to XCD b % 8.  With remap, XCD x processes the
-// contiguous tile range [x*per + min(x, rem), ...) instead of every 8th tile,
-// so the x entries shared by neighbouring tiles stay in one L2.  Bijective for
-// any nb.
-__device__ __forceinline__ int tile_of_block(int b, int nb, int remap)
-{
-    if (remap != 1) return b;
-    const int xcd = b % kXcds, local = b / kXcds;
-    const int per = nb / kXcds, rem = nb % kXcds;
-    return xcd * per + min(xcd, rem) + local;
-}
-
-// Sum over each aligned group of LPR lanes (LPR a power of two <= 64).  The
-// butterfly order is fixed, so the result depends only on the lane values.
-template <int LPR>
-__device__ __forceinline__ double group_sum(double v)
-{
-#pragma unroll
-    for (int off = LPR / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// y = A x over n_rows rows; LPR lanes per row, kBlock/LPR rows per block.
-// acc == nullptr: out[row] = sum.  Otherwise acc[rows[row]] += sum (the remote
-// product adding into y after the local product on the same stream).
-template <int LPR>
+// out = A x over n_rows rows (acc == nullptr), or acc[rows[j]] += (A x)_j.
+// LPR lanes per row; each lane group handles ROWS rows of the block's tile of
+// (kBlock/LPR)*ROWS consecutive rows.  Row r of the tile belongs to sub-tile
+// r / G and group r % G, so at every unrolled step consecutive groups read
+// consecutive rows.
+template <int LPR, int ROWS>
 __global__ __launch_bounds__(kBlock) void k_csr_vector(
     int n_rows, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
     const double *__restrict__ val, const double *__restrict__ x, double *__restrict__ out,
     const int32_t *__restrict__ rows, double *__restrict__ acc, int remap)
 {
-    constexpr int RPB = kBlock / LPR;
+    constexpr int G = kBlock / LPR;
+    constexpr int RPB = G * ROWS;
     __shared__ int32_t s_rp[RPB + 1];
     const int tile = tile_of_block(int(blockIdx.x), int(gridDim.x), remap);
     const int row0 = tile * RPB;
@@ -56,22 +45,57 @@ __global__ __launch_bounds__(kBlock) void k_csr_vector(
     __syncthreads();
 
     const int g = int(threadIdx.x) / LPR, lane = int(threadIdx.x) % LPR;
-    const int row = row0 + g;
-    double sum = 0.0;
-    if (row < n_rows) {
-        const int b = s_rp[g], e = s_rp[g + 1];
-        for (int k = b + lane; k < e; k += LPR) {
-            const int32_t c = __builtin_nontemporal_load(col + k);
-            const double a = __builtin_nontemporal_load(val + k);
-            sum = fma(a, x[c], sum);
+    const int first = s_rp[0];
+    int k[ROWS], e[ROWS];
+    double sum[ROWS];
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+        k[i] = s_rp[i * G + g] + lane;
+        e[i] = s_rp[i * G + g + 1];
+        sum[i] = 0.0;
+    }
+    // Rows past n_rows have s_rp = rp[n_rows] on both ends: empty.  When the
+    // whole tile is empty there is no valid entry to clamp to, so skip.
+    if (first < s_rp[RPB]) {
+        bool more = true;
+        while (more) {
+            int32_t c[ROWS];
+            double a[ROWS];
+            // all loads of the step first; a finished slot re-reads the tile's
+            // first entry (always valid) and is masked out below
+#pragma unroll
+            for (int i = 0; i < ROWS; ++i) {
+                const int kc = k[i] < e[i] ? k[i] : first;
+                c[i] = __builtin_nontemporal_load(col + kc);
+                a[i] = __builtin_nontemporal_load(val + kc);
+            }
+#pragma unroll
+            for (int i = 0; i < ROWS; ++i) {
+                const double xv = x[c[i]];
+                const double f = fma(a[i], xv, sum[i]);
+                sum[i] = k[i] < e[i] ? f : sum[i];
+            }
+            more = false;
+#pragma unroll
+            for (int i = 0; i < ROWS; ++i) {
+                k[i] += LPR;
+                more |= k[i] < e[i];
+            }
         }
     }
-    sum = group_sum<LPR>(sum);
-    if (lane == 0 && row < n_rows) {
-        if (acc)
-            acc[rows[row]] += sum;
-        else
-            out[row] = sum;
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) sum[i] = group_sum<LPR>(sum[i]);
+    if (lane == LPR - 1) {
+#pragma unroll
+        for (int i = 0; i < ROWS; ++i) {
+            const int row = row0 + i * G + g;
+            if (row < n_rows) {
+                if (acc)
+                    acc[rows[row]] += sum[i];
+                else
+                    out[row] = sum[i];
+            }
+        }
     }
 }
 
@@ -99,15 +123,28 @@ unsigned grid_for(int64_t n)
     return unsigned(std::min<int64_t>(std::max<int64_t>(b, 1), 65536));
 }
 
-template <int LPR>
+template <int LPR, int ROWS>
 hipError_t launch_csr_t(const CsrDev &A, const double *x, double *out, double *acc, int remap,
                         hipStream_t s)
 {
-    constexpr int RPB = kBlock / LPR;
+    constexpr int RPB = (kBlock / LPR) * ROWS;
     const int64_t nb = (int64_t(A.n_rows) + RPB - 1) / RPB;
-    hipLaunchKernelGGL(k_csr_vector<LPR>, dim3(unsigned(nb)), dim3(kBlock), 0, s, A.n_rows, A.rp,
-                       A.col, A.val, x, out, A.rows, acc, remap);
+    hipLaunchKernelGGL((k_csr_vector<LPR, ROWS>), dim3(unsigned(nb)), dim3(kBlock), 0, s,
+                       A.n_rows, A.rp, A.col, A.val, x, out, A.rows, acc, remap);
     return hipGetLastError();
+}
+
+template <int LPR>
+hipError_t launch_csr_l(const CsrDev &A, const double *x, double *out, double *acc, int rows,
+                        int remap, hipStream_t s)
+{
+    switch (rows) {
+        case 1: return launch_csr_t<LPR, 1>(A, x, out, acc, remap, s);
+        case 2: return launch_csr_t<LPR, 2>(A, x, out, acc, remap, s);
+        case 4: return launch_csr_t<LPR, 4>(A, x, out, acc, remap, s);
+        case 8: return launch_csr_t<LPR, 8>(A, x, out, acc, remap, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -119,6 +156,16 @@ int auto_lanes(int64_t nnz, int64_t rows)
     int l = 1;
     while (l < 64 && double(l) < mean) l <<= 1;
     return l;
+}
+
+int auto_rows(int lanes, int64_t rows)
+{
+    // Enough rows per lane group to keep several loads in flight per lane.
+    // Four rows per lane group was the best setting for every lane count on
+    // the stencil shares; fewer for inputs too small to fill the chip.
+    int r = 4;
+    while (r > 1 && rows < int64_t(kBlock / lanes) * r * 512) r >>= 1;
+    return r;
 }
 
 hipError_t launch_pack(const double *x, const int32_t *idx, double *out, int64_t n,
@@ -146,18 +193,18 @@ hipError_t launch_combine(const int32_t *rows, const double *part, double *y, in
 }
 
 hipError_t launch_csr(const CsrDev &A, const double *x, double *out, double *acc, int lanes,
-                      int xcd_remap, hipStream_t s)
+                      int rows, int xcd_remap, hipStream_t s)
 {
     if (A.n_rows <= 0) return hipSuccess;
     const int remap = xcd_remap == 2 ? 0 : 1;
     switch (lanes) {
-        case 1: return launch_csr_t<1>(A, x, out, acc, remap, s);
-        case 2: return launch_csr_t<2>(A, x, out, acc, remap, s);
-        case 4: return launch_csr_t<4>(A, x, out, acc, remap, s);
-        case 8: return launch_csr_t<8>(A, x, out, acc, remap, s);
-        case 16: return launch_csr_t<16>(A, x, out, acc, remap, s);
-        case 32: return launch_csr_t<32>(A, x, out, acc, remap, s);
-        case 64: return launch_csr_t<64>(A, x, out, acc, remap, s);
+        case 1: return launch_csr_l<1>(A, x, out, acc, rows, remap, s);
+        case 2: return launch_csr_l<2>(A, x, out, acc, rows, remap, s);
+        case 4: return launch_csr_l<4>(A, x, out, acc, rows, remap, s);
+        case 8: return launch_csr_l<8>(A, x, out, acc, rows, remap, s);
+        case 16: return launch_csr_l<16>(A, x, out, acc, rows, remap, s);
+        case 32: return launch_csr_l<32>(A, x, out, acc, rows, remap, s);
+        case 64: return launch_csr_l<64>(A, x, out, acc, rows, remap, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -16,7 +16,7 @@
 struct spmv_plan {
     spmv::Share share;
     spmv::Schedule sch;
-    int32_t lanes_local = 1, lanes_remote = 1, xcd_remap = 1;
+    int32_t lanes_local = 1, lanes_remote = 1, rows_local = 1, rows_remote = 1, xcd_remap = 1;
     bool fuse_unpack = false, fused_combine = false, host_only = false, profile = false;
     int device = 0;
 
@@ -156,8 +156,11 @@ extern "C" int spmv_plan_create_ex(const spmv_csr_t *csr, int32_t nranks, int32_
     spmv_tune_t t{};
     if (tune) t = *tune;
     auto valid_lanes = [](int32_t l) { return l == 0 || (l >= 1 && l <= 64 && !(l & (l - 1))); };
+    auto valid_rows = [](int32_t r) { return r == 0 || r == 1 || r == 2 || r == 4 || r == 8; };
     if (!valid_lanes(t.lanes_local) || !valid_lanes(t.lanes_remote))
         return set_error(SPMV_EINVAL, "lanes per row must be 0 or a power of two <= 64");
+    if (!valid_rows(t.rows_local) || !valid_rows(t.rows_remote))
+        return set_error(SPMV_EINVAL, "rows per lane group must be 0, 1, 2, 4 or 8");
     if (t.xcd_remap < 0 || t.xcd_remap > 2 || t.fuse_unpack < 0 || t.fuse_unpack > 1)
         return set_error(SPMV_EINVAL, "tune field out of range");
 
@@ -184,6 +187,9 @@ extern "C" int spmv_plan_create_ex(const spmv_csr_t *csr, int32_t nranks, int32_
     p->lanes_remote = t.lanes_remote ? t.lanes_remote
                                      : auto_lanes(int64_t(S.R_col.size()),
                                                   int64_t(S.R_rows.size()));
+    p->rows_local = t.rows_local ? t.rows_local : auto_rows(p->lanes_local, S.n_loc);
+    p->rows_remote = t.rows_remote ? t.rows_remote
+                                   : auto_rows(p->lanes_remote, int64_t(S.R_rows.size()));
     p->xcd_remap = t.xcd_remap ? t.xcd_remap : 1;
     p->fuse_unpack = t.fuse_unpack == 1;
     p->host_only = (t.flags & SPMV_F_HOST_ONLY) != 0;
@@ -299,7 +305,7 @@ extern "C" int spmv_exec(spmv_plan_t *p, const double *x, double *y, void *strea
                 A.col = p->dL_col;
                 A.val = p->dL_val;
                 SPMV_HIP(prof_begin(p, tok, s));
-                SPMV_HIP(launch_csr(A, x, y, nullptr, p->lanes_local, p->xcd_remap, s));
+                SPMV_HIP(launch_csr(A, x, y, nullptr, p->lanes_local, p->rows_local, p->xcd_remap, s));
                 SPMV_HIP(prof_end(p, tok, s));
                 ran[tok] = true;
                 break;
@@ -344,9 +350,11 @@ extern "C" int spmv_exec(spmv_plan_t *p, const double *x, double *y, void *strea
                 const double *xh = p->fuse_unpack ? p->d_recvbuf : p->d_xhalo;
                 SPMV_HIP(prof_begin(p, tok, s));
                 if (p->fused_combine)
-                    SPMV_HIP(launch_csr(A, xh, nullptr, y, p->lanes_remote, p->xcd_remap, s));
+                    SPMV_HIP(launch_csr(A, xh, nullptr, y, p->lanes_remote, p->rows_remote,
+                                        p->xcd_remap, s));
                 else
-                    SPMV_HIP(launch_csr(A, xh, p->d_part, nullptr, p->lanes_remote, p->xcd_remap, s));
+                    SPMV_HIP(launch_csr(A, xh, p->d_part, nullptr, p->lanes_remote, p->rows_remote,
+                                        p->xcd_remap, s));
                 SPMV_HIP(prof_end(p, tok, s));
                 combine = !p->fused_combine && n_rr > 0;
                 ran[tok] = true;
@@ -380,6 +388,50 @@ extern "C" int spmv_exec(spmv_plan_t *p, const double *x, double *y, void *strea
     return SPMV_OK;
 }
 
+extern "C" int spmv_op_launch(spmv_plan_t *p, int32_t op, const double *x, double *y,
+                              void *stream_v)
+{
+    if (!p) return set_error(SPMV_EINVAL, "plan is NULL");
+    if (p->host_only) return set_error(SPMV_ESTATE, "plan was created host-only");
+    const Share &S = p->share;
+    hipStream_t s = static_cast<hipStream_t>(stream_v);
+    const int64_t n_rr = int64_t(S.R_rows.size());
+    switch (op) {
+        case SPMV_OP_PACK:
+            if (!x && !S.send_idx.empty()) return set_error(SPMV_EINVAL, "x is NULL");
+            SPMV_HIP(launch_pack(x, p->d_send_idx, p->d_sendbuf, int64_t(S.send_idx.size()), s));
+            return SPMV_OK;
+        case SPMV_OP_YL: {
+            if (S.n_loc > 0 && (!x || !y)) return set_error(SPMV_EINVAL, "x or y is NULL");
+            CsrDev A;
+            A.n_rows = int32_t(S.n_loc);
+            A.rp = p->dL_ptr;
+            A.col = p->dL_col;
+            A.val = p->dL_val;
+            SPMV_HIP(launch_csr(A, x, y, nullptr, p->lanes_local, p->rows_local, p->xcd_remap, s));
+            return SPMV_OK;
+        }
+        case SPMV_OP_UNPACK:
+            if (!p->fuse_unpack)
+                SPMV_HIP(launch_unpack(p->d_recvbuf, p->d_perm, p->d_xhalo,
+                                       int64_t(S.halo.size()), s));
+            return SPMV_OK;
+        case SPMV_OP_YR: {
+            if (n_rr > 0 && !y) return set_error(SPMV_EINVAL, "y is NULL");
+            CsrDev A;
+            A.n_rows = int32_t(n_rr);
+            A.rp = p->dR_ptr;
+            A.col = p->dR_col;
+            A.val = p->dR_val;
+            A.rows = p->dR_rows;
+            const double *xh = p->fuse_unpack ? p->d_recvbuf : p->d_xhalo;
+            SPMV_HIP(launch_csr(A, xh, nullptr, y, p->lanes_remote, p->rows_remote, p->xcd_remap, s));
+            return SPMV_OK;
+        }
+        default: return set_error(SPMV_EINVAL, "not a GPU operation: " + std::to_string(op));
+    }
+}
+
 extern "C" int spmv_plan_info(const spmv_plan_t *p, spmv_info_t *info)
 {
     if (!p || !info) return set_error(SPMV_EINVAL, "NULL argument");
@@ -400,6 +452,8 @@ extern "C" int spmv_plan_info(const spmv_plan_t *p, spmv_info_t *info)
     info->n_ops = int32_t(p->sch.order.size());
     info->lanes_local = p->lanes_local;
     info->lanes_remote = p->lanes_remote;
+    info->rows_local = p->rows_local;
+    info->rows_remote = p->rows_remote;
     info->xcd_remap = p->xcd_remap;
     info->fuse_unpack = p->fuse_unpack;
     info->fused_combine = p->fused_combine;

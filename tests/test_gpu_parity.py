@@ -69,15 +69,41 @@ def test_share_default_plan(name, build, P, ranks, xf):
 
 
 @pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64])
-@pytest.mark.parametrize("remap", [1, 2])
-def test_lane_variants(lanes, remap):
+@pytest.mark.parametrize("rows", [1, 2, 4, 8])
+def test_lane_variants(lanes, rows):
     A = gen.power_law(30000, seed=17)
     x = gen.x_normal(A.n_cols, 18)
-    log(f"power-law 30k lanes={lanes} remap={remap}")
-    for fuse in (0, 1):
+    log(f"power-law 30k lanes={lanes} rows={rows}")
+    for fuse, remap in ((0, 1), (1, 2)):
         res, ref = run_share(A, 4, 2, x, tune={"lanes_local": lanes, "lanes_remote": lanes,
+                                               "rows_local": rows, "rows_remote": rows,
                                                "xcd_remap": remap, "fuse_unpack": fuse})
         assert_share_parity(res, ref)
+
+
+def test_op_launch_matches_exec():
+    """The op-level entry point (used for kernel timing) computes what the
+    exec computes: y_L then y_R on one stream."""
+    import torch
+    A = gen.stencil_3d27(20, seed=3)
+    x = gen.x_normal(A.n_cols, 30)
+    res, ref = run_share(A, 4, 1, x, keep_plan=True)
+    plan = res.pop("plan")
+    try:
+        info = res["info"]
+        lo, n = info["lo"], info["n_loc"]
+        xd = torch.from_numpy(x[lo:lo + n].copy()).cuda()
+        yd = torch.empty(n, dtype=torch.float64, device="cuda")
+        s = torch.cuda.current_stream()
+        sp.spmv_op_launch(plan, sp.SPMV_OP_UNPACK, None, None, s)
+        sp.spmv_op_launch(plan, sp.SPMV_OP_YL, xd, yd, s)
+        sp.spmv_op_launch(plan, sp.SPMV_OP_YR, xd, yd, s)
+        torch.cuda.synchronize()
+        assert np.array_equal(bits(yd.cpu().numpy()), bits(res["y"]))
+        with pytest.raises(sp.SpmvError):
+            sp.spmv_op_launch(plan, sp.SPMV_OP_POST_SEND, xd, yd, s)
+    finally:
+        sp.spmv_plan_destroy(plan)
 
 
 def test_every_plan_bit_identical():
