@@ -105,12 +105,21 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="laplace3d_128_p4r1")
     ap.add_argument("--replicas", type=int, default=0, help="0 = enough to exceed 2x MALL")
-    ap.add_argument("--plan", default="default", help="'default' or a plan-space index")
+    ap.add_argument("--plan", default="auto",
+                    help="'auto' (sweep the design space, keep the fastest), 'default', "
+                         "or a plan-space index")
+    ap.add_argument("--sweep-measure", type=float, default=0.01,
+                    help="seconds per measurement in the plan sweep (paper: 0.01)")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--rows", type=int, default=0)
+    ap.add_argument("--kernel", type=int, default=0, help="0 auto, 1 vector CSR, 2 stream CSR")
+    ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=0)
     ap.add_argument("--fuse-unpack", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only launch the dominant kernel back-to-back and the copy probe of "
+                         "known size (for hardware-counter runs), print their timings")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -131,10 +140,23 @@ def main() -> int:
     x = w["x"](A.n_cols)
 
     ops = smap = None
-    if args.plan != "default":
+    sweep = None
+    if args.plan == "auto" and P > 1:
+        from paper_2203_02530_amd import tune as tuner
+        ktune = {"lanes_local": args.lanes, "rows_local": args.rows, "kernel_local": args.kernel,
+                 "chunk_local": args.chunk}
+        res = tuner.sweep_plans(A, P, r, x, 2, ktune, t_measure=args.sweep_measure, n_measure=1)
+        top = [d["index"] for d in tuner.best_plans(res, 8)]
+        again = tuner.sweep_plans(A, P, r, x, 2, ktune, t_measure=args.sweep_measure, n_measure=5,
+                                  indices=top)
+        best = tuner.best_plans(again, 1)[0]["index"]
+        sweep = tuner.sweep_summary(res)
+        sweep["chosen_index"] = best
+        ops, smap = sp.spmv_plan_space_get(P, 2, best)
+    elif args.plan not in ("auto", "default"):
         ops, smap = sp.spmv_plan_space_get(P, 2, int(args.plan))
     tune = {"flags": sp.SPMV_F_PROFILE, "lanes_local": args.lanes, "lanes_remote": 0,
-            "rows_local": args.rows,
+            "rows_local": args.rows, "kernel_local": args.kernel, "chunk_local": args.chunk,
             "xcd_remap": args.xcd_remap, "fuse_unpack": args.fuse_unpack}
 
     first = sp.spmv_plan_create(A, P, r, ops, smap, 2, tune)
@@ -151,6 +173,26 @@ def main() -> int:
         ys.append(torch.empty(n, dtype=torch.float64, device="cuda"))
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
+
+    if args.kernel_only:
+        # counter runs: y_L over the cold replicas, then a plain copy of known
+        # size whose FETCH_SIZE / WRITE_SIZE readings calibrate the counters
+        launches = 10 * R
+        us = time_op(sp, torch, plans, sp.SPMV_OP_YL, xs, ys, launches)
+        nbytes = 64 << 20
+        src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").normal_()
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(10):
+            sp.spmv_hbm_probe(1, src, dst, nbytes, 0, stream)
+        torch.cuda.synchronize()
+        B = step_bytes(info)
+        print(json.dumps({"kernel_only": True, "yL_us": round(us, 3), "yL_launches": launches + 2 * R,
+                          "yL_bytes": B["yL"], "copy_bytes_each_way": nbytes, "copy_launches": 10}),
+              flush=True)
+        for p in plans:
+            sp.spmv_plan_destroy(p)
+        return 0
 
     for i in range(args.warmup):
         sp.spmv_exec(plans[i % R], xs[i % R], ys[i % R], stream)
@@ -207,12 +249,16 @@ def main() -> int:
         "config": {"workload": w["desc"], "rows": int(A.n_rows), "nnz": int(A.nnz),
                    "nranks": P, "rank": r, "n_loc": n, "nnz_local": info["nnz_local"],
                    "nnz_remote": info["nnz_remote"], "n_halo": info["n_halo"],
-                   "plan": args.plan, "lanes_local": info["lanes_local"],
+                   "plan": args.plan, "kernel_local": info["kernel_local"],
+                   "chunk_local": info["chunk_local"], "n_tiles_local": info["n_tiles_local"],
+                   "lanes_local": info["lanes_local"],
                    "rows_local": info["rows_local"], "lanes_remote": info["lanes_remote"],
                    "rows_remote": info["rows_remote"], "xcd_remap": info["xcd_remap"],
                    "fuse_unpack": info["fuse_unpack"], "replicas": R,
                    "step_device_bytes": B["total"], "step_host_link_bytes": B["host_link"]},
-        "roofline": {"bound": "hbm", "kernel": "y_L local CSR (k_csr_vector)",
+        "roofline": {"bound": "hbm",
+                     "kernel": "y_L local CSR (%s)" % ("k_csr_stream" if info["kernel_local"] == 2
+                                                       else "k_csr_vector"),
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_launch": B["yL"], "avg_us": round(kern_us["yL"], 3),
@@ -221,6 +267,11 @@ def main() -> int:
         "kernel_gbs": {k: round(B[k] / (kern_us[k] * 1e-6) / 1e9, 1) for k in kern_us
                        if kern_us[k] > 0 and B[k] > 0},
         "in_plan_event_us": {k: round(float(v), 3) for k, v in in_plan_us.items()},
+        "plan_sweep": sweep,
+        "plan_order": [sp.spmv_op_name(int(t)) for t in sp.spmv_plan_get_i32(
+            first, sp.SPMV_I32_OP_ORDER)],
+        "plan_streams": {sp.spmv_op_name(v): int(m) for v, m in enumerate(
+            sp.spmv_plan_get_i32(first, sp.SPMV_I32_STREAM_MAP)) if m >= 0},
         "gflops": round(2.0 * (info["nnz_local"] + info["nnz_remote"]) / (ms_step * 1e-3) / 1e9, 3),
         "cpu_baseline": cpu,
     }

@@ -107,27 +107,45 @@ typedef struct {
 } spmv_csr_t;
 
 /* Kernel variant knobs (not part of the paper's plan; chosen by the tuner).
- * Zero-initialised = automatic choice for every field.                    */
+ * Zero-initialised = automatic choice for every field.
+ *
+ * Two CSR kernel families compute y_L and y_R:
+ *   vector CSR  each row is reduced by a group of `lanes` lanes; each lane
+ *               group handles `rows` rows with all their loads in flight
+ *   stream CSR  rows are cut into tiles whose entries fit one window of
+ *               256 * `chunk` entries; the block streams the window with
+ *               `width`-entry loads, stages the products in LDS and `lanes`
+ *               lanes per row sum them                                       */
+#define SPMV_KERNEL_VECTOR 1
+#define SPMV_KERNEL_STREAM 2
+
 typedef struct {
-    int32_t lanes_local;   /* lanes per row for y_L: 0 = auto, 1..64 pow2  */
-    int32_t lanes_remote;  /* lanes per row for y_R: 0 = auto, 1..64 pow2  */
-    int32_t rows_local;    /* rows per lane group per block for y_L (all
-                              their loads in flight together): 0 = auto,
-                              1, 2, 4 or 8                                   */
-    int32_t rows_remote;   /* same for y_R                                  */
+    int32_t kernel_local;  /* 0 = auto, 1 = vector CSR, 2 = stream CSR      */
+    int32_t kernel_remote; /* same for y_R                                   */
+    int32_t lanes_local;   /* lanes per row: 0 = auto, 1..64 pow2 (stream:
+                              1..16)                                         */
+    int32_t lanes_remote;
+    int32_t rows_local;    /* vector: rows per lane group, 0 = auto, 1/2/4/8 */
+    int32_t rows_remote;
+    int32_t chunk_local;   /* stream: entries per thread per window, 0 = auto,
+                              4, 8 or 16                                      */
+    int32_t chunk_remote;
+    int32_t width;         /* stream: entries per load, 0 = auto, 2 or 4     */
     int32_t xcd_remap;     /* 0 = auto, 1 = contiguous row tiles per XCD,
                               2 = plain round-robin block order             */
     int32_t fuse_unpack;   /* 0 = explicit Unpack kernel, 1 = y_R reads the
                               receive buffer directly (valid because the
                               receive layout equals the halo order)          */
     int32_t flags;         /* SPMV_F_* below                               */
-    int32_t reserved;
 } spmv_tune_t;
 
 #define SPMV_F_HOST_ONLY  1  /* build metadata only: no device resources;
                                 inspection works, spmv_exec returns
                                 SPMV_ESTATE                                  */
 #define SPMV_F_PROFILE    2  /* time every GPU op and copy with HIP events   */
+#define SPMV_F_NO_BUFFER  4  /* CSR kernels address memory with 64-bit
+                                pointers instead of buffer resources (the
+                                latter is used when every array < 4 GiB)     */
 
 typedef struct spmv_plan  spmv_plan_t;   /* opaque */
 
@@ -144,10 +162,13 @@ typedef struct {
     int32_t nranks, rank;
     int32_t n_streams;     /* plan streams (excluding the two copy streams) */
     int32_t n_ops;         /* tokens in the canonical operation order        */
+    int32_t kernel_local, kernel_remote;   /* 1 = vector CSR, 2 = stream CSR */
     int32_t lanes_local, lanes_remote, rows_local, rows_remote;
+    int32_t chunk_local, chunk_remote, width;
     int32_t xcd_remap, fuse_unpack;
     int32_t fused_combine; /* 1: y_R adds into y itself; 0: a combine step
                               at end adds the remote partial sums            */
+    int32_t n_tiles_local, n_tiles_remote;  /* stream CSR tiles (0: vector) */
     int32_t reserved;
 } spmv_info_t;
 
@@ -167,6 +188,11 @@ typedef struct {
 #define SPMV_I32_OP_ORDER    10  /* [n_ops] canonical operation order          */
 #define SPMV_I32_STREAM_MAP  11  /* [SPMV_N_VERTICES] canonical streams, -1
                                     for CPU vertices                          */
+#define SPMV_I32_TILE_ROW_L  12  /* [n_tiles_local+1] stream-CSR tile rows of
+                                    A_L: tile t = rows [row[t], row[t+1])     */
+#define SPMV_I32_TILE_K_L    13  /* [n_tiles_local+1] first entry of each tile */
+#define SPMV_I32_TILE_ROW_R  14  /* same for A_R (compressed rows)            */
+#define SPMV_I32_TILE_K_R    15
 
 /* FP64 selectors for spmv_plan_get_f64 (device contents are copied back). */
 #define SPMV_F64_AL_VAL       0  /* [nnz_local]                               */
@@ -255,6 +281,26 @@ int spmv_exec(spmv_plan_t *plan, const double *x_local, double *y_local, void *s
  */
 int spmv_op_launch(spmv_plan_t *plan, int32_t op, const double *x_local, double *y_local,
                    void *stream);
+
+/*
+ * Replace the plan's operation order and stream map (same rules and errors as
+ * spmv_plan_create), keeping the uploaded share.  The plan owns
+ * max(n_streams given at creation, streams the order uses) plan streams; an
+ * order that needs more returns SPMV_EPLAN.  For sweeping the design space
+ * over one matrix.  On error the previous order stays in force.
+ */
+int spmv_plan_reorder(spmv_plan_t *plan, const int32_t *op_order, int32_t n_ops,
+                      const int32_t *stream_map, int32_t n_streams);
+
+/*
+ * The paper's benchmark protocol (Sec. III-C3) for one plan: a measurement
+ * repeats spmv_exec (a sample) until t_measure seconds have elapsed on the
+ * host clock and records elapsed / samples.  Runs n_measure measurements and
+ * writes their per-sample times (seconds) to host times[0..n_measure).  The
+ * inbox contents, x_local, y_local and stream are as for spmv_exec.
+ */
+int spmv_plan_time(spmv_plan_t *plan, const double *x_local, double *y_local, void *stream,
+                   double t_measure, int32_t n_measure, double *times);
 
 int spmv_plan_info(const spmv_plan_t *plan, spmv_info_t *info);
 

@@ -62,12 +62,14 @@ def SPMV_CES_B4(v): return SPMV_SYNC_CES | v
 def SPMV_CSWE_B4(v): return SPMV_SYNC_CSWE | v
 
 
-SPMV_F_HOST_ONLY, SPMV_F_PROFILE = 1, 2
+SPMV_F_HOST_ONLY, SPMV_F_PROFILE, SPMV_F_NO_BUFFER = 1, 2, 4
+SPMV_KERNEL_VECTOR, SPMV_KERNEL_STREAM = 1, 2
 
 (SPMV_I32_HALO_COLS, SPMV_I32_RECV_OFF, SPMV_I32_SEND_IDX, SPMV_I32_SEND_OFF,
  SPMV_I32_AL_PTR, SPMV_I32_AL_COLS, SPMV_I32_AR_ROWS, SPMV_I32_AR_PTR,
  SPMV_I32_AR_COLS, SPMV_I32_UNPACK_PERM, SPMV_I32_OP_ORDER,
- SPMV_I32_STREAM_MAP) = range(12)
+ SPMV_I32_STREAM_MAP, SPMV_I32_TILE_ROW_L, SPMV_I32_TILE_K_L, SPMV_I32_TILE_ROW_R,
+ SPMV_I32_TILE_K_R) = range(16)
 (SPMV_F64_AL_VAL, SPMV_F64_AR_VAL, SPMV_F64_SENDBUF, SPMV_F64_RECVBUF,
  SPMV_F64_X_HALO, SPMV_F64_OP_MS, SPMV_F64_OP_COUNT) = range(7)
 
@@ -81,17 +83,19 @@ class spmv_csr_t(ctypes.Structure):
 
 class spmv_tune_t(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int32) for k in (
-        "lanes_local", "lanes_remote", "rows_local", "rows_remote", "xcd_remap",
-        "fuse_unpack", "flags", "reserved")]
+        "kernel_local", "kernel_remote", "lanes_local", "lanes_remote", "rows_local",
+        "rows_remote", "chunk_local", "chunk_remote", "width", "xcd_remap", "fuse_unpack",
+        "flags")]
 
 
 class spmv_info_t(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "n_global", "lo", "n_loc", "nnz_local", "nnz_remote", "n_halo", "n_send",
         "n_remote_rows", "device_bytes")] + [(k, ctypes.c_int32) for k in (
-            "nranks", "rank", "n_streams", "n_ops", "lanes_local", "lanes_remote",
-            "rows_local", "rows_remote", "xcd_remap", "fuse_unpack", "fused_combine",
-            "reserved")]
+            "nranks", "rank", "n_streams", "n_ops", "kernel_local", "kernel_remote",
+            "lanes_local", "lanes_remote", "rows_local", "rows_remote", "chunk_local",
+            "chunk_remote", "width", "xcd_remap", "fuse_unpack", "fused_combine",
+            "n_tiles_local", "n_tiles_remote", "reserved")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -114,6 +118,8 @@ _proto("spmv_plan_destroy", [_P])
 _proto("spmv_exec", [_P, _P, _P, _P])
 _proto("spmv_plan_info", [_P, _P])
 _proto("spmv_op_launch", [_P, _I32, _P, _P, _P])
+_proto("spmv_plan_reorder", [_P, _P, _I32, _P, _I32])
+_proto("spmv_plan_time", [_P, _P, _P, _P, ctypes.c_double, _I32, _P])
 _proto("spmv_plan_get_i32", [_P, _I32, _P, _I64])
 _proto("spmv_plan_get_f64", [_P, _I32, _P, _I64])
 _proto("spmv_plan_reset_times", [_P])
@@ -180,14 +186,7 @@ def spmv_plan_create(A, nranks: int, rank: int, op_order=None, stream_map=None,
     """Build a plan for rank ``rank`` of ``nranks``; returns the plan handle."""
     c, keep = make_csr(A)
     ops = None if op_order is None else _i32(op_order)
-    smap = None
-    if stream_map is not None:
-        smap = np.full(SPMV_N_VERTICES, -1, np.int32)
-        if isinstance(stream_map, dict):
-            for k, v in stream_map.items():
-                smap[k] = v
-        else:
-            smap[:len(stream_map)] = stream_map
+    smap = _smap_array(stream_map)
     if isinstance(tune, dict):
         t = spmv_tune_t()
         for k, v in tune.items():
@@ -216,6 +215,35 @@ def spmv_op_launch(plan, op: int, x=None, y=None, stream=None) -> None:
     _check(_lib.spmv_op_launch(plan, op, _addr(x), _addr(y), _stream_handle(stream)))
 
 
+def _smap_array(stream_map):
+    if stream_map is None:
+        return None
+    smap = np.full(SPMV_N_VERTICES, -1, np.int32)
+    if isinstance(stream_map, dict):
+        for k, v in stream_map.items():
+            smap[k] = v
+    else:
+        smap[:len(stream_map)] = stream_map
+    return smap
+
+
+def spmv_plan_reorder(plan, op_order, stream_map=None, n_streams: int = 2) -> None:
+    """Swap the plan's operation order and stream map (same share)."""
+    ops = _i32(op_order)
+    smap = _smap_array(stream_map)
+    _check(_lib.spmv_plan_reorder(plan, _addr(ops), ops.size, _addr(smap), n_streams))
+
+
+def spmv_plan_time(plan, x, y, stream=None, t_measure: float = 0.01,
+                   n_measure: int = 5) -> np.ndarray:
+    """The paper's protocol: per measurement, repeat exec for t_measure
+    seconds; returns seconds per exec for each measurement."""
+    out = np.empty(n_measure, np.float64)
+    _check(_lib.spmv_plan_time(plan, _addr(x), _addr(y), _stream_handle(stream), t_measure,
+                               n_measure, out.ctypes.data))
+    return out
+
+
 def spmv_plan_info(plan) -> dict:
     info = spmv_info_t()
     _check(_lib.spmv_plan_info(plan, ctypes.byref(info)))
@@ -230,6 +258,10 @@ _I32_LEN = {
     SPMV_I32_AR_PTR: lambda i: i["n_remote_rows"] + 1,
     SPMV_I32_AR_COLS: lambda i: i["nnz_remote"], SPMV_I32_UNPACK_PERM: lambda i: i["n_halo"],
     SPMV_I32_OP_ORDER: lambda i: i["n_ops"], SPMV_I32_STREAM_MAP: lambda i: SPMV_N_VERTICES,
+    SPMV_I32_TILE_ROW_L: lambda i: i["n_tiles_local"] + 1 if i["kernel_local"] == 2 else 0,
+    SPMV_I32_TILE_K_L: lambda i: i["n_tiles_local"] + 1 if i["kernel_local"] == 2 else 0,
+    SPMV_I32_TILE_ROW_R: lambda i: i["n_tiles_remote"] + 1 if i["kernel_remote"] == 2 else 0,
+    SPMV_I32_TILE_K_R: lambda i: i["n_tiles_remote"] + 1 if i["kernel_remote"] == 2 else 0,
 }
 _F64_LEN = {
     SPMV_F64_AL_VAL: lambda i: i["nnz_local"], SPMV_F64_AR_VAL: lambda i: i["nnz_remote"],

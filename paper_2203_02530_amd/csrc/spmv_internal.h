@@ -86,7 +86,16 @@ struct CsrDev {
     const int32_t *col = nullptr;
     const double *val = nullptr;
     const int32_t *rows = nullptr; // compressed-row ids (remote), else null
+    int64_t nnz_alloc = 0;         // entries allocated (rp[n_rows] + padding)
+    int64_t n_x = 0;               // length of the x vector the columns index
+    // CSR-stream tiles: [tile_row[t], tile_row[t+1]) rows, entries from tile_k[t]
+    const int32_t *tile_row = nullptr, *tile_k = nullptr;
+    int32_t n_tiles = 0;
 };
+
+// Entries of padding after col/val on the device (vector loads of the
+// CSR-stream kernel never straddle the end of a buffer).
+constexpr int kEntryPad = 16;
 
 hipError_t launch_pack(const double *x, const int32_t *idx, double *out, int64_t n,
                        hipStream_t s);
@@ -94,9 +103,16 @@ hipError_t launch_unpack(const double *recv, const int32_t *perm, double *xh, in
                          hipStream_t s);
 // y[row] = sum (store) or y[rows[j]] += sum (accumulate) when acc_into != null
 hipError_t launch_csr(const CsrDev &A, const double *x, double *out, double *acc_into,
-                      int lanes, int rows, int xcd_remap, hipStream_t s);
+                      int lanes, int rows, int xcd_remap, bool allow_buffer, hipStream_t s);
 hipError_t launch_combine(const int32_t *rows, const double *part, double *y, int64_t n,
                           hipStream_t s);
+hipError_t launch_csr_stream(const CsrDev &A, const double *x, double *out, double *acc,
+                             int npt, int vw, int sum_lanes, int xcd_remap, hipStream_t s);
+int stream_cap(int npt);
+int stream_maxr(int sum_lanes);
+// Cut [0, n_rows) into CSR-stream tiles (host).
+void build_tiles(const std::vector<int32_t> &rp, int64_t n_rows, int cap, int maxr, int vw,
+                 std::vector<int32_t> &tile_row, std::vector<int32_t> &tile_k);
 int auto_lanes(int64_t nnz, int64_t rows);
 int auto_rows(int lanes, int64_t rows);
 

@@ -9,15 +9,29 @@
 // device receive buffer, each on a private copy stream; WaitSend/WaitRecv
 // block the host on the copy's completion event, as MPI_Wait would.
 #include <algorithm>
+#include <array>
+#include <chrono>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "spmv_internal.h"
+
+// Kernel configuration of one product (y_L or y_R).
+struct CsrCfg {
+    int32_t kernel = SPMV_KERNEL_VECTOR;
+    int32_t lanes = 1, rows = 1;   // vector CSR
+    int32_t chunk = 8, width = 2;  // stream CSR (lanes = summing lanes)
+    std::vector<int32_t> tile_row, tile_k;
+};
 
 struct spmv_plan {
     spmv::Share share;
     spmv::Schedule sch;
-    int32_t lanes_local = 1, lanes_remote = 1, rows_local = 1, rows_remote = 1, xcd_remap = 1;
+    CsrCfg cfg[2];                 // [0] = y_L, [1] = y_R
+    int32_t xcd_remap = 1;
     bool fuse_unpack = false, fused_combine = false, host_only = false, profile = false;
+    bool use_buffer = true;
     int device = 0;
 
     // device arena and its views
@@ -29,13 +43,15 @@ struct spmv_plan {
     double *dR_val = nullptr;
     int32_t *d_send_idx = nullptr, *d_perm = nullptr;
     double *d_sendbuf = nullptr, *d_recvbuf = nullptr, *d_xhalo = nullptr, *d_part = nullptr;
+    int32_t *d_tile_row[2] = {}, *d_tile_k[2] = {};
 
     // pinned host mailboxes
     double *h_inbox = nullptr, *h_outbox = nullptr;
 
     // streams and events
     hipStream_t st[SPMV_MAX_STREAMS] = {};
-    int32_t n_st = 0;
+    int32_t n_st = 0;           // plan streams owned
+    int32_t n_streams_max = 1;  // as requested at creation
     hipStream_t cs_send = nullptr, cs_recv = nullptr;
     hipEvent_t ev_start = nullptr, ev_send = nullptr, ev_recv = nullptr;
     hipEvent_t ev_rec[SPMV_N_VERTICES] = {};
@@ -47,6 +63,36 @@ struct spmv_plan {
 };
 
 namespace spmv {
+
+// Streams are shared by every plan on a device: plan stream i of any plan is
+// pool stream i, plus one send and one receive copy stream.  Plans on one
+// device then use a handful of HIP streams however many plans exist (many
+// streams would be multiplexed over the few hardware queues and add latency),
+// and since an exec ends with all its work finished, sharing adds no
+// ordering that an exec on the same thread did not already have.  The pool
+// lives until the process ends.
+struct StreamPool {
+    std::array<hipStream_t, SPMV_MAX_STREAMS + 2> st{};
+};
+
+int pool_streams(int device, int32_t n_plan, hipStream_t *plan_st, hipStream_t *send,
+                 hipStream_t *recv)
+{
+    static std::mutex mu;
+    static std::map<int, StreamPool> pools;
+    std::lock_guard<std::mutex> lock(mu);
+    StreamPool &pool = pools[device];
+    for (int32_t i = 0; i < n_plan + 2; ++i) {
+        const int32_t slot = i < n_plan ? i : SPMV_MAX_STREAMS + (i - n_plan);
+        if (!pool.st[size_t(slot)])
+            SPMV_HIP(hipStreamCreateWithFlags(&pool.st[size_t(slot)], hipStreamNonBlocking));
+    }
+    for (int32_t i = 0; i < n_plan; ++i) plan_st[i] = pool.st[size_t(i)];
+    *send = pool.st[SPMV_MAX_STREAMS];
+    *recv = pool.st[SPMV_MAX_STREAMS + 1];
+    return SPMV_OK;
+}
+
 namespace {
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
@@ -54,10 +100,6 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 void release(spmv_plan *p)
 {
     if (!p) return;
-    for (int32_t i = 0; i < p->n_st; ++i)
-        if (p->st[i]) (void)hipStreamDestroy(p->st[i]);
-    if (p->cs_send) (void)hipStreamDestroy(p->cs_send);
-    if (p->cs_recv) (void)hipStreamDestroy(p->cs_recv);
     hipEvent_t *evs[] = {&p->ev_start, &p->ev_send, &p->ev_recv};
     for (hipEvent_t *e : evs)
         if (*e) (void)hipEventDestroy(*e);
@@ -84,36 +126,41 @@ int allocate_and_upload(spmv_plan *p)
         void **dst;
         size_t bytes;
         const void *src;
+        size_t pad;  // zero bytes after the data
     };
     const size_t n_halo = S.halo.size(), n_send = S.send_idx.size(), n_rr = S.R_rows.size();
+    const size_t pad = kEntryPad;
     Item items[] = {
-        {(void **)&p->dL_ptr, S.L_ptr.size() * 4, S.L_ptr.data()},
-        {(void **)&p->dL_col, S.L_col.size() * 4, S.L_col.data()},
-        {(void **)&p->dR_rows, S.R_rows.size() * 4, S.R_rows.data()},
-        {(void **)&p->dR_ptr, S.R_ptr.size() * 4, S.R_ptr.data()},
-        {(void **)&p->dR_col, S.R_col.size() * 4, S.R_col.data()},
-        {(void **)&p->d_send_idx, n_send * 4, S.send_idx.data()},
-        {(void **)&p->d_perm, n_halo * 4, S.unpack_perm.data()},
-        {(void **)&p->dL_val, S.L_val.size() * 8, S.L_val.data()},
-        {(void **)&p->dR_val, S.R_val.size() * 8, S.R_val.data()},
-        {(void **)&p->d_sendbuf, n_send * 8, nullptr},
-        {(void **)&p->d_recvbuf, n_halo * 8, nullptr},
-        {(void **)&p->d_xhalo, n_halo * 8, nullptr},
-        {(void **)&p->d_part, n_rr * 8, nullptr},
+        {(void **)&p->dL_ptr, S.L_ptr.size() * 4, S.L_ptr.data(), 0},
+        {(void **)&p->dL_col, S.L_col.size() * 4, S.L_col.data(), pad * 4},
+        {(void **)&p->dR_rows, S.R_rows.size() * 4, S.R_rows.data(), 0},
+        {(void **)&p->dR_ptr, S.R_ptr.size() * 4, S.R_ptr.data(), 0},
+        {(void **)&p->dR_col, S.R_col.size() * 4, S.R_col.data(), pad * 4},
+        {(void **)&p->d_send_idx, n_send * 4, S.send_idx.data(), 0},
+        {(void **)&p->d_perm, n_halo * 4, S.unpack_perm.data(), 0},
+        {(void **)&p->d_tile_row[0], p->cfg[0].tile_row.size() * 4, p->cfg[0].tile_row.data(), 0},
+        {(void **)&p->d_tile_k[0], p->cfg[0].tile_k.size() * 4, p->cfg[0].tile_k.data(), 0},
+        {(void **)&p->d_tile_row[1], p->cfg[1].tile_row.size() * 4, p->cfg[1].tile_row.data(), 0},
+        {(void **)&p->d_tile_k[1], p->cfg[1].tile_k.size() * 4, p->cfg[1].tile_k.data(), 0},
+        {(void **)&p->dL_val, S.L_val.size() * 8, S.L_val.data(), pad * 8},
+        {(void **)&p->dR_val, S.R_val.size() * 8, S.R_val.data(), pad * 8},
+        {(void **)&p->d_sendbuf, n_send * 8, nullptr, 0},
+        {(void **)&p->d_recvbuf, n_halo * 8, nullptr, 0},
+        {(void **)&p->d_xhalo, n_halo * 8, nullptr, 0},
+        {(void **)&p->d_part, n_rr * 8, nullptr, 0},
     };
     size_t total = 0;
-    for (const Item &it : items) total += align_up(std::max<size_t>(it.bytes, 1));
+    for (const Item &it : items) total += align_up(std::max<size_t>(it.bytes + it.pad, 1));
     SPMV_HIP(hipMalloc(&p->arena, total));
     p->arena_bytes = total;
+    // zero everything first: padding after col/val, and the buffers
+    SPMV_HIP(hipMemset(p->arena, 0, total));
     char *cur = static_cast<char *>(p->arena);
     for (const Item &it : items) {
         *it.dst = cur;
         if (it.src && it.bytes) SPMV_HIP(hipMemcpy(cur, it.src, it.bytes, hipMemcpyHostToDevice));
-        cur += align_up(std::max<size_t>(it.bytes, 1));
+        cur += align_up(std::max<size_t>(it.bytes + it.pad, 1));
     }
-    SPMV_HIP(hipMemset(p->d_sendbuf, 0, std::max<size_t>(n_send * 8, 1)));
-    SPMV_HIP(hipMemset(p->d_recvbuf, 0, std::max<size_t>(n_halo * 8, 1)));
-    SPMV_HIP(hipMemset(p->d_xhalo, 0, std::max<size_t>(n_halo * 8, 1)));
     SPMV_HIP(hipHostMalloc((void **)&p->h_inbox, std::max<size_t>(n_halo * 8, 8),
                            hipHostMallocDefault));
     SPMV_HIP(hipHostMalloc((void **)&p->h_outbox, std::max<size_t>(n_send * 8, 8),
@@ -121,11 +168,8 @@ int allocate_and_upload(spmv_plan *p)
     std::memset(p->h_inbox, 0, std::max<size_t>(n_halo * 8, 8));
     std::memset(p->h_outbox, 0, std::max<size_t>(n_send * 8, 8));
 
-    p->n_st = std::max<int32_t>(p->sch.n_streams_used, 1);
-    for (int32_t i = 0; i < p->n_st; ++i)
-        SPMV_HIP(hipStreamCreateWithFlags(&p->st[i], hipStreamNonBlocking));
-    SPMV_HIP(hipStreamCreateWithFlags(&p->cs_send, hipStreamNonBlocking));
-    SPMV_HIP(hipStreamCreateWithFlags(&p->cs_recv, hipStreamNonBlocking));
+    p->n_st = std::max<int32_t>(std::max(p->sch.n_streams_used, p->n_streams_max), 1);
+    if (int rc = pool_streams(p->device, p->n_st, p->st, &p->cs_send, &p->cs_recv)) return rc;
     SPMV_HIP(hipEventCreateWithFlags(&p->ev_start, hipEventDisableTiming));
     SPMV_HIP(hipEventCreateWithFlags(&p->ev_send, hipEventDisableTiming));
     SPMV_HIP(hipEventCreateWithFlags(&p->ev_recv, hipEventDisableTiming));
@@ -141,10 +185,100 @@ int allocate_and_upload(spmv_plan *p)
     return SPMV_OK;
 }
 
+// y_R adds into y itself when it runs after y_L on the same stream;
+// otherwise its partial sums are added by a combine step at end.
+bool fuses_combine(const Schedule &sch)
+{
+    if (!sch.multi) return false;
+    auto pos = [&](int32_t tok) {
+        return std::find(sch.order.begin(), sch.order.end(), tok) - sch.order.begin();
+    };
+    return sch.stream[SPMV_OP_YL] == sch.stream[SPMV_OP_YR] && pos(SPMV_OP_YL) < pos(SPMV_OP_YR);
+}
+
 }  // namespace
 }  // namespace spmv
 
 using namespace spmv;
+
+namespace {
+
+CsrDev local_csr(const spmv_plan *p)
+{
+    CsrDev A;
+    A.n_rows = int32_t(p->share.n_loc);
+    A.rp = p->dL_ptr;
+    A.col = p->dL_col;
+    A.val = p->dL_val;
+    A.nnz_alloc = int64_t(p->share.L_col.size()) + kEntryPad;
+    A.n_x = p->share.n_loc;
+    return A;
+}
+
+CsrDev remote_csr(const spmv_plan *p)
+{
+    CsrDev A;
+    A.n_rows = int32_t(p->share.R_rows.size());
+    A.rp = p->dR_ptr;
+    A.col = p->dR_col;
+    A.val = p->dR_val;
+    A.rows = p->dR_rows;
+    A.nnz_alloc = int64_t(p->share.R_col.size()) + kEntryPad;
+    A.n_x = int64_t(p->share.halo.size());
+    return A;
+}
+
+// Resolve the automatic choices for one product and cut its stream tiles.
+void configure(CsrCfg &c, const std::vector<int32_t> &rp, int64_t n_rows, int32_t kernel,
+               int32_t lanes, int32_t rows, int32_t chunk, int32_t width)
+{
+    const int64_t nnz = n_rows > 0 ? rp[size_t(n_rows)] : 0;
+    // Stream CSR measured faster than vector CSR on the stencil shares
+    // (7-point 12.0 vs 15.4 us, 27-point 27.3 vs 35.1 us on MI355X); the
+    // vector kernel remains for arrays beyond 32-bit buffer offsets.
+    const int64_t kMax = (int64_t(1) << 32) - 64;
+    const bool fits = (nnz + kEntryPad) * 8 < kMax;
+    c.kernel = kernel ? kernel : (fits ? SPMV_KERNEL_STREAM : SPMV_KERNEL_VECTOR);
+    if (c.kernel == SPMV_KERNEL_VECTOR) {
+        c.lanes = lanes ? lanes : auto_lanes(nnz, n_rows);
+        c.rows = rows ? rows : auto_rows(c.lanes, n_rows);
+        return;
+    }
+    // short rows: a smaller window gives more tiles in flight (7-point:
+    // chunk 4 -> 12.0 us, 8 -> 12.3, 16 -> 16.1); longer rows: 8 (27-point:
+    // 27.3 us vs 29.2 with 16).  Width 2 beat width 4 on both.
+    const double mean_len = n_rows > 0 ? double(nnz) / double(n_rows) : 1.0;
+    c.chunk = chunk ? chunk : (mean_len < 12.0 ? 4 : 8);
+    c.width = width ? width : 2;
+    if (lanes) {
+        c.lanes = lanes;
+    } else {
+        // enough summing lanes that the rows-per-tile limit (256 / lanes)
+        // does not bind before the window of 256 * chunk entries is full
+        const double mean = n_rows > 0 ? double(nnz) / double(n_rows) : 1.0;
+        c.lanes = 1;
+        while (c.lanes < 16 && double(stream_maxr(c.lanes * 2)) * mean >= stream_cap(c.chunk))
+            c.lanes <<= 1;
+    }
+    build_tiles(rp, n_rows, stream_cap(c.chunk), stream_maxr(c.lanes), c.width, c.tile_row,
+                c.tile_k);
+}
+
+hipError_t launch_product(const spmv_plan *p, int side, const double *x, double *out,
+                          double *acc, hipStream_t s)
+{
+    CsrDev A = side == 0 ? local_csr(p) : remote_csr(p);
+    const CsrCfg &c = p->cfg[side];
+    if (c.kernel == SPMV_KERNEL_STREAM) {
+        A.tile_row = p->d_tile_row[side];
+        A.tile_k = p->d_tile_k[side];
+        A.n_tiles = int32_t(c.tile_row.size()) - 1;
+        return launch_csr_stream(A, x, out, acc, c.chunk, c.width, c.lanes, p->xcd_remap, s);
+    }
+    return launch_csr(A, x, out, acc, c.lanes, c.rows, p->xcd_remap, p->use_buffer, s);
+}
+
+}  // namespace
 
 extern "C" int spmv_plan_create_ex(const spmv_csr_t *csr, int32_t nranks, int32_t rank,
                                    const int32_t *op_order, int32_t n_ops,
@@ -157,10 +291,20 @@ extern "C" int spmv_plan_create_ex(const spmv_csr_t *csr, int32_t nranks, int32_
     if (tune) t = *tune;
     auto valid_lanes = [](int32_t l) { return l == 0 || (l >= 1 && l <= 64 && !(l & (l - 1))); };
     auto valid_rows = [](int32_t r) { return r == 0 || r == 1 || r == 2 || r == 4 || r == 8; };
+    auto valid_chunk = [](int32_t c) { return c == 0 || c == 4 || c == 8 || c == 16; };
     if (!valid_lanes(t.lanes_local) || !valid_lanes(t.lanes_remote))
         return set_error(SPMV_EINVAL, "lanes per row must be 0 or a power of two <= 64");
     if (!valid_rows(t.rows_local) || !valid_rows(t.rows_remote))
         return set_error(SPMV_EINVAL, "rows per lane group must be 0, 1, 2, 4 or 8");
+    if (!valid_chunk(t.chunk_local) || !valid_chunk(t.chunk_remote))
+        return set_error(SPMV_EINVAL, "chunk must be 0, 4, 8 or 16");
+    if (t.kernel_local < 0 || t.kernel_local > 2 || t.kernel_remote < 0 || t.kernel_remote > 2)
+        return set_error(SPMV_EINVAL, "kernel must be 0, 1 or 2");
+    if ((t.kernel_local == SPMV_KERNEL_STREAM && t.lanes_local > 16) ||
+        (t.kernel_remote == SPMV_KERNEL_STREAM && t.lanes_remote > 16))
+        return set_error(SPMV_EINVAL, "stream CSR sums with at most 16 lanes per row");
+    if (t.width != 0 && t.width != 2 && t.width != 4)
+        return set_error(SPMV_EINVAL, "width must be 0, 2 or 4");
     if (t.xcd_remap < 0 || t.xcd_remap > 2 || t.fuse_unpack < 0 || t.fuse_unpack > 1)
         return set_error(SPMV_EINVAL, "tune field out of range");
 
@@ -182,27 +326,29 @@ extern "C" int spmv_plan_create_ex(const spmv_csr_t *csr, int32_t nranks, int32_
         return rc;
     }
     const Share &S = p->share;
-    p->lanes_local = t.lanes_local ? t.lanes_local
-                                   : auto_lanes(int64_t(S.L_col.size()), S.n_loc);
-    p->lanes_remote = t.lanes_remote ? t.lanes_remote
-                                     : auto_lanes(int64_t(S.R_col.size()),
-                                                  int64_t(S.R_rows.size()));
-    p->rows_local = t.rows_local ? t.rows_local : auto_rows(p->lanes_local, S.n_loc);
-    p->rows_remote = t.rows_remote ? t.rows_remote
-                                   : auto_rows(p->lanes_remote, int64_t(S.R_rows.size()));
+    {
+        // the stream kernel addresses col/val/x through 32-bit buffer offsets
+        const int64_t kMax = (int64_t(1) << 32) - 64;
+        const bool big_l = (int64_t(S.L_col.size()) + kEntryPad) * 8 >= kMax || S.n_loc * 8 >= kMax;
+        const bool big_r = (int64_t(S.R_col.size()) + kEntryPad) * 8 >= kMax ||
+                           int64_t(S.halo.size()) * 8 >= kMax;
+        if ((t.kernel_local == SPMV_KERNEL_STREAM && big_l) ||
+            (t.kernel_remote == SPMV_KERNEL_STREAM && big_r)) {
+            delete p;
+            return set_error(SPMV_EINVAL, "stream CSR needs arrays below 4 GiB");
+        }
+    }
+    configure(p->cfg[0], S.L_ptr, S.n_loc, t.kernel_local, t.lanes_local, t.rows_local,
+              t.chunk_local, t.width);
+    configure(p->cfg[1], S.R_ptr, int64_t(S.R_rows.size()), t.kernel_remote, t.lanes_remote,
+              t.rows_remote, t.chunk_remote, t.width);
     p->xcd_remap = t.xcd_remap ? t.xcd_remap : 1;
     p->fuse_unpack = t.fuse_unpack == 1;
     p->host_only = (t.flags & SPMV_F_HOST_ONLY) != 0;
     p->profile = (t.flags & SPMV_F_PROFILE) != 0;
-    // y_R adds into y itself when it runs after y_L on the same stream;
-    // otherwise its partial sums are added by a combine step at end.
-    if (p->sch.multi) {
-        auto pos = [&](int32_t tok) {
-            return std::find(p->sch.order.begin(), p->sch.order.end(), tok) - p->sch.order.begin();
-        };
-        p->fused_combine = p->sch.stream[SPMV_OP_YL] == p->sch.stream[SPMV_OP_YR] &&
-                           pos(SPMV_OP_YL) < pos(SPMV_OP_YR);
-    }
+    p->use_buffer = (t.flags & SPMV_F_NO_BUFFER) == 0;
+    p->fused_combine = fuses_combine(p->sch);
+    p->n_streams_max = n_streams;
     if (!p->host_only) {
         rc = allocate_and_upload(p);
         if (rc != SPMV_OK) {
@@ -264,6 +410,7 @@ extern "C" int spmv_exec(spmv_plan_t *p, const double *x, double *y, void *strea
     const int64_t n_rr = int64_t(S.R_rows.size());
     bool ran[SPMV_N_VERTICES + 1] = {};
     bool combine = false;
+    const int32_t n_used = std::max<int32_t>(p->sch.n_streams_used, 1);
 
     for (int32_t tok : p->sch.order) {
         if (is_sync(tok)) {
@@ -286,7 +433,7 @@ extern "C" int spmv_exec(spmv_plan_t *p, const double *x, double *y, void *strea
         switch (tok) {
             case SPMV_OP_START:
                 SPMV_HIP(hipEventRecord(p->ev_start, caller));
-                for (int32_t i = 0; i < p->n_st; ++i)
+                for (int32_t i = 0; i < n_used; ++i)
                     SPMV_HIP(hipStreamWaitEvent(p->st[i], p->ev_start, 0));
                 break;
             case SPMV_OP_PACK: {
@@ -299,13 +446,8 @@ extern "C" int spmv_exec(spmv_plan_t *p, const double *x, double *y, void *strea
             }
             case SPMV_OP_YL: {
                 hipStream_t s = p->st[smap[tok]];
-                CsrDev A;
-                A.n_rows = int32_t(S.n_loc);
-                A.rp = p->dL_ptr;
-                A.col = p->dL_col;
-                A.val = p->dL_val;
                 SPMV_HIP(prof_begin(p, tok, s));
-                SPMV_HIP(launch_csr(A, x, y, nullptr, p->lanes_local, p->rows_local, p->xcd_remap, s));
+                SPMV_HIP(launch_product(p, 0, x, y, nullptr, s));
                 SPMV_HIP(prof_end(p, tok, s));
                 ran[tok] = true;
                 break;
@@ -341,27 +483,19 @@ extern "C" int spmv_exec(spmv_plan_t *p, const double *x, double *y, void *strea
             }
             case SPMV_OP_YR: {
                 hipStream_t s = p->st[smap[tok]];
-                CsrDev A;
-                A.n_rows = int32_t(n_rr);
-                A.rp = p->dR_ptr;
-                A.col = p->dR_col;
-                A.val = p->dR_val;
-                A.rows = p->dR_rows;
                 const double *xh = p->fuse_unpack ? p->d_recvbuf : p->d_xhalo;
                 SPMV_HIP(prof_begin(p, tok, s));
                 if (p->fused_combine)
-                    SPMV_HIP(launch_csr(A, xh, nullptr, y, p->lanes_remote, p->rows_remote,
-                                        p->xcd_remap, s));
+                    SPMV_HIP(launch_product(p, 1, xh, nullptr, y, s));
                 else
-                    SPMV_HIP(launch_csr(A, xh, p->d_part, nullptr, p->lanes_remote, p->rows_remote,
-                                        p->xcd_remap, s));
+                    SPMV_HIP(launch_product(p, 1, xh, p->d_part, nullptr, s));
                 SPMV_HIP(prof_end(p, tok, s));
                 combine = !p->fused_combine && n_rr > 0;
                 ran[tok] = true;
                 break;
             }
             case SPMV_OP_END:
-                for (int32_t i = 0; i < p->n_st; ++i) {
+                for (int32_t i = 0; i < n_used; ++i) {
                     SPMV_HIP(hipEventRecord(p->ev_join[i], p->st[i]));
                     SPMV_HIP(hipStreamWaitEvent(caller, p->ev_join[i], 0));
                 }
@@ -403,12 +537,7 @@ extern "C" int spmv_op_launch(spmv_plan_t *p, int32_t op, const double *x, doubl
             return SPMV_OK;
         case SPMV_OP_YL: {
             if (S.n_loc > 0 && (!x || !y)) return set_error(SPMV_EINVAL, "x or y is NULL");
-            CsrDev A;
-            A.n_rows = int32_t(S.n_loc);
-            A.rp = p->dL_ptr;
-            A.col = p->dL_col;
-            A.val = p->dL_val;
-            SPMV_HIP(launch_csr(A, x, y, nullptr, p->lanes_local, p->rows_local, p->xcd_remap, s));
+            SPMV_HIP(launch_product(p, 0, x, y, nullptr, s));
             return SPMV_OK;
         }
         case SPMV_OP_UNPACK:
@@ -418,18 +547,47 @@ extern "C" int spmv_op_launch(spmv_plan_t *p, int32_t op, const double *x, doubl
             return SPMV_OK;
         case SPMV_OP_YR: {
             if (n_rr > 0 && !y) return set_error(SPMV_EINVAL, "y is NULL");
-            CsrDev A;
-            A.n_rows = int32_t(n_rr);
-            A.rp = p->dR_ptr;
-            A.col = p->dR_col;
-            A.val = p->dR_val;
-            A.rows = p->dR_rows;
             const double *xh = p->fuse_unpack ? p->d_recvbuf : p->d_xhalo;
-            SPMV_HIP(launch_csr(A, xh, nullptr, y, p->lanes_remote, p->rows_remote, p->xcd_remap, s));
+            SPMV_HIP(launch_product(p, 1, xh, nullptr, y, s));
             return SPMV_OK;
         }
         default: return set_error(SPMV_EINVAL, "not a GPU operation: " + std::to_string(op));
     }
+}
+
+extern "C" int spmv_plan_reorder(spmv_plan_t *p, const int32_t *op_order, int32_t n_ops,
+                                 const int32_t *stream_map, int32_t n_streams)
+{
+    if (!p) return set_error(SPMV_EINVAL, "plan is NULL");
+    Schedule sch;
+    if (int rc = validate_schedule(p->share.nranks, op_order, n_ops, stream_map, n_streams, sch))
+        return rc;
+    if (!p->host_only && sch.n_streams_used > p->n_st)
+        return set_error(SPMV_EPLAN, "order uses " + std::to_string(sch.n_streams_used) +
+                                         " streams, the plan owns " + std::to_string(p->n_st));
+    p->sch = std::move(sch);
+    p->fused_combine = fuses_combine(p->sch);
+    return SPMV_OK;
+}
+
+extern "C" int spmv_plan_time(spmv_plan_t *p, const double *x, double *y, void *stream,
+                              double t_measure, int32_t n_measure, double *times)
+{
+    if (!p || !times || n_measure < 1 || !(t_measure > 0))
+        return set_error(SPMV_EINVAL, "bad argument to spmv_plan_time");
+    using clock = std::chrono::steady_clock;
+    for (int32_t m = 0; m < n_measure; ++m) {
+        const auto t0 = clock::now();
+        int64_t samples = 0;
+        double el = 0.0;
+        do {
+            if (int rc = spmv_exec(p, x, y, stream)) return rc;
+            ++samples;
+            el = std::chrono::duration<double>(clock::now() - t0).count();
+        } while (el < t_measure);
+        times[m] = el / double(samples);
+    }
+    return SPMV_OK;
 }
 
 extern "C" int spmv_plan_info(const spmv_plan_t *p, spmv_info_t *info)
@@ -450,10 +608,19 @@ extern "C" int spmv_plan_info(const spmv_plan_t *p, spmv_info_t *info)
     info->rank = S.rank;
     info->n_streams = p->n_st;
     info->n_ops = int32_t(p->sch.order.size());
-    info->lanes_local = p->lanes_local;
-    info->lanes_remote = p->lanes_remote;
-    info->rows_local = p->rows_local;
-    info->rows_remote = p->rows_remote;
+    info->kernel_local = p->cfg[0].kernel;
+    info->kernel_remote = p->cfg[1].kernel;
+    info->lanes_local = p->cfg[0].lanes;
+    info->lanes_remote = p->cfg[1].lanes;
+    info->rows_local = p->cfg[0].rows;
+    info->rows_remote = p->cfg[1].rows;
+    info->chunk_local = p->cfg[0].chunk;
+    info->chunk_remote = p->cfg[1].chunk;
+    info->width = p->cfg[0].kernel == SPMV_KERNEL_STREAM ? p->cfg[0].width : p->cfg[1].width;
+    info->n_tiles_local = p->cfg[0].kernel == SPMV_KERNEL_STREAM
+                              ? int32_t(p->cfg[0].tile_row.size()) - 1 : 0;
+    info->n_tiles_remote = p->cfg[1].kernel == SPMV_KERNEL_STREAM
+                               ? int32_t(p->cfg[1].tile_row.size()) - 1 : 0;
     info->xcd_remap = p->xcd_remap;
     info->fuse_unpack = p->fuse_unpack;
     info->fused_combine = p->fused_combine;
@@ -482,6 +649,10 @@ extern "C" int spmv_plan_get_i32(const spmv_plan_t *p, int32_t which, int32_t *o
             tmp.assign(p->sch.stream, p->sch.stream + SPMV_N_VERTICES);
             src = &tmp;
             break;
+        case SPMV_I32_TILE_ROW_L: src = &p->cfg[0].tile_row; break;
+        case SPMV_I32_TILE_K_L: src = &p->cfg[0].tile_k; break;
+        case SPMV_I32_TILE_ROW_R: src = &p->cfg[1].tile_row; break;
+        case SPMV_I32_TILE_K_R: src = &p->cfg[1].tile_k; break;
         default: return set_error(SPMV_EINVAL, "unknown i32 selector");
     }
     if (n < int64_t(src->size()))

@@ -169,4 +169,26 @@ int build_share(const spmv_csr_t *csr, int32_t P, int32_t r, Share &S)
     return SPMV_OK;
 }
 
+// Tiles of the CSR-stream kernel: consecutive rows, at most `maxr` of them,
+// whose entries fit the window [rp[r0] rounded down to vw, + cap); a row
+// whose entries alone overflow the window is a tile of its own.
+void build_tiles(const std::vector<int32_t> &rp, int64_t n_rows, int cap, int maxr, int vw,
+                 std::vector<int32_t> &tile_row, std::vector<int32_t> &tile_k)
+{
+    tile_row.clear();
+    tile_k.clear();
+    int64_t r = 0;
+    while (r < n_rows) {
+        tile_row.push_back(int32_t(r));
+        tile_k.push_back(rp[size_t(r)]);
+        const int64_t base = rp[size_t(r)] & ~int64_t(vw - 1);
+        int64_t e = r + 1;
+        if (rp[size_t(e)] - base <= cap)
+            while (e < n_rows && e - r < maxr && rp[size_t(e) + 1] - base <= cap) ++e;
+        r = e;
+    }
+    tile_row.push_back(int32_t(n_rows));
+    tile_k.push_back(n_rows > 0 ? rp[size_t(n_rows)] : (rp.empty() ? 0 : rp[0]));
+}
+
 }  // namespace spmv

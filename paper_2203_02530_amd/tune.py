@@ -1,0 +1,159 @@
+"""Autotuner over the paper's design space and the kernel variants.
+
+Two searches, both timed on the device by the library itself:
+
+* :func:`sweep_plans` -- every (operation order, stream map) of the SpMV DAG
+  (the design space of Sec. III-B/C, enumerated by the library), timed with
+  the paper's benchmark protocol (Sec. III-C3): a measurement repeats the
+  program until t_measure = 0.01 s has elapsed and records time / samples.
+  One plan object is re-ordered in place (``spmv_plan_reorder``), so the
+  share is uploaded once.
+* :func:`tune_kernel` -- lanes per row, rows per lane group and tile order of
+  the CSR kernel, timed with HIP events around back-to-back launches over
+  cold replicas.
+
+Results can be appended to a JSONL cache keyed by the matrix digest, so an
+interrupted sweep resumes where it stopped.
+"""
+from __future__ import annotations
+
+import hashlib
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+
+from . import (SPMV_OP_YL, spmv_op_launch, spmv_plan_create, spmv_plan_destroy,
+               spmv_plan_get_i32, spmv_plan_inbox, spmv_plan_info, spmv_plan_reorder,
+               spmv_plan_space_count, spmv_plan_space_get, spmv_plan_time, SPMV_I32_HALO_COLS)
+
+MALL_BYTES = 256 << 20
+
+
+def matrix_digest(A, nranks: int, rank: int) -> str:
+    h = hashlib.blake2b(digest_size=16)
+    for a in (A.row_ptr, A.col_idx, A.val):
+        h.update(np.ascontiguousarray(a).view(np.uint8))
+    h.update(f"{A.n_rows}:{nranks}:{rank}".encode())
+    return h.hexdigest()
+
+
+def _load_cache(path, key):
+    done = {}
+    if path and os.path.exists(path):
+        with open(path) as f:
+            for line in f:
+                try:
+                    d = json.loads(line)
+                except json.JSONDecodeError:
+                    continue
+                if d.get("key") == key:
+                    done[d["index"]] = d
+    return done
+
+
+def sweep_plans(A, nranks: int, rank: int, x: np.ndarray, n_streams: int = 2,
+                tune: dict | None = None, t_measure: float = 0.01, n_measure: int = 1,
+                indices=None, cache_path: str | None = None, log=None):
+    """Time every plan of the design space on rank ``rank``'s share.
+
+    Returns a list of dicts {index, times (s), t (median s)} in index order.
+    """
+    import torch
+    n_plans = spmv_plan_space_count(nranks, n_streams)
+    idx = list(range(n_plans)) if indices is None else list(indices)
+    key = f"{matrix_digest(A, nranks, rank)}:{n_streams}:{json.dumps(tune or {}, sort_keys=True)}"
+    done = _load_cache(cache_path, key)
+    ops0, smap0 = spmv_plan_space_get(nranks, n_streams, 0)
+    plan = spmv_plan_create(A, nranks, rank, ops0, smap0, n_streams, tune)
+    out = []
+    try:
+        info = spmv_plan_info(plan)
+        lo, n = info["lo"], info["n_loc"]
+        halo = spmv_plan_get_i32(plan, SPMV_I32_HALO_COLS).astype(np.int64)
+        spmv_plan_inbox(plan)[:] = x[halo]
+        xd = torch.from_numpy(np.ascontiguousarray(x[lo:lo + n])).cuda()
+        yd = torch.empty(n, dtype=torch.float64, device="cuda")
+        stream = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        spmv_plan_time(plan, xd, yd, stream, t_measure, 1)       # warm-up
+        fh = open(cache_path, "a") if cache_path else None
+        try:
+            for j, i in enumerate(idx):
+                if i in done:
+                    out.append(done[i])
+                    continue
+                ops, smap = spmv_plan_space_get(nranks, n_streams, i)
+                spmv_plan_reorder(plan, ops, smap, n_streams)
+                t = spmv_plan_time(plan, xd, yd, stream, t_measure, n_measure)
+                d = {"key": key, "index": i, "times": t.tolist(), "t": float(np.median(t))}
+                out.append(d)
+                if fh:
+                    fh.write(json.dumps(d) + "\n")
+                    fh.flush()
+                if log and j % 250 == 0:
+                    log(f"plan {j}/{len(idx)}: {d['t'] * 1e6:.1f} us")
+        finally:
+            if fh:
+                fh.close()
+    finally:
+        spmv_plan_destroy(plan)
+    return out
+
+
+def best_plans(results, k: int = 1):
+    return sorted(results, key=lambda d: d["t"])[:k]
+
+
+def sweep_summary(results) -> dict:
+    t = np.array([d["t"] for d in results])
+    i_best = int(np.argmin(t))
+    i_worst = int(np.argmax(t))
+    return {"n_plans": int(t.size), "fastest_us": round(float(t[i_best]) * 1e6, 3),
+            "slowest_us": round(float(t[i_worst]) * 1e6, 3),
+            "median_us": round(float(np.median(t)) * 1e6, 3),
+            "slowest_over_fastest": round(float(t[i_worst] / t[i_best]), 3),
+            "fastest_index": results[i_best]["index"], "slowest_index": results[i_worst]["index"]}
+
+
+def tune_kernel(A, nranks: int, rank: int, x: np.ndarray, lanes=(4, 8, 16, 32, 64),
+                rows=(1, 2, 4, 8), remaps=(1, 2), launches: int = 100, log=None):
+    """Search (lanes, rows, tile order) for y_L by timing back-to-back
+    launches over cold replicas.  Returns (best tune dict, all results)."""
+    import torch
+    results = []
+    stream = torch.cuda.Stream()
+    for l, r_, m in itertools.product(lanes, rows, remaps):
+        tune = {"lanes_local": l, "rows_local": r_, "xcd_remap": m}
+        p0 = spmv_plan_create(A, nranks, rank, None, None, 2, tune)
+        info = spmv_plan_info(p0)
+        n = info["n_loc"]
+        R = max(1, math.ceil(2 * MALL_BYTES / max(info["device_bytes"] + 16 * n, 1)))
+        plans = [p0] + [spmv_plan_create(A, nranks, rank, None, None, 2, tune)
+                        for _ in range(R - 1)]
+        try:
+            lo = info["lo"]
+            xs = [torch.from_numpy(np.ascontiguousarray(x[lo:lo + n])).cuda() for _ in plans]
+            ys = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in plans]
+            torch.cuda.synchronize()
+            with torch.cuda.stream(stream):
+                for i in range(2 * R):
+                    spmv_op_launch(plans[i % R], SPMV_OP_YL, xs[i % R], ys[i % R], stream)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for i in range(launches):
+                    spmv_op_launch(plans[i % R], SPMV_OP_YL, xs[i % R], ys[i % R], stream)
+                e1.record(stream)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / launches
+        finally:
+            for p in plans:
+                spmv_plan_destroy(p)
+        results.append({**tune, "us": us})
+        if log:
+            log(json.dumps(results[-1]))
+    best = min(results, key=lambda d: d["us"])
+    return {k: best[k] for k in ("lanes_local", "rows_local", "xcd_remap")}, results

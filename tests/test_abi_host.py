@@ -273,6 +273,78 @@ def test_default_plan_fuses_combine():
     p = sp.spmv_plan_create(A, 2, 1, tune=HOST_ONLY)
     try:
         info = sp.spmv_plan_info(p)
-        assert info["fused_combine"] == 1 and info["lanes_local"] == 8
+        assert info["fused_combine"] == 1
+        # automatic kernel: stream CSR, window chunk 4 for 7-entry rows
+        assert info["kernel_local"] == 2 and info["chunk_local"] == 4
     finally:
         sp.spmv_plan_destroy(p)
+    p = sp.spmv_plan_create(A, 2, 1, tune={"flags": sp.SPMV_F_HOST_ONLY, "kernel_local": 1})
+    try:
+        info = sp.spmv_plan_info(p)
+        assert info["kernel_local"] == 1 and info["lanes_local"] == 8
+    finally:
+        sp.spmv_plan_destroy(p)
+
+
+def test_reorder_host_only():
+    A = gen.laplacian_3d7(8)
+    p = sp.spmv_plan_create(A, 2, 1, tune=HOST_ONLY)
+    try:
+        before = sp.spmv_plan_get_i32(p, sp.SPMV_I32_OP_ORDER).tolist()
+        with pytest.raises(sp.SpmvError) as e:
+            sp.spmv_plan_reorder(p, _codes(BASE[:-1]), None, 2)
+        assert e.value.code == sp.SPMV_EPLAN
+        assert sp.spmv_plan_get_i32(p, sp.SPMV_I32_OP_ORDER).tolist() == before
+        ops, smap = sp.spmv_plan_space_get(2, 2, 17)
+        sp.spmv_plan_reorder(p, ops, smap, 2)
+        got = sp.spmv_plan_get_i32(p, sp.SPMV_I32_OP_ORDER).tolist()
+        # the stored order has the implied Unpack inserted before y_R
+        assert [t for t in got if t != sp.SPMV_OP_UNPACK] == ops.tolist()
+        assert got.index(sp.SPMV_OP_UNPACK) == got.index(sp.SPMV_OP_YR) - 1
+    finally:
+        sp.spmv_plan_destroy(p)
+
+
+def _check_tiles(rp, trow, tk, cap, maxr, vw):
+    """Invariants the stream kernel relies on (its LDS indices stay inside
+    the window and the row-pointer stage): tiles partition the rows in order,
+    tile_k is the tile's first entry, a tile's entries fit the window from
+    its first entry rounded down to vw unless it is a single row, and a tile
+    has at most maxr rows."""
+    n = rp.size - 1
+    assert trow[0] == 0 and trow[-1] == n and np.all(np.diff(trow) >= 1) or n == 0
+    assert np.array_equal(tk, rp[trow])
+    for t in range(trow.size - 1):
+        r0, r1 = trow[t], trow[t + 1]
+        base = rp[r0] & ~(vw - 1)
+        assert r1 - r0 <= maxr
+        if r1 - r0 > 1:
+            assert rp[r1] - base <= cap
+        # maximal: the next row would not have fitted
+        if r1 < n and r1 - r0 < maxr and rp[r0 + 1] - base <= cap:
+            assert rp[r1 + 1] - base > cap
+
+
+@pytest.mark.parametrize("chunk,width,lanes", [(4, 2, 1), (8, 2, 2), (8, 4, 4), (16, 4, 16),
+                                               (16, 2, 8)])
+def test_stream_tiles_invariants(chunk, width, lanes):
+    for A, P, r in [(gen.power_law(30000, mean_len=40.0, seed=8), 4, 1),
+                    (gen.power_law(20000, mean_len=300.0, seed=9), 2, 0),
+                    (gen.laplacian_3d7(16), 4, 1), (gen.stencil_3d27(10, seed=3), 2, 1),
+                    (gen.laplacian_2d5(2, 2), 6, 5)]:
+        p = sp.spmv_plan_create(A, P, r, tune={"flags": sp.SPMV_F_HOST_ONLY, "kernel_local": 2,
+                                               "kernel_remote": 2, "chunk_local": chunk,
+                                               "chunk_remote": chunk, "width": width,
+                                               "lanes_local": lanes, "lanes_remote": lanes})
+        try:
+            info = sp.spmv_plan_info(p)
+            cap, maxr = 256 * chunk, 256 // lanes
+            for rpw, trw, tkw in ((sp.SPMV_I32_AL_PTR, sp.SPMV_I32_TILE_ROW_L, sp.SPMV_I32_TILE_K_L),
+                                  (sp.SPMV_I32_AR_PTR, sp.SPMV_I32_TILE_ROW_R, sp.SPMV_I32_TILE_K_R)):
+                rp = sp.spmv_plan_get_i32(p, rpw).astype(np.int64)
+                trow = sp.spmv_plan_get_i32(p, trw).astype(np.int64)
+                tk = sp.spmv_plan_get_i32(p, tkw).astype(np.int64)
+                _check_tiles(rp, trow, tk, cap, maxr, width)
+            assert info["kernel_local"] == 2
+        finally:
+            sp.spmv_plan_destroy(p)

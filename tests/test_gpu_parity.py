@@ -74,11 +74,37 @@ def test_lane_variants(lanes, rows):
     A = gen.power_law(30000, seed=17)
     x = gen.x_normal(A.n_cols, 18)
     log(f"power-law 30k lanes={lanes} rows={rows}")
-    for fuse, remap in ((0, 1), (1, 2)):
+    for fuse, remap, flags in ((0, 1, 0), (1, 2, sp.SPMV_F_NO_BUFFER)):
         res, ref = run_share(A, 4, 2, x, tune={"lanes_local": lanes, "lanes_remote": lanes,
                                                "rows_local": rows, "rows_remote": rows,
-                                               "xcd_remap": remap, "fuse_unpack": fuse})
+                                               "xcd_remap": remap, "fuse_unpack": fuse,
+                                               "flags": flags})
         assert_share_parity(res, ref)
+
+
+@pytest.mark.parametrize("chunk", [4, 8, 16])
+@pytest.mark.parametrize("width", [2, 4])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
+def test_stream_variants(chunk, width, lanes):
+    """Stream CSR on uneven rows, including rows longer than the window."""
+    log(f"stream chunk={chunk} width={width} lanes={lanes}")
+    for A, P, r, seed in [(gen.power_law(30000, seed=17), 4, 2, 18),
+                          (gen.power_law(12000, mean_len=300.0, seed=44), 4, 1, 45)]:
+        x = gen.x_normal(A.n_cols, seed)
+        for fuse, remap in ((0, 1), (1, 2)):
+            res, ref = run_share(A, P, r, x, tune={
+                "kernel_local": 2, "kernel_remote": 2, "chunk_local": chunk,
+                "chunk_remote": chunk, "width": width, "lanes_local": lanes,
+                "lanes_remote": lanes, "xcd_remap": remap, "fuse_unpack": fuse})
+            assert res["info"]["kernel_local"] == 2
+            assert_share_parity(res, ref)
+
+
+def test_stream_stencils_bit_exact_integer():
+    for A, P, r in [(gen.laplacian_3d7(32), 4, 1), (gen.laplacian_2d5(64), 1, 0)]:
+        x = gen.x_integer(A.n_cols, 9)
+        res, ref = run_share(A, P, r, x, tune={"kernel_local": 2, "kernel_remote": 2})
+        assert np.array_equal(bits(res["y"]), bits(ref["y"]))
 
 
 def test_op_launch_matches_exec():
@@ -130,6 +156,42 @@ def test_every_plan_bit_identical():
             assert np.array_equal(bits(res["y"]), first), i
             assert np.array_equal(bits(res["outbox"]), bits(ref["sendbuf"])), i
     assert 0 < fused < n   # both the fused and the combine path were exercised
+
+
+def test_reorder_and_plan_time():
+    """One plan re-ordered through part of the design space keeps giving the
+    same bits; the paper's timing protocol returns sane per-sample times."""
+    import torch
+    A = gen.banded_uniform(8000, 10, 2000, seed=23)
+    x = gen.x_normal(A.n_cols, 24)
+    P, r = 4, 2
+    ref = oracle.share_reference(A, P, r, x)
+    ops, smap = sp.spmv_plan_space_get(P, 2, 0)
+    plan = sp.spmv_plan_create(A, P, r, ops, smap, 2)
+    try:
+        first = None
+        rng = np.random.default_rng(3)
+        for i in rng.choice(2016, 40, replace=False):
+            ops, smap = sp.spmv_plan_space_get(P, 2, int(i))
+            sp.spmv_plan_reorder(plan, ops, smap, 2)
+            res, _ = run_share(A, P, r, x, ref=ref, plan=plan)
+            if first is None:
+                assert_share_parity(res, ref)
+                first = bits(res["y"])
+            assert np.array_equal(bits(res["y"]), first), i
+        info = sp.spmv_plan_info(plan)
+        lo, n = info["lo"], info["n_loc"]
+        xd = torch.from_numpy(x[lo:lo + n].copy()).cuda()
+        yd = torch.empty(n, dtype=torch.float64, device="cuda")
+        t = sp.spmv_plan_time(plan, xd, yd, torch.cuda.current_stream(), 0.005, 3)
+        assert t.shape == (3,) and np.all(t > 0) and np.all(t < 0.005)
+        # an order needing a third stream does not fit a two-stream plan
+        bad = {sp.SPMV_OP_PACK: 0, sp.SPMV_OP_YL: 1, sp.SPMV_OP_YR: 2}
+        with pytest.raises(sp.SpmvError) as e:
+            sp.spmv_plan_reorder(plan, ops, bad, 3)
+        assert e.value.code == sp.SPMV_EPLAN
+    finally:
+        sp.spmv_plan_destroy(plan)
 
 
 def test_three_streams_and_explicit_unpack():
