@@ -137,25 +137,48 @@ def stencil_3d27(n: int, seed: int = 3) -> CSR:
 def _distinct_sorted_rows(rng, lo: np.ndarray, hi: np.ndarray, lengths: np.ndarray,
                           n_cols: int) -> np.ndarray:
     """Per row i, ``lengths[i]`` distinct columns uniform in [lo[i], hi[i]],
-    concatenated row by row in ascending order.  Duplicates are redrawn."""
+    concatenated row by row in ascending order.
+
+    Sorted uniforms come directly as order statistics: with E_1..E_{L+1}
+    i.i.d. exponential, (E_1 + .. + E_j) / (E_1 + .. + E_{L+1}), j = 1..L, are
+    L sorted U(0,1) draws, so no sort is needed.  A row whose floored columns
+    collide (rare) is redrawn without replacement.
+    """
     n = lengths.size
     total = int(lengths.sum())
+    if total == 0:
+        return np.zeros(0, np.int64)
+    seg = lengths + 1                                   # L + 1 spacings per row
+    e = rng.standard_exponential(int(seg.sum()))
+    c = np.cumsum(e)
+    ends = np.cumsum(seg) - 1                           # index of each row's last spacing
+    starts = ends - lengths                             # first spacing of each row
+    before = np.where(starts > 0, c[starts - 1], 0.0)   # cumsum before the row
+    tot = c[ends] - before
     row = np.repeat(np.arange(n, dtype=np.int64), lengths)
-    cols = lo[row] + (rng.random(total) * (hi[row] - lo[row] + 1)).astype(np.int64)
-    cols = np.minimum(cols, hi[row])
-    while True:
-        key = row * np.int64(n_cols) + cols
-        order = np.argsort(key, kind="stable")
-        key = key[order]
-        cols = cols[order]
-        dup = np.zeros(total, bool)
-        dup[1:] = key[1:] == key[:-1]
-        nd = int(dup.sum())
-        if nd == 0:
-            return cols
-        r = row[dup]
-        cols[dup] = lo[r] + (rng.random(nd) * (hi[r] - lo[r] + 1)).astype(np.int64)
-        cols[dup] = np.minimum(cols[dup], hi[r])
+    # positions of the first L partial sums of each row inside c
+    keep = np.ones(c.size, bool)
+    keep[ends] = False
+    u = c[keep]
+    u -= before[row]
+    u /= tot[row]
+    if np.all(lo == lo[0]) and np.all(hi == hi[0]):      # one common range
+        width = int(hi[0] - lo[0] + 1)
+        cols = np.minimum((u * width).astype(np.int64), width - 1)
+        cols += int(lo[0])
+    else:
+        width = (hi - lo + 1)[row]
+        cols = lo[row] + np.minimum((u * width).astype(np.int64), width - 1)
+    dup = np.zeros(total, bool)
+    dup[1:] = (cols[1:] == cols[:-1]) & (row[1:] == row[:-1])
+    if dup.any():
+        offs = np.zeros(n + 1, np.int64)
+        np.cumsum(lengths, out=offs[1:])
+        for r in np.unique(row[dup]):
+            a, b = offs[r], offs[r + 1]
+            cols[a:b] = np.sort(lo[r] + rng.choice(int(hi[r] - lo[r] + 1), size=int(b - a),
+                                                   replace=False))
+    return cols
 
 
 def banded_uniform(n: int = 150_000, per_row: int = 10, half_bw: int = 37_500,

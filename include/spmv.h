@@ -346,6 +346,127 @@ int spmv_plan_space_get(int32_t nranks, int32_t n_streams, int64_t index,
  * full length, or SPMV_EINVAL for an unknown token. */
 int spmv_op_name(int32_t op, char *buf, int32_t cap);
 
+/* ------------------------------------------------------------ batches */
+
+/*
+ * A batch runs the SpMVs of many rank shares (plans, possibly of different
+ * matrices and sizes) together: every GPU step of every share goes into one
+ * of three grouped persistent kernels (Pack + y_L | Unpack | y_R), whose work
+ * lists hold the stream-CSR tiles and gather ranges of all shares, balanced
+ * over the blocks longest-first; the halo staging of all shares becomes copy
+ * nodes.  The paper's host-blocking synchronisations (CER/CES before
+ * PostSend, WaitRecv before y_R) become graph edges: Pack+y_L -> send copies;
+ * receive copies -> Unpack -> y_R; Pack+y_L -> y_R.  The whole batch is one
+ * hipGraph launch.  A share's y is bit-identical to spmv_exec of its plan:
+ * the same tiles are summed by the same device code.
+ */
+typedef struct spmv_batch spmv_batch_t;   /* opaque */
+
+typedef struct {
+    int32_t blocks_per_cu;  /* persistent grid = 256 * blocks_per_cu, 0 = 8  */
+    int32_t use_graph;      /* 0 = auto (graph), 1 = hipGraph, 2 = stream launches */
+    int32_t xcd_affinity;   /* 0 = auto (on when >= 8 shares), 1 = on: the work
+                               of share s runs on XCD s mod 8, 2 = off        */
+    int32_t reserved[5];
+} spmv_batch_opts_t;
+
+typedef struct {
+    int32_t n_shares;
+    int32_t n_blocks;        /* grid of each grouped kernel                 */
+    int64_t n_items[3];      /* work items: Pack+y_L, Unpack, y_R           */
+    int64_t device_bytes;    /* algorithmic device bytes of one batch exec  */
+    int64_t host_link_bytes; /* bytes staged over the host link, both ways  */
+    int32_t chunk, width;    /* stream-CSR window and load width shared by all */
+    int32_t use_graph, xcd_affinity;
+} spmv_batch_info_t;
+
+/*
+ * Build a batch over `n` plans (borrowed: they must outlive the batch and are
+ * not executed meanwhile).  Every plan must be a device plan whose y_L and
+ * y_R use the stream-CSR kernel with one common chunk and width (the lanes
+ * per row may differ).  SPMV_EINVAL otherwise.
+ */
+int spmv_batch_create(spmv_plan_t *const *plans, int32_t n, const spmv_batch_opts_t *opts,
+                      spmv_batch_t **out);
+
+/*
+ * Run the batch: for share i, y[i] = (A_i x_i) over its owned rows, with the
+ * same halo semantics as spmv_exec (inboxes filled by the caller, outboxes
+ * filled on return).  x, y: host arrays of n device pointers (n_loc each).
+ * Host-synchronous on return.
+ */
+int spmv_batch_exec(spmv_batch_t *batch, const double *const *x, double *const *y, void *stream);
+
+int spmv_batch_info(const spmv_batch_t *batch, spmv_batch_info_t *info);
+int spmv_batch_destroy(spmv_batch_t *batch);   /* NULL-safe */
+
+/* ------------------------------------------------------------ serving */
+
+/*
+ * A server keeps matrices resident on the device and answers y = A x
+ * requests with continuous batching: a worker thread admits queued requests
+ * while the HBM budget (resident matrices + buffers of requests on the
+ * device) and the in-flight limit allow, launches every admitted request
+ * that is not yet running as one batch (one grouped stream-CSR launch, with
+ * its x/y copies on the batch's stream), keeps up to max_epochs batches on
+ * the device at once, and retires them as their events complete.  Requests
+ * that arrive while batches run join the next batch.  Each request's y is
+ * computed by the same tiles and device code whatever it is batched with,
+ * so its bits do not depend on the mix.  mode 1 serves one request at a
+ * time (the plain per-call path) with the same kernels.
+ */
+typedef struct spmv_server spmv_server_t;   /* opaque */
+
+typedef struct {
+    int64_t budget_bytes;   /* device bytes for resident matrices and request
+                               buffers (0 = 64 GiB)                          */
+    int32_t max_inflight;   /* requests on the device at once (0 = 256)      */
+    int32_t max_epochs;     /* batches on the device at once (0 = 4)         */
+    int32_t max_batch;      /* requests per batch (0 = 64)                   */
+    int32_t chunk;          /* stream-CSR chunk of resident matrices (0 = 8) */
+    int32_t mode;           /* 0 = continuous batching, 1 = plain per-call   */
+    int32_t reserved[3];
+} spmv_server_opts_t;
+
+typedef struct {
+    int64_t submitted, completed, batches;
+    int64_t resident_bytes;     /* matrices                                  */
+    int64_t peak_inflight_bytes;/* request buffers on the device, peak       */
+    int64_t arena_bytes;        /* request-buffer arena                      */
+    int32_t peak_inflight;      /* requests on the device, peak              */
+    int32_t n_matrices;
+    double mean_batch;          /* requests per batch                        */
+} spmv_server_stats_t;
+
+int spmv_server_create(const spmv_server_opts_t *opts, spmv_server_t **out);
+/* Upload a matrix (square, host CSR, borrowed) as a resident single-rank
+ * plan; *id receives its index.  SPMV_EBUDGET if it does not fit the budget
+ * (leaving room for one request on it).  Only before spmv_server_start. */
+int spmv_server_add_matrix(spmv_server_t *srv, const spmv_csr_t *csr, int32_t *id);
+/* Start the worker thread (after adding the matrices). */
+int spmv_server_start(spmv_server_t *srv);
+/* Queue y_host = A[matrix] x_host.  x_host / y_host: host buffers of n rows
+ * (pinned memory for asynchronous copies), valid until completion.
+ * Non-blocking.  SPMV_EBUDGET if the request could never fit the budget. */
+int spmv_server_submit(spmv_server_t *srv, int32_t matrix, const double *x_host, double *y_host,
+                       int64_t tag);
+/* Completed requests since the last poll: up to cap (tag, latency seconds =
+ * completion - submission) pairs; *n receives the count.  Non-blocking. */
+int spmv_server_poll(spmv_server_t *srv, int64_t *tags, double *latency_s, int32_t cap,
+                     int32_t *n);
+/* Block until every submitted request has completed. */
+int spmv_server_drain(spmv_server_t *srv);
+/* Replay an arrival trace: request i is submitted at arrival_s[i] seconds
+ * after the call starts (ascending), for matrix[i] with x_host[i] /
+ * y_host[i]; returns when all completed, latency_s[i] = completion -
+ * arrival.  *wall_s receives the time from the first arrival to the last
+ * completion. */
+int spmv_server_run_trace(spmv_server_t *srv, int64_t n, const int32_t *matrix,
+                          const double *arrival_s, const double *const *x_host,
+                          double *const *y_host, double *latency_s, double *wall_s);
+int spmv_server_stats(spmv_server_t *srv, spmv_server_stats_t *stats);
+int spmv_server_destroy(spmv_server_t *srv);   /* drains, stops, frees; NULL-safe */
+
 /* ------------------------------------------------------------ measurement */
 
 /*

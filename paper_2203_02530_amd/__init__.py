@@ -88,6 +88,42 @@ class spmv_tune_t(ctypes.Structure):
         "flags")]
 
 
+class spmv_batch_opts_t(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("xcd_affinity", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+class spmv_batch_info_t(ctypes.Structure):
+    _fields_ = [("n_shares", ctypes.c_int32), ("n_blocks", ctypes.c_int32),
+                ("n_items", ctypes.c_int64 * 3), ("device_bytes", ctypes.c_int64),
+                ("host_link_bytes", ctypes.c_int64), ("chunk", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("xcd_affinity", ctypes.c_int32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["n_items"] = list(self.n_items)
+        return d
+
+
+class spmv_server_opts_t(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("max_epochs", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+
+class spmv_server_stats_t(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("resident_bytes", ctypes.c_int64),
+                ("peak_inflight_bytes", ctypes.c_int64), ("arena_bytes", ctypes.c_int64),
+                ("peak_inflight", ctypes.c_int32), ("n_matrices", ctypes.c_int32),
+                ("mean_batch", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class spmv_info_t(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "n_global", "lo", "n_loc", "nnz_local", "nnz_remote", "n_halo", "n_send",
@@ -130,6 +166,19 @@ _proto("spmv_plan_space_count", [_I32, _I32, _P])
 _proto("spmv_plan_space_get", [_I32, _I32, _I64, _P, _P, _P])
 _proto("spmv_op_name", [_I32, ctypes.c_char_p, _I32])
 _proto("spmv_hbm_probe", [_I32, _P, _P, _I64, _I32, _P])
+_proto("spmv_batch_create", [_P, _I32, _P, _P])
+_proto("spmv_batch_exec", [_P, _P, _P, _P])
+_proto("spmv_batch_info", [_P, _P])
+_proto("spmv_batch_destroy", [_P])
+_proto("spmv_server_create", [_P, _P])
+_proto("spmv_server_add_matrix", [_P, _P, _P])
+_proto("spmv_server_start", [_P])
+_proto("spmv_server_submit", [_P, _I32, _P, _P, _I64])
+_proto("spmv_server_poll", [_P, _P, _P, _I32, _P])
+_proto("spmv_server_drain", [_P])
+_proto("spmv_server_run_trace", [_P, _I64, _P, _P, _P, _P, _P, _P])
+_proto("spmv_server_stats", [_P, _P])
+_proto("spmv_server_destroy", [_P])
 _proto("spmv_last_error", [], ctypes.c_char_p)
 _proto("spmv_version", [], ctypes.c_char_p)
 
@@ -342,6 +391,98 @@ def spmv_hbm_probe(mode: int, src, dst, nbytes: int, blocks: int = 0, stream=Non
     """Launch the read (mode 0) or copy (mode 1) bandwidth probe."""
     _check(_lib.spmv_hbm_probe(mode, _addr(src), _addr(dst), nbytes, blocks,
                                _stream_handle(stream)))
+
+
+def spmv_batch_create(plans, opts: dict | None = None):
+    """Batch over a list of plan handles; returns the batch handle."""
+    arr = (ctypes.c_void_p * len(plans))(*plans)
+    o = spmv_batch_opts_t()
+    for k, v in (opts or {}).items():
+        setattr(o, k, v)
+    out = ctypes.c_void_p()
+    _check(_lib.spmv_batch_create(arr, len(plans), ctypes.byref(o), ctypes.byref(out)))
+    return out.value
+
+
+def spmv_batch_exec(batch, xs, ys, stream=None) -> None:
+    """xs, ys: sequences of device arrays (one per share)."""
+    n = len(xs)
+    xa = (ctypes.c_void_p * n)(*[_addr(v) or None for v in xs])
+    ya = (ctypes.c_void_p * n)(*[_addr(v) or None for v in ys])
+    _check(_lib.spmv_batch_exec(batch, xa, ya, _stream_handle(stream)))
+
+
+def spmv_batch_info(batch) -> dict:
+    info = spmv_batch_info_t()
+    _check(_lib.spmv_batch_info(batch, ctypes.byref(info)))
+    return info.as_dict()
+
+
+def spmv_batch_destroy(batch) -> None:
+    _check(_lib.spmv_batch_destroy(batch))
+
+
+def spmv_server_create(opts: dict | None = None):
+    o = spmv_server_opts_t()
+    for k, v in (opts or {}).items():
+        setattr(o, k, v)
+    out = ctypes.c_void_p()
+    _check(_lib.spmv_server_create(ctypes.byref(o), ctypes.byref(out)))
+    return out.value
+
+
+def spmv_server_add_matrix(srv, A) -> int:
+    c, keep = make_csr(A)
+    mid = ctypes.c_int32()
+    _check(_lib.spmv_server_add_matrix(srv, ctypes.byref(c), ctypes.byref(mid)))
+    del keep
+    return mid.value
+
+
+def spmv_server_start(srv) -> None:
+    _check(_lib.spmv_server_start(srv))
+
+
+def spmv_server_submit(srv, matrix: int, x_host, y_host, tag: int) -> None:
+    """x_host / y_host: pinned host arrays (torch pinned tensors or addresses)."""
+    _check(_lib.spmv_server_submit(srv, matrix, _addr(x_host), _addr(y_host), tag))
+
+
+def spmv_server_poll(srv, cap: int = 4096):
+    tags = np.empty(cap, np.int64)
+    lat = np.empty(cap, np.float64)
+    n = ctypes.c_int32()
+    _check(_lib.spmv_server_poll(srv, tags.ctypes.data, lat.ctypes.data, cap, ctypes.byref(n)))
+    return tags[:n.value].copy(), lat[:n.value].copy()
+
+
+def spmv_server_drain(srv) -> None:
+    _check(_lib.spmv_server_drain(srv))
+
+
+def spmv_server_run_trace(srv, matrix, arrival_s, xs, ys):
+    """Replay an arrival trace natively; returns (latency seconds per request,
+    wall seconds from first arrival to last completion)."""
+    n = len(matrix)
+    m = np.ascontiguousarray(matrix, np.int32)
+    a = np.ascontiguousarray(arrival_s, np.float64)
+    xa = (ctypes.c_void_p * n)(*[_addr(v) for v in xs])
+    ya = (ctypes.c_void_p * n)(*[_addr(v) for v in ys])
+    lat = np.empty(n, np.float64)
+    wall = ctypes.c_double()
+    _check(_lib.spmv_server_run_trace(srv, n, m.ctypes.data, a.ctypes.data, xa, ya,
+                                      lat.ctypes.data, ctypes.byref(wall)))
+    return lat, wall.value
+
+
+def spmv_server_stats(srv) -> dict:
+    st = spmv_server_stats_t()
+    _check(_lib.spmv_server_stats(srv, ctypes.byref(st)))
+    return st.as_dict()
+
+
+def spmv_server_destroy(srv) -> None:
+    _check(_lib.spmv_server_destroy(srv))
 
 
 def spmv_last_error() -> str:

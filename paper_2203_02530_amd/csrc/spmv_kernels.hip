@@ -18,13 +18,12 @@
 //     fixed butterfly order, so results depend only on the lane values;
 //   - block tiles can be laid out so that each XCD (with its private L2) walks
 //     a contiguous range of rows and reuses the x entries neighbours touch.
-#include "spmv_device.h"
 #include "spmv_internal.h"
+#include "spmv_stream.h"
 
 namespace spmv {
 namespace {
 
-constexpr int kBlock = 256;   // 4 wave64 per block
 // out = A x over n_rows rows (acc == nullptr), or acc[rows[j]] += (A x)_j.
 // LPR lanes per row; each lane group handles ROWS rows of the block's tile of
 // (kBlock/LPR)*ROWS consecutive rows.  Row r of the tile belongs to sub-tile
@@ -105,14 +104,6 @@ __global__ __launch_bounds__(kBlock) void k_csr_vector(
 // fewer VGPRs, so ROWS = 8 still runs 8 waves per SIMD) and turns a finished
 // slot into an out-of-range load that returns 0 without touching memory.
 // Valid while every array is below 4 GiB (checked by the launcher).
-constexpr int kRsrcWord3 = 0x00020000;   // raw buffer, gfx9-family data format
-constexpr uint32_t kOff = 0xFFFFFFF0u;   // out of range: returns 0
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, uint32_t bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, int(bytes), kRsrcWord3);
-}
-
 template <int LPR, int ROWS>
 __global__ __launch_bounds__(kBlock) void k_csr_vector_buf(
     int n_rows, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
@@ -185,153 +176,13 @@ __global__ __launch_bounds__(kBlock) void k_csr_vector_buf(
     }
 }
 
-constexpr uint32_t kNoEntry = 0xFFFFFFFFu;
-
-// VW consecutive entries (columns and values) starting at entry e; e ==
-// kNoEntry loads nothing (returns zeros).  Device arrays are padded, so a
-// vector never straddles the end of its buffer.
-template <int VW>
-__device__ __forceinline__ void load_vec(__amdgpu_buffer_rsrc_t rc, __amdgpu_buffer_rsrc_t rv,
-                                         uint32_t e, int32_t *c, double *a)
-{
-    const uint32_t oc = e == kNoEntry ? kOff : e * 4u;
-    const uint32_t ov = e == kNoEntry ? kOff : e * 8u;
-    if constexpr (VW == 1) {
-        c[0] = __builtin_amdgcn_raw_buffer_load_b32(rc, oc, 0, 2);
-        a[0] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rv, ov, 0, 2));
-    } else if constexpr (VW == 2) {
-        const auto cc = __builtin_amdgcn_raw_buffer_load_b64(rc, oc, 0, 2);
-        const auto vv = __builtin_amdgcn_raw_buffer_load_b128(rv, ov, 0, 2);
-        c[0] = int32_t(cc[0]);
-        c[1] = int32_t(cc[1]);
-        a[0] = __builtin_bit_cast(double, (uint64_t(vv[1]) << 32) | vv[0]);
-        a[1] = __builtin_bit_cast(double, (uint64_t(vv[3]) << 32) | vv[2]);
-    } else {
-        static_assert(VW == 4, "VW must be 1, 2 or 4");
-        const auto cc = __builtin_amdgcn_raw_buffer_load_b128(rc, oc, 0, 2);
-        const auto v0 = __builtin_amdgcn_raw_buffer_load_b128(rv, ov, 0, 2);
-        const auto v1 = __builtin_amdgcn_raw_buffer_load_b128(rv, ov == kOff ? kOff : ov + 16u, 0, 2);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) c[j] = int32_t(cc[j]);
-        a[0] = __builtin_bit_cast(double, (uint64_t(v0[1]) << 32) | v0[0]);
-        a[1] = __builtin_bit_cast(double, (uint64_t(v0[3]) << 32) | v0[2]);
-        a[2] = __builtin_bit_cast(double, (uint64_t(v1[1]) << 32) | v1[0]);
-        a[3] = __builtin_bit_cast(double, (uint64_t(v1[3]) << 32) | v1[2]);
-    }
-}
-
-__device__ __forceinline__ double load_x(__amdgpu_buffer_rsrc_t rx, uint32_t off)
-{
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rx, off, 0, 0));
-}
-
-template <int VW>
-__device__ __forceinline__ void store_lds(double *dst, const double *p)
-{
-#pragma unroll
-    for (int j = 0; j < VW; ++j) dst[j] = p[j];
-}
-
-// ---------------------------------------------------------------- CSR-stream
-// Tiles are cut on the host at row boundaries: a tile holds at most MAXR rows
-// whose entries fit one window of CAP = kBlock * NPT entries starting at the
-// tile's first entry rounded down to VW (or it is a single long row).  The
-// block streams the window with fully coalesced VW-wide loads of col/val (no
-// idle lanes, no per-row pointer chase before the loads), gathers x, stores
-// the products in LDS, and SL lanes per row sum them in a fixed order.  A
-// single row longer than the window is summed by the whole block, chunk by
-// chunk, with a fixed-order block reduction.
+// Single-share stream-CSR product: one block per tile (see spmv_stream.h).
 template <int NPT, int VW, int SL>
-__global__ __launch_bounds__(kBlock) void k_csr_stream(
-    const int32_t *__restrict__ tile_row, const int32_t *__restrict__ tile_k,
-    const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-    const double *__restrict__ val, const double *__restrict__ x, double *__restrict__ out,
-    const int32_t *__restrict__ rows, double *__restrict__ acc, int remap, uint32_t nnz,
-    uint32_t n_x)
+__global__ __launch_bounds__(kBlock) void k_csr_stream(StreamArgs A, int remap)
 {
-    constexpr int CAP = kBlock * NPT;
-    constexpr int MAXR = kBlock / SL;
-    constexpr int NV = NPT / VW;
-    static_assert(NPT % VW == 0, "NPT must be a multiple of VW");
-    __shared__ double s_p[CAP];
-    __shared__ int32_t s_rp[MAXR + 1];
-    const auto r_col = rsrc(col, nnz * 4u);
-    const auto r_val = rsrc(val, nnz * 8u);
-    const auto r_x = rsrc(x, n_x * 8u);
-    const int t = tile_of_block(int(blockIdx.x), int(gridDim.x), remap);
-    const int r0 = tile_row[t], r1 = tile_row[t + 1];
-    const int k0 = tile_k[t], k1 = tile_k[t + 1];
-    const int base = k0 & ~(VW - 1);
-    const int tid = int(threadIdx.x);
-
-    if (r1 - r0 == 1 && k1 - base > CAP) {
-        // one long row: per-thread fma chains over all chunks, then a
-        // fixed-order reduction over the block
-        double s = 0.0;
-        for (int w0 = base; w0 < k1; w0 += CAP) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const int e = w0 + (v * kBlock + tid) * VW;
-                int32_t c[VW];
-                double a[VW];
-                load_vec<VW>(r_col, r_val, e < k1 ? uint32_t(e) : kNoEntry, c, a);
-#pragma unroll
-                for (int j = 0; j < VW; ++j) {
-                    const bool ok = e + j >= k0 && e + j < k1;
-                    const double xv = load_x(r_x, ok ? uint32_t(c[j]) * 8u : kOff);
-                    const double f = fma(a[j], xv, s);
-                    s = ok ? f : s;
-                }
-            }
-        }
-        s = group_sum<64>(s);
-        if ((tid & 63) == 63) s_p[tid >> 6] = s;
-        __syncthreads();
-        if (tid == 0) {
-            const double tot = (s_p[0] + s_p[1]) + (s_p[2] + s_p[3]);
-            if (acc)
-                acc[rows[r0]] += tot;
-            else
-                out[r0] = tot;
-        }
-        return;
-    }
-
-    for (int i = tid; i <= r1 - r0; i += kBlock) s_rp[i] = rp[r0 + i];
-    int32_t c[NV][VW];
-    double a[NV][VW];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const int e = base + (v * kBlock + tid) * VW;
-        load_vec<VW>(r_col, r_val, e < k1 ? uint32_t(e) : kNoEntry, c[v], a[v]);
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        double p[VW];
-#pragma unroll
-        for (int j = 0; j < VW; ++j) {
-            const int k = base + (v * kBlock + tid) * VW + j;
-            const bool ok = k >= k0 && k < k1;
-            p[j] = a[v][j] * load_x(r_x, ok ? uint32_t(c[v][j]) * 8u : kOff);
-        }
-        store_lds<VW>(s_p + (v * kBlock + tid) * VW, p);
-    }
-    __syncthreads();
-
-    const int g = tid / SL, lane = tid % SL;
-    const int nr = r1 - r0;
-    double s = 0.0;
-    if (g < nr) {
-        const int b = s_rp[g] - base, e = s_rp[g + 1] - base;
-        for (int k = b + lane; k < e; k += SL) s += s_p[k];
-    }
-    s = group_sum<SL>(s);
-    if (lane == SL - 1 && g < nr) {
-        if (acc)
-            acc[rows[r0 + g]] += s;
-        else
-            out[r0 + g] = s;
-    }
+    __shared__ double s_p[kBlock * NPT];
+    __shared__ int32_t s_rp[kBlock / SL + 1];
+    stream_tile<NPT, VW, SL>(A, tile_of_block(int(blockIdx.x), int(gridDim.x), remap), s_p, s_rp);
 }
 
 __global__ __launch_bounds__(kBlock) void k_gather(const double *__restrict__ src,
@@ -392,9 +243,20 @@ template <int NPT, int VW, int SL>
 hipError_t launch_stream_t(const CsrDev &A, const double *x, double *out, double *acc, int remap,
                            hipStream_t s)
 {
+    StreamArgs a;
+    a.tile_row = A.tile_row;
+    a.tile_k = A.tile_k;
+    a.rp = A.rp;
+    a.col = A.col;
+    a.rows = A.rows;
+    a.val = A.val;
+    a.x = x;
+    a.out = out;
+    a.acc = acc;
+    a.nnz_alloc = uint32_t(A.nnz_alloc);
+    a.n_x = uint32_t(A.n_x);
     hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL>), dim3(unsigned(A.n_tiles)), dim3(kBlock), 0, s,
-                       A.tile_row, A.tile_k, A.rp, A.col, A.val, x, out, A.rows, acc, remap,
-                       uint32_t(A.nnz_alloc), uint32_t(A.n_x));
+                       a, remap);
     return hipGetLastError();
 }
 

@@ -17,51 +17,6 @@
 
 #include "spmv_internal.h"
 
-// Kernel configuration of one product (y_L or y_R).
-struct CsrCfg {
-    int32_t kernel = SPMV_KERNEL_VECTOR;
-    int32_t lanes = 1, rows = 1;   // vector CSR
-    int32_t chunk = 8, width = 2;  // stream CSR (lanes = summing lanes)
-    std::vector<int32_t> tile_row, tile_k;
-};
-
-struct spmv_plan {
-    spmv::Share share;
-    spmv::Schedule sch;
-    CsrCfg cfg[2];                 // [0] = y_L, [1] = y_R
-    int32_t xcd_remap = 1;
-    bool fuse_unpack = false, fused_combine = false, host_only = false, profile = false;
-    bool use_buffer = true;
-    int device = 0;
-
-    // device arena and its views
-    void *arena = nullptr;
-    size_t arena_bytes = 0;
-    int32_t *dL_ptr = nullptr, *dL_col = nullptr;
-    double *dL_val = nullptr;
-    int32_t *dR_rows = nullptr, *dR_ptr = nullptr, *dR_col = nullptr;
-    double *dR_val = nullptr;
-    int32_t *d_send_idx = nullptr, *d_perm = nullptr;
-    double *d_sendbuf = nullptr, *d_recvbuf = nullptr, *d_xhalo = nullptr, *d_part = nullptr;
-    int32_t *d_tile_row[2] = {}, *d_tile_k[2] = {};
-
-    // pinned host mailboxes
-    double *h_inbox = nullptr, *h_outbox = nullptr;
-
-    // streams and events
-    hipStream_t st[SPMV_MAX_STREAMS] = {};
-    int32_t n_st = 0;           // plan streams owned
-    int32_t n_streams_max = 1;  // as requested at creation
-    hipStream_t cs_send = nullptr, cs_recv = nullptr;
-    hipEvent_t ev_start = nullptr, ev_send = nullptr, ev_recv = nullptr;
-    hipEvent_t ev_rec[SPMV_N_VERTICES] = {};
-    hipEvent_t ev_join[SPMV_MAX_STREAMS] = {};
-    // profiling: begin/end per vertex, index SPMV_N_VERTICES = combine
-    hipEvent_t ev_b[SPMV_N_VERTICES + 1] = {}, ev_e[SPMV_N_VERTICES + 1] = {};
-    double ms[SPMV_N_VERTICES + 1] = {};
-    double cnt[SPMV_N_VERTICES + 1] = {};
-};
-
 namespace spmv {
 
 // Streams are shared by every plan on a device: plan stream i of any plan is

@@ -1,0 +1,166 @@
+// Device code shared by the single-share and the grouped (batched) kernels:
+// buffer-resource loads and the stream-CSR tile body.
+//
+// Stream CSR: rows are cut on the host into tiles at row boundaries; a tile
+// holds at most MAXR = kBlock / SL rows whose entries fit one window of
+// CAP = kBlock * NPT entries starting at the tile's first entry rounded down
+// to VW (or it is a single row longer than the window).  The block streams
+// the window with coalesced VW-wide loads of col/val (no idle lanes, no
+// per-row pointer chase before the loads), gathers x, stages the products in
+// LDS, and SL lanes per row sum them in a fixed order.  A single row longer
+// than the window is summed by the whole block, chunk by chunk, with a
+// fixed-order block reduction.  The result of a tile depends only on the
+// tile, so a share computes the same bits alone or in any batch.
+#pragma once
+
+#include "spmv_device.h"
+
+namespace spmv {
+
+constexpr int kBlock = 256;                // 4 wave64 per block
+constexpr int kRsrcWord3 = 0x00020000;     // raw buffer, gfx9-family data format
+constexpr uint32_t kOff = 0xFFFFFFF0u;     // out-of-range offset: the load returns 0
+constexpr uint32_t kNoEntry = 0xFFFFFFFFu; // "no vector" marker for load_vec
+
+// Buffer resource over [p, p + bytes): 32-bit offsets against a scalar
+// descriptor keep 64-bit addresses out of vector registers, and a load past
+// `bytes` returns 0 without touching memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, int(bytes), kRsrcWord3);
+}
+
+// VW consecutive entries (columns and values) starting at entry e; e ==
+// kNoEntry loads nothing (zeros).  Device col/val arrays are padded, so a
+// vector never straddles the end of its buffer.
+template <int VW>
+__device__ __forceinline__ void load_vec(__amdgpu_buffer_rsrc_t rc, __amdgpu_buffer_rsrc_t rv,
+                                         uint32_t e, int32_t *c, double *a)
+{
+    const uint32_t oc = e == kNoEntry ? kOff : e * 4u;
+    const uint32_t ov = e == kNoEntry ? kOff : e * 8u;
+    if constexpr (VW == 1) {
+        c[0] = __builtin_amdgcn_raw_buffer_load_b32(rc, oc, 0, 2);
+        a[0] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rv, ov, 0, 2));
+    } else if constexpr (VW == 2) {
+        const auto cc = __builtin_amdgcn_raw_buffer_load_b64(rc, oc, 0, 2);
+        const auto vv = __builtin_amdgcn_raw_buffer_load_b128(rv, ov, 0, 2);
+        c[0] = int32_t(cc[0]);
+        c[1] = int32_t(cc[1]);
+        a[0] = __builtin_bit_cast(double, (uint64_t(vv[1]) << 32) | vv[0]);
+        a[1] = __builtin_bit_cast(double, (uint64_t(vv[3]) << 32) | vv[2]);
+    } else {
+        static_assert(VW == 4, "VW must be 1, 2 or 4");
+        const auto cc = __builtin_amdgcn_raw_buffer_load_b128(rc, oc, 0, 2);
+        const auto v0 = __builtin_amdgcn_raw_buffer_load_b128(rv, ov, 0, 2);
+        const auto v1 = __builtin_amdgcn_raw_buffer_load_b128(rv, ov == kOff ? kOff : ov + 16u, 0, 2);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[j] = int32_t(cc[j]);
+        a[0] = __builtin_bit_cast(double, (uint64_t(v0[1]) << 32) | v0[0]);
+        a[1] = __builtin_bit_cast(double, (uint64_t(v0[3]) << 32) | v0[2]);
+        a[2] = __builtin_bit_cast(double, (uint64_t(v1[1]) << 32) | v1[0]);
+        a[3] = __builtin_bit_cast(double, (uint64_t(v1[3]) << 32) | v1[2]);
+    }
+}
+
+__device__ __forceinline__ double load_x(__amdgpu_buffer_rsrc_t rx, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rx, off, 0, 0));
+}
+
+// Operands of one stream-CSR product.  out[r] = row sum (acc == nullptr) or
+// acc[rows[r]] += row sum.  nnz_alloc = entries incl. padding, n_x = |x|.
+struct StreamArgs {
+    const int32_t *tile_row, *tile_k, *rp, *col, *rows;
+    const double *val, *x;
+    double *out, *acc;
+    uint32_t nnz_alloc, n_x;
+};
+
+// One tile.  s_p: LDS[kBlock * NPT] doubles, s_rp: LDS[kBlock / SL + 1] ints.
+// Block-uniform control flow; the caller separates consecutive tiles with a
+// barrier (LDS is reused).
+template <int NPT, int VW, int SL>
+__device__ __forceinline__ void stream_tile(const StreamArgs &A, int t, double *s_p, int32_t *s_rp)
+{
+    constexpr int CAP = kBlock * NPT;
+    constexpr int NV = NPT / VW;
+    static_assert(NPT % VW == 0, "NPT must be a multiple of VW");
+    const auto r_col = rsrc(A.col, A.nnz_alloc * 4u);
+    const auto r_val = rsrc(A.val, A.nnz_alloc * 8u);
+    const auto r_x = rsrc(A.x, A.n_x * 8u);
+    const int r0 = A.tile_row[t], r1 = A.tile_row[t + 1];
+    const int k0 = A.tile_k[t], k1 = A.tile_k[t + 1];
+    const int base = k0 & ~(VW - 1);
+    const int tid = int(threadIdx.x);
+
+    if (r1 - r0 == 1 && k1 - base > CAP) {
+        // one long row: per-thread fma chains over all windows, then a
+        // fixed-order reduction over the block
+        double s = 0.0;
+        for (int w0 = base; w0 < k1; w0 += CAP) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const int e = w0 + (v * kBlock + tid) * VW;
+                int32_t c[VW];
+                double a[VW];
+                load_vec<VW>(r_col, r_val, e < k1 ? uint32_t(e) : kNoEntry, c, a);
+#pragma unroll
+                for (int j = 0; j < VW; ++j) {
+                    const bool ok = e + j >= k0 && e + j < k1;
+                    const double xv = load_x(r_x, ok ? uint32_t(c[j]) * 8u : kOff);
+                    const double f = fma(a[j], xv, s);
+                    s = ok ? f : s;
+                }
+            }
+        }
+        s = group_sum<64>(s);
+        if ((tid & 63) == 63) s_p[tid >> 6] = s;
+        __syncthreads();
+        if (tid == 0) {
+            const double tot = (s_p[0] + s_p[1]) + (s_p[2] + s_p[3]);
+            if (A.acc)
+                A.acc[A.rows[r0]] += tot;
+            else
+                A.out[r0] = tot;
+        }
+        return;
+    }
+
+    for (int i = tid; i <= r1 - r0; i += kBlock) s_rp[i] = A.rp[r0 + i];
+    int32_t c[NV][VW];
+    double a[NV][VW];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int e = base + (v * kBlock + tid) * VW;
+        load_vec<VW>(r_col, r_val, e < k1 ? uint32_t(e) : kNoEntry, c[v], a[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int j = 0; j < VW; ++j) {
+            const int k = base + (v * kBlock + tid) * VW + j;
+            const bool ok = k >= k0 && k < k1;
+            s_p[(v * kBlock + tid) * VW + j] =
+                a[v][j] * load_x(r_x, ok ? uint32_t(c[v][j]) * 8u : kOff);
+        }
+    }
+    __syncthreads();
+
+    const int g = tid / SL, lane = tid % SL;
+    const int nr = r1 - r0;
+    double s = 0.0;
+    if (g < nr) {
+        const int b = s_rp[g] - base, e = s_rp[g + 1] - base;
+        for (int k = b + lane; k < e; k += SL) s += s_p[k];
+    }
+    s = group_sum<SL>(s);
+    if (lane == SL - 1 && g < nr) {
+        if (A.acc)
+            A.acc[A.rows[r0 + g]] += s;
+        else
+            A.out[r0 + g] = s;
+    }
+}
+
+}  // namespace spmv

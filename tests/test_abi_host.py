@@ -348,3 +348,24 @@ def test_stream_tiles_invariants(chunk, width, lanes):
             assert info["kernel_local"] == 2
         finally:
             sp.spmv_plan_destroy(p)
+
+
+def test_batch_rejects_bad_plans_on_host():
+    A = gen.laplacian_3d7(8)
+    p = sp.spmv_plan_create(A, 2, 0, tune=HOST_ONLY)
+    try:
+        with pytest.raises(sp.SpmvError) as e:
+            sp.spmv_batch_create([p])
+        assert e.value.code == sp.SPMV_EINVAL
+        with pytest.raises(sp.SpmvError) as e:
+            sp.spmv_batch_create([])
+        assert e.value.code == sp.SPMV_EINVAL
+    finally:
+        sp.spmv_plan_destroy(p)
+
+
+def test_server_rejects_bad_options_on_host():
+    for opts in ({"mode": 3}, {"chunk": 5}, {"budget_bytes": -1}):
+        with pytest.raises(sp.SpmvError) as e:
+            sp.spmv_server_create(opts)
+        assert e.value.code == sp.SPMV_EINVAL

@@ -1,0 +1,134 @@
+"""Batched execution: many rank shares in grouped persistent kernels inside
+one hipGraph.  Each share's y must be bit-identical to its own spmv_exec
+(same tiles, same device code), and within tolerance of the oracle; halo
+buffers bit-exact; every graph replay equal to the eager result."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+import paper_2203_02530_amd as sp
+from gpu_util import bits, log, run_share
+
+pytestmark = pytest.mark.gpu
+TUNE = {"kernel_local": 2, "kernel_remote": 2, "chunk_local": 8, "chunk_remote": 8, "width": 2}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    assert torch.cuda.is_available()
+    oracle.build(force=False)
+    yield
+
+
+def _shares():
+    out = []
+    for s in range(3):
+        A = gen.power_law(20000, seed=4000 + s)
+        out.append((A, 16, 5, gen.x_normal(A.n_cols, 4100 + s)))
+    A = gen.banded_uniform(6000, 10, 1500, seed=11)
+    out.append((A, 4, 1, gen.x_normal(A.n_cols, 12)))
+    A = gen.laplacian_3d7(16)
+    out.append((A, 4, 1, gen.x_uniform(A.n_cols, 2)))
+    A = gen.laplacian_2d5(64)
+    out.append((A, 1, 0, gen.x_uniform(A.n_cols, 1)))
+    A = gen.laplacian_2d5(2, 2)
+    out.append((A, 6, 5, gen.x_normal(4, 3)))          # empty share
+    A = gen.stencil_3d27(12, seed=3)
+    out.append((A, 8, 3, gen.x_normal(A.n_cols, 30)))
+    A = gen.power_law(12000, mean_len=300.0, seed=44)  # rows longer than the window
+    out.append((A, 4, 1, gen.x_normal(A.n_cols, 45)))
+    return out
+
+
+def _setup(shares, tune=TUNE):
+    import torch
+    plans, xs, ys, refs, solo = [], [], [], [], []
+    for A, P, r, x in shares:
+        ref = oracle.share_reference(A, P, r, x)
+        res, _ = run_share(A, P, r, x, tune=tune, ref=ref, keep_plan=True)
+        p = res.pop("plan")
+        info = res["info"]
+        lo, n = info["lo"], info["n_loc"]
+        plans.append(p)
+        xs.append(torch.from_numpy(x[lo:lo + n].copy()).cuda() if n else None)
+        ys.append(torch.full((n,), float("nan"), dtype=torch.float64, device="cuda") if n else None)
+        refs.append(ref)
+        solo.append(res)
+    return plans, xs, ys, refs, solo
+
+
+def _check(plans, ys, refs, solo):
+    for i, (p, y, ref, res) in enumerate(zip(plans, ys, refs, solo)):
+        if y is None:
+            continue
+        yb = y.cpu().numpy()
+        assert np.array_equal(bits(yb), bits(res["y"])), i
+        assert oracle.within_tolerance(yb, ref["y"], ref["absax"]).all(), i
+        assert np.array_equal(bits(sp.spmv_plan_outbox(p)), bits(ref["sendbuf"])), i
+        assert np.array_equal(bits(sp.spmv_plan_get_f64(p, sp.SPMV_F64_X_HALO)),
+                              bits(ref["inbox"])), i
+
+
+@pytest.mark.parametrize("opts", [{"use_graph": 1}, {"use_graph": 2},
+                                  {"use_graph": 1, "xcd_affinity": 1, "blocks_per_cu": 2},
+                                  {"use_graph": 2, "xcd_affinity": 2, "blocks_per_cu": 1}])
+def test_batch_bit_identical_to_solo(opts):
+    import torch
+    log(f"batch opts {opts}")
+    shares = _shares()
+    plans, xs, ys, refs, solo = _setup(shares)
+    try:
+        b = sp.spmv_batch_create(plans, opts)
+        try:
+            info = sp.spmv_batch_info(b)
+            assert info["n_shares"] == len(plans) and sum(info["n_items"]) > 0
+            for rep in range(3):
+                for y in ys:
+                    if y is not None:
+                        y.fill_(float("nan"))          # eager work between replays
+                torch.cuda.synchronize()
+                sp.spmv_batch_exec(b, xs, ys, torch.cuda.current_stream())
+                _check(plans, ys, refs, solo)
+        finally:
+            sp.spmv_batch_destroy(b)
+    finally:
+        for p in plans:
+            sp.spmv_plan_destroy(p)
+
+
+def test_batch_same_alone_and_in_mix():
+    """A share's bits do not depend on which other shares are batched with it."""
+    import torch
+    shares = _shares()
+    plans, xs, ys, refs, solo = _setup(shares)
+    try:
+        out = {}
+        for subset in ([0], [0, 1, 2], list(range(len(plans)))):
+            b = sp.spmv_batch_create([plans[i] for i in subset])
+            try:
+                sp.spmv_batch_exec(b, [xs[i] for i in subset], [ys[i] for i in subset],
+                                   torch.cuda.current_stream())
+                out[len(subset)] = bits(ys[0].cpu().numpy())
+            finally:
+                sp.spmv_batch_destroy(b)
+        assert np.array_equal(out[1], out[3]) and np.array_equal(out[1], out[len(plans)])
+    finally:
+        for p in plans:
+            sp.spmv_plan_destroy(p)
+
+
+def test_batch_rejects_mixed_configs():
+    A = gen.laplacian_3d7(12)
+    p1 = sp.spmv_plan_create(A, 2, 0, tune=TUNE)
+    p2 = sp.spmv_plan_create(A, 2, 1, tune={**TUNE, "chunk_local": 4})
+    p3 = sp.spmv_plan_create(A, 2, 1, tune={"kernel_local": 1})
+    try:
+        for bad in ([p1, p2], [p1, p3]):
+            with pytest.raises(sp.SpmvError) as e:
+                sp.spmv_batch_create(bad)
+            assert e.value.code == sp.SPMV_EINVAL
+    finally:
+        for p in (p1, p2, p3):
+            sp.spmv_plan_destroy(p)
