@@ -32,6 +32,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
 MALL_BYTES = 256 << 20         # Infinity Cache
 
+# HBM bytes per launch of the dominant kernel from the two rocprofv3 --pmc
+# runs (FETCH_SIZE x 1.9994 + WRITE_SIZE x 1.0, factors from the copy probe of
+# known size), keyed by workload and kernel variant; a variant that is not
+# listed (or a kernel changed since) reports null.
+MEASURED_TRAFFIC = {
+    ("laplace3d_128_p4r1", "k_csr_stream<4,2,1>"): 56_460_000,
+}
+
 
 def step_bytes(info: dict) -> dict:
     """Algorithmic device bytes of each GPU step of one exec (unique data
@@ -54,6 +62,12 @@ def step_bytes(info: dict) -> dict:
     b["total"] = sum(v for k, v in b.items())
     b["host_link"] = 8 * (s + h)                         # staged each way
     return b
+
+
+def kernel_variant(info: dict) -> str:
+    if info["kernel_local"] == 2:
+        return "k_csr_stream<%d,%d,%d>" % (info["chunk_local"], info["width"], info["lanes_local"])
+    return "k_csr_vector_buf<%d,%d>" % (info["lanes_local"], info["rows_local"])
 
 
 def time_op(sp, torch, plans, op, xs, ys, launches: int) -> float:
@@ -256,11 +270,10 @@ def main() -> int:
                    "rows_remote": info["rows_remote"], "xcd_remap": info["xcd_remap"],
                    "fuse_unpack": info["fuse_unpack"], "replicas": R,
                    "step_device_bytes": B["total"], "step_host_link_bytes": B["host_link"]},
-        "roofline": {"bound": "hbm",
-                     "kernel": "y_L local CSR (%s)" % ("k_csr_stream" if info["kernel_local"] == 2
-                                                       else "k_csr_vector"),
+        "roofline": {"bound": "hbm", "kernel": "y_L " + kernel_variant(info),
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": MEASURED_TRAFFIC.get((args.workload, kernel_variant(info))),
                      "bytes_per_launch": B["yL"], "avg_us": round(kern_us["yL"], 3),
                      "launches": launches},
         "kernel_us": {k: round(float(v), 3) for k, v in kern_us.items()},

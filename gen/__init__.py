@@ -33,7 +33,7 @@ import numpy as np
 
 __all__ = [
     "CSR", "laplacian_2d5", "laplacian_3d7", "stencil_3d27", "banded_uniform",
-    "power_law", "banded_random", "x_uniform", "x_normal", "x_integer",
+    "power_law", "power_law_share", "banded_random", "x_uniform", "x_normal", "x_integer",
     "sine_mode", "WORKLOADS", "workload",
 ]
 
@@ -219,6 +219,46 @@ def power_law(n: int = 4_000_000, mean_len: float = 16.0, sigma: float = 1.2,
         raise ValueError("nnz does not fit int32")
     val = rng.standard_normal(cols.size)
     return CSR(n, n, row_ptr.astype(np.int32), cols.astype(np.int32), val)
+
+
+def power_law_share(n: int = 4_000_000, nranks: int = 16, rank: int = 5,
+                    mean_len: float = 16.0, sigma: float = 1.2, max_len: int = 10_000,
+                    seed: int = 4000) -> dict:
+    """One rank's share of a power-law matrix, generated without the rest of
+    the matrix: the rank's own rows in full (lengths, distinct uniform
+    columns over [0, n), N(0,1) values), and, for every other rank q, the
+    owned columns q's rows reference: q's entries land in this rank's column
+    block with probability n_loc / n, so their count is binomial over q's
+    total entries and the columns are uniform in the block (within-row
+    distinctness of q's rows is not modelled).
+
+    Returns dict(local=CSR with n_loc rows and global columns, lo, n_global,
+    send_idx, send_off) -- the inputs of spmv_plan_create_local."""
+    rng = np.random.default_rng(seed)
+    mu = math.log(mean_len) - 0.5 * sigma * sigma
+    lengths = np.clip(np.rint(rng.lognormal(mu, sigma, n)).astype(np.int64), 1, min(max_len, n))
+    q = np.arange(nranks + 1, dtype=np.int64)
+    blo = q * (n // nranks) + np.minimum(q, n % nranks)
+    lo, hi = int(blo[rank]), int(blo[rank + 1])
+    nl = hi - lo
+    own = lengths[lo:hi]
+    cols = _distinct_sorted_rows(rng, np.zeros(nl, np.int64), np.full(nl, n - 1, np.int64), own, n)
+    row_ptr = np.zeros(nl + 1, np.int64)
+    np.cumsum(own, out=row_ptr[1:])
+    local = CSR(nl, n, row_ptr.astype(np.int32), cols.astype(np.int32),
+                rng.standard_normal(cols.size))
+    send, send_off = [], np.zeros(nranks + 1, np.int64)
+    for qq in range(nranks):
+        if qq == rank or nl == 0:
+            idx = np.zeros(0, np.int64)
+        else:
+            tot = int(lengths[blo[qq]:blo[qq + 1]].sum())
+            m = int(rng.binomial(tot, nl / n))
+            idx = np.unique(rng.integers(0, nl, m))
+        send.append(idx)
+        send_off[qq + 1] = send_off[qq] + idx.size
+    return dict(local=local, lo=lo, n_global=n, nranks=nranks, rank=rank,
+                send_idx=np.concatenate(send).astype(np.int32), send_off=send_off.astype(np.int32))
 
 
 def banded_random(n: int, lo_len: int = 5, hi_len: int = 27, half_bw: int = 2000,

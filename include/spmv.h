@@ -246,6 +246,23 @@ int spmv_plan_create_ex(const spmv_csr_t *csr, int32_t nranks, int32_t rank,
                         const int32_t *stream_map, int32_t n_streams,
                         const spmv_tune_t *tune, spmv_plan_t **out);
 
+/*
+ * Same as spmv_plan_create_ex, from what one rank of a distributed code
+ * holds instead of the global matrix: its own rows and its send lists.
+ *   local      host CSR of the rank's n_loc rows (n_rows = n_loc of the
+ *              contiguous partition of n_global rows over nranks) with
+ *              GLOBAL column indices (n_cols = n_global), ascending per row
+ *   send_idx   host [send_off[nranks]] local indices of owned x entries that
+ *              each other rank needs, ascending per destination,
+ *              destinations ascending (the rank itself gets none)
+ *   send_off   host [nranks + 1]
+ * The halo is derived from the local rows as in the global form.
+ */
+int spmv_plan_create_local(const spmv_csr_t *local, int64_t n_global, int32_t nranks,
+                           int32_t rank, const int32_t *send_idx, const int32_t *send_off,
+                           const int32_t *op_order, int32_t n_ops, const int32_t *stream_map,
+                           int32_t n_streams, const spmv_tune_t *tune, spmv_plan_t **out);
+
 /* Release everything the plan owns.  NULL-safe. */
 int spmv_plan_destroy(spmv_plan_t *plan);
 

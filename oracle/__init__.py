@@ -121,6 +121,40 @@ def row_blocks(n: int, P: int) -> np.ndarray:
     return q * (n // P) + np.minimum(q, n % P)
 
 
+def _split_rows(rp_rows, cols_all, vals_all, n: int, P: int, r: int) -> dict:
+    """A_L / A_R / halo of rank r from its own rows (global column indices):
+    rp_rows[0..n_loc] indexes cols_all / vals_all."""
+    lo_all = row_blocks(n, P)
+    lo, hi = int(lo_all[r]), int(lo_all[r + 1])
+    n_loc = hi - lo
+    grp = np.asarray(rp_rows, np.int64)
+    b, e = grp[0], grp[-1]
+    cols = np.asarray(cols_all[b:e], np.int64)
+    vals = vals_all[b:e]
+    row_of = np.repeat(np.arange(n_loc, dtype=np.int64), np.diff(grp))
+    local = (cols >= lo) & (cols < hi)
+
+    L_cnt = np.bincount(row_of[local], minlength=n_loc)
+    L_ptr = np.zeros(n_loc + 1, np.int64)
+    np.cumsum(L_cnt, out=L_ptr[1:])
+
+    rem_cols = cols[~local]
+    H = np.unique(rem_cols)
+    recv_off = np.searchsorted(H, lo_all)          # owners are contiguous blocks
+    rem_rows = row_of[~local]
+    R_rows = np.unique(rem_rows)
+    R_cnt = np.bincount(rem_rows, minlength=n_loc)[R_rows]
+    R_ptr = np.zeros(R_rows.size + 1, np.int64)
+    np.cumsum(R_cnt, out=R_ptr[1:])
+    i32 = lambda a: np.ascontiguousarray(a, np.int32)
+    return dict(
+        lo=lo, hi=hi, n_loc=n_loc,
+        L_ptr=i32(L_ptr), L_col=i32(cols[local] - lo), L_val=np.ascontiguousarray(vals[local]),
+        H=i32(H), recv_off=i32(recv_off),
+        R_rows=i32(R_rows), R_ptr=i32(R_ptr), R_col=i32(np.searchsorted(H, rem_cols)),
+        R_val=np.ascontiguousarray(vals[~local]))
+
+
 def split(A, P: int, r: int) -> dict:
     """Rank r's share of A under the contiguous row-block partition.
 
@@ -138,27 +172,8 @@ def split(A, P: int, r: int) -> dict:
     n = A.n_rows
     lo_all = row_blocks(n, P)
     lo, hi = int(lo_all[r]), int(lo_all[r + 1])
-    n_loc = hi - lo
     grp = A.row_ptr.astype(np.int64)
-    b, e = grp[lo], grp[hi]
-    cols = A.col_idx[b:e].astype(np.int64)
-    vals = A.val[b:e]
-    row_of = np.repeat(np.arange(n_loc, dtype=np.int64), np.diff(grp[lo:hi + 1]))
-    local = (cols >= lo) & (cols < hi)
-
-    L_cnt = np.bincount(row_of[local], minlength=n_loc)
-    L_ptr = np.zeros(n_loc + 1, np.int64)
-    np.cumsum(L_cnt, out=L_ptr[1:])
-
-    rem_cols = cols[~local]
-    H = np.unique(rem_cols)
-    recv_off = np.searchsorted(H, lo_all)          # owners are contiguous blocks
-    rem_rows = row_of[~local]
-    R_rows = np.unique(rem_rows)
-    R_cnt = np.bincount(rem_rows, minlength=n_loc)[R_rows]
-    R_ptr = np.zeros(R_rows.size + 1, np.int64)
-    np.cumsum(R_cnt, out=R_ptr[1:])
-
+    out = _split_rows(grp[lo:hi + 1], A.col_idx, A.val, n, P, r)
     send = []
     send_off = np.zeros(P + 1, np.int64)
     for q in range(P):
@@ -169,15 +184,27 @@ def split(A, P: int, r: int) -> dict:
             s = np.zeros(0, np.int64)
         send.append(s)
         send_off[q + 1] = send_off[q] + s.size
-    i32 = lambda a: np.ascontiguousarray(a, np.int32)
-    return dict(
-        lo=lo, hi=hi, n_loc=n_loc,
-        L_ptr=i32(L_ptr), L_col=i32(cols[local] - lo), L_val=np.ascontiguousarray(vals[local]),
-        H=i32(H), recv_off=i32(recv_off),
-        R_rows=i32(R_rows), R_ptr=i32(R_ptr), R_col=i32(np.searchsorted(H, rem_cols)),
-        R_val=np.ascontiguousarray(vals[~local]),
-        send_idx=i32(np.concatenate(send) if send else np.zeros(0)), send_off=i32(send_off),
-    )
+    out["send_idx"] = np.ascontiguousarray(np.concatenate(send) if send else np.zeros(0), np.int32)
+    out["send_off"] = np.ascontiguousarray(send_off, np.int32)
+    return out
+
+
+def split_local(local, n: int, P: int, r: int, send_idx, send_off) -> dict:
+    """The same share from the rank's own rows (global columns) and its send
+    lists, as one rank of a distributed code holds it."""
+    out = _split_rows(local.row_ptr, local.col_idx, local.val, n, P, r)
+    out["send_idx"] = np.ascontiguousarray(send_idx, np.int32)
+    out["send_off"] = np.ascontiguousarray(send_off, np.int32)
+    return out
+
+
+def share_reference_local(local, n: int, P: int, r: int, send_idx, send_off, x: np.ndarray,
+                          dynamic: bool = False) -> dict:
+    """share_reference for a rank-local share: y over the own rows with the
+    global x, and the same derived quantities."""
+    s = split_local(local, n, P, r, send_idx, send_off)
+    y, absax = spmv_dot2(local.row_ptr, local.col_idx, local.val, x, dynamic)
+    return _reference_from_parts(s, x, y, absax, dynamic)
 
 
 def share_reference(A, P: int, r: int, x: np.ndarray, parts: dict | None = None,
@@ -195,6 +222,11 @@ def share_reference(A, P: int, r: int, x: np.ndarray, parts: dict | None = None,
     s = split(A, P, r) if parts is None else parts
     lo, hi = s["lo"], s["hi"]
     y, absax = spmv_dot2(A.row_ptr[lo:hi + 1], A.col_idx, A.val, x, dynamic)
+    return _reference_from_parts(s, x, y, absax, dynamic)
+
+
+def _reference_from_parts(s, x, y, absax, dynamic) -> dict:
+    lo, hi = s["lo"], s["hi"]
     xL = x[lo:hi]
     yL, _ = spmv_dot2(s["L_ptr"], s["L_col"], s["L_val"], xL, dynamic)
     inbox = x[s["H"].astype(np.int64)]

@@ -150,6 +150,7 @@ def _proto(name, args, res=ctypes.c_int):
 
 _proto("spmv_plan_create", [_P, _I32, _I32, _P, _I32, _P, _I32, _P])
 _proto("spmv_plan_create_ex", [_P, _I32, _I32, _P, _I32, _P, _I32, _P, _P])
+_proto("spmv_plan_create_local", [_P, _I64, _I32, _I32, _P, _P, _P, _I32, _P, _I32, _P, _P])
 _proto("spmv_plan_destroy", [_P])
 _proto("spmv_exec", [_P, _P, _P, _P])
 _proto("spmv_plan_info", [_P, _P])
@@ -246,6 +247,28 @@ def spmv_plan_create(A, nranks: int, rank: int, op_order=None, stream_map=None,
         ctypes.byref(c), nranks, rank, _addr(ops), 0 if ops is None else ops.size,
         _addr(smap), n_streams, ctypes.byref(tune) if tune is not None else None,
         ctypes.byref(out)))
+    del keep
+    return out.value
+
+
+def spmv_plan_create_local(local, n_global: int, nranks: int, rank: int, send_idx, send_off,
+                           op_order=None, stream_map=None, n_streams: int = 2, tune=None):
+    """Plan from the rank's own rows (global columns) and its send lists."""
+    c, keep = make_csr(local)
+    si = _i32(send_idx)
+    so = _i32(send_off)
+    ops = None if op_order is None else _i32(op_order)
+    smap = _smap_array(stream_map)
+    if isinstance(tune, dict):
+        t = spmv_tune_t()
+        for k, v in tune.items():
+            setattr(t, k, v)
+        tune = t
+    out = ctypes.c_void_p()
+    _check(_lib.spmv_plan_create_local(
+        ctypes.byref(c), n_global, nranks, rank, _addr(si) if si.size else None, _addr(so),
+        _addr(ops), 0 if ops is None else ops.size, _addr(smap), n_streams,
+        ctypes.byref(tune) if tune is not None else None, ctypes.byref(out)))
     del keep
     return out.value
 

@@ -46,6 +46,9 @@ struct Share {
 int validate_csr(const spmv_csr_t *csr);
 int64_t block_lo(int64_t n, int32_t P, int32_t q);
 int build_share(const spmv_csr_t *csr, int32_t nranks, int32_t rank, Share &out);
+// From the rank's own rows (global columns) and its send lists.
+int build_share_local(const spmv_csr_t *local, int64_t n_global, int32_t nranks, int32_t rank,
+                      const int32_t *send_idx, const int32_t *send_off, Share &out);
 
 // ----------------------------------------------------------------- DAG
 enum class VType : uint8_t { CPU, GPU };

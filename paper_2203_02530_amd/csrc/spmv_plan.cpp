@@ -193,7 +193,11 @@ void configure(CsrCfg &c, const std::vector<int32_t> &rp, int64_t n_rows, int32_
     // vector kernel remains for arrays beyond 32-bit buffer offsets.
     const int64_t kMax = (int64_t(1) << 32) - 64;
     const bool fits = (nnz + kEntryPad) * 8 < kMax;
-    c.kernel = kernel ? kernel : (fits ? SPMV_KERNEL_STREAM : SPMV_KERNEL_VECTOR);
+    // knobs that only the vector kernel has (rows per group, > 16 lanes)
+    // select it when the kernel is left automatic
+    const bool vector_knobs = rows != 0 || lanes > 16;
+    c.kernel = kernel ? kernel
+                      : (fits && !vector_knobs ? SPMV_KERNEL_STREAM : SPMV_KERNEL_VECTOR);
     if (c.kernel == SPMV_KERNEL_VECTOR) {
         c.lanes = lanes ? lanes : auto_lanes(nnz, n_rows);
         c.rows = rows ? rows : auto_rows(c.lanes, n_rows);
@@ -235,10 +239,12 @@ hipError_t launch_product(const spmv_plan *p, int side, const double *x, double 
 
 }  // namespace
 
-extern "C" int spmv_plan_create_ex(const spmv_csr_t *csr, int32_t nranks, int32_t rank,
-                                   const int32_t *op_order, int32_t n_ops,
-                                   const int32_t *stream_map, int32_t n_streams,
-                                   const spmv_tune_t *tune, spmv_plan_t **out)
+namespace {
+
+template <class Build>
+int create_plan(Build build_share_fn, int32_t nranks, const int32_t *op_order, int32_t n_ops,
+                const int32_t *stream_map, int32_t n_streams, const spmv_tune_t *tune,
+                spmv_plan_t **out)
 {
     if (!out) return set_error(SPMV_EINVAL, "out is NULL");
     *out = nullptr;
@@ -275,7 +281,7 @@ extern "C" int spmv_plan_create_ex(const spmv_csr_t *csr, int32_t nranks, int32_
     auto *p = new (std::nothrow) spmv_plan();
     if (!p) return set_error(SPMV_ENOMEM, "plan allocation");
     int rc = validate_schedule(nranks, op_order, n_ops, stream_map, n_streams, p->sch);
-    if (rc == SPMV_OK) rc = build_share(csr, nranks, rank, p->share);
+    if (rc == SPMV_OK) rc = build_share_fn(p->share);
     if (rc != SPMV_OK) {
         delete p;
         return rc;
@@ -313,6 +319,31 @@ extern "C" int spmv_plan_create_ex(const spmv_csr_t *csr, int32_t nranks, int32_
     }
     *out = p;
     return SPMV_OK;
+}
+
+}  // namespace
+
+extern "C" int spmv_plan_create_ex(const spmv_csr_t *csr, int32_t nranks, int32_t rank,
+                                   const int32_t *op_order, int32_t n_ops,
+                                   const int32_t *stream_map, int32_t n_streams,
+                                   const spmv_tune_t *tune, spmv_plan_t **out)
+{
+    return create_plan([&](Share &S) { return build_share(csr, nranks, rank, S); }, nranks,
+                       op_order, n_ops, stream_map, n_streams, tune, out);
+}
+
+extern "C" int spmv_plan_create_local(const spmv_csr_t *local, int64_t n_global, int32_t nranks,
+                                      int32_t rank, const int32_t *send_idx,
+                                      const int32_t *send_off, const int32_t *op_order,
+                                      int32_t n_ops, const int32_t *stream_map,
+                                      int32_t n_streams, const spmv_tune_t *tune,
+                                      spmv_plan_t **out)
+{
+    return create_plan(
+        [&](Share &S) {
+            return build_share_local(local, n_global, nranks, rank, send_idx, send_off, S);
+        },
+        nranks, op_order, n_ops, stream_map, n_streams, tune, out);
 }
 
 extern "C" int spmv_plan_create(const spmv_csr_t *csr, int32_t nranks, int32_t rank,

@@ -49,31 +49,21 @@ int64_t block_lo(int64_t n, int32_t P, int32_t q)
     return int64_t(q) * (n / P) + std::min<int64_t>(q, n % P);
 }
 
-int build_share(const spmv_csr_t *csr, int32_t P, int32_t r, Share &S)
-{
-    if (int rc = validate_csr(csr)) return rc;
-    if (P < 1) return set_error(SPMV_EINVAL, "nranks < 1");
-    if (r < 0 || r >= P) return set_error(SPMV_EINVAL, "rank out of range");
-    const int64_t n = csr->n_rows;
-    const int32_t *rp = csr->row_ptr, *ci = csr->col_idx;
-    const double *va = csr->val;
-    const int64_t lo = block_lo(n, P, r), hi = block_lo(n, P, r + 1);
-    const int64_t nl = hi - lo;
-    S = Share();
-    S.n_global = n;
-    S.lo = lo;
-    S.n_loc = nl;
-    S.nranks = P;
-    S.rank = r;
+namespace {
 
-    // A_L and the set of remote columns.
+// The rank's own rows: rp[0..nl] indexes col/val (rp[0] may be non-zero when
+// the rows sit inside a global matrix).  Splits them into A_L / A_R and
+// derives the halo and its owners (Sec. III-A).
+void split_rows(const int32_t *rp, const int32_t *ci, const double *va, int64_t nl, int64_t n,
+                int32_t P, int64_t lo, int64_t hi, Share &S)
+{
     std::vector<uint8_t> remote_mark(size_t(n), 0);
     S.L_ptr.assign(size_t(nl) + 1, 0);
     int64_t nnz_rem = 0;
     for (int64_t i = 0; i < nl; ++i) {
         int32_t cnt = 0;
-        for (int32_t k = rp[lo + i]; k < rp[lo + i + 1]; ++k) {
-            int32_t c = ci[k];
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int32_t c = ci[k];
             if (c >= lo && c < hi) {
                 ++cnt;
             } else {
@@ -101,14 +91,14 @@ int build_share(const spmv_csr_t *csr, int32_t P, int32_t r, Share &S)
             std::lower_bound(S.halo.begin(), S.halo.end(), block_lo(n, P, q)) - S.halo.begin());
 
     // Fill A_L values and A_R over the rows that touch the halo.
-    S.R_ptr.push_back(0);
+    S.R_ptr.assign(1, 0);
     S.R_col.reserve(size_t(nnz_rem));
     S.R_val.reserve(size_t(nnz_rem));
     for (int64_t i = 0; i < nl; ++i) {
         int32_t w = S.L_ptr[size_t(i)];
         int32_t rcount = 0;
-        for (int32_t k = rp[lo + i]; k < rp[lo + i + 1]; ++k) {
-            int32_t c = ci[k];
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int32_t c = ci[k];
             if (c >= lo && c < hi) {
                 S.L_col[size_t(w)] = int32_t(c - lo);
                 S.L_val[size_t(w)] = va[k];
@@ -124,6 +114,32 @@ int build_share(const spmv_csr_t *csr, int32_t P, int32_t r, Share &S)
             S.R_ptr.push_back(S.R_ptr.back() + rcount);
         }
     }
+    S.unpack_perm.resize(S.halo.size());
+    for (size_t p = 0; p < S.halo.size(); ++p) S.unpack_perm[p] = int32_t(p);
+}
+
+void init_share(Share &S, int64_t n, int32_t P, int32_t r)
+{
+    S = Share();
+    S.n_global = n;
+    S.lo = block_lo(n, P, r);
+    S.n_loc = block_lo(n, P, r + 1) - S.lo;
+    S.nranks = P;
+    S.rank = r;
+}
+
+}  // namespace
+
+int build_share(const spmv_csr_t *csr, int32_t P, int32_t r, Share &S)
+{
+    if (int rc = validate_csr(csr)) return rc;
+    if (P < 1) return set_error(SPMV_EINVAL, "nranks < 1");
+    if (r < 0 || r >= P) return set_error(SPMV_EINVAL, "rank out of range");
+    const int64_t n = csr->n_rows;
+    const int32_t *rp = csr->row_ptr, *ci = csr->col_idx;
+    init_share(S, n, P, r);
+    const int64_t lo = S.lo, hi = S.lo + S.n_loc, nl = S.n_loc;
+    split_rows(rp + lo, ci, csr->val, nl, n, P, lo, hi, S);
 
     // Send lists: for each other rank q, the owned columns appearing in q's
     // rows, as local indices, ascending.  A stamp per local index avoids
@@ -136,7 +152,7 @@ int build_share(const spmv_csr_t *csr, int32_t P, int32_t r, Share &S)
         const int64_t qlo = block_lo(n, P, q), qhi = block_lo(n, P, q + 1);
         int64_t found = 0;
         for (int32_t k = rp[qlo]; k < rp[qhi]; ++k) {
-            int32_t c = ci[k];
+            const int32_t c = ci[k];
             if (c >= lo && c < hi && stamp[size_t(c - lo)] != q) {
                 stamp[size_t(c - lo)] = q;
                 ++found;
@@ -147,7 +163,7 @@ int build_share(const spmv_csr_t *csr, int32_t P, int32_t r, Share &S)
         if (found * 8 < nl) {
             // few entries: collect and sort
             for (int32_t k = rp[qlo]; k < rp[qhi]; ++k) {
-                int32_t c = ci[k];
+                const int32_t c = ci[k];
                 if (c >= lo && c < hi && stamp[size_t(c - lo)] == q) {
                     stamp[size_t(c - lo)] = P + q;  // collected
                     S.send_idx.push_back(int32_t(c - lo));
@@ -163,9 +179,57 @@ int build_share(const spmv_csr_t *csr, int32_t P, int32_t r, Share &S)
         }
         S.send_off[size_t(q) + 1] = int32_t(S.send_idx.size());
     }
+    return SPMV_OK;
+}
 
-    S.unpack_perm.resize(S.halo.size());
-    for (size_t p = 0; p < S.halo.size(); ++p) S.unpack_perm[p] = int32_t(p);
+int build_share_local(const spmv_csr_t *local, int64_t n, int32_t P, int32_t r,
+                      const int32_t *send_idx, const int32_t *send_off, Share &S)
+{
+    if (!local) return set_error(SPMV_EINVAL, "local rows are NULL");
+    if (P < 1) return set_error(SPMV_EINVAL, "nranks < 1");
+    if (r < 0 || r >= P) return set_error(SPMV_EINVAL, "rank out of range");
+    if (n < 0 || n >= (int64_t(1) << 31)) return set_error(SPMV_EINVAL, "n_global out of range");
+    if (local->n_cols != n)
+        return set_error(SPMV_EINVAL, "local rows must carry global columns (n_cols = n_global)");
+    init_share(S, n, P, r);
+    if (local->n_rows != S.n_loc)
+        return set_error(SPMV_EINVAL, "local rows do not match the rank's row block (" +
+                                          std::to_string(S.n_loc) + " rows)");
+    // same structural checks as a global matrix, minus squareness
+    {
+        const int32_t *rp = local->row_ptr;
+        if (!rp || rp[0] != 0 || rp[local->n_rows] != local->nnz)
+            return set_error(SPMV_ECSR, "local row_ptr malformed");
+        for (int32_t i = 0; i < local->n_rows; ++i) {
+            if (rp[i + 1] < rp[i]) return set_error(SPMV_ECSR, "row_ptr decreases");
+            int32_t prev = -1;
+            for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+                const int32_t c = local->col_idx[k];
+                if (c < 0 || c >= n) return set_error(SPMV_ECSR, "column out of range");
+                if (c <= prev) return set_error(SPMV_ECSR, "columns not strictly ascending");
+                prev = c;
+            }
+        }
+    }
+    if (!send_off) return set_error(SPMV_EINVAL, "send_off is NULL");
+    if (send_off[0] != 0) return set_error(SPMV_EINVAL, "send_off[0] != 0");
+    for (int32_t q = 0; q < P; ++q) {
+        if (send_off[q + 1] < send_off[q]) return set_error(SPMV_EINVAL, "send_off decreases");
+        if (q == r && send_off[q + 1] != send_off[q])
+            return set_error(SPMV_EINVAL, "a rank sends nothing to itself");
+        if (send_off[q + 1] > send_off[q] && !send_idx)
+            return set_error(SPMV_EINVAL, "send_idx is NULL");
+        for (int32_t k = send_off[q]; k < send_off[q + 1]; ++k) {
+            if (send_idx[k] < 0 || send_idx[k] >= S.n_loc)
+                return set_error(SPMV_EINVAL, "send index out of the rank's rows");
+            if (k > send_off[q] && send_idx[k] <= send_idx[k - 1])
+                return set_error(SPMV_EINVAL, "send indices must ascend per destination");
+        }
+    }
+    split_rows(local->row_ptr, local->col_idx, local->val, S.n_loc, n, P, S.lo,
+               S.lo + S.n_loc, S);
+    S.send_off.assign(send_off, send_off + P + 1);
+    if (send_off[P] > 0) S.send_idx.assign(send_idx, send_idx + send_off[P]);
     return SPMV_OK;
 }
 

@@ -369,3 +369,80 @@ def test_server_rejects_bad_options_on_host():
         with pytest.raises(sp.SpmvError) as e:
             sp.spmv_server_create(opts)
         assert e.value.code == sp.SPMV_EINVAL
+
+
+def _local_rows(A, P, r):
+    lo = oracle.row_blocks(A.n_rows, P)
+    a, b = int(lo[r]), int(lo[r + 1])
+    rp = A.row_ptr[a:b + 1].astype(np.int64)
+    return gen.CSR(b - a, A.n_cols, (rp - rp[0]).astype(np.int32),
+                   A.col_idx[rp[0]:rp[-1]].copy(), A.val[rp[0]:rp[-1]].copy())
+
+
+@pytest.mark.parametrize("P,r", [(4, 1), (16, 5), (3, 0), (6, 5)])
+def test_local_plan_matches_global(P, r):
+    """A plan built from the rank's own rows and the send lists equals the
+    plan built from the global matrix (the send lists come from the oracle)."""
+    A = gen.power_law(20000, seed=11) if P >= 6 else gen.banded_uniform(3000, 10, 750, seed=4)
+    ref = oracle.split(A, P, r)
+    pl = sp.spmv_plan_create_local(_local_rows(A, P, r), A.n_rows, P, r, ref["send_idx"],
+                                   ref["send_off"], tune=HOST_ONLY)
+    pg = sp.spmv_plan_create(A, P, r, tune=HOST_ONLY)
+    try:
+        for w in range(16):
+            if w in (sp.SPMV_I32_OP_ORDER, sp.SPMV_I32_STREAM_MAP):
+                continue
+            assert np.array_equal(sp.spmv_plan_get_i32(pl, w), sp.spmv_plan_get_i32(pg, w)), w
+        for w in (sp.SPMV_F64_AL_VAL, sp.SPMV_F64_AR_VAL):
+            assert np.array_equal(sp.spmv_plan_get_f64(pl, w), sp.spmv_plan_get_f64(pg, w))
+    finally:
+        sp.spmv_plan_destroy(pl)
+        sp.spmv_plan_destroy(pg)
+
+
+def test_local_plan_rejects_bad_send_lists():
+    A = gen.banded_uniform(3000, 10, 750, seed=4)
+    P, r = 4, 1
+    ref = oracle.split(A, P, r)
+    loc = _local_rows(A, P, r)
+    bad = []
+    s = ref["send_idx"].copy()
+    s[[0, 1]] = s[[1, 0]]                                   # not ascending
+    bad.append((s, ref["send_off"]))
+    s = ref["send_idx"].copy()
+    s[-1] = 10 ** 6                                         # out of the rows
+    bad.append((s, ref["send_off"]))
+    off = ref["send_off"].copy()
+    off[r + 1] += 1                                         # sends to itself
+    bad.append((np.concatenate([ref["send_idx"], [0]]), np.maximum.accumulate(off)))
+    for si, so in bad:
+        with pytest.raises(sp.SpmvError) as e:
+            sp.spmv_plan_create_local(loc, A.n_rows, P, r, si, so, tune=HOST_ONLY)
+        assert e.value.code == sp.SPMV_EINVAL
+    with pytest.raises(sp.SpmvError):      # wrong number of local rows
+        sp.spmv_plan_create_local(_local_rows(A, 3, 0), A.n_rows, P, r, ref["send_idx"],
+                                  ref["send_off"], tune=HOST_ONLY)
+
+
+def test_power_law_share_structure():
+    d = gen.power_law_share(200000, 16, 5, seed=3)
+    loc = d["local"]
+    loc.n_cols = d["n_global"]
+    so = d["send_off"]
+    assert so[0] == 0 and np.all(np.diff(so) >= 0) and so[6] == so[5]
+    for q in range(16):
+        seg = d["send_idx"][so[q]:so[q + 1]]
+        assert np.all(np.diff(seg) > 0) and (seg.size == 0 or (seg.min() >= 0 and seg.max() < loc.n_rows))
+    L = np.diff(loc.row_ptr)
+    assert abs(L.mean() - 16) < 0.5
+    # rank 0's ~12500*16 entries hit this 12500-column block with p = 1/16:
+    # ~12500 uniform hits, of which 12500 * (1 - 1/e) distinct on average
+    import math
+    assert abs(np.diff(so)[0] - 12500 * (1 - math.exp(-1))) < 0.05 * 12500
+    p = sp.spmv_plan_create_local(loc, d["n_global"], 16, 5, d["send_idx"], so, tune=HOST_ONLY)
+    try:
+        info = sp.spmv_plan_info(p)
+        ref = oracle.split_local(loc, d["n_global"], 16, 5, d["send_idx"], so)
+        assert info["n_halo"] == ref["H"].size and info["nnz_remote"] == ref["R_val"].size
+    finally:
+        sp.spmv_plan_destroy(p)

@@ -75,7 +75,8 @@ def test_lane_variants(lanes, rows):
     x = gen.x_normal(A.n_cols, 18)
     log(f"power-law 30k lanes={lanes} rows={rows}")
     for fuse, remap, flags in ((0, 1, 0), (1, 2, sp.SPMV_F_NO_BUFFER)):
-        res, ref = run_share(A, 4, 2, x, tune={"lanes_local": lanes, "lanes_remote": lanes,
+        res, ref = run_share(A, 4, 2, x, tune={"kernel_local": 1, "kernel_remote": 1,
+                                               "lanes_local": lanes, "lanes_remote": lanes,
                                                "rows_local": rows, "rows_remote": rows,
                                                "xcd_remap": remap, "fuse_unpack": fuse,
                                                "flags": flags})
@@ -222,6 +223,24 @@ def test_repeated_exec_new_x():
         sp.spmv_plan_destroy(plan)
 
 
+def test_local_plan_power_law_share():
+    """Rank-local plans (own rows + send lists) against the oracle's
+    rank-local definition, power-law share of 400k rows, rank 5 of 16."""
+    import torch
+    d = gen.power_law_share(400_000, 16, 5, seed=4001)
+    x = gen.x_normal(d["n_global"], 4101)
+    ref = oracle.share_reference_local(d["local"], d["n_global"], 16, 5, d["send_idx"],
+                                       d["send_off"], x)
+    for tune in ({}, {"kernel_local": 1, "kernel_remote": 1}):
+        plan = sp.spmv_plan_create_local(d["local"], d["n_global"], 16, 5, d["send_idx"],
+                                         d["send_off"], tune=tune)
+        try:
+            res, _ = run_share(None, 16, 5, x, ref=ref, plan=plan)
+            assert_share_parity(res, ref)
+        finally:
+            sp.spmv_plan_destroy(plan)
+
+
 # ------------------------------------------------------------ edge cases
 
 def test_empty_share_and_empty_rows():
@@ -245,8 +264,9 @@ def test_long_rows():
     """Rows far longer than a wavefront (up to 10^4 entries)."""
     A = gen.power_law(40000, mean_len=200.0, sigma=1.2, max_len=10000, seed=44)
     x = gen.x_normal(A.n_cols, 45)
-    for lanes in (0, 64, 8):
-        res, ref = run_share(A, 4, 1, x, tune={"lanes_local": lanes, "lanes_remote": lanes})
+    for kern, lanes in ((0, 0), (1, 64), (1, 8), (2, 16)):
+        res, ref = run_share(A, 4, 1, x, tune={"kernel_local": kern, "kernel_remote": kern,
+                                               "lanes_local": lanes, "lanes_remote": lanes})
         assert_share_parity(res, ref)
 
 
