@@ -310,14 +310,18 @@ int spmv_plan_reorder(spmv_plan_t *plan, const int32_t *op_order, int32_t n_ops,
                       const int32_t *stream_map, int32_t n_streams);
 
 /*
- * The paper's benchmark protocol (Sec. III-C3) for one plan: a measurement
- * repeats spmv_exec (a sample) until t_measure seconds have elapsed on the
- * host clock and records elapsed / samples.  Runs n_measure measurements and
- * writes their per-sample times (seconds) to host times[0..n_measure).  The
- * inbox contents, x_local, y_local and stream are as for spmv_exec.
+ * The paper's benchmark protocol (Sec. III-C3): a measurement repeats the
+ * program (a sample) until t_measure seconds have elapsed on the host clock
+ * and records elapsed / samples; n_measure measurements are written to host
+ * times[0..n_measure) in seconds.  Sample i runs spmv_exec(plans[i % n_plans],
+ * x[i % n_plans], y[i % n_plans], stream): with n_plans = 1 this is the
+ * paper's protocol on one plan; with several replicas of one share (same
+ * order and streams) the samples rotate over independent device copies,
+ * which keeps the matrix out of the last-level cache between samples.
  */
-int spmv_plan_time(spmv_plan_t *plan, const double *x_local, double *y_local, void *stream,
-                   double t_measure, int32_t n_measure, double *times);
+int spmv_plan_time(spmv_plan_t *const *plans, int32_t n_plans, const double *const *x,
+                   double *const *y, void *stream, double t_measure, int32_t n_measure,
+                   double *times);
 
 int spmv_plan_info(const spmv_plan_t *plan, spmv_info_t *info);
 
@@ -384,7 +388,12 @@ typedef struct {
     int32_t use_graph;      /* 0 = auto (graph), 1 = hipGraph, 2 = stream launches */
     int32_t xcd_affinity;   /* 0 = auto (on when >= 8 shares), 1 = on: the work
                                of share s runs on XCD s mod 8, 2 = off        */
-    int32_t reserved[5];
+    int32_t staging;        /* 0 = halo staged through the plans' pinned
+                               mailboxes (the program), 1 = device phase only
+                               (no copies: for timing the grouped kernels;
+                               y_R then uses whatever the receive buffers
+                               hold)                                          */
+    int32_t reserved[4];
 } spmv_batch_opts_t;
 
 typedef struct {
@@ -394,7 +403,8 @@ typedef struct {
     int64_t device_bytes;    /* algorithmic device bytes of one batch exec  */
     int64_t host_link_bytes; /* bytes staged over the host link, both ways  */
     int32_t chunk, width;    /* stream-CSR window and load width shared by all */
-    int32_t use_graph, xcd_affinity;
+    int32_t use_graph, xcd_affinity, staging;
+    int32_t reserved;
 } spmv_batch_info_t;
 
 /*

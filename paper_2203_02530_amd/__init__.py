@@ -90,7 +90,8 @@ class spmv_tune_t(ctypes.Structure):
 
 class spmv_batch_opts_t(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("xcd_affinity", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("xcd_affinity", ctypes.c_int32), ("staging", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class spmv_batch_info_t(ctypes.Structure):
@@ -98,7 +99,8 @@ class spmv_batch_info_t(ctypes.Structure):
                 ("n_items", ctypes.c_int64 * 3), ("device_bytes", ctypes.c_int64),
                 ("host_link_bytes", ctypes.c_int64), ("chunk", ctypes.c_int32),
                 ("width", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("xcd_affinity", ctypes.c_int32)]
+                ("xcd_affinity", ctypes.c_int32), ("staging", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -156,7 +158,7 @@ _proto("spmv_exec", [_P, _P, _P, _P])
 _proto("spmv_plan_info", [_P, _P])
 _proto("spmv_op_launch", [_P, _I32, _P, _P, _P])
 _proto("spmv_plan_reorder", [_P, _P, _I32, _P, _I32])
-_proto("spmv_plan_time", [_P, _P, _P, _P, ctypes.c_double, _I32, _P])
+_proto("spmv_plan_time", [_P, _I32, _P, _P, _P, ctypes.c_double, _I32, _P])
 _proto("spmv_plan_get_i32", [_P, _I32, _P, _I64])
 _proto("spmv_plan_get_f64", [_P, _I32, _P, _I64])
 _proto("spmv_plan_reset_times", [_P])
@@ -306,13 +308,20 @@ def spmv_plan_reorder(plan, op_order, stream_map=None, n_streams: int = 2) -> No
     _check(_lib.spmv_plan_reorder(plan, _addr(ops), ops.size, _addr(smap), n_streams))
 
 
-def spmv_plan_time(plan, x, y, stream=None, t_measure: float = 0.01,
+def spmv_plan_time(plans, xs, ys, stream=None, t_measure: float = 0.01,
                    n_measure: int = 5) -> np.ndarray:
     """The paper's protocol: per measurement, repeat exec for t_measure
-    seconds; returns seconds per exec for each measurement."""
+    seconds, rotating over `plans` (a plan handle or a list of replicas) and
+    their x / y; returns seconds per exec for each measurement."""
+    if not isinstance(plans, (list, tuple)):
+        plans, xs, ys = [plans], [xs], [ys]
+    n = len(plans)
+    pa = (ctypes.c_void_p * n)(*plans)
+    xa = (ctypes.c_void_p * n)(*[_addr(v) or None for v in xs])
+    ya = (ctypes.c_void_p * n)(*[_addr(v) or None for v in ys])
     out = np.empty(n_measure, np.float64)
-    _check(_lib.spmv_plan_time(plan, _addr(x), _addr(y), _stream_handle(stream), t_measure,
-                               n_measure, out.ctypes.data))
+    _check(_lib.spmv_plan_time(pa, n, xa, ya, _stream_handle(stream), t_measure, n_measure,
+                               out.ctypes.data))
     return out
 
 

@@ -181,7 +181,7 @@ using namespace spmv;
 struct spmv_batch {
     std::vector<spmv_plan *> plans;
     int32_t n = 0, npt = 8, vw = 2, n_blocks = 0;
-    bool use_graph = true, xcd_aff = false;
+    bool use_graph = true, xcd_aff = false, staging = true;
     int device = 0;
     GroupedFn fn = nullptr;
 
@@ -272,7 +272,7 @@ int build_graph(spmv_batch *b)
     hipGraphNode_t n_a = nullptr, n_b = nullptr, n_c = nullptr;
     if (int rc = kernel_node(0, &n_t, 1, &n_a)) return rc;
     std::vector<hipGraphNode_t> recv;
-    for (spmv_plan *p : b->plans) {
+    for (spmv_plan *p : b->staging ? b->plans : std::vector<spmv_plan *>{}) {
         const size_t ns = p->share.send_idx.size() * 8, nh = p->share.halo.size() * 8;
         if (ns) {
             hipGraphNode_t n;
@@ -310,7 +310,7 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
     spmv_batch_opts_t o{};
     if (opts) o = *opts;
     if (o.blocks_per_cu < 0 || o.blocks_per_cu > 32 || o.use_graph < 0 || o.use_graph > 2 ||
-        o.xcd_affinity < 0 || o.xcd_affinity > 2)
+        o.xcd_affinity < 0 || o.xcd_affinity > 2 || o.staging < 0 || o.staging > 1)
         return set_error(SPMV_EINVAL, "batch option out of range");
     const int npt = plans[0] ? plans[0]->cfg[0].chunk : 0;
     const int vw = plans[0] ? plans[0]->cfg[0].width : 0;
@@ -342,6 +342,7 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
     b->n_blocks = kCUs * (o.blocks_per_cu ? o.blocks_per_cu : 8);
     b->use_graph = o.use_graph != 2;
     b->xcd_aff = o.xcd_affinity == 1 || (o.xcd_affinity == 0 && n >= kXcds);
+    b->staging = o.staging == 0;
 
     // descriptors and work items
     std::vector<ShareDev> sh(static_cast<size_t>(n));
@@ -404,7 +405,7 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
         b->dev_bytes += 20 * n_send + 12 * nl + 4 * (nloc + 1) + 16 * nloc +
                         (p->fuse_unpack ? 0 : 20 * n_halo) + 12 * nr + 8 * rr + 4 + 8 * n_halo +
                         16 * rr;
-        b->link_bytes += 8 * (n_send + n_halo);
+        if (o.staging == 0) b->link_bytes += 8 * (n_send + n_halo);
     }
     std::vector<Item> grouped[3];
     std::vector<int32_t> blk[3];
@@ -495,7 +496,7 @@ extern "C" int spmv_batch_exec(spmv_batch_t *b, const double *const *x, double *
     SPMV_HIP(launch(0));
     SPMV_HIP(hipEventRecord(b->ev_a, s));
     SPMV_HIP(hipStreamWaitEvent(b->cs_send, b->ev_a, 0));
-    for (spmv_plan *p : b->plans) {
+    for (spmv_plan *p : b->staging ? b->plans : std::vector<spmv_plan *>{}) {
         const size_t ns = p->share.send_idx.size() * 8, nh = p->share.halo.size() * 8;
         if (ns)
             SPMV_HIP(hipMemcpyAsync(p->h_outbox, p->d_sendbuf, ns, hipMemcpyDeviceToHost,
@@ -526,6 +527,7 @@ extern "C" int spmv_batch_info(const spmv_batch_t *b, spmv_batch_info_t *info)
     info->chunk = b->npt;
     info->width = b->vw;
     info->use_graph = b->use_graph ? 1 : 0;
+    info->staging = b->staging ? 0 : 1;
     info->xcd_affinity = b->xcd_aff ? 1 : 0;
     return SPMV_OK;
 }

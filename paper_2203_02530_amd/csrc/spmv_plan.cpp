@@ -556,18 +556,21 @@ extern "C" int spmv_plan_reorder(spmv_plan_t *p, const int32_t *op_order, int32_
     return SPMV_OK;
 }
 
-extern "C" int spmv_plan_time(spmv_plan_t *p, const double *x, double *y, void *stream,
-                              double t_measure, int32_t n_measure, double *times)
+extern "C" int spmv_plan_time(spmv_plan_t *const *plans, int32_t n_plans, const double *const *x,
+                              double *const *y, void *stream, double t_measure, int32_t n_measure,
+                              double *times)
 {
-    if (!p || !times || n_measure < 1 || !(t_measure > 0))
+    if (!plans || n_plans < 1 || !x || !y || !times || n_measure < 1 || !(t_measure > 0))
         return set_error(SPMV_EINVAL, "bad argument to spmv_plan_time");
     using clock = std::chrono::steady_clock;
+    int64_t i = 0;
     for (int32_t m = 0; m < n_measure; ++m) {
         const auto t0 = clock::now();
         int64_t samples = 0;
         double el = 0.0;
         do {
-            if (int rc = spmv_exec(p, x, y, stream)) return rc;
+            const int32_t j = int32_t(i++ % n_plans);
+            if (int rc = spmv_exec(plans[j], x[j], y[j], stream)) return rc;
             ++samples;
             el = std::chrono::duration<double>(clock::now() - t0).count();
         } while (el < t_measure);

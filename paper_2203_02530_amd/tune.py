@@ -6,11 +6,12 @@ Two searches, both timed on the device by the library itself:
   (the design space of Sec. III-B/C, enumerated by the library), timed with
   the paper's benchmark protocol (Sec. III-C3): a measurement repeats the
   program until t_measure = 0.01 s has elapsed and records time / samples.
-  One plan object is re-ordered in place (``spmv_plan_reorder``), so the
-  share is uploaded once.
-* :func:`tune_kernel` -- lanes per row, rows per lane group and tile order of
-  the CSR kernel, timed with HIP events around back-to-back launches over
-  cold replicas.
+  Plan objects are re-ordered in place (``spmv_plan_reorder``), so the share
+  is uploaded once per replica; samples rotate over cold replicas.
+* :func:`tune_kernel` -- the CSR kernel variant (stream CSR: window chunk,
+  load width, summing lanes; vector CSR: lanes per row, rows per lane
+  group), timed with HIP events around back-to-back launches over cold
+  replicas.
 
 Results can be appended to a JSONL cache keyed by the matrix digest, so an
 interrupted sweep resumes where it stopped.
@@ -18,7 +19,6 @@ interrupted sweep resumes where it stopped.
 from __future__ import annotations
 
 import hashlib
-import itertools
 import json
 import math
 import os
@@ -56,29 +56,37 @@ def _load_cache(path, key):
 
 def sweep_plans(A, nranks: int, rank: int, x: np.ndarray, n_streams: int = 2,
                 tune: dict | None = None, t_measure: float = 0.01, n_measure: int = 1,
-                indices=None, cache_path: str | None = None, log=None):
+                indices=None, cache_path: str | None = None, replicas: int = 1, log=None):
     """Time every plan of the design space on rank ``rank``'s share.
 
-    Returns a list of dicts {index, times (s), t (median s)} in index order.
+    With replicas > 1 the share is uploaded that many times and the samples
+    of a measurement rotate over the copies (each one re-ordered to the
+    candidate plan), so plans are ranked with the matrix streamed from HBM
+    as in a cold run.  Returns a list of dicts {index, times (s), t (median
+    s)} in index order.
     """
     import torch
     n_plans = spmv_plan_space_count(nranks, n_streams)
     idx = list(range(n_plans)) if indices is None else list(indices)
-    key = f"{matrix_digest(A, nranks, rank)}:{n_streams}:{json.dumps(tune or {}, sort_keys=True)}"
+    key = (f"{matrix_digest(A, nranks, rank)}:{n_streams}:{replicas}:"
+           f"{json.dumps(tune or {}, sort_keys=True)}")
     done = _load_cache(cache_path, key)
     ops0, smap0 = spmv_plan_space_get(nranks, n_streams, 0)
-    plan = spmv_plan_create(A, nranks, rank, ops0, smap0, n_streams, tune)
+    plans = [spmv_plan_create(A, nranks, rank, ops0, smap0, n_streams, tune)
+             for _ in range(max(1, replicas))]
     out = []
     try:
-        info = spmv_plan_info(plan)
+        info = spmv_plan_info(plans[0])
         lo, n = info["lo"], info["n_loc"]
-        halo = spmv_plan_get_i32(plan, SPMV_I32_HALO_COLS).astype(np.int64)
-        spmv_plan_inbox(plan)[:] = x[halo]
-        xd = torch.from_numpy(np.ascontiguousarray(x[lo:lo + n])).cuda()
-        yd = torch.empty(n, dtype=torch.float64, device="cuda")
+        halo = spmv_plan_get_i32(plans[0], SPMV_I32_HALO_COLS).astype(np.int64)
+        xs, ys = [], []
+        for p in plans:
+            spmv_plan_inbox(p)[:] = x[halo]
+            xs.append(torch.from_numpy(np.ascontiguousarray(x[lo:lo + n])).cuda())
+            ys.append(torch.empty(n, dtype=torch.float64, device="cuda"))
         stream = torch.cuda.current_stream()
         torch.cuda.synchronize()
-        spmv_plan_time(plan, xd, yd, stream, t_measure, 1)       # warm-up
+        spmv_plan_time(plans, xs, ys, stream, t_measure, 1)      # warm-up
         fh = open(cache_path, "a") if cache_path else None
         try:
             for j, i in enumerate(idx):
@@ -86,8 +94,9 @@ def sweep_plans(A, nranks: int, rank: int, x: np.ndarray, n_streams: int = 2,
                     out.append(done[i])
                     continue
                 ops, smap = spmv_plan_space_get(nranks, n_streams, i)
-                spmv_plan_reorder(plan, ops, smap, n_streams)
-                t = spmv_plan_time(plan, xd, yd, stream, t_measure, n_measure)
+                for p in plans:
+                    spmv_plan_reorder(p, ops, smap, n_streams)
+                t = spmv_plan_time(plans, xs, ys, stream, t_measure, n_measure)
                 d = {"key": key, "index": i, "times": t.tolist(), "t": float(np.median(t))}
                 out.append(d)
                 if fh:
@@ -99,7 +108,8 @@ def sweep_plans(A, nranks: int, rank: int, x: np.ndarray, n_streams: int = 2,
             if fh:
                 fh.close()
     finally:
-        spmv_plan_destroy(plan)
+        for p in plans:
+            spmv_plan_destroy(p)
     return out
 
 
@@ -118,15 +128,22 @@ def sweep_summary(results) -> dict:
             "fastest_index": results[i_best]["index"], "slowest_index": results[i_worst]["index"]}
 
 
-def tune_kernel(A, nranks: int, rank: int, x: np.ndarray, lanes=(4, 8, 16, 32, 64),
-                rows=(1, 2, 4, 8), remaps=(1, 2), launches: int = 100, log=None):
-    """Search (lanes, rows, tile order) for y_L by timing back-to-back
-    launches over cold replicas.  Returns (best tune dict, all results)."""
+DEFAULT_CANDIDATES = (
+    [{"kernel_local": 2, "chunk_local": c, "width": 2} for c in (4, 8, 16)] +
+    [{"kernel_local": 2, "chunk_local": c, "width": 2, "lanes_local": l}
+     for c in (4, 8) for l in (1, 2, 4)] +
+    [{"kernel_local": 1, "lanes_local": l, "rows_local": r} for l in (8, 32) for r in (4, 8)])
+
+
+def tune_kernel(A, nranks: int, rank: int, x: np.ndarray, candidates=DEFAULT_CANDIDATES,
+                launches: int = 100, log=None):
+    """Search kernel variants for y_L (both CSR kernels: stream chunk / width
+    / summing lanes, vector lanes / rows) by timing back-to-back launches
+    over cold replicas.  Returns (best tune dict, all results)."""
     import torch
     results = []
     stream = torch.cuda.Stream()
-    for l, r_, m in itertools.product(lanes, rows, remaps):
-        tune = {"lanes_local": l, "rows_local": r_, "xcd_remap": m}
+    for tune in candidates:
         p0 = spmv_plan_create(A, nranks, rank, None, None, 2, tune)
         info = spmv_plan_info(p0)
         n = info["n_loc"]
@@ -152,8 +169,8 @@ def tune_kernel(A, nranks: int, rank: int, x: np.ndarray, lanes=(4, 8, 16, 32, 6
         finally:
             for p in plans:
                 spmv_plan_destroy(p)
-        results.append({**tune, "us": us})
+        results.append({"tune": dict(tune), "us": us})
         if log:
             log(json.dumps(results[-1]))
     best = min(results, key=lambda d: d["us"])
-    return {k: best[k] for k in ("lanes_local", "rows_local", "xcd_remap")}, results
+    return best["tune"], results
