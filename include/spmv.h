@@ -367,6 +367,80 @@ int spmv_plan_space_get(int32_t nranks, int32_t n_streams, int64_t index,
  * full length, or SPMV_EINVAL for an unknown token. */
 int spmv_op_name(int32_t op, char *buf, int32_t cap);
 
+/* ------------------------------------------------------------ tree search */
+
+/*
+ * Monte-Carlo tree search over the same design space (Sec. III-C).  A tree
+ * node is a prefix P_k; its children are the tokens spmv_plan_space would
+ * place next (same order: token code, then stream).  Each iteration
+ *   selection:  from the root, take the child maximising
+ *               c * sqrt(ln N / n) + V  (N, n: rollouts through the node and
+ *               the child; the first term is -inf for a fully explored
+ *               child; V = (t_max - t_min of the child) / (t_max - t_min of
+ *               the node) when n >= 2 and N >= 2 and the node's range is not
+ *               zero, else 1; the first of equal scores in creation order);
+ *               stop at a node that still has an uncreated child;
+ *   expansion:  create one uncreated child, drawn at random;
+ *   rollout:    complete the program with random children, keep every node
+ *               in the tree, benchmark the program;
+ *   backprop:   n += 1, t_min = min(t, t_min), t_max = max(t, t_max) on the
+ *               path; a node whose children all exist and are fully explored
+ *               (or that is complete) is fully explored.
+ * Every iteration benchmarks a plan not benchmarked before; the search ends
+ * after `iterations` rollouts or when the root is fully explored.
+ *
+ * Random draws: draw k picks entry r % m of the m candidates, with
+ * r = rand[k] when `rand` is given (error SPMV_EINVAL once it runs out),
+ * else the k-th output of a 64-bit Mersenne twister seeded with `seed`.
+ */
+typedef struct {
+    int64_t iterations;   /* rollouts; 0 = until the space is exhausted        */
+    uint64_t seed;
+    double c;             /* exploration constant; 0 = sqrt(2)                 */
+    int32_t n_streams;    /* 0 = 2                                             */
+    int32_t n_measure;    /* spmv_mcts_run: measurements per plan; 0 = 1       */
+    double t_measure;     /* spmv_mcts_run: seconds per measurement; 0 = 0.01  */
+    const uint64_t *rand; /* host [n_rand] random draws, or NULL               */
+    int64_t n_rand;
+    int64_t reserved[4];
+} spmv_mcts_opts_t;
+
+/* One node of the final tree (node 0 is the root, the empty prefix). */
+typedef struct {
+    int32_t parent;       /* -1 for the root                                   */
+    int32_t token;        /* token appended to the parent's prefix (-1: root)  */
+    int32_t stream;       /* canonical stream of a GPU vertex, else -1         */
+    int32_t full;         /* 1 when the subtree is fully explored              */
+    int64_t n;            /* rollouts through the node                         */
+    double t_min, t_max;  /* over those rollouts (+inf / -inf when n == 0)     */
+} spmv_mcts_node_t;
+
+/*
+ * Search with a cost table instead of a device: cost[i] is the time of plan
+ * i of spmv_plan_space(nranks, n_streams) (n_cost must equal the count).
+ * Host only.  Outputs, all host and optional except n_out:
+ *   index_out [cap]  plan index of each rollout, in order
+ *   time_out  [cap]  its time
+ *   *n_out           rollouts made (entries beyond cap are not written)
+ *   nodes     [node_cap] the final tree; *n_nodes = nodes in the tree
+ */
+int spmv_mcts_run_table(int32_t nranks, const double *cost, int64_t n_cost,
+                        const spmv_mcts_opts_t *opts, int64_t *index_out, double *time_out,
+                        int64_t cap, int64_t *n_out, spmv_mcts_node_t *nodes,
+                        int64_t node_cap, int64_t *n_nodes);
+
+/*
+ * Search on the device: every rollout re-orders `plans` (spmv_plan_reorder)
+ * to the plan and times it with spmv_plan_time(plans, n_plans, x, y,
+ * stream, t_measure, n_measure): the time is the median of the n_measure
+ * measurements (Sec. III-C3's protocol).  All plans must share nranks.  The
+ * plans are left in the order of the last rollout.  Outputs as above.
+ */
+int spmv_mcts_run(spmv_plan_t *const *plans, int32_t n_plans, const double *const *x,
+                  double *const *y, void *stream, const spmv_mcts_opts_t *opts,
+                  int64_t *index_out, double *time_out, int64_t cap, int64_t *n_out,
+                  spmv_mcts_node_t *nodes, int64_t node_cap, int64_t *n_nodes);
+
 /* ------------------------------------------------------------ batches */
 
 /*

@@ -126,6 +126,25 @@ class spmv_server_stats_t(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class spmv_mcts_opts_t(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("c", ctypes.c_double), ("n_streams", ctypes.c_int32),
+                ("n_measure", ctypes.c_int32), ("t_measure", ctypes.c_double),
+                ("rand", ctypes.c_void_p), ("n_rand", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 4)]
+
+
+class spmv_mcts_node_t(ctypes.Structure):
+    _fields_ = [("parent", ctypes.c_int32), ("token", ctypes.c_int32),
+                ("stream", ctypes.c_int32), ("full", ctypes.c_int32),
+                ("n", ctypes.c_int64), ("t_min", ctypes.c_double), ("t_max", ctypes.c_double)]
+
+
+MCTS_NODE_DTYPE = np.dtype([("parent", np.int32), ("token", np.int32), ("stream", np.int32),
+                            ("full", np.int32), ("n", np.int64), ("t_min", np.float64),
+                            ("t_max", np.float64)])
+
+
 class spmv_info_t(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "n_global", "lo", "n_loc", "nnz_local", "nnz_remote", "n_halo", "n_send",
@@ -168,6 +187,8 @@ _proto("spmv_plan_validate", [_I32, _P, _I32, _P, _I32])
 _proto("spmv_plan_space_count", [_I32, _I32, _P])
 _proto("spmv_plan_space_get", [_I32, _I32, _I64, _P, _P, _P])
 _proto("spmv_op_name", [_I32, ctypes.c_char_p, _I32])
+_proto("spmv_mcts_run_table", [_I32, _P, _I64, _P, _P, _P, _I64, _P, _P, _I64, _P])
+_proto("spmv_mcts_run", [_P, _I32, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _I64, _P])
 _proto("spmv_hbm_probe", [_I32, _P, _P, _I64, _I32, _P])
 _proto("spmv_batch_create", [_P, _I32, _P, _P])
 _proto("spmv_batch_exec", [_P, _P, _P, _P])
@@ -411,6 +432,60 @@ def spmv_plan_space_get(nranks: int, n_streams: int, index: int):
     _check(_lib.spmv_plan_space_get(nranks, n_streams, index, ops.ctypes.data,
                                     ctypes.byref(n), smap.ctypes.data))
     return ops[:n.value].copy(), smap
+
+
+def _mcts_opts(iterations, seed, c, n_streams, n_measure, t_measure, rand):
+    o = spmv_mcts_opts_t()
+    o.iterations, o.seed, o.c = int(iterations), int(seed), float(c)
+    o.n_streams, o.n_measure, o.t_measure = int(n_streams), int(n_measure), float(t_measure)
+    keep = None
+    if rand is not None:
+        keep = np.ascontiguousarray(rand, dtype=np.uint64)
+        o.rand, o.n_rand = keep.ctypes.data, keep.size
+    return o, keep
+
+
+def _mcts_result(fn, args, o, cap):
+    idx = np.empty(cap, np.int64)
+    tim = np.empty(cap, np.float64)
+    n = ctypes.c_int64()
+    n_nodes = ctypes.c_int64()
+    node_cap = cap * SPMV_MAX_OPS + 1     # a rollout creates at most one node per token
+    nodes = np.zeros(node_cap, MCTS_NODE_DTYPE)
+    _check(fn(*args, ctypes.byref(o), idx.ctypes.data, tim.ctypes.data, cap, ctypes.byref(n),
+              nodes.ctypes.data, node_cap, ctypes.byref(n_nodes)))
+    k = min(n.value, cap)
+    return {"index": idx[:k].copy(), "time": tim[:k].copy(),
+            "nodes": nodes[:min(n_nodes.value, node_cap)].copy()}
+
+
+def spmv_mcts_run_table(nranks: int, cost, iterations: int = 0, seed: int = 0, c: float = 0.0,
+                        n_streams: int = 2, rand=None) -> dict:
+    """Tree search over the plan space with cost[i] as plan i's time.
+    Returns {index, time (per rollout, in order), nodes (structured array of
+    the final tree, MCTS_NODE_DTYPE)}."""
+    cost = np.ascontiguousarray(cost, dtype=np.float64)
+    o, keep = _mcts_opts(iterations, seed, c, n_streams, 1, 0.01, rand)
+    cap = int(iterations) if iterations > 0 else cost.size
+    return _mcts_result(_lib.spmv_mcts_run_table, (nranks, cost.ctypes.data, cost.size), o, cap)
+
+
+def spmv_mcts_run(plans, xs, ys, stream=None, iterations: int = 0, seed: int = 0,
+                  c: float = 0.0, n_streams: int = 2, t_measure: float = 0.01,
+                  n_measure: int = 1, rand=None) -> dict:
+    """Tree search timing every rollout on the device (the plans, a handle
+    or a list of replicas, are re-ordered in place).  Same result as
+    spmv_mcts_run_table."""
+    if not isinstance(plans, (list, tuple)):
+        plans, xs, ys = [plans], [xs], [ys]
+    n = len(plans)
+    pa = (ctypes.c_void_p * n)(*plans)
+    xa = (ctypes.c_void_p * n)(*[_addr(v) or None for v in xs])
+    ya = (ctypes.c_void_p * n)(*[_addr(v) or None for v in ys])
+    o, keep = _mcts_opts(iterations, seed, c, n_streams, n_measure, t_measure, rand)
+    nranks = spmv_plan_info(plans[0])["nranks"]
+    cap = int(iterations) if iterations > 0 else spmv_plan_space_count(nranks, max(n_streams, 1))
+    return _mcts_result(_lib.spmv_mcts_run, (pa, n, xa, ya, _stream_handle(stream)), o, cap)
 
 
 def spmv_op_name(op: int) -> str:

@@ -248,99 +248,147 @@ void default_order(int32_t nranks, std::vector<int32_t> &ops, int32_t *stream_ma
 }
 
 // ---------------------------------------------------------------- enumeration
-namespace {
+// A program prefix P_k (Sec. III-B): the tokens placed so far and the
+// canonical streams of the GPU vertices among them.  The token universe is
+// the DAG's vertices without Unpack (implied before y_R) plus the Table III
+// tokens whose need does not depend on streams (in this DAG only GPU -> CPU
+// edges need synchronisation).
 
-struct Enumerator {
-    bool multi;
-    int32_t n_streams;
-    std::vector<int32_t> tokens;  // the token universe, ascending by code
-    std::vector<PlanEntry> out;
-    std::vector<int32_t> prefix;
-    int32_t stream[SPMV_N_VERTICES];
-    int32_t used = 0;
-    uint64_t placed = 0;
-
-    static uint64_t bit(int32_t t) { return uint64_t(1) << t; }
-
-    // Predecessors of a vertex inside the enumerated DAG (Unpack implied, so
-    // y_R follows WaitRecv directly).
-    bool preds_done(int32_t v) const
-    {
-        bool ok = true;
-        for_edges(multi, [&](int32_t u, int32_t w) {
-            if (w == SPMV_OP_UNPACK || u == SPMV_OP_UNPACK) return;
-            if (w == v && !(placed & bit(u))) ok = false;
+void Prefix::init(bool multi_, int32_t n_streams_)
+{
+    multi = multi_;
+    n_streams = n_streams_;
+    tokens.clear();
+    if (multi) {
+        for (int32_t v = 0; v < SPMV_N_VERTICES; ++v)
+            if (v != SPMV_OP_UNPACK) tokens.push_back(v);
+        for_edges(true, [&](int32_t u, int32_t v) {
+            if (u == SPMV_OP_UNPACK || v == SPMV_OP_UNPACK) return;
+            int32_t rec, wait, none[SPMV_N_VERTICES];
+            std::fill(none, none + SPMV_N_VERTICES, 0);
+            if (edge_sync(u, v, none, rec, wait)) {
+                tokens.push_back(rec);
+                tokens.push_back(wait);
+            }
         });
-        if (multi && v == SPMV_OP_YR && !(placed & bit(SPMV_OP_WAIT_RECV))) ok = false;
-        return ok;
+    } else {
+        tokens = {SPMV_OP_START, SPMV_OP_YL, SPMV_OP_END};
     }
+    std::sort(tokens.begin(), tokens.end());
+    clear();
+}
 
-    bool ready(int32_t t) const
-    {
-        if (placed & bit(t)) return false;
-        if (is_sync(t)) {
-            int32_t k = sync_kind(t), x = sync_operand(t);
-            if (k == SPMV_SYNC_CER) return (placed & bit(x)) != 0;
-            // a wait is ready once every record it waits on is placed
-            bool ok = true;
-            for_edges(multi, [&](int32_t u, int32_t v) {
-                int32_t rec, wait;
-                if (v == x && edge_sync(u, v, stream, rec, wait) && wait == t &&
-                    !(placed & bit(rec)))
-                    ok = false;
-            });
-            return ok;
-        }
-        if (t == SPMV_OP_END) {
-            for (int32_t o : tokens)
-                if (o != SPMV_OP_END && !(placed & bit(o))) return false;
-            return true;
-        }
-        if (!preds_done(t)) return false;
+void Prefix::clear()
+{
+    order.clear();
+    std::fill(stream, stream + SPMV_N_VERTICES, -1);
+    used = 0;
+    placed = 0;
+}
+
+// Predecessors of a vertex inside the enumerated DAG (Unpack implied, so y_R
+// follows WaitRecv directly).
+bool Prefix::preds_done(int32_t v) const
+{
+    bool ok = true;
+    for_edges(multi, [&](int32_t u, int32_t w) {
+        if (w == SPMV_OP_UNPACK || u == SPMV_OP_UNPACK) return;
+        if (w == v && !(placed & bit(u))) ok = false;
+    });
+    if (multi && v == SPMV_OP_YR && !(placed & bit(SPMV_OP_WAIT_RECV))) ok = false;
+    return ok;
+}
+
+bool Prefix::ready(int32_t t) const
+{
+    if (placed & bit(t)) return false;
+    if (is_sync(t)) {
+        int32_t k = sync_kind(t), x = sync_operand(t);
+        if (k == SPMV_SYNC_CER) return (placed & bit(x)) != 0;
+        // a wait is ready once every record it waits on is placed
         bool ok = true;
         for_edges(multi, [&](int32_t u, int32_t v) {
             int32_t rec, wait;
-            if (v == t && edge_sync(u, v, stream, rec, wait) && !(placed & bit(wait)))
+            if (v == x && edge_sync(u, v, stream, rec, wait) && wait == t && !(placed & bit(rec)))
                 ok = false;
         });
         return ok;
     }
+    if (t == SPMV_OP_END) {
+        for (int32_t o : tokens)
+            if (o != SPMV_OP_END && !(placed & bit(o))) return false;
+        return true;
+    }
+    if (!preds_done(t)) return false;
+    bool ok = true;
+    for_edges(multi, [&](int32_t u, int32_t v) {
+        int32_t rec, wait;
+        if (v == t && edge_sync(u, v, stream, rec, wait) && !(placed & bit(wait))) ok = false;
+    });
+    return ok;
+}
 
-    void dfs()
-    {
-        if (prefix.size() == tokens.size()) {
-            PlanEntry e;
-            e.order = prefix;
-            std::copy(stream, stream + SPMV_N_VERTICES, e.stream);
-            out.push_back(std::move(e));
-            return;
-        }
-        for (int32_t t : tokens) {
-            if (!ready(t)) continue;
-            if (is_vertex(t) && vertex_type(t) == VType::GPU) {
-                int32_t lim = std::min(used + 1, n_streams);
-                for (int32_t s = 0; s < lim; ++s) {
-                    bool fresh = s == used;
-                    stream[t] = s;
-                    if (fresh) ++used;
-                    placed |= bit(t);
-                    prefix.push_back(t);
-                    dfs();
-                    prefix.pop_back();
-                    placed &= ~bit(t);
-                    if (fresh) --used;
-                    stream[t] = -1;
-                }
-            } else {
-                placed |= bit(t);
-                prefix.push_back(t);
-                dfs();
-                prefix.pop_back();
-                placed &= ~bit(t);
-            }
+void Prefix::next(std::vector<Step> &out) const
+{
+    out.clear();
+    for (int32_t t : tokens) {
+        if (!ready(t)) continue;
+        if (is_vertex(t) && vertex_type(t) == VType::GPU) {
+            // streams already used, plus one new stream while any is left:
+            // children equal under a stream bijection are one child
+            const int32_t lim = std::min(used + 1, n_streams);
+            for (int32_t s = 0; s < lim; ++s) out.push_back({t, s});
+        } else {
+            out.push_back({t, -1});
         }
     }
-};
+}
+
+void Prefix::push(Step st)
+{
+    placed |= bit(st.token);
+    order.push_back(st.token);
+    if (st.stream >= 0) {
+        stream[st.token] = st.stream;
+        if (st.stream == used) ++used;
+    }
+}
+
+void Prefix::pop()
+{
+    const int32_t t = order.back();
+    order.pop_back();
+    placed &= ~bit(t);
+    if (stream[t] >= 0) {
+        if (stream[t] == used - 1) {
+            bool again = false;   // still used by an earlier vertex?
+            for (int32_t o : order)
+                if (is_vertex(o) && stream[o] == stream[t] && o != t) again = true;
+            if (!again) --used;
+        }
+        stream[t] = -1;
+    }
+}
+
+namespace {
+
+void enumerate(Prefix &p, std::vector<PlanEntry> &out)
+{
+    if (p.complete()) {
+        PlanEntry e;
+        e.order = p.order;
+        std::copy(p.stream, p.stream + SPMV_N_VERTICES, e.stream);
+        out.push_back(std::move(e));
+        return;
+    }
+    std::vector<Prefix::Step> kids;
+    p.next(kids);
+    for (const Prefix::Step &k : kids) {
+        p.push(k);
+        enumerate(p, out);
+        p.pop();
+    }
+}
 
 }  // namespace
 
@@ -352,32 +400,33 @@ const std::vector<PlanEntry> &plan_space(bool multi, int32_t n_streams)
     auto key = std::make_pair(multi, n_streams);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
-    Enumerator E;
-    E.multi = multi;
-    E.n_streams = n_streams;
-    std::fill(E.stream, E.stream + SPMV_N_VERTICES, -1);
-    if (multi) {
-        for (int32_t v = 0; v < SPMV_N_VERTICES; ++v)
-            if (v != SPMV_OP_UNPACK) E.tokens.push_back(v);
-        // Table III tokens of the edges whose need does not depend on streams
-        // (in this DAG: only GPU -> CPU edges need synchronisation).
-        for_edges(true, [&](int32_t u, int32_t v) {
-            if (u == SPMV_OP_UNPACK || v == SPMV_OP_UNPACK) return;
-            int32_t rec, wait, none[SPMV_N_VERTICES];
-            std::fill(none, none + SPMV_N_VERTICES, 0);
-            if (edge_sync(u, v, none, rec, wait)) {
-                E.tokens.push_back(rec);
-                E.tokens.push_back(wait);
-            }
-        });
-    } else {
-        E.tokens = {SPMV_OP_START, SPMV_OP_YL, SPMV_OP_END};
-    }
-    std::sort(E.tokens.begin(), E.tokens.end());
-    E.dfs();
+    Prefix p;
+    p.init(multi, n_streams);
+    std::vector<PlanEntry> out;
+    enumerate(p, out);
     auto &v = cache[key];
-    v = std::move(E.out);
+    v = std::move(out);
     return v;
+}
+
+int64_t plan_index(bool multi, int32_t n_streams, const std::vector<int32_t> &order,
+                   const int32_t *stream)
+{
+    static std::mutex mu;
+    static std::map<std::pair<bool, int32_t>, std::map<std::string, int64_t>> cache;
+    auto key_of = [](const std::vector<int32_t> &o, const int32_t *s) {
+        std::string k(o.begin(), o.end());
+        k.push_back(char(-2));
+        for (int32_t v = 0; v < SPMV_N_VERTICES; ++v) k.push_back(char(s[v]));
+        return k;
+    };
+    const auto &space = plan_space(multi, n_streams);
+    std::lock_guard<std::mutex> lock(mu);
+    auto &m = cache[std::make_pair(multi, n_streams)];
+    if (m.empty())
+        for (size_t i = 0; i < space.size(); ++i) m[key_of(space[i].order, space[i].stream)] = int64_t(i);
+    auto f = m.find(key_of(order, stream));
+    return f == m.end() ? -1 : f->second;
 }
 
 }  // namespace spmv

@@ -79,6 +79,38 @@ struct PlanEntry {
     int32_t stream[SPMV_N_VERTICES];
 };
 const std::vector<PlanEntry> &plan_space(bool multi, int32_t n_streams);
+// Index of a complete plan in plan_space(multi, n_streams), -1 if absent.
+int64_t plan_index(bool multi, int32_t n_streams, const std::vector<int32_t> &order,
+                   const int32_t *stream);
+
+// A program prefix P_k built one token at a time (Sec. III-B): next() lists
+// the tokens that may follow -- DAG vertices whose predecessors are placed
+// and Table III tokens whose operands are placed, GPU vertices once per
+// canonical stream -- in ascending token code, then stream.
+struct Prefix {
+    struct Step {
+        int32_t token, stream;   // stream -1 for CPU vertices and sync tokens
+    };
+    bool multi = true;
+    int32_t n_streams = 1;
+    std::vector<int32_t> tokens;            // the token universe, ascending
+    std::vector<int32_t> order;             // placed tokens
+    int32_t stream[SPMV_N_VERTICES];
+    int32_t used = 0;                       // canonical streams in use
+    uint64_t placed = 0;
+
+    void init(bool multi, int32_t n_streams);
+    void clear();
+    void next(std::vector<Step> &out) const;
+    void push(Step s);
+    void pop();
+    bool complete() const { return order.size() == tokens.size(); }
+
+  private:
+    static uint64_t bit(int32_t t) { return uint64_t(1) << t; }
+    bool preds_done(int32_t v) const;
+    bool ready(int32_t t) const;
+};
 
 // ----------------------------------------------------------------- kernels
 // Launchers (spmv_kernels.hip).  All are asynchronous on `s` and launch
