@@ -249,6 +249,60 @@ def serving_section(sp, torch, gen, n_req: int, rate: float, n_mats: int) -> dic
     return out
 
 
+def rules_section(sp, torch, A, P, r, x, sweep_res, replicas, ktune) -> dict:
+    """Design rules from the exhaustive sweep (Sec. IV), the Table V
+    experiment on those times (classes and tree from tree-search subsets,
+    accuracy over the whole space), and one live tree search on the device."""
+    from paper_2203_02530_amd import rules
+    t_all = np.empty(len(sweep_res))
+    for d in sweep_res:
+        t_all[d["index"]] = d["t"]
+    space = rules.plan_space(P, 2)
+    dr = rules.design_rules(space, t_all)
+    y = dr["labels"]["labels"]
+    classes = [{"class": int(c), "n": int((y == c).sum()),
+                "us": [round(float(t_all[y == c].min()) * 1e6, 2),
+                       round(float(t_all[y == c].max()) * 1e6, 2)]} for c in np.unique(y)]
+    top = {}
+    for rs in dr["rules"]:
+        top.setdefault(rs["class"], [])
+        if len(top[rs["class"]]) < 3:
+            top[rs["class"]].append({"samples": rs["samples"], "rules": rs["text"]})
+    table_v = {}
+    for it in (50, 100, 200, 400, 0):
+        res = sp.spmv_mcts_run_table(P, t_all, iterations=it, seed=1)
+        acc = rules.class_accuracy(space, t_all, res["index"])
+        table_v[str(it or len(space))] = round(acc["accuracy"], 3)
+    # live search: rollouts timed on the device over cold replicas
+    plans = [sp.spmv_plan_create(A, P, r, None, None, 2, ktune) for _ in range(replicas)]
+    try:
+        info = sp.spmv_plan_info(plans[0])
+        lo, n = info["lo"], info["n_loc"]
+        halo = sp.spmv_plan_get_i32(plans[0], sp.SPMV_I32_HALO_COLS).astype(np.int64)
+        xs, ys = [], []
+        for p in plans:
+            sp.spmv_plan_inbox(p)[:] = x[halo]
+            xs.append(torch.from_numpy(np.ascontiguousarray(x[lo:lo + n])).cuda())
+            ys.append(torch.empty(n, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        live = sp.spmv_mcts_run(plans, xs, ys, torch.cuda.current_stream(), iterations=200,
+                                seed=2)
+        wall = time.perf_counter() - t0
+    finally:
+        for p in plans:
+            sp.spmv_plan_destroy(p)
+    best_live = int(live["index"][int(np.argmin(live["time"]))])
+    return {"n_classes": len(classes), "classes": classes, "leaves": dr["mln"],
+            "depth": int(dr["tree"].get_depth()) if dr["tree"] is not None else 0,
+            "n_features": len(dr["names"]), "rules_top3": top, "table_v_accuracy": table_v,
+            "live_search": {"iterations": int(live["index"].size), "wall_s": round(wall, 2),
+                            "best_us": round(float(live["time"].min()) * 1e6, 2),
+                            "best_index": best_live,
+                            "best_class_in_sweep": int(y[best_live]),
+                            "sweep_fastest_us": round(float(t_all.min()) * 1e6, 2)}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,6 +322,8 @@ def main() -> int:
     ap.add_argument("--xcd-remap", type=int, default=0)
     ap.add_argument("--fuse-unpack", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-rules", action="store_true",
+                    help="skip design rules, the Table V experiment and the live tree search")
     ap.add_argument("--batch-shares", type=int, default=64,
                     help="rank shares in the batched section (0 = skip it)")
     ap.add_argument("--serve-requests", type=int, default=20000,
@@ -295,7 +351,7 @@ def main() -> int:
     x = w["x"](A.n_cols)
 
     ops = smap = None
-    sweep = None
+    sweep = design = None
     if args.plan == "auto" and P > 1:
         from paper_2203_02530_amd import tune as tuner
         ktune = {"lanes_local": args.lanes, "rows_local": args.rows, "kernel_local": args.kernel,
@@ -309,11 +365,13 @@ def main() -> int:
                                   indices=top, replicas=R0)
         best = tuner.best_plans(again, 1)[0]["index"]
         sweep = tuner.sweep_summary(res)
+        if not args.no_rules:
+            design = rules_section(sp, torch, A, P, r, x, res, R0, ktune)
         sweep["chosen_index"] = best
         ops, smap = sp.spmv_plan_space_get(P, 2, best)
     elif args.plan not in ("auto", "default"):
         ops, smap = sp.spmv_plan_space_get(P, 2, int(args.plan))
-    tune = {"flags": sp.SPMV_F_PROFILE, "lanes_local": args.lanes, "lanes_remote": 0,
+    tune = {"flags": 0, "lanes_local": args.lanes, "lanes_remote": 0,
             "rows_local": args.rows, "kernel_local": args.kernel, "chunk_local": args.chunk,
             "xcd_remap": args.xcd_remap, "fuse_unpack": args.fuse_unpack}
 
@@ -358,8 +416,6 @@ def main() -> int:
     sh = stream.cuda_stream
     for i in range(args.warmup):
         sp.spmv_exec(plans[i % R], xs[i % R], ys[i % R], stream)
-    for p in plans:
-        sp.spmv_plan_reset_times(p)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -370,6 +426,14 @@ def main() -> int:
     elapsed = time.perf_counter() - t0
     ms_step = elapsed / args.steps * 1e3
 
+    # per-step event times inside the plan, from a separate profiled pass
+    # (the event records add host work, so they stay out of the timed loop)
+    for p in plans:
+        sp.spmv_plan_set_profile(p, True)
+        sp.spmv_plan_reset_times(p)
+    for i in range(min(args.steps, 100)):
+        sp.spmv_exec(plans[i % R], xs[i % R], ys[i % R], stream)
+    torch.cuda.synchronize()
     ms = np.zeros(sp.SPMV_N_VERTICES + 1)
     cnt = np.zeros(sp.SPMV_N_VERTICES + 1)
     for p in plans:
@@ -441,6 +505,7 @@ def main() -> int:
                        if kern_us[k] > 0 and B[k] > 0},
         "in_plan_event_us": {k: round(float(v), 3) for k, v in in_plan_us.items()},
         "plan_sweep": sweep,
+        "design_rules": design,
         "plan_order": plan_order,
         "plan_streams": plan_streams,
         "gflops": round(2.0 * (info["nnz_local"] + info["nnz_remote"]) / (ms_step * 1e-3) / 1e9, 3),

@@ -332,6 +332,9 @@ int spmv_plan_get_i32(const spmv_plan_t *plan, int32_t which, int32_t *out, int6
 int spmv_plan_get_f64(spmv_plan_t *plan, int32_t which, double *out, int64_t n);
 /* Zero the per-op timing accumulators of a SPMV_F_PROFILE plan. */
 int spmv_plan_reset_times(spmv_plan_t *plan);
+/* Switch per-op timing (SPMV_F_PROFILE) on (on != 0) or off for later
+ * executions; timing adds two event records per GPU step and copy. */
+int spmv_plan_set_profile(spmv_plan_t *plan, int32_t on);
 
 /* Pinned host buffers owned by the plan: the inbox [n_halo] the caller
  * fills before spmv_exec, and the outbox [n_send] the exec fills. */

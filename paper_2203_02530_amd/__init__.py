@@ -181,6 +181,7 @@ _proto("spmv_plan_time", [_P, _I32, _P, _P, _P, ctypes.c_double, _I32, _P])
 _proto("spmv_plan_get_i32", [_P, _I32, _P, _I64])
 _proto("spmv_plan_get_f64", [_P, _I32, _P, _I64])
 _proto("spmv_plan_reset_times", [_P])
+_proto("spmv_plan_set_profile", [_P, _I32])
 _proto("spmv_plan_inbox", [_P, _P, _P])
 _proto("spmv_plan_outbox", [_P, _P, _P])
 _proto("spmv_plan_validate", [_I32, _P, _I32, _P, _I32])
@@ -385,6 +386,10 @@ def spmv_plan_get_f64(plan, which: int) -> np.ndarray:
     out = np.empty(max(n, 1), np.float64)
     _check(_lib.spmv_plan_get_f64(plan, which, out.ctypes.data, out.size))
     return out[:n]
+
+
+def spmv_plan_set_profile(plan, on: bool = True) -> None:
+    _check(_lib.spmv_plan_set_profile(plan, 1 if on else 0))
 
 
 def spmv_plan_reset_times(plan) -> None:

@@ -680,6 +680,24 @@ extern "C" int spmv_plan_get_f64(spmv_plan_t *p, int32_t which, double *out, int
     return SPMV_OK;
 }
 
+extern "C" int spmv_plan_set_profile(spmv_plan_t *p, int32_t on)
+{
+    if (!p) return set_error(SPMV_EINVAL, "plan is NULL");
+    if (p->host_only) return set_error(SPMV_ESTATE, "plan was created host-only");
+    if (on && !p->ev_b[0]) {
+        int dev = 0;
+        SPMV_HIP(hipGetDevice(&dev));
+        if (dev != p->device) SPMV_HIP(hipSetDevice(p->device));
+        for (int i = 0; i <= SPMV_N_VERTICES; ++i) {
+            SPMV_HIP(hipEventCreate(&p->ev_b[i]));
+            SPMV_HIP(hipEventCreate(&p->ev_e[i]));
+        }
+        if (dev != p->device) SPMV_HIP(hipSetDevice(dev));
+    }
+    p->profile = on != 0;
+    return SPMV_OK;
+}
+
 extern "C" int spmv_plan_reset_times(spmv_plan_t *p)
 {
     if (!p) return set_error(SPMV_EINVAL, "plan is NULL");
