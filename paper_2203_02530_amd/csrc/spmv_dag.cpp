@@ -359,7 +359,7 @@ void Prefix::pop()
     const int32_t t = order.back();
     order.pop_back();
     placed &= ~bit(t);
-    if (stream[t] >= 0) {
+    if (is_vertex(t) && stream[t] >= 0) {   // sync tokens carry no stream
         if (stream[t] == used - 1) {
             bool again = false;   // still used by an earlier vertex?
             for (int32_t o : order)

@@ -202,3 +202,24 @@ def test_library_search_errors():
         sp.spmv_mcts_run_table(4, cost, iterations=-1)
     with pytest.raises(sp.SpmvError):
         sp.spmv_mcts_run_table(4, cost, n_streams=99)
+
+
+def test_device_search_on_host_only_plans_is_an_error():
+    """The device search needs executable plans: host-only plans give
+    SPMV_ESTATE from the first rollout's timing (and nothing is corrupted on
+    the way: the prefix undo of a synchronisation token touches no stream)."""
+    import gen
+    A = gen.banded_uniform(2000, 7, 300, seed=4)
+    plans = [sp.spmv_plan_create(A, 4, 1, None, None, 2, {"flags": sp.SPMV_F_HOST_ONLY})
+             for _ in range(2)]
+    try:
+        xs = [np.zeros(500) for _ in plans]
+        ys = [np.zeros(500) for _ in plans]
+        with pytest.raises(sp.SpmvError) as e:
+            sp.spmv_mcts_run(plans, xs, ys, None, iterations=5, seed=5, t_measure=0.001)
+        assert e.value.code == sp.SPMV_ESTATE
+        # the enumeration itself is unchanged
+        assert sp.spmv_plan_space_count(4, 3) == 504 * 5
+    finally:
+        for p in plans:
+            sp.spmv_plan_destroy(p)
