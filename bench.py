@@ -37,7 +37,7 @@ MALL_BYTES = 256 << 20         # Infinity Cache
 # known size), keyed by workload and kernel variant; a variant that is not
 # listed (or a kernel changed since) reports null.
 MEASURED_TRAFFIC = {
-    ("laplace3d_128_p4r1", "k_csr_stream<4,2,1>"): 56_460_000,
+    ("laplace3d_128_p4r1", "k_sell<8>"): 54_290_000,
 }
 
 
@@ -77,6 +77,8 @@ def replicas_for(A, P, r, tune, sp) -> int:
 
 
 def kernel_variant(info: dict) -> str:
+    if info["kernel_local"] == 2 and info["form_local"] == 2:
+        return "k_sell<%d>" % info["chunk_local"]
     if info["kernel_local"] == 2:
         return "k_csr_stream<%d,%d,%d>" % (info["chunk_local"], info["width"], info["lanes_local"])
     return "k_csr_vector_buf<%d,%d>" % (info["lanes_local"], info["rows_local"])
@@ -129,7 +131,8 @@ def batched_section(sp, torch, gen, n_shares: int, reps: int) -> dict:
     one batch: grouped persistent kernels inside one hipGraph, against the
     same shares run one spmv_exec after another."""
     plans, xs, ys = [], [], []
-    tune = {"kernel_local": 2, "kernel_remote": 2, "chunk_local": 8, "chunk_remote": 8, "width": 2}
+    tune = {"kernel_local": 2, "kernel_remote": 2, "chunk_local": 8, "chunk_remote": 8, "width": 2,
+            "form": 1}
     t_gen = time.perf_counter()
     for i in range(n_shares):
         d = gen.power_law_share(4_000_000, 16, 5, seed=4000 + i)
@@ -488,7 +491,9 @@ def main() -> int:
                    "nranks": P, "rank": r, "n_loc": n, "nnz_local": info["nnz_local"],
                    "nnz_remote": info["nnz_remote"], "n_halo": info["n_halo"],
                    "plan": args.plan, "kernel_local": info["kernel_local"],
-                   "chunk_local": info["chunk_local"], "n_tiles_local": info["n_tiles_local"],
+                   "chunk_local": info["chunk_local"], "form_local": info["form_local"],
+                   "n_tiles_local": info["n_tiles_local"],
+                   "n_slices_local": info["n_slices_local"],
                    "lanes_local": info["lanes_local"],
                    "rows_local": info["rows_local"], "lanes_remote": info["lanes_remote"],
                    "rows_remote": info["rows_remote"], "xcd_remap": info["xcd_remap"],

@@ -137,6 +137,15 @@ typedef struct {
                               receive buffer directly (valid because the
                               receive layout equals the halo order)          */
     int32_t flags;         /* SPMV_F_* below                               */
+    int32_t form;          /* stream: 1 = packed tiles (rows cut to fill
+                              each window), 2 = sliced ELL (a wave per 64
+                              rows, entries stored column-major per slice,
+                              each row an fma chain; taken only when padding
+                              stays within 15%, else packed tiles; chunk =
+                              entries per batch of loads: 4, 8, 16), 0 =
+                              auto: sliced when every slice of 64 rows has
+                              the same width of at most 8, else packed.
+                              Plans in sliced form cannot join a batch.     */
 } spmv_tune_t;
 
 #define SPMV_F_HOST_ONLY  1  /* build metadata only: no device resources;
@@ -168,7 +177,11 @@ typedef struct {
     int32_t xcd_remap, fuse_unpack;
     int32_t fused_combine; /* 1: y_R adds into y itself; 0: a combine step
                               at end adds the remote partial sums            */
-    int32_t n_tiles_local, n_tiles_remote;  /* stream CSR tiles (0: vector) */
+    int32_t n_tiles_local, n_tiles_remote;  /* packed stream tiles (0: none) */
+    int32_t form_local;    /* y_L stream form: 1 packed tiles, 2 sliced ELL,
+                              0 vector CSR                                   */
+    int32_t form_remote;   /* same for y_R                                   */
+    int32_t n_slices_local, n_slices_remote;  /* sliced-ELL slices (0: none) */
     int32_t reserved;
 } spmv_info_t;
 

@@ -85,7 +85,7 @@ class spmv_tune_t(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int32) for k in (
         "kernel_local", "kernel_remote", "lanes_local", "lanes_remote", "rows_local",
         "rows_remote", "chunk_local", "chunk_remote", "width", "xcd_remap", "fuse_unpack",
-        "flags")]
+        "flags", "form")]
 
 
 class spmv_batch_opts_t(ctypes.Structure):
@@ -152,7 +152,8 @@ class spmv_info_t(ctypes.Structure):
             "nranks", "rank", "n_streams", "n_ops", "kernel_local", "kernel_remote",
             "lanes_local", "lanes_remote", "rows_local", "rows_remote", "chunk_local",
             "chunk_remote", "width", "xcd_remap", "fuse_unpack", "fused_combine",
-            "n_tiles_local", "n_tiles_remote", "reserved")]
+            "n_tiles_local", "n_tiles_remote", "form_local", "form_remote",
+            "n_slices_local", "n_slices_remote", "reserved")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -361,10 +362,10 @@ _I32_LEN = {
     SPMV_I32_AR_PTR: lambda i: i["n_remote_rows"] + 1,
     SPMV_I32_AR_COLS: lambda i: i["nnz_remote"], SPMV_I32_UNPACK_PERM: lambda i: i["n_halo"],
     SPMV_I32_OP_ORDER: lambda i: i["n_ops"], SPMV_I32_STREAM_MAP: lambda i: SPMV_N_VERTICES,
-    SPMV_I32_TILE_ROW_L: lambda i: i["n_tiles_local"] + 1 if i["kernel_local"] == 2 else 0,
-    SPMV_I32_TILE_K_L: lambda i: i["n_tiles_local"] + 1 if i["kernel_local"] == 2 else 0,
-    SPMV_I32_TILE_ROW_R: lambda i: i["n_tiles_remote"] + 1 if i["kernel_remote"] == 2 else 0,
-    SPMV_I32_TILE_K_R: lambda i: i["n_tiles_remote"] + 1 if i["kernel_remote"] == 2 else 0,
+    SPMV_I32_TILE_ROW_L: lambda i: i["n_tiles_local"] + 1 if i["form_local"] == 1 else 0,
+    SPMV_I32_TILE_K_L: lambda i: i["n_tiles_local"] + 1 if i["form_local"] == 1 else 0,
+    SPMV_I32_TILE_ROW_R: lambda i: i["n_tiles_remote"] + 1 if i["form_remote"] == 1 else 0,
+    SPMV_I32_TILE_K_R: lambda i: i["n_tiles_remote"] + 1 if i["form_remote"] == 1 else 0,
 }
 _F64_LEN = {
     SPMV_F64_AL_VAL: lambda i: i["nnz_local"], SPMV_F64_AR_VAL: lambda i: i["nnz_remote"],

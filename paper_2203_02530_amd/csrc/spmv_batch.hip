@@ -322,10 +322,10 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
                                               " is host-only or on another device");
         for (int side = 0; side < 2; ++side)
             if (p->cfg[side].kernel != SPMV_KERNEL_STREAM || p->cfg[side].chunk != npt ||
-                p->cfg[side].width != vw)
+                p->cfg[side].width != vw || p->cfg[side].form != 1)
                 return set_error(SPMV_EINVAL, "plan " + std::to_string(i) +
-                                                  ": batched shares need stream-CSR products "
-                                                  "with one common chunk and width");
+                                                  ": batched shares need packed-tile stream-CSR "
+                                                  "products with one common chunk and width");
     }
     const int dev = plans[0]->device;
     int cur_dev = 0;

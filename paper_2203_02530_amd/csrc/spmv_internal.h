@@ -126,6 +126,12 @@ struct CsrDev {
     // CSR-stream tiles: [tile_row[t], tile_row[t+1]) rows, entries from tile_k[t]
     const int32_t *tile_row = nullptr, *tile_k = nullptr;
     int32_t n_tiles = 0;
+    // sliced ELL (form 2): col/val hold the sliced layout, sell_ptr[s] is
+    // the first entry of slice s (64 rows), n_slices slices, U entries per
+    // batch of loads
+    const int32_t *sell_ptr = nullptr;
+    int32_t n_slices = 0, sell_u = 0;
+    int32_t sell_width = 0;        // > 0: every slice this wide (sell_ptr unused)
 };
 
 // Entries of padding after col/val on the device (vector loads of the
@@ -143,8 +149,21 @@ hipError_t launch_combine(const int32_t *rows, const double *part, double *y, in
                           hipStream_t s);
 hipError_t launch_csr_stream(const CsrDev &A, const double *x, double *out, double *acc,
                              int npt, int vw, int sum_lanes, int xcd_remap, hipStream_t s);
+// Sliced-ELL product (CsrDev.sell_ptr set): one wave per slice of 64 rows.
+hipError_t launch_sell(const CsrDev &A, const double *x, double *out, double *acc,
+                       int xcd_remap, hipStream_t s);
 int stream_cap(int npt);
 int stream_maxr(int sum_lanes);
+// Sliced ELL with slices of 64 rows (one wave): entry v of row 64 s + l is
+// stored at ptr[s] + 64 v + l, a slice as wide as its longest row (or every
+// slice as wide as the longest row, `uniform`, when that padding fits too),
+// padding entries column -1 and value 0.  Returns false, leaving the
+// outputs empty, when the padded size exceeds max_ratio times the entries
+// or 32-bit offsets would overflow.
+bool build_sell(const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
+                const std::vector<double> &val, int64_t n_rows, double max_ratio,
+                std::vector<int32_t> &ptr, std::vector<int32_t> &scol, std::vector<double> &sval,
+                int32_t &max_width, bool &uniform);
 // Cut [0, n_rows) into CSR-stream tiles (host).
 void build_tiles(const std::vector<int32_t> &rp, int64_t n_rows, int cap, int maxr, int vw,
                  std::vector<int32_t> &tile_row, std::vector<int32_t> &tile_k);
@@ -181,6 +200,11 @@ struct CsrCfg {
     int32_t kernel = SPMV_KERNEL_VECTOR;
     int32_t lanes = 1, rows = 1;   // vector CSR
     int32_t chunk = 8, width = 2;  // stream CSR (lanes = summing lanes)
+    int32_t form = 1;              // stream: 1 packed tiles, 2 sliced ELL
+    std::vector<int32_t> sell_ptr, sell_col;   // form 2, host copies for upload
+    std::vector<double> sell_val;
+    int32_t sell_width = 0;
+    bool sell_uniform = false;
     std::vector<int32_t> tile_row, tile_k;
 };
 }  // namespace spmv
@@ -204,6 +228,7 @@ struct spmv_plan {
     int32_t *d_send_idx = nullptr, *d_perm = nullptr;
     double *d_sendbuf = nullptr, *d_recvbuf = nullptr, *d_xhalo = nullptr, *d_part = nullptr;
     int32_t *d_tile_row[2] = {}, *d_tile_k[2] = {};
+    int32_t *d_sell_ptr[2] = {};
 
     // pinned host mailboxes
     double *h_inbox = nullptr, *h_outbox = nullptr;

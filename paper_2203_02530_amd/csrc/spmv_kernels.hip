@@ -185,6 +185,67 @@ __global__ __launch_bounds__(kBlock) void k_csr_stream(StreamArgs A, int remap)
     stream_tile<NPT, VW, SL>(A, tile_of_block(int(blockIdx.x), int(gridDim.x), remap), s_p, s_rp);
 }
 
+// Sliced-ELL product: one wave per slice of 64 rows; lane l owns row
+// 64 s + l and walks its entries in order, U at a time with all their loads
+// in flight.  The v-th entries of a slice are contiguous (one 256-byte
+// column load and one 512-byte value load per wave), and for banded and
+// stencil matrices so are the x values they gather.  Padding entries carry
+// column -1 and are skipped, so no row length is read.  With one width for
+// all slices (width > 0) the slice offsets are computed, not loaded, and the
+// first loads of a wave depend on nothing but its index.  Each row is an fma
+// chain in entry order.
+struct SellArgs {
+    const int32_t *ptr, *col, *rows;
+    const double *val, *x;
+    double *out, *acc;
+    int32_t n_rows, n_slices, width;
+    uint32_t n_alloc, n_x;
+};
+
+template <int U>
+__global__ __launch_bounds__(kBlock) void k_sell(SellArgs A, int remap)
+{
+    constexpr int kWaves = kBlock / 64;
+    const int q = tile_of_block(int(blockIdx.x), int(gridDim.x), remap);
+    const int slice = q * kWaves + int(threadIdx.x >> 6);
+    if (slice >= A.n_slices) return;   // whole waves; no barrier below
+    const int lane = int(threadIdx.x & 63);
+    const int r = slice * 64 + lane;
+    const auto r_col = rsrc(A.col, A.n_alloc * 4u);
+    const auto r_val = rsrc(A.val, A.n_alloc * 8u);
+    const auto r_x = rsrc(A.x, A.n_x * 8u);
+    const int off = A.width > 0 ? slice * 64 * A.width : A.ptr[slice];
+    const int w = A.width > 0 ? A.width : (A.ptr[slice + 1] - off) >> 6;
+    double s = 0.0;
+    for (int v0 = 0; v0 < w; v0 += U) {
+        int32_t c[U];
+        double a[U], xv[U];
+        // columns first: the x gathers wait only for them, and the values
+        // arrive while the gathers are in flight
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            c[u] = v0 + u < w ? int32_t(__builtin_amdgcn_raw_buffer_load_b32(
+                                    r_col, uint32_t(off + (v0 + u) * 64 + lane) * 4u, 0, 2))
+                              : -1;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            a[u] = v0 + u < w ? __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                    r_val, uint32_t(off + (v0 + u) * 64 + lane) * 8u, 0, 2))
+                              : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = load_x(r_x, c[u] >= 0 ? uint32_t(c[u]) * 8u : kOff);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (c[u] >= 0) s = fma(a[u], xv[u], s);
+    }
+    if (r < A.n_rows) {
+        if (A.acc)
+            A.acc[A.rows[r]] += s;
+        else
+            A.out[r] = s;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_gather(const double *__restrict__ src,
                                                    const int32_t *__restrict__ idx,
                                                    double *__restrict__ dst, int64_t n)
@@ -316,6 +377,34 @@ hipError_t launch_combine(const int32_t *rows, const double *part, double *y, in
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_combine, dim3(grid_for(n)), dim3(kBlock), 0, s, rows, part, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sell(const CsrDev &A, const double *x, double *out, double *acc,
+                       int xcd_remap, hipStream_t s)
+{
+    if (A.n_slices <= 0) return hipSuccess;
+    SellArgs a;
+    a.ptr = A.sell_ptr;
+    a.col = A.col;
+    a.rows = A.rows;
+    a.val = A.val;
+    a.x = x;
+    a.out = out;
+    a.acc = acc;
+    a.n_rows = A.n_rows;
+    a.n_slices = A.n_slices;
+    a.width = A.sell_width;
+    a.n_alloc = uint32_t(A.nnz_alloc);
+    a.n_x = uint32_t(A.n_x);
+    const unsigned grid = unsigned((A.n_slices + kBlock / 64 - 1) / (kBlock / 64));
+    const int remap = xcd_remap == 2 ? 0 : 1;
+    switch (A.sell_u) {
+        case 4: hipLaunchKernelGGL(k_sell<4>, dim3(grid), dim3(kBlock), 0, s, a, remap); break;
+        case 8: hipLaunchKernelGGL(k_sell<8>, dim3(grid), dim3(kBlock), 0, s, a, remap); break;
+        case 16: hipLaunchKernelGGL(k_sell<16>, dim3(grid), dim3(kBlock), 0, s, a, remap); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

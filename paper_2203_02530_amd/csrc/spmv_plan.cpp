@@ -85,20 +85,36 @@ int allocate_and_upload(spmv_plan *p)
     };
     const size_t n_halo = S.halo.size(), n_send = S.send_idx.size(), n_rr = S.R_rows.size();
     const size_t pad = kEntryPad;
+    // col/val of each product: the CSR arrays, or the sliced layout (form 2)
+    auto sliced = [&](int side) { return p->cfg[side].form == 2; };
+    auto colsz = [&](int side) {
+        return (sliced(side) ? p->cfg[side].sell_col.size()
+                             : (side == 0 ? S.L_col.size() : S.R_col.size())) * 4;
+    };
+    auto coldata = [&](int side) -> const void * {
+        return sliced(side) ? p->cfg[side].sell_col.data()
+                            : (side == 0 ? S.L_col.data() : S.R_col.data());
+    };
+    auto valdata = [&](int side) -> const void * {
+        return sliced(side) ? p->cfg[side].sell_val.data()
+                            : (side == 0 ? S.L_val.data() : S.R_val.data());
+    };
     Item items[] = {
         {(void **)&p->dL_ptr, S.L_ptr.size() * 4, S.L_ptr.data(), 0},
-        {(void **)&p->dL_col, S.L_col.size() * 4, S.L_col.data(), pad * 4},
+        {(void **)&p->dL_col, colsz(0), coldata(0), pad * 4},
         {(void **)&p->dR_rows, S.R_rows.size() * 4, S.R_rows.data(), 0},
         {(void **)&p->dR_ptr, S.R_ptr.size() * 4, S.R_ptr.data(), 0},
-        {(void **)&p->dR_col, S.R_col.size() * 4, S.R_col.data(), pad * 4},
+        {(void **)&p->dR_col, colsz(1), coldata(1), pad * 4},
         {(void **)&p->d_send_idx, n_send * 4, S.send_idx.data(), 0},
         {(void **)&p->d_perm, n_halo * 4, S.unpack_perm.data(), 0},
         {(void **)&p->d_tile_row[0], p->cfg[0].tile_row.size() * 4, p->cfg[0].tile_row.data(), 0},
         {(void **)&p->d_tile_k[0], p->cfg[0].tile_k.size() * 4, p->cfg[0].tile_k.data(), 0},
         {(void **)&p->d_tile_row[1], p->cfg[1].tile_row.size() * 4, p->cfg[1].tile_row.data(), 0},
         {(void **)&p->d_tile_k[1], p->cfg[1].tile_k.size() * 4, p->cfg[1].tile_k.data(), 0},
-        {(void **)&p->dL_val, S.L_val.size() * 8, S.L_val.data(), pad * 8},
-        {(void **)&p->dR_val, S.R_val.size() * 8, S.R_val.data(), pad * 8},
+        {(void **)&p->d_sell_ptr[0], p->cfg[0].sell_ptr.size() * 4, p->cfg[0].sell_ptr.data(), 0},
+        {(void **)&p->d_sell_ptr[1], p->cfg[1].sell_ptr.size() * 4, p->cfg[1].sell_ptr.data(), 0},
+        {(void **)&p->dL_val, colsz(0) * 2, valdata(0), pad * 8},
+        {(void **)&p->dR_val, colsz(1) * 2, valdata(1), pad * 8},
         {(void **)&p->d_sendbuf, n_send * 8, nullptr, 0},
         {(void **)&p->d_recvbuf, n_halo * 8, nullptr, 0},
         {(void **)&p->d_xhalo, n_halo * 8, nullptr, 0},
@@ -183,9 +199,17 @@ CsrDev remote_csr(const spmv_plan *p)
     return A;
 }
 
+// The padding a sliced layout may add (padded entries / entries), and the
+// widest rows for which the automatic choice takes the sliced form: on the
+// 7-point share (rows <= 7, one width for all slices) it ran y_L in 10.8 us
+// against 11.7 for packed tiles; on the 27-point share packed tiles won
+// (25.3 vs 28.2 us).
+constexpr double kSellMaxRatio = 1.15;
+constexpr int32_t kAutoSellWidth = 8;
+
 // Resolve the automatic choices for one product and cut its stream tiles.
 void configure(CsrCfg &c, const std::vector<int32_t> &rp, int64_t n_rows, int32_t kernel,
-               int32_t lanes, int32_t rows, int32_t chunk, int32_t width)
+               int32_t lanes, int32_t rows, int32_t chunk, int32_t width, int32_t form)
 {
     const int64_t nnz = n_rows > 0 ? rp[size_t(n_rows)] : 0;
     // Stream CSR measured faster than vector CSR on the stencil shares
@@ -221,6 +245,33 @@ void configure(CsrCfg &c, const std::vector<int32_t> &rp, int64_t n_rows, int32_
     }
     build_tiles(rp, n_rows, stream_cap(c.chunk), stream_maxr(c.lanes), c.width, c.tile_row,
                 c.tile_k);
+    c.form = form;   // 0 = automatic, resolved by select_sell
+}
+
+// Sliced ELL for a stream product when its form asks for it (2) and its
+// rows are even enough (padding within kSellMaxRatio), or when the form is
+// automatic (0) and moreover every slice has one width of at most
+// kAutoSellWidth; otherwise packed tiles stay.  U (entries per batch of
+// loads) is the chunk when given, else the smallest of 4, 8, 16 that covers
+// the widest slice (16 beyond).
+void select_sell(CsrCfg &c, const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
+                 const std::vector<double> &val, int64_t n_rows, int32_t chunk)
+{
+    const bool ask = c.kernel == SPMV_KERNEL_STREAM && c.form != 1;
+    const bool ok = ask && build_sell(rp, col, val, n_rows, kSellMaxRatio, c.sell_ptr,
+                                      c.sell_col, c.sell_val, c.sell_width, c.sell_uniform);
+    if (!ok || (c.form == 0 && !(c.sell_uniform && c.sell_width <= kAutoSellWidth))) {
+        c.form = 1;
+        c.sell_ptr.clear();
+        c.sell_col.clear();
+        c.sell_val.clear();
+        return;
+    }
+    c.form = 2;
+    c.chunk = chunk ? chunk : c.sell_width <= 4 ? 4 : c.sell_width <= 8 ? 8 : 16;
+    c.lanes = 1;
+    c.tile_row.clear();
+    c.tile_k.clear();
 }
 
 hipError_t launch_product(const spmv_plan *p, int side, const double *x, double *out,
@@ -228,6 +279,14 @@ hipError_t launch_product(const spmv_plan *p, int side, const double *x, double 
 {
     CsrDev A = side == 0 ? local_csr(p) : remote_csr(p);
     const CsrCfg &c = p->cfg[side];
+    if (c.kernel == SPMV_KERNEL_STREAM && c.form == 2) {
+        A.sell_ptr = p->d_sell_ptr[side];
+        A.n_slices = int32_t(c.sell_ptr.size()) - 1;
+        A.sell_u = c.chunk;
+        A.sell_width = c.sell_uniform ? c.sell_width : 0;
+        A.nnz_alloc = int64_t(c.sell_col.size()) + kEntryPad;
+        return launch_sell(A, x, out, acc, p->xcd_remap, s);
+    }
     if (c.kernel == SPMV_KERNEL_STREAM) {
         A.tile_row = p->d_tile_row[side];
         A.tile_k = p->d_tile_k[side];
@@ -268,6 +327,7 @@ int create_plan(Build build_share_fn, int32_t nranks, const int32_t *op_order, i
         return set_error(SPMV_EINVAL, "width must be 0, 2 or 4");
     if (t.xcd_remap < 0 || t.xcd_remap > 2 || t.fuse_unpack < 0 || t.fuse_unpack > 1)
         return set_error(SPMV_EINVAL, "tune field out of range");
+    if (t.form < 0 || t.form > 2) return set_error(SPMV_EINVAL, "form must be 0, 1 or 2");
 
     std::vector<int32_t> def_ops;
     int32_t def_map[SPMV_N_VERTICES];
@@ -300,9 +360,11 @@ int create_plan(Build build_share_fn, int32_t nranks, const int32_t *op_order, i
         }
     }
     configure(p->cfg[0], S.L_ptr, S.n_loc, t.kernel_local, t.lanes_local, t.rows_local,
-              t.chunk_local, t.width);
+              t.chunk_local, t.width, t.form);
     configure(p->cfg[1], S.R_ptr, int64_t(S.R_rows.size()), t.kernel_remote, t.lanes_remote,
-              t.rows_remote, t.chunk_remote, t.width);
+              t.rows_remote, t.chunk_remote, t.width, t.form);
+    select_sell(p->cfg[0], S.L_ptr, S.L_col, S.L_val, S.n_loc, t.chunk_local);
+    select_sell(p->cfg[1], S.R_ptr, S.R_col, S.R_val, int64_t(S.R_rows.size()), t.chunk_remote);
     p->xcd_remap = t.xcd_remap ? t.xcd_remap : 1;
     p->fuse_unpack = t.fuse_unpack == 1;
     p->host_only = (t.flags & SPMV_F_HOST_ONLY) != 0;
@@ -606,10 +668,18 @@ extern "C" int spmv_plan_info(const spmv_plan_t *p, spmv_info_t *info)
     info->chunk_local = p->cfg[0].chunk;
     info->chunk_remote = p->cfg[1].chunk;
     info->width = p->cfg[0].kernel == SPMV_KERNEL_STREAM ? p->cfg[0].width : p->cfg[1].width;
-    info->n_tiles_local = p->cfg[0].kernel == SPMV_KERNEL_STREAM
-                              ? int32_t(p->cfg[0].tile_row.size()) - 1 : 0;
-    info->n_tiles_remote = p->cfg[1].kernel == SPMV_KERNEL_STREAM
-                               ? int32_t(p->cfg[1].tile_row.size()) - 1 : 0;
+    auto tiles = [](const CsrCfg &c) {
+        return c.kernel == SPMV_KERNEL_STREAM && c.form == 1 ? int32_t(c.tile_row.size()) - 1 : 0;
+    };
+    auto slices = [](const CsrCfg &c) {
+        return c.kernel == SPMV_KERNEL_STREAM && c.form == 2 ? int32_t(c.sell_ptr.size()) - 1 : 0;
+    };
+    info->n_tiles_local = tiles(p->cfg[0]);
+    info->n_tiles_remote = tiles(p->cfg[1]);
+    info->n_slices_local = slices(p->cfg[0]);
+    info->n_slices_remote = slices(p->cfg[1]);
+    info->form_local = p->cfg[0].kernel == SPMV_KERNEL_STREAM ? p->cfg[0].form : 0;
+    info->form_remote = p->cfg[1].kernel == SPMV_KERNEL_STREAM ? p->cfg[1].form : 0;
     info->xcd_remap = p->xcd_remap;
     info->fuse_unpack = p->fuse_unpack;
     info->fused_combine = p->fused_combine;

@@ -355,6 +355,7 @@ extern "C" int spmv_server_add_matrix(spmv_server_t *s, const spmv_csr_t *csr, i
     t.chunk_local = s->o.chunk;
     t.chunk_remote = s->o.chunk;
     t.width = 2;
+    t.form = 1;   // the serving kernel walks packed tiles
     // budget check before allocating: matrix + room for one request on it
     spmv_tune_t th = t;
     th.flags = SPMV_F_HOST_ONLY;

@@ -255,4 +255,48 @@ void build_tiles(const std::vector<int32_t> &rp, int64_t n_rows, int cap, int ma
     tile_k.push_back(n_rows > 0 ? rp[size_t(n_rows)] : (rp.empty() ? 0 : rp[0]));
 }
 
+bool build_sell(const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
+                const std::vector<double> &val, int64_t n_rows, double max_ratio,
+                std::vector<int32_t> &ptr, std::vector<int32_t> &scol, std::vector<double> &sval,
+                int32_t &max_width, bool &uniform)
+{
+    ptr.clear();
+    scol.clear();
+    sval.clear();
+    max_width = 0;
+    uniform = false;
+    const int64_t n_slices = (n_rows + 63) / 64;
+    const int64_t nnz = n_rows > 0 ? rp[size_t(n_rows)] : 0;
+    std::vector<int64_t> width(size_t(n_slices), 0);
+    for (int64_t sl = 0; sl < n_slices; ++sl) {
+        for (int64_t r = sl * 64; r < std::min(n_rows, sl * 64 + 64); ++r)
+            width[size_t(sl)] = std::max<int64_t>(width[size_t(sl)], rp[size_t(r) + 1] - rp[size_t(r)]);
+        max_width = int32_t(std::max<int64_t>(max_width, width[size_t(sl)]));
+    }
+    const double budget = max_ratio * double(std::max<int64_t>(nnz, 1));
+    // one width for every slice (no per-slice offsets to read) when that
+    // padding fits too
+    uniform = double(64 * max_width) * double(n_slices) <= budget;
+    if (uniform) std::fill(width.begin(), width.end(), int64_t(max_width));
+    std::vector<int64_t> off(size_t(n_slices) + 1, 0);
+    for (int64_t sl = 0; sl < n_slices; ++sl) off[size_t(sl) + 1] = off[size_t(sl)] + 64 * width[size_t(sl)];
+    const int64_t total = off[size_t(n_slices)];
+    if (double(total) > budget || (total + 64) * 8 >= (int64_t(1) << 32)) {
+        uniform = false;
+        return false;
+    }
+    ptr.assign(off.begin(), off.end());
+    scol.assign(size_t(total), -1);
+    sval.assign(size_t(total), 0.0);
+    for (int64_t r = 0; r < n_rows; ++r) {
+        const int64_t sl = r / 64, l = r % 64;
+        for (int64_t k = rp[size_t(r)]; k < rp[size_t(r) + 1]; ++k) {
+            const int64_t v = k - rp[size_t(r)];
+            scol[size_t(off[size_t(sl)] + 64 * v + l)] = col[size_t(k)];
+            sval[size_t(off[size_t(sl)] + 64 * v + l)] = val[size_t(k)];
+        }
+    }
+    return true;
+}
+
 }  // namespace spmv

@@ -63,6 +63,37 @@ __device__ __forceinline__ void load_vec(__amdgpu_buffer_rsrc_t rc, __amdgpu_buf
     }
 }
 
+// The two halves of load_vec, so that a caller can issue all columns first.
+template <int VW>
+__device__ __forceinline__ void load_cols(__amdgpu_buffer_rsrc_t rc, uint32_t e, int32_t *c)
+{
+    const uint32_t oc = e == kNoEntry ? kOff : e * 4u;
+    if constexpr (VW == 2) {
+        const auto cc = __builtin_amdgcn_raw_buffer_load_b64(rc, oc, 0, 2);
+        c[0] = int32_t(cc[0]);
+        c[1] = int32_t(cc[1]);
+    } else {
+        static_assert(VW == 4, "VW must be 2 or 4");
+        const auto cc = __builtin_amdgcn_raw_buffer_load_b128(rc, oc, 0, 2);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[j] = int32_t(cc[j]);
+    }
+}
+
+template <int VW>
+__device__ __forceinline__ void load_vals(__amdgpu_buffer_rsrc_t rv, uint32_t e, double *a)
+{
+    const uint32_t ov = e == kNoEntry ? kOff : e * 8u;
+    const auto v0 = __builtin_amdgcn_raw_buffer_load_b128(rv, ov, 0, 2);
+    a[0] = __builtin_bit_cast(double, (uint64_t(v0[1]) << 32) | v0[0]);
+    a[1] = __builtin_bit_cast(double, (uint64_t(v0[3]) << 32) | v0[2]);
+    if constexpr (VW == 4) {
+        const auto v1 = __builtin_amdgcn_raw_buffer_load_b128(rv, ov == kOff ? kOff : ov + 16u, 0, 2);
+        a[2] = __builtin_bit_cast(double, (uint64_t(v1[1]) << 32) | v1[0]);
+        a[3] = __builtin_bit_cast(double, (uint64_t(v1[3]) << 32) | v1[2]);
+    }
+}
+
 __device__ __forceinline__ double load_x(__amdgpu_buffer_rsrc_t rx, uint32_t off)
 {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rx, off, 0, 0));
@@ -76,6 +107,108 @@ struct StreamArgs {
     double *out, *acc;
     uint32_t nnz_alloc, n_x;
 };
+
+// Registers of one short-row tile between its stages: window entries,
+// gathered x values, row pointers, and the tile's bounds.
+template <int NPT, int VW>
+struct TileRegs {
+    static constexpr int NV = NPT / VW;
+    int32_t c[NV][VW];
+    double a[NV][VW];
+    double xv[NV][VW];
+    int32_t rp_a, rp_b;
+    int r0, nr, k0, k1, base;
+};
+
+// Stage 1: the tile's bounds, its window's columns and values, then its row
+// pointers.  The two load groups are independent, so their memory latencies
+// overlap (the row pointers wait in registers until the LDS stage).
+template <int NPT, int VW>
+__device__ __forceinline__ void tile_load(const StreamArgs &A, __amdgpu_buffer_rsrc_t r_col,
+                                          __amdgpu_buffer_rsrc_t r_val, int t,
+                                          TileRegs<NPT, VW> &T)
+{
+    const int tid = int(threadIdx.x);
+    T.r0 = A.tile_row[t];
+    T.nr = A.tile_row[t + 1] - T.r0;
+    T.k0 = A.tile_k[t];
+    T.k1 = A.tile_k[t + 1];
+    T.base = T.k0 & ~(VW - 1);
+    // columns of the whole window first, then values: the x gathers wait
+    // only for the columns
+#pragma unroll
+    for (int v = 0; v < T.NV; ++v) {
+        const int e = T.base + (v * kBlock + tid) * VW;
+        load_cols<VW>(r_col, e < T.k1 ? uint32_t(e) : kNoEntry, T.c[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < T.NV; ++v) {
+        const int e = T.base + (v * kBlock + tid) * VW;
+        load_vals<VW>(r_val, e < T.k1 ? uint32_t(e) : kNoEntry, T.a[v]);
+    }
+    // nr + 1 <= kBlock / SL + 1 pointers: one per thread, plus the last one
+    // by thread 0 when the tile has kBlock rows
+    T.rp_a = tid <= T.nr ? A.rp[T.r0 + tid] : 0;
+    T.rp_b = (tid == 0 && T.nr == kBlock) ? A.rp[T.r0 + kBlock] : 0;
+}
+
+// Stage 2: gather x for the window's entries (entries outside the tile read
+// nothing and give 0).
+template <int NPT, int VW>
+__device__ __forceinline__ void tile_gather(__amdgpu_buffer_rsrc_t r_x, TileRegs<NPT, VW> &T)
+{
+    const int tid = int(threadIdx.x);
+#pragma unroll
+    for (int v = 0; v < T.NV; ++v) {
+#pragma unroll
+        for (int j = 0; j < VW; ++j) {
+            const int k = T.base + (v * kBlock + tid) * VW + j;
+            const bool ok = k >= T.k0 && k < T.k1;
+            T.xv[v][j] = load_x(r_x, ok ? uint32_t(T.c[v][j]) * 8u : kOff);
+        }
+    }
+}
+
+// Stage 3: products into LDS, row sums by SL lanes per row in a fixed
+// order, results stored.  Contains one barrier; the caller separates
+// consecutive tiles with another (LDS is reused).
+template <int NPT, int VW, int SL>
+__device__ __forceinline__ void tile_reduce(const StreamArgs &A, const TileRegs<NPT, VW> &T,
+                                            double *s_p, int32_t *s_rp)
+{
+    const int tid = int(threadIdx.x);
+#pragma unroll
+    for (int v = 0; v < T.NV; ++v)
+#pragma unroll
+        for (int j = 0; j < VW; ++j) s_p[(v * kBlock + tid) * VW + j] = T.a[v][j] * T.xv[v][j];
+    if (tid <= T.nr) s_rp[tid] = T.rp_a;
+    if (tid == 0 && T.nr == kBlock) s_rp[kBlock] = T.rp_b;
+    __syncthreads();
+
+    const int g = tid / SL, lane = tid % SL;
+    double s = 0.0;
+    if (g < T.nr) {
+        // left-to-right sum of the row's products owned by this lane; four
+        // LDS reads are issued together, the additions keep their order
+        const int b = s_rp[g] - T.base, e = s_rp[g + 1] - T.base;
+        int k = b + lane;
+        for (; k + 3 * SL < e; k += 4 * SL) {
+            const double p0 = s_p[k], p1 = s_p[k + SL], p2 = s_p[k + 2 * SL], p3 = s_p[k + 3 * SL];
+            s += p0;
+            s += p1;
+            s += p2;
+            s += p3;
+        }
+        for (; k < e; k += SL) s += s_p[k];
+    }
+    s = group_sum<SL>(s);
+    if (lane == SL - 1 && g < T.nr) {
+        if (A.acc)
+            A.acc[A.rows[T.r0 + g]] += s;
+        else
+            A.out[T.r0 + g] = s;
+    }
+}
 
 // One tile.  s_p: LDS[kBlock * NPT] doubles, s_rp: LDS[kBlock / SL + 1] ints.
 // Block-uniform control flow; the caller separates consecutive tiles with a
@@ -127,40 +260,10 @@ __device__ __forceinline__ void stream_tile(const StreamArgs &A, int t, double *
         return;
     }
 
-    for (int i = tid; i <= r1 - r0; i += kBlock) s_rp[i] = A.rp[r0 + i];
-    int32_t c[NV][VW];
-    double a[NV][VW];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const int e = base + (v * kBlock + tid) * VW;
-        load_vec<VW>(r_col, r_val, e < k1 ? uint32_t(e) : kNoEntry, c[v], a[v]);
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-#pragma unroll
-        for (int j = 0; j < VW; ++j) {
-            const int k = base + (v * kBlock + tid) * VW + j;
-            const bool ok = k >= k0 && k < k1;
-            s_p[(v * kBlock + tid) * VW + j] =
-                a[v][j] * load_x(r_x, ok ? uint32_t(c[v][j]) * 8u : kOff);
-        }
-    }
-    __syncthreads();
-
-    const int g = tid / SL, lane = tid % SL;
-    const int nr = r1 - r0;
-    double s = 0.0;
-    if (g < nr) {
-        const int b = s_rp[g] - base, e = s_rp[g + 1] - base;
-        for (int k = b + lane; k < e; k += SL) s += s_p[k];
-    }
-    s = group_sum<SL>(s);
-    if (lane == SL - 1 && g < nr) {
-        if (A.acc)
-            A.acc[A.rows[r0 + g]] += s;
-        else
-            A.out[r0 + g] = s;
-    }
+    TileRegs<NPT, VW> T;
+    tile_load<NPT, VW>(A, r_col, r_val, t, T);
+    tile_gather<NPT, VW>(r_x, T);
+    tile_reduce<NPT, VW, SL>(A, T, s_p, s_rp);
 }
 
 }  // namespace spmv

@@ -8,10 +8,10 @@ Two searches, both timed on the device by the library itself:
   program until t_measure = 0.01 s has elapsed and records time / samples.
   Plan objects are re-ordered in place (``spmv_plan_reorder``), so the share
   is uploaded once per replica; samples rotate over cold replicas.
-* :func:`tune_kernel` -- the CSR kernel variant (stream CSR: window chunk,
-  load width, summing lanes; vector CSR: lanes per row, rows per lane
-  group), timed with HIP events around back-to-back launches over cold
-  replicas.
+* :func:`tune_kernel` -- the product kernel variant (stream CSR in packed
+  tiles: window chunk, load width, summing lanes; sliced ELL: entries per
+  batch of loads; vector CSR: lanes per row, rows per lane group), timed
+  with HIP events around back-to-back launches over cold replicas.
 
 Results can be appended to a JSONL cache keyed by the matrix digest, so an
 interrupted sweep resumes where it stopped.
@@ -129,8 +129,9 @@ def sweep_summary(results) -> dict:
 
 
 DEFAULT_CANDIDATES = (
-    [{"kernel_local": 2, "chunk_local": c, "width": 2} for c in (4, 8, 16)] +
-    [{"kernel_local": 2, "chunk_local": c, "width": 2, "lanes_local": l}
+    [{"kernel_local": 2, "form": 2, "chunk_local": c} for c in (4, 8, 16)] +
+    [{"kernel_local": 2, "form": 1, "chunk_local": c, "width": 2} for c in (4, 8, 16)] +
+    [{"kernel_local": 2, "form": 1, "chunk_local": c, "width": 2, "lanes_local": l}
      for c in (4, 8) for l in (1, 2, 4)] +
     [{"kernel_local": 1, "lanes_local": l, "rows_local": r} for l in (8, 32) for r in (4, 8)])
 

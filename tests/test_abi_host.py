@@ -335,7 +335,8 @@ def test_stream_tiles_invariants(chunk, width, lanes):
         p = sp.spmv_plan_create(A, P, r, tune={"flags": sp.SPMV_F_HOST_ONLY, "kernel_local": 2,
                                                "kernel_remote": 2, "chunk_local": chunk,
                                                "chunk_remote": chunk, "width": width,
-                                               "lanes_local": lanes, "lanes_remote": lanes})
+                                               "lanes_local": lanes, "lanes_remote": lanes,
+                                               "form": 1})
         try:
             info = sp.spmv_plan_info(p)
             cap, maxr = 256 * chunk, 256 // lanes
@@ -446,3 +447,33 @@ def test_power_law_share_structure():
         assert info["n_halo"] == ref["H"].size and info["nnz_remote"] == ref["R_val"].size
     finally:
         sp.spmv_plan_destroy(p)
+
+
+def test_sliced_form_choice_on_host():
+    """Automatic form: sliced ELL when every slice of 64 rows has one width
+    of at most 8 (7-point share, its one-entry remote rows), packed tiles
+    otherwise (27-point rows, uneven power-law rows); explicit form 2 takes
+    the sliced layout whenever padding stays within 15%."""
+    def info(A, P, r, **tune):
+        p = sp.spmv_plan_create(A, P, r, tune={"flags": sp.SPMV_F_HOST_ONLY, **tune})
+        try:
+            return sp.spmv_plan_info(p)
+        finally:
+            sp.spmv_plan_destroy(p)
+    i = info(gen.laplacian_3d7(32), 4, 1)
+    assert (i["form_local"], i["form_remote"]) == (2, 2)
+    assert i["n_slices_local"] == (i["n_loc"] + 63) // 64 and i["n_tiles_local"] == 0
+    assert i["n_slices_remote"] == (i["n_remote_rows"] + 63) // 64
+    assert i["chunk_local"] == 8 and i["chunk_remote"] == 4
+    i = info(gen.stencil_3d27(20, seed=3), 4, 1)
+    assert i["form_local"] == 1 and i["n_slices_local"] == 0 and i["n_tiles_local"] > 0
+    i = info(gen.stencil_3d27(20, seed=3), 4, 1, form=2)
+    assert i["form_local"] == 2 and i["chunk_local"] == 16
+    i = info(gen.power_law(20000, seed=3), 4, 1, form=2)
+    assert i["form_local"] == 1                      # padding far beyond 15%
+    i = info(gen.laplacian_3d7(32), 4, 1, form=1)
+    assert i["form_local"] == 1 and i["n_tiles_local"] > 0
+    i = info(gen.laplacian_3d7(32), 4, 1, kernel_local=1)
+    assert i["form_local"] == 0
+    with pytest.raises(sp.SpmvError):
+        info(gen.laplacian_3d7(8), 4, 1, form=3)

@@ -11,7 +11,8 @@ import paper_2203_02530_amd as sp
 from gpu_util import bits, log, run_share
 
 pytestmark = pytest.mark.gpu
-TUNE = {"kernel_local": 2, "kernel_remote": 2, "chunk_local": 8, "chunk_remote": 8, "width": 2}
+TUNE = {"kernel_local": 2, "kernel_remote": 2, "chunk_local": 8, "chunk_remote": 8, "width": 2,
+        "form": 1}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -124,11 +125,13 @@ def test_batch_rejects_mixed_configs():
     p1 = sp.spmv_plan_create(A, 2, 0, tune=TUNE)
     p2 = sp.spmv_plan_create(A, 2, 1, tune={**TUNE, "chunk_local": 4})
     p3 = sp.spmv_plan_create(A, 2, 1, tune={"kernel_local": 1})
+    p4 = sp.spmv_plan_create(A, 2, 1, tune={**TUNE, "form": 2})     # sliced: no tiles
+    assert sp.spmv_plan_info(p4)["form_local"] == 2
     try:
-        for bad in ([p1, p2], [p1, p3]):
+        for bad in ([p1, p2], [p1, p3], [p1, p4]):
             with pytest.raises(sp.SpmvError) as e:
                 sp.spmv_batch_create(bad)
             assert e.value.code == sp.SPMV_EINVAL
     finally:
-        for p in (p1, p2, p3):
+        for p in (p1, p2, p3, p4):
             sp.spmv_plan_destroy(p)

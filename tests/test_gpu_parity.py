@@ -101,6 +101,70 @@ def test_stream_variants(chunk, width, lanes):
             assert_share_parity(res, ref)
 
 
+@pytest.mark.parametrize("chunk", [0, 4, 8, 16])
+def test_sliced_form(chunk):
+    """Sliced ELL against the oracle: stencils (integer x bit-exact), banded
+    rows, slices cut by the end of the rows, the remote product over
+    compressed rows, y_R fused or combined, and the fall back to packed
+    tiles when padding would exceed 15% (uneven rows)."""
+    log(f"sliced form chunk={chunk}")
+    cases = [(gen.laplacian_3d7(48), 4, 1, 3),
+             (gen.stencil_3d27(30, seed=5), 4, 2, 6),
+             (gen.banded_uniform(60000, 10, 15000, seed=8), 4, 3, 9),
+             (gen.laplacian_2d5(40), 2, 1, 10),
+             (gen.laplacian_2d5(37, 29), 1, 0, 12),                # 1073 rows: ragged last slice
+             (gen.banded_random(50000, 5, 27, 2000, seed=13), 1, 0, 11),   # uneven: packed tiles
+             (gen.power_law(30000, seed=17), 4, 2, 18)]
+    for A, P, r, seed in cases:
+        x = gen.x_normal(A.n_cols, seed)
+        ref = oracle.share_reference(A, P, r, x)
+        split = oracle.split(A, P, r)
+        for plan in (0, 5):
+            ops, smap = sp.spmv_plan_space_get(P, 2, plan) if P > 1 else (None, None)
+            res, _ = run_share(A, P, r, x, ops, smap, tune={
+                "kernel_local": 2, "kernel_remote": 2, "chunk_local": chunk,
+                "chunk_remote": chunk, "form": 2}, ref=ref)
+            assert_share_parity(res, ref)
+        # sliced exactly when padding stays within 15% of the entries
+        rp = split["L_ptr"]
+        lens = np.diff(rp)
+        n = lens.size
+        widths = [lens[i:i + 64].max() for i in range(0, n, 64)] if n else []
+        padded = 64 * int(np.sum(widths))
+        expect = 2 if n and padded <= 1.15 * max(int(rp[-1]), 1) else 1
+        assert res["info"]["form_local"] == expect, (A.n_rows, padded, rp[-1])
+    for A, P, r in [(gen.laplacian_3d7(32), 4, 1), (gen.laplacian_2d5(64), 1, 0)]:
+        x = gen.x_integer(A.n_cols, 9)
+        res, ref = run_share(A, P, r, x, tune={"kernel_local": 2, "kernel_remote": 2,
+                                               "chunk_local": chunk, "form": 2})
+        assert res["info"]["form_local"] == 2
+        assert np.array_equal(bits(res["y"]), bits(ref["y"]))
+
+
+def test_sliced_form_all_plans_identical_and_not_batched():
+    import torch
+    A = gen.stencil_3d27(24, seed=7)
+    x = gen.x_normal(A.n_cols, 70)
+    P, r = 4, 2
+    ref = oracle.share_reference(A, P, r, x)
+    first = None
+    for i in range(0, 2016, 97):
+        ops, smap = sp.spmv_plan_space_get(P, 2, i)
+        res, _ = run_share(A, P, r, x, ops, smap, tune={"form": 2}, ref=ref)
+        assert res["info"]["form_local"] == 2
+        if first is None:
+            assert_share_parity(res, ref)
+            first = bits(res["y"])
+        assert np.array_equal(bits(res["y"]), first), i
+    plan = sp.spmv_plan_create(A, P, r, None, None, 2, {"form": 2})
+    try:
+        with pytest.raises(sp.SpmvError):
+            sp.spmv_batch_create([plan])
+    finally:
+        sp.spmv_plan_destroy(plan)
+    torch.cuda.synchronize()
+
+
 def test_stream_stencils_bit_exact_integer():
     for A, P, r in [(gen.laplacian_3d7(32), 4, 1), (gen.laplacian_2d5(64), 1, 0)]:
         x = gen.x_integer(A.n_cols, 9)
