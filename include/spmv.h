@@ -91,7 +91,14 @@ extern "C" {
 #define SPMV_CES_B4(v)     (SPMV_SYNC_CES  | (v))
 #define SPMV_CSWE_B4(v)    (SPMV_SYNC_CSWE | (v))
 
-#define SPMV_MAX_OPS     24   /* longest valid operation order              */
+/* Fine-grained program (Sec. III-A): one Pack, PostSend and WaitSend per
+ * destination rank q and one PostRecv and WaitRecv per source rank q, token
+ * SPMV_PEER(op, q); start, y_L, y_R and end are shared, Unpack is implied
+ * before y_R, and the synchronisation macros above wrap peer tokens too
+ * (SPMV_CER_AFTER(SPMV_PEER(SPMV_OP_PACK, q)), ...).                      */
+#define SPMV_PEER(op, q)   ((op) | (((q) + 1) << 8))
+
+#define SPMV_MAX_OPS     24   /* longest valid coarse operation order       */
 #define SPMV_MAX_STREAMS  8
 
 /* ------------------------------------------------------------ types */
@@ -182,7 +189,7 @@ typedef struct {
                               0 vector CSR                                   */
     int32_t form_remote;   /* same for y_R                                   */
     int32_t n_slices_local, n_slices_remote;  /* sliced-ELL slices (0: none) */
-    int32_t reserved;
+    int32_t fine;          /* 1 while a fine-grained order is in force       */
 } spmv_info_t;
 
 /* Integer metadata selectors for spmv_plan_get_i32. */
@@ -206,6 +213,9 @@ typedef struct {
 #define SPMV_I32_TILE_K_L    13  /* [n_tiles_local+1] first entry of each tile */
 #define SPMV_I32_TILE_ROW_R  14  /* same for A_R (compressed rows)            */
 #define SPMV_I32_TILE_K_R    15
+#define SPMV_I32_OP_STREAM   16  /* [n_ops] canonical stream of each position of
+                                    the order in force, -1 for tokens that
+                                    run on no plan stream                     */
 
 /* FP64 selectors for spmv_plan_get_f64 (device contents are copied back). */
 #define SPMV_F64_AL_VAL       0  /* [nnz_local]                               */
@@ -383,6 +393,39 @@ int spmv_plan_space_get(int32_t nranks, int32_t n_streams, int64_t index,
  * full length, or SPMV_EINVAL for an unknown token. */
 int spmv_op_name(int32_t op, char *buf, int32_t cap);
 
+/* ------------------------------------------------------------ fine-grained */
+
+/*
+ * The fine-grained program of a plan's share (multi-rank plans only; see
+ * SPMV_PEER).  Its DAG: start -> {Pack[q], y_L, PostRecv[q]};
+ * Pack[q] -> PostSend[q] -> WaitSend[q] -> end with CER-after-Pack[q] and
+ * CES-b4-PostSend[q] in between (Table III); PostRecv[q] -> WaitRecv[q] ->
+ * y_R for every source q; y_L, y_R -> end.  Destinations are the ranks whose
+ * send list is not empty, sources the owners of halo entries.
+ *
+ * spmv_fine_tokens: the DAG's tokens, ascending; tokens [cap] host out,
+ *   *n = count (tokens beyond cap are not written).
+ * spmv_fine_default: a valid order (receives first, each Pack with its record
+ *   on stream 0, y_L and y_R on stream 1); ops / streams [cap] host out.
+ * spmv_fine_count: number of fine-grained programs with up to n_streams
+ *   streams (orders times canonical stream maps), as a double; SPMV_EINVAL
+ *   beyond 40 tokens.
+ * spmv_plan_set_fine: make a validated fine-grained order the plan's program
+ *   for later execs; op_stream[i] is the stream of position i when it holds
+ *   a GPU vertex (ignored otherwise); op_order NULL = the default order.
+ *   Errors as spmv_plan_reorder, which returns the plan to coarse orders.
+ *   The per-op profile is not kept while a fine-grained order is in force.
+ * spmv_fine_validate: the same checks without changing the plan.
+ */
+int spmv_fine_tokens(const spmv_plan_t *plan, int32_t *tokens, int32_t cap, int32_t *n);
+int spmv_fine_default(const spmv_plan_t *plan, int32_t *ops, int32_t *streams, int32_t cap,
+                      int32_t *n_ops);
+int spmv_fine_count(const spmv_plan_t *plan, int32_t n_streams, double *count);
+int spmv_plan_set_fine(spmv_plan_t *plan, const int32_t *op_order, const int32_t *op_stream,
+                       int32_t n_ops, int32_t n_streams);
+int spmv_fine_validate(const spmv_plan_t *plan, const int32_t *op_order,
+                       const int32_t *op_stream, int32_t n_ops, int32_t n_streams);
+
 /* ------------------------------------------------------------ tree search */
 
 /*
@@ -456,6 +499,25 @@ int spmv_mcts_run(spmv_plan_t *const *plans, int32_t n_plans, const double *cons
                   double *const *y, void *stream, const spmv_mcts_opts_t *opts,
                   int64_t *index_out, double *time_out, int64_t cap, int64_t *n_out,
                   spmv_mcts_node_t *nodes, int64_t node_cap, int64_t *n_nodes);
+
+/*
+ * Search over the coarse DAG (fine = 0) or the fine-grained DAG of plans[0]'s
+ * share (fine = 1), reporting each rollout as an order and its per-position
+ * streams: ops_out / streams_out [cap * max_ops] host, rollout k at
+ * k * max_ops (max_ops at least the order length).  A rollout is costed by
+ * cost(ops, streams, n_ops, user) when cost is given (host only: the plans
+ * may be host-only and x / y NULL), else timed on the device as in
+ * spmv_mcts_run with the plans switched to the rollout's order
+ * (spmv_plan_reorder or spmv_plan_set_fine).  Other outputs as above.
+ */
+typedef double (*spmv_cost_fn)(const int32_t *ops, const int32_t *streams, int32_t n_ops,
+                               void *user);
+int spmv_mcts_run_seq(spmv_plan_t *const *plans, int32_t n_plans, const double *const *x,
+                      double *const *y, void *stream, int32_t fine, spmv_cost_fn cost,
+                      void *user, const spmv_mcts_opts_t *opts, int32_t *ops_out,
+                      int32_t *streams_out, int32_t max_ops, double *time_out, int64_t cap,
+                      int64_t *n_out, spmv_mcts_node_t *nodes, int64_t node_cap,
+                      int64_t *n_nodes);
 
 /* ------------------------------------------------------------ batches */
 

@@ -19,7 +19,33 @@ from __future__ import annotations
 
 import math
 
-from . import DAG_EDGES, GPU_VERTICES, VERTEX_TYPE, required_syncs, plan_tokens
+from . import DAG_EDGES, GPU_VERTICES, required_syncs, plan_tokens
+
+
+class Dag:
+    """A program DAG as the search sees it: the tokens of an order, what
+    must precede each token (DAG predecessors and the Table III pairs), and
+    which tokens are GPU vertices."""
+
+    def __init__(self, tokens, need, gpu):
+        self.tokens = list(tokens)
+        self.need = {t: set(need.get(t, ())) for t in self.tokens}
+        self.gpu = set(gpu)
+
+
+def coarse_dag() -> Dag:
+    """The SpMV DAG of Sec. III-A with the Table III tokens its GPU -> CPU
+    edges need (Unpack implied before yR)."""
+    toks = ["start"] + plan_tokens() + ["end"]
+    need = {t: set() for t in toks}
+    for u, v in DAG_EDGES:
+        need[v].add(u)
+    for u, v, rec, wait in required_syncs():
+        need[rec].add(u)
+        need[wait].add(rec)
+        need[v].add(wait)
+    need["end"] = set(toks) - {"end"}
+    return Dag(toks, need, [g for g in GPU_VERTICES])
 
 
 def _default_key(token, stream):
@@ -27,37 +53,28 @@ def _default_key(token, stream):
     return (names.index(token), -1 if stream is None else stream)
 
 
-def children(prefix, n_streams: int, key=_default_key):
+def children(prefix, n_streams: int, key=_default_key, dag: Dag | None = None):
     """Next steps of a prefix (Sec. III-C, Expansion): every DAG vertex not
     yet placed whose predecessors are placed, and every Table III token whose
     operand is placed -- a record after its GPU vertex, a host wait after its
     record; a CPU vertex needing a wait also needs the wait placed.  GPU
     vertices are bound to each stream already used and to one new stream
     while fewer than ``n_streams`` are used.  ``end`` comes last."""
+    dag = dag or _COARSE
     placed = {t for t, _ in prefix}
     used = len({s for _, s in prefix if s is not None})
-    syncs = required_syncs()
-    toks = ["start"] + plan_tokens() + ["end"]
     out = []
-    for t in toks:
-        if t in placed:
+    for t in dag.tokens:
+        if t in placed or not dag.need[t] <= placed:
             continue
-        if t == "end":
-            ok = all(o in placed for o in toks if o != "end")
-        elif t.startswith("CER-after-"):
-            ok = t[len("CER-after-"):] in placed
-        elif t.startswith("CES-b4-"):
-            ok = all(rec in placed for _, _, rec, wait in syncs if wait == t)
-        else:
-            ok = all(u in placed for u, v in DAG_EDGES if v == t)
-            ok = ok and all(wait in placed for _, v, _, wait in syncs if v == t)
-        if not ok:
-            continue
-        if VERTEX_TYPE.get(t) == "GPU":
+        if t in dag.gpu:
             out += [(t, s) for s in range(min(used + 1, n_streams))]
         else:
             out.append((t, None))
     return sorted(out, key=lambda st: key(*st))
+
+
+_COARSE = coarse_dag()
 
 
 def plan_of(prefix):
@@ -68,9 +85,9 @@ def plan_of(prefix):
 
 
 class Node:
-    def __init__(self, prefix, n_streams, key):
+    def __init__(self, prefix, n_streams, key, dag):
         self.prefix = prefix
-        self.untried = children(prefix, n_streams, key)
+        self.untried = children(prefix, n_streams, key, dag)
         self.complete = not self.untried
         self.children = []              # created children, in creation order
         self.n = 0                      # rollouts through this node
@@ -98,14 +115,15 @@ def exploration(parent: Node, child: Node, c: float) -> float:
 
 
 def mcts(cost, n_streams: int = 2, iterations: int = 0, draws=(), c: float = math.sqrt(2.0),
-         key=_default_key, trace=None):
+         key=_default_key, trace=None, dag: Dag | None = None):
     """Run the search.  ``cost(plan)`` gives the time of a complete plan (in
-    :func:`plan_of` form).  Stops after ``iterations`` rollouts (0: until the
+    :func:`plan_of` form for the coarse DAG, the prefix tuple itself for any
+    other ``dag``).  Stops after ``iterations`` rollouts (0: until the
     root is fully explored).  Returns (list of (plan, time) per rollout, root
     node).  ``trace``, when given, is called as trace(event, data) with
     events "select" (parent, child, V, score), "path" (the nodes of a
     rollout, root first, before their statistics are updated)."""
-    root = Node((), n_streams, key)
+    root = Node((), n_streams, key, dag)
     draws = iter(draws)
     log = []
     while not root.full and (iterations == 0 or len(log) < iterations):
@@ -128,11 +146,11 @@ def mcts(cost, n_streams: int = 2, iterations: int = 0, draws=(), c: float = mat
         while not node.complete:
             k = next(draws) % len(node.untried)
             step = node.untried.pop(k)
-            child = Node(node.prefix + (step,), n_streams, key)
+            child = Node(node.prefix + (step,), n_streams, key, dag)
             node.children.append(child)
             node = child
             path.append(node)
-        plan = plan_of(node.prefix)
+        plan = plan_of(node.prefix) if dag is None else node.prefix
         t = cost(plan)
         log.append((plan, t))
         if trace:

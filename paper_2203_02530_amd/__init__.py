@@ -60,6 +60,7 @@ SPMV_MAX_OPS, SPMV_MAX_STREAMS = 24, 8
 def SPMV_CER_AFTER(u): return SPMV_SYNC_CER | u
 def SPMV_CES_B4(v): return SPMV_SYNC_CES | v
 def SPMV_CSWE_B4(v): return SPMV_SYNC_CSWE | v
+def SPMV_PEER(op, q): return op | ((q + 1) << 8)
 
 
 SPMV_F_HOST_ONLY, SPMV_F_PROFILE, SPMV_F_NO_BUFFER = 1, 2, 4
@@ -69,7 +70,7 @@ SPMV_KERNEL_VECTOR, SPMV_KERNEL_STREAM = 1, 2
  SPMV_I32_AL_PTR, SPMV_I32_AL_COLS, SPMV_I32_AR_ROWS, SPMV_I32_AR_PTR,
  SPMV_I32_AR_COLS, SPMV_I32_UNPACK_PERM, SPMV_I32_OP_ORDER,
  SPMV_I32_STREAM_MAP, SPMV_I32_TILE_ROW_L, SPMV_I32_TILE_K_L, SPMV_I32_TILE_ROW_R,
- SPMV_I32_TILE_K_R) = range(16)
+ SPMV_I32_TILE_K_R, SPMV_I32_OP_STREAM) = range(17)
 (SPMV_F64_AL_VAL, SPMV_F64_AR_VAL, SPMV_F64_SENDBUF, SPMV_F64_RECVBUF,
  SPMV_F64_X_HALO, SPMV_F64_OP_MS, SPMV_F64_OP_COUNT) = range(7)
 
@@ -153,7 +154,7 @@ class spmv_info_t(ctypes.Structure):
             "lanes_local", "lanes_remote", "rows_local", "rows_remote", "chunk_local",
             "chunk_remote", "width", "xcd_remap", "fuse_unpack", "fused_combine",
             "n_tiles_local", "n_tiles_remote", "form_local", "form_remote",
-            "n_slices_local", "n_slices_remote", "reserved")]
+            "n_slices_local", "n_slices_remote", "fine")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -191,6 +192,15 @@ _proto("spmv_plan_space_get", [_I32, _I32, _I64, _P, _P, _P])
 _proto("spmv_op_name", [_I32, ctypes.c_char_p, _I32])
 _proto("spmv_mcts_run_table", [_I32, _P, _I64, _P, _P, _P, _I64, _P, _P, _I64, _P])
 _proto("spmv_mcts_run", [_P, _I32, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _I64, _P])
+COST_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
+                           ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_void_p)
+_proto("spmv_mcts_run_seq", [_P, _I32, _P, _P, _P, _I32, COST_FN, _P, _P, _P, _P, _I32, _P,
+                             _I64, _P, _P, _I64, _P])
+_proto("spmv_fine_tokens", [_P, _P, _I32, _P])
+_proto("spmv_fine_default", [_P, _P, _P, _I32, _P])
+_proto("spmv_fine_count", [_P, _I32, _P])
+_proto("spmv_plan_set_fine", [_P, _P, _P, _I32, _I32])
+_proto("spmv_fine_validate", [_P, _P, _P, _I32, _I32])
 _proto("spmv_hbm_probe", [_I32, _P, _P, _I64, _I32, _P])
 _proto("spmv_batch_create", [_P, _I32, _P, _P])
 _proto("spmv_batch_exec", [_P, _P, _P, _P])
@@ -362,6 +372,7 @@ _I32_LEN = {
     SPMV_I32_AR_PTR: lambda i: i["n_remote_rows"] + 1,
     SPMV_I32_AR_COLS: lambda i: i["nnz_remote"], SPMV_I32_UNPACK_PERM: lambda i: i["n_halo"],
     SPMV_I32_OP_ORDER: lambda i: i["n_ops"], SPMV_I32_STREAM_MAP: lambda i: SPMV_N_VERTICES,
+    SPMV_I32_OP_STREAM: lambda i: i["n_ops"],
     SPMV_I32_TILE_ROW_L: lambda i: i["n_tiles_local"] + 1 if i["form_local"] == 1 else 0,
     SPMV_I32_TILE_K_L: lambda i: i["n_tiles_local"] + 1 if i["form_local"] == 1 else 0,
     SPMV_I32_TILE_ROW_R: lambda i: i["n_tiles_remote"] + 1 if i["form_remote"] == 1 else 0,
@@ -492,6 +503,98 @@ def spmv_mcts_run(plans, xs, ys, stream=None, iterations: int = 0, seed: int = 0
     nranks = spmv_plan_info(plans[0])["nranks"]
     cap = int(iterations) if iterations > 0 else spmv_plan_space_count(nranks, max(n_streams, 1))
     return _mcts_result(_lib.spmv_mcts_run, (pa, n, xa, ya, _stream_handle(stream)), o, cap)
+
+
+def spmv_mcts_run_seq(plans, xs=None, ys=None, stream=None, fine: bool = False, cost=None,
+                      iterations: int = 0, seed: int = 0, c: float = 0.0, n_streams: int = 2,
+                      t_measure: float = 0.01, n_measure: int = 1, rand=None,
+                      max_rollouts: int = 100000) -> dict:
+    """Tree search over the coarse or the fine-grained DAG of the plans'
+    share.  ``cost(ops, streams)`` (numpy int32 arrays) gives a rollout's
+    time on the host; without it rollouts are timed on the device.  Returns
+    {ops [k, n_ops], streams [k, n_ops], time [k], nodes}."""
+    if not isinstance(plans, (list, tuple)):
+        plans = [plans]
+        xs = [xs] if xs is not None else None
+        ys = [ys] if ys is not None else None
+    n = len(plans)
+    pa = (ctypes.c_void_p * n)(*plans)
+    xa = (ctypes.c_void_p * n)(*[_addr(v) or None for v in xs]) if xs else None
+    ya = (ctypes.c_void_p * n)(*[_addr(v) or None for v in ys]) if ys else None
+    o, keep = _mcts_opts(iterations, seed, c, n_streams, n_measure, t_measure, rand)
+    if fine:
+        max_ops = len(spmv_fine_tokens(plans[0]))
+    else:
+        max_ops = SPMV_MAX_OPS
+    cap = int(iterations) if iterations > 0 else int(max_rollouts)
+    ops = np.full((cap, max_ops), -1, np.int32)
+    sts = np.full((cap, max_ops), -1, np.int32)
+    tim = np.empty(cap, np.float64)
+    nn = ctypes.c_int64()
+    n_nodes = ctypes.c_int64()
+    node_cap = cap * max_ops + 1
+    nodes = np.zeros(node_cap, MCTS_NODE_DTYPE)
+    err = []
+
+    def _cb(po, ps, k, _user):
+        try:
+            a = np.ctypeslib.as_array(po, shape=(k,)).copy()
+            b = np.ctypeslib.as_array(ps, shape=(k,)).copy()
+            return float(cost(a, b))
+        except Exception as e:          # reported after the call returns
+            err.append(e)
+            return 0.0
+    cb = COST_FN(_cb) if cost is not None else COST_FN()
+    _check(_lib.spmv_mcts_run_seq(pa, n, xa, ya, _stream_handle(stream), 1 if fine else 0, cb,
+                                  None, ctypes.byref(o), ops.ctypes.data, sts.ctypes.data,
+                                  max_ops, tim.ctypes.data, cap, ctypes.byref(nn),
+                                  nodes.ctypes.data, node_cap, ctypes.byref(n_nodes)))
+    if err:
+        raise err[0]
+    k = min(nn.value, cap)
+    n_ops = int(np.max(np.sum(ops[:k] >= 0, axis=1))) if k else 0
+    return {"ops": ops[:k, :n_ops].copy(), "streams": sts[:k, :n_ops].copy(),
+            "time": tim[:k].copy(), "nodes": nodes[:min(n_nodes.value, node_cap)].copy()}
+
+
+def spmv_fine_tokens(plan) -> np.ndarray:
+    n = ctypes.c_int32()
+    _check(_lib.spmv_fine_tokens(plan, None, 0, ctypes.byref(n)))
+    out = np.empty(n.value, np.int32)
+    _check(_lib.spmv_fine_tokens(plan, out.ctypes.data, n.value, ctypes.byref(n)))
+    return out
+
+
+def spmv_fine_default(plan):
+    """(ops, streams) of the default fine-grained order."""
+    cap = len(spmv_fine_tokens(plan))
+    ops = np.empty(cap, np.int32)
+    sts = np.empty(cap, np.int32)
+    n = ctypes.c_int32()
+    _check(_lib.spmv_fine_default(plan, ops.ctypes.data, sts.ctypes.data, cap, ctypes.byref(n)))
+    return ops[:n.value].copy(), sts[:n.value].copy()
+
+
+def spmv_fine_count(plan, n_streams: int = 2) -> float:
+    c = ctypes.c_double()
+    _check(_lib.spmv_fine_count(plan, n_streams, ctypes.byref(c)))
+    return c.value
+
+
+def spmv_plan_set_fine(plan, op_order=None, op_stream=None, n_streams: int = 2) -> None:
+    if op_order is None:
+        _check(_lib.spmv_plan_set_fine(plan, None, None, 0, n_streams))
+        return
+    ops = _i32(op_order)
+    sts = _i32(op_stream if op_stream is not None else np.zeros(ops.size, np.int32))
+    _check(_lib.spmv_plan_set_fine(plan, ops.ctypes.data, sts.ctypes.data, ops.size, n_streams))
+
+
+def spmv_fine_validate(plan, op_order, op_stream=None, n_streams: int = 2) -> int:
+    ops = _i32(op_order)
+    sts = _i32(op_stream if op_stream is not None else np.zeros(ops.size, np.int32))
+    return _check(_lib.spmv_fine_validate(plan, ops.ctypes.data, sts.ctypes.data, ops.size,
+                                          n_streams))
 
 
 def spmv_op_name(op: int) -> str:

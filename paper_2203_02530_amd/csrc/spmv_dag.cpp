@@ -90,6 +90,19 @@ bool is_sync(int32_t t)
 
 int op_name(int32_t t, std::string &out)
 {
+    // peer tokens (fine-grained program): the per-peer vertices, and their
+    // synchronisation tokens, with the peer rank in brackets
+    if (t >= 0x100) {
+        const int32_t peer = ((t >> 8) & 0xff) - 1, base = t & 0xff;
+        const int32_t v = base & 0x0f;
+        const bool per_peer = v == SPMV_OP_PACK || v == SPMV_OP_POST_SEND ||
+                              v == SPMV_OP_POST_RECV || v == SPMV_OP_WAIT_SEND ||
+                              v == SPMV_OP_WAIT_RECV;
+        if ((t >> 16) != 0 || peer < 0 || !per_peer || op_name(base, out) != SPMV_OK)
+            return SPMV_EINVAL;
+        out += "[" + std::to_string(peer) + "]";
+        return SPMV_OK;
+    }
     if (is_vertex(t)) {
         out = kVertexName[t];
         return SPMV_OK;
@@ -102,12 +115,14 @@ int op_name(int32_t t, std::string &out)
     return SPMV_OK;
 }
 
-static std::string tok_str(int32_t t)
+std::string tok_name(int32_t t)
 {
     std::string s;
     if (op_name(t, s) != SPMV_OK) s = "token " + std::to_string(t);
     return s;
 }
+
+static std::string tok_str(int32_t t) { return tok_name(t); }
 
 int validate_schedule(int32_t nranks, const int32_t *ops, int32_t n_ops,
                       const int32_t *stream_map, int32_t n_streams, Schedule &out)

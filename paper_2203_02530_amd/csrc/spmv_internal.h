@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -111,6 +112,51 @@ struct Prefix {
     bool preds_done(int32_t v) const;
     bool ready(int32_t t) const;
 };
+
+// ----------------------------------------------------------------- fine DAG
+// Token fields: op (low 4 bits), synchronisation kind (bits 4-5), peer rank
+// + 1 (bits 8-15, 0 for tokens without a peer).
+int32_t tok_op(int32_t t);
+int32_t tok_kind(int32_t t);
+int32_t tok_peer(int32_t t);
+std::string tok_name(int32_t t);   // printable name, "token N" if unknown
+
+// The fine-grained program DAG of one share (see spmv_fine.cpp).
+struct FineDag {
+    std::vector<int32_t> dests, srcs;          // peer ranks, ascending
+    std::vector<int32_t> tokens;               // every token of an order, ascending
+    std::map<int32_t, int32_t> index;          // token -> position in tokens
+    std::vector<std::vector<int32_t>> need;    // positions that must come first
+    std::vector<bool> gpu;                     // token is a GPU vertex
+    void build(const Share &S);
+    int find(int32_t t) const;
+};
+
+// A prefix of a fine-grained order (same interface as Prefix).
+struct FinePrefix {
+    const FineDag *dag = nullptr;
+    int32_t n_streams = 1;
+    std::vector<int32_t> order, ostream;       // tokens and their streams (-1: none)
+    std::vector<bool> placed;
+    int32_t used = 0;
+    void init(const FineDag *d, int32_t n_streams);
+    void clear();
+    bool ready(int32_t i) const;
+    void next(std::vector<Prefix::Step> &out) const;
+    void push(Prefix::Step s);
+    bool complete() const { return order.size() == dag->tokens.size(); }
+};
+
+struct FineSchedule {
+    std::vector<int32_t> order, ostream;       // canonical streams per position
+    int32_t n_streams_used = 0;
+};
+
+int validate_fine(const FineDag &dag, const int32_t *ops, const int32_t *op_stream,
+                  int32_t n_ops, int32_t n_streams, FineSchedule &out);
+void fine_default(const FineDag &dag, std::vector<int32_t> &ops, std::vector<int32_t> &streams);
+// Number of fine-grained programs: orders times canonical stream maps.
+int fine_count(const FineDag &dag, int32_t n_streams, double &count);
 
 // ----------------------------------------------------------------- kernels
 // Launchers (spmv_kernels.hip).  All are asynchronous on `s` and launch
@@ -241,6 +287,11 @@ struct spmv_plan {
     hipEvent_t ev_start = nullptr, ev_send = nullptr, ev_recv = nullptr;
     hipEvent_t ev_rec[SPMV_N_VERTICES] = {};
     hipEvent_t ev_join[SPMV_MAX_STREAMS] = {};
+    // fine-grained mode: the order is fsch over fdag (per-peer vertices)
+    bool fine = false;
+    spmv::FineDag fdag;
+    spmv::FineSchedule fsch;
+    std::vector<hipEvent_t> ev_pack, ev_psend, ev_precv;   // per peer rank
     // profiling: begin/end per vertex, index SPMV_N_VERTICES = combine
     hipEvent_t ev_b[SPMV_N_VERTICES + 1] = {}, ev_e[SPMV_N_VERTICES + 1] = {};
     double ms[SPMV_N_VERTICES + 1] = {};

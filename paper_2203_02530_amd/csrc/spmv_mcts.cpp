@@ -2,9 +2,10 @@
 // paper): selection by exploration + exploitation value, expansion of one
 // zero-rollout child, a random rollout whose nodes stay in the tree, and
 // min/max backpropagation.  The children of a node are the next tokens of
-// its prefix (Prefix::next: DAG-ready vertices bound to canonical streams,
-// and the Table III tokens), so the tree covers exactly the enumerated plan
-// space and every rollout reaches a plan not benchmarked before.
+// its prefix (Prefix::next over the coarse DAG, FinePrefix::next over the
+// per-peer DAG: ready vertices bound to canonical streams, and the Table III
+// tokens), so the tree covers exactly the plan space of its DAG and every
+// rollout reaches a plan not benchmarked before.
 #include <algorithm>
 #include <cmath>
 #include <functional>
@@ -48,11 +49,11 @@ struct Draws {
     }
 };
 
-// bench(plan index, seconds out) -> status
-using Bench = std::function<int(int64_t, double &)>;
-
+template <class Pre>
 struct Search {
-    Prefix pre;
+    // bench(complete prefix, seconds out) -> status
+    using Bench = std::function<int(const Pre &, double &)>;
+    Pre pre;
     std::vector<Node> tree;
     double c = 0;
 
@@ -86,7 +87,7 @@ struct Search {
         return 1.0;
     }
 
-    int iterate(Draws &rng, const Bench &bench, int64_t &index, double &t)
+    int iterate(Draws &rng, const Bench &bench, double &t)
     {
         pre.clear();
         std::vector<int32_t> path{0};
@@ -119,9 +120,7 @@ struct Search {
             cur = create(cur, k);
             path.push_back(cur);
         }
-        index = plan_index(pre.multi, pre.n_streams, pre.order, pre.stream);
-        if (index < 0) return set_error(SPMV_ESTATE, "MCTS reached a plan outside the space");
-        if (int rc = bench(index, t)) return rc;
+        if (int rc = bench(pre, t)) return rc;
         // backpropagation, and fully-explored marks from the leaf up
         for (int32_t i : path) {
             Node &nd = at(i);
@@ -154,14 +153,18 @@ int options(const spmv_mcts_opts_t *o, spmv_mcts_opts_t &d)
     return SPMV_OK;
 }
 
-int run(int32_t nranks, const spmv_mcts_opts_t &o, const Bench &bench, int64_t *index_out,
-        double *time_out, int64_t cap, int64_t *n_out, spmv_mcts_node_t *nodes,
-        int64_t node_cap, int64_t *n_nodes)
+// Runs the search from an initialised empty prefix; bench records each
+// rollout's plan where the caller wants it, run() its time.
+template <class Pre>
+int run(const Pre &root_prefix, const spmv_mcts_opts_t &o,
+        const typename Search<Pre>::Bench &bench, double *time_out, int64_t cap, int64_t *n_out,
+        spmv_mcts_node_t *nodes, int64_t node_cap, int64_t *n_nodes)
 {
     if (cap < 0 || node_cap < 0) return set_error(SPMV_EINVAL, "negative output capacity");
-    Search S;
+    Search<Pre> S;
     S.c = o.c;
-    S.pre.init(nranks > 1, o.n_streams);
+    S.pre = root_prefix;
+    S.pre.clear();
     S.tree.emplace_back();
     S.list(0);
     Draws rng;
@@ -170,13 +173,9 @@ int run(int32_t nranks, const spmv_mcts_opts_t &o, const Bench &bench, int64_t *
     rng.mt.seed(o.seed);
     int64_t done = 0;
     while ((o.iterations == 0 || done < o.iterations) && !S.tree[0].full) {
-        int64_t idx;
         double t;
-        if (int rc = S.iterate(rng, bench, idx, t)) return rc;
-        if (done < cap) {
-            if (index_out) index_out[done] = idx;
-            if (time_out) time_out[done] = t;
-        }
+        if (int rc = S.iterate(rng, bench, t)) return rc;
+        if (done < cap && time_out) time_out[done] = t;
         ++done;
     }
     *n_out = done;
@@ -188,6 +187,23 @@ int run(int32_t nranks, const spmv_mcts_opts_t &o, const Bench &bench, int64_t *
                                         nd.full ? 1 : 0,  nd.n,     nd.tmin, nd.tmax};
         }
     return SPMV_OK;
+}
+
+// Per-position streams of a complete prefix (-1 for tokens without one).
+void seq_streams(const Prefix &p, std::vector<int32_t> &out)
+{
+    out.clear();
+    for (int32_t t : p.order)
+        out.push_back(is_vertex(t) && vertex_type(t) == VType::GPU ? p.stream[t] : -1);
+}
+
+void seq_streams(const FinePrefix &p, std::vector<int32_t> &out) { out = p.ostream; }
+
+// Median of a measurement set.
+double median(std::vector<double> s)
+{
+    std::nth_element(s.begin(), s.begin() + long(s.size() / 2), s.end());
+    return s[s.size() / 2];
 }
 
 }  // namespace
@@ -206,43 +222,134 @@ extern "C" int spmv_mcts_run_table(int32_t nranks, const double *cost, int64_t n
     if (int rc = options(opts, o)) return rc;
     if (n_cost != int64_t(plan_space(nranks > 1, o.n_streams).size()))
         return set_error(SPMV_EINVAL, "cost table must hold one time per plan of the space");
-    Bench bench = [&](int64_t i, double &t) {
+    Prefix root;
+    root.init(nranks > 1, o.n_streams);
+    int64_t k = 0;
+    Search<Prefix>::Bench bench = [&](const Prefix &p, double &t) {
+        const int64_t i = plan_index(p.multi, p.n_streams, p.order, p.stream);
+        if (i < 0) return set_error(SPMV_ESTATE, "MCTS reached a plan outside the space");
+        if (index_out && k < cap) index_out[k] = i;
+        ++k;
         t = cost[i];
         return SPMV_OK;
     };
-    return run(nranks, o, bench, index_out, time_out, cap, n_out, nodes, node_cap, n_nodes);
+    return run(root, o, bench, time_out, cap, n_out, nodes, node_cap, n_nodes);
 }
+
+namespace {
+
+// Checks shared by the device searches; nranks out.
+int check_plans(spmv_plan_t *const *plans, int32_t n_plans, int32_t &nranks)
+{
+    if (!plans || n_plans < 1) return set_error(SPMV_EINVAL, "need at least one plan");
+    for (int32_t k = 0; k < n_plans; ++k)
+        if (!plans[k]) return set_error(SPMV_EINVAL, "null plan");
+    nranks = plans[0]->share.nranks;
+    for (int32_t k = 1; k < n_plans; ++k)
+        if ((plans[k]->share.nranks > 1) != (nranks > 1))
+            return set_error(SPMV_EINVAL, "plans of one search must share the DAG");
+    return SPMV_OK;
+}
+
+}  // namespace
 
 extern "C" int spmv_mcts_run(spmv_plan_t *const *plans, int32_t n_plans, const double *const *x,
                              double *const *y, void *stream, const spmv_mcts_opts_t *opts,
                              int64_t *index_out, double *time_out, int64_t cap, int64_t *n_out,
                              spmv_mcts_node_t *nodes, int64_t node_cap, int64_t *n_nodes)
 {
-    if (!plans || n_plans < 1 || !x || !y || !n_out)
-        return set_error(SPMV_EINVAL, "bad argument to spmv_mcts_run");
-    for (int32_t k = 0; k < n_plans; ++k)
-        if (!plans[k]) return set_error(SPMV_EINVAL, "null plan");
+    int32_t nranks = 0;
+    if (int rc = check_plans(plans, n_plans, nranks)) return rc;
+    if (!x || !y || !n_out) return set_error(SPMV_EINVAL, "bad argument to spmv_mcts_run");
     spmv_mcts_opts_t o;
     if (int rc = options(opts, o)) return rc;
-    const int32_t nranks = plans[0]->share.nranks;
-    for (int32_t k = 1; k < n_plans; ++k)
-        if ((plans[k]->share.nranks > 1) != (nranks > 1))
-            return set_error(SPMV_EINVAL, "plans of one search must share the DAG");
     const auto &space = plan_space(nranks > 1, o.n_streams);
     std::vector<double> times(size_t(o.n_measure));
-    Bench bench = [&](int64_t i, double &t) {
+    Prefix root;
+    root.init(nranks > 1, o.n_streams);
+    int64_t k = 0;
+    Search<Prefix>::Bench bench = [&](const Prefix &p, double &t) {
+        const int64_t i = plan_index(p.multi, p.n_streams, p.order, p.stream);
+        if (i < 0) return set_error(SPMV_ESTATE, "MCTS reached a plan outside the space");
         const PlanEntry &e = space[size_t(i)];
-        for (int32_t k = 0; k < n_plans; ++k)
-            if (int rc = spmv_plan_reorder(plans[k], e.order.data(), int32_t(e.order.size()),
+        for (int32_t j = 0; j < n_plans; ++j)
+            if (int rc = spmv_plan_reorder(plans[j], e.order.data(), int32_t(e.order.size()),
                                            e.stream, o.n_streams))
                 return rc;
         if (int rc = spmv_plan_time(plans, n_plans, x, y, stream, o.t_measure, o.n_measure,
                                     times.data()))
             return rc;
-        std::vector<double> s = times;
-        std::nth_element(s.begin(), s.begin() + long(s.size() / 2), s.end());
-        t = s[s.size() / 2];
+        if (index_out && k < cap) index_out[k] = i;
+        ++k;
+        t = median(times);
         return SPMV_OK;
     };
-    return run(nranks, o, bench, index_out, time_out, cap, n_out, nodes, node_cap, n_nodes);
+    return run(root, o, bench, time_out, cap, n_out, nodes, node_cap, n_nodes);
+}
+
+extern "C" int spmv_mcts_run_seq(spmv_plan_t *const *plans, int32_t n_plans,
+                                 const double *const *x, double *const *y, void *stream,
+                                 int32_t fine, spmv_cost_fn cost, void *user,
+                                 const spmv_mcts_opts_t *opts, int32_t *ops_out,
+                                 int32_t *streams_out, int32_t max_ops, double *time_out,
+                                 int64_t cap, int64_t *n_out, spmv_mcts_node_t *nodes,
+                                 int64_t node_cap, int64_t *n_nodes)
+{
+    int32_t nranks = 0;
+    if (int rc = check_plans(plans, n_plans, nranks)) return rc;
+    if (!n_out || (!cost && (!x || !y)) || max_ops < 0 || (max_ops > 0 && (!ops_out || !streams_out)))
+        return set_error(SPMV_EINVAL, "bad argument to spmv_mcts_run_seq");
+    if (fine && nranks < 2) return set_error(SPMV_EINVAL, "a single rank has no fine-grained DAG");
+    if (fine)
+        for (int32_t k = 1; k < n_plans; ++k)
+            if (plans[k]->fdag.tokens != plans[0]->fdag.tokens)
+                return set_error(SPMV_EINVAL, "plans of one search must share the DAG");
+    spmv_mcts_opts_t o;
+    if (int rc = options(opts, o)) return rc;
+    std::vector<double> times(size_t(o.n_measure));
+    std::vector<int32_t> ss;
+    int64_t k = 0;
+    // record the rollout, then cost it (callback) or time it on the device
+    auto record = [&](const std::vector<int32_t> &order, double &t, auto &&apply) -> int {
+        const int32_t n = int32_t(order.size());
+        if (k < cap && max_ops > 0) {
+            if (n > max_ops) return set_error(SPMV_EINVAL, "max_ops smaller than an order");
+            std::copy(order.begin(), order.end(), ops_out + k * max_ops);
+            std::copy(ss.begin(), ss.end(), streams_out + k * max_ops);
+        }
+        ++k;
+        if (cost) {
+            t = cost(order.data(), ss.data(), n, user);
+            return SPMV_OK;
+        }
+        for (int32_t j = 0; j < n_plans; ++j)
+            if (int rc = apply(plans[j])) return rc;
+        if (int rc = spmv_plan_time(plans, n_plans, x, y, stream, o.t_measure, o.n_measure,
+                                    times.data()))
+            return rc;
+        t = median(times);
+        return SPMV_OK;
+    };
+    if (!fine) {
+        Prefix root;
+        root.init(nranks > 1, o.n_streams);
+        Search<Prefix>::Bench bench = [&](const Prefix &p, double &t) {
+            seq_streams(p, ss);
+            return record(p.order, t, [&](spmv_plan_t *q) {
+                return spmv_plan_reorder(q, p.order.data(), int32_t(p.order.size()), p.stream,
+                                         o.n_streams);
+            });
+        };
+        return run(root, o, bench, time_out, cap, n_out, nodes, node_cap, n_nodes);
+    }
+    FinePrefix root;
+    root.init(&plans[0]->fdag, o.n_streams);
+    Search<FinePrefix>::Bench bench = [&](const FinePrefix &p, double &t) {
+        seq_streams(p, ss);
+        return record(p.order, t, [&](spmv_plan_t *q) {
+            return spmv_plan_set_fine(q, p.order.data(), p.ostream.data(), int32_t(p.order.size()),
+                                      o.n_streams);
+        });
+    };
+    return run(root, o, bench, time_out, cap, n_out, nodes, node_cap, n_nodes);
 }

@@ -62,6 +62,9 @@ void release(spmv_plan *p)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : p->ev_join)
         if (e) (void)hipEventDestroy(e);
+    for (auto *v : {&p->ev_pack, &p->ev_psend, &p->ev_precv})
+        for (auto &e : *v)
+            if (e) (void)hipEventDestroy(e);
     for (int i = 0; i <= SPMV_N_VERTICES; ++i) {
         if (p->ev_b[i]) (void)hipEventDestroy(p->ev_b[i]);
         if (p->ev_e[i]) (void)hipEventDestroy(p->ev_e[i]);
@@ -372,6 +375,7 @@ int create_plan(Build build_share_fn, int32_t nranks, const int32_t *op_order, i
     p->use_buffer = (t.flags & SPMV_F_NO_BUFFER) == 0;
     p->fused_combine = fuses_combine(p->sch);
     p->n_streams_max = n_streams;
+    if (nranks > 1) p->fdag.build(p->share);
     if (!p->host_only) {
         rc = allocate_and_upload(p);
         if (rc != SPMV_OK) {
@@ -441,6 +445,86 @@ inline hipError_t prof_end(spmv_plan *p, int slot, hipStream_t s)
 
 }  // namespace
 
+namespace {
+
+// One exec of a fine-grained order (per-peer Pack, copies and waits; see
+// spmv_fine.cpp).  Per-op profiling is not kept in this mode.
+int exec_fine(spmv_plan_t *p, const double *x, double *y, hipStream_t caller)
+{
+    const Share &S = p->share;
+    const FineSchedule &F = p->fsch;
+    const int32_t n_used = std::max<int32_t>(F.n_streams_used, 1);
+    const int64_t n_halo = int64_t(S.halo.size()), n_rr = int64_t(S.R_rows.size());
+    std::vector<int32_t> pack_stream(size_t(S.nranks), 0);
+    for (size_t k = 0; k < F.order.size(); ++k)
+        if (tok_kind(F.order[k]) == 0 && tok_op(F.order[k]) == SPMV_OP_PACK)
+            pack_stream[size_t(tok_peer(F.order[k]))] = F.ostream[k];
+    bool combine = false;
+    for (size_t k = 0; k < F.order.size(); ++k) {
+        const int32_t t = F.order[k], kind = tok_kind(t), op = tok_op(t), q = tok_peer(t);
+        if (kind == SPMV_SYNC_CER) {
+            SPMV_HIP(hipEventRecord(p->ev_pack[size_t(q)], p->st[pack_stream[size_t(q)]]));
+            continue;
+        }
+        if (kind == SPMV_SYNC_CES) {
+            SPMV_HIP(hipEventSynchronize(p->ev_pack[size_t(q)]));
+            continue;
+        }
+        const hipStream_t s = F.ostream[k] >= 0 ? p->st[F.ostream[k]] : nullptr;
+        const int64_t so = q >= 0 ? S.send_off[size_t(q)] : 0;
+        const int64_t sn = q >= 0 ? S.send_off[size_t(q) + 1] - so : 0;
+        const int64_t ro = q >= 0 ? S.recv_off[size_t(q)] : 0;
+        const int64_t rn = q >= 0 ? S.recv_off[size_t(q) + 1] - ro : 0;
+        switch (op) {
+            case SPMV_OP_START:
+                SPMV_HIP(hipEventRecord(p->ev_start, caller));
+                for (int32_t i = 0; i < n_used; ++i)
+                    SPMV_HIP(hipStreamWaitEvent(p->st[i], p->ev_start, 0));
+                break;
+            case SPMV_OP_PACK:
+                SPMV_HIP(launch_pack(x, p->d_send_idx + so, p->d_sendbuf + so, sn, s));
+                break;
+            case SPMV_OP_YL: SPMV_HIP(launch_product(p, 0, x, y, nullptr, s)); break;
+            case SPMV_OP_POST_SEND:
+                SPMV_HIP(hipMemcpyAsync(p->h_outbox + so, p->d_sendbuf + so, size_t(sn) * 8,
+                                        hipMemcpyDeviceToHost, p->cs_send));
+                SPMV_HIP(hipEventRecord(p->ev_psend[size_t(q)], p->cs_send));
+                break;
+            case SPMV_OP_POST_RECV:
+                SPMV_HIP(hipMemcpyAsync(p->d_recvbuf + ro, p->h_inbox + ro, size_t(rn) * 8,
+                                        hipMemcpyHostToDevice, p->cs_recv));
+                SPMV_HIP(hipEventRecord(p->ev_precv[size_t(q)], p->cs_recv));
+                break;
+            case SPMV_OP_WAIT_SEND: SPMV_HIP(hipEventSynchronize(p->ev_psend[size_t(q)])); break;
+            case SPMV_OP_WAIT_RECV: SPMV_HIP(hipEventSynchronize(p->ev_precv[size_t(q)])); break;
+            case SPMV_OP_YR: {
+                // Unpack, implied on y_R's stream right before it
+                if (!p->fuse_unpack)
+                    SPMV_HIP(launch_unpack(p->d_recvbuf, p->d_perm, p->d_xhalo, n_halo, s));
+                const double *xh = p->fuse_unpack ? p->d_recvbuf : p->d_xhalo;
+                if (p->fused_combine)
+                    SPMV_HIP(launch_product(p, 1, xh, nullptr, y, s));
+                else
+                    SPMV_HIP(launch_product(p, 1, xh, p->d_part, nullptr, s));
+                combine = !p->fused_combine && n_rr > 0;
+                break;
+            }
+            case SPMV_OP_END:
+                for (int32_t i = 0; i < n_used; ++i) {
+                    SPMV_HIP(hipEventRecord(p->ev_join[i], p->st[i]));
+                    SPMV_HIP(hipStreamWaitEvent(caller, p->ev_join[i], 0));
+                }
+                if (combine) SPMV_HIP(launch_combine(p->dR_rows, p->d_part, y, n_rr, caller));
+                SPMV_HIP(hipStreamSynchronize(caller));
+                break;
+            default: return set_error(SPMV_EPLAN, "unexpected token in fine-grained schedule");
+        }
+    }
+    return SPMV_OK;
+}
+
+}  // namespace
+
 extern "C" int spmv_exec(spmv_plan_t *p, const double *x, double *y, void *stream_v)
 {
     if (!p) return set_error(SPMV_EINVAL, "plan is NULL");
@@ -452,6 +536,7 @@ extern "C" int spmv_exec(spmv_plan_t *p, const double *x, double *y, void *strea
     int dev = 0;
     SPMV_HIP(hipGetDevice(&dev));
     if (dev != p->device) SPMV_HIP(hipSetDevice(p->device));
+    if (p->fine) return exec_fine(p, x, y, caller);
 
     const int32_t *smap = p->sch.stream;
     const int64_t n_send = int64_t(S.send_idx.size()), n_halo = int64_t(S.halo.size());
@@ -614,7 +699,45 @@ extern "C" int spmv_plan_reorder(spmv_plan_t *p, const int32_t *op_order, int32_
         return set_error(SPMV_EPLAN, "order uses " + std::to_string(sch.n_streams_used) +
                                          " streams, the plan owns " + std::to_string(p->n_st));
     p->sch = std::move(sch);
+    p->fine = false;
     p->fused_combine = fuses_combine(p->sch);
+    return SPMV_OK;
+}
+
+extern "C" int spmv_plan_set_fine(spmv_plan_t *p, const int32_t *op_order,
+                                  const int32_t *op_stream, int32_t n_ops, int32_t n_streams)
+{
+    if (!p) return set_error(SPMV_EINVAL, "plan is NULL");
+    if (p->share.nranks < 2) return set_error(SPMV_EINVAL, "a single rank has no fine-grained DAG");
+    FineSchedule f;
+    std::vector<int32_t> def_ops, def_st;
+    if (!op_order) {
+        fine_default(p->fdag, def_ops, def_st);
+        op_order = def_ops.data();
+        op_stream = def_st.data();
+        n_ops = int32_t(def_ops.size());
+        n_streams = std::max<int32_t>(n_streams, 2);
+    }
+    if (int rc = validate_fine(p->fdag, op_order, op_stream, n_ops, n_streams, f)) return rc;
+    if (!p->host_only && f.n_streams_used > p->n_st)
+        return set_error(SPMV_EPLAN, "order uses " + std::to_string(f.n_streams_used) +
+                                         " streams, the plan owns " + std::to_string(p->n_st));
+    if (!p->host_only && p->ev_pack.empty()) {
+        const size_t P = size_t(p->share.nranks);
+        for (auto *v : {&p->ev_pack, &p->ev_psend, &p->ev_precv}) {
+            v->assign(P, nullptr);
+            for (auto &e : *v) SPMV_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        }
+    }
+    // y_R adds into y itself when it follows y_L on the same stream
+    int32_t pos_l = -1, pos_r = -1;
+    for (size_t k = 0; k < f.order.size(); ++k) {
+        if (f.order[k] == SPMV_OP_YL) pos_l = int32_t(k);
+        if (f.order[k] == SPMV_OP_YR) pos_r = int32_t(k);
+    }
+    p->fsch = std::move(f);
+    p->fine = true;
+    p->fused_combine = pos_l < pos_r && p->fsch.ostream[size_t(pos_l)] == p->fsch.ostream[size_t(pos_r)];
     return SPMV_OK;
 }
 
@@ -658,7 +781,8 @@ extern "C" int spmv_plan_info(const spmv_plan_t *p, spmv_info_t *info)
     info->nranks = S.nranks;
     info->rank = S.rank;
     info->n_streams = p->n_st;
-    info->n_ops = int32_t(p->sch.order.size());
+    info->n_ops = int32_t(p->fine ? p->fsch.order.size() : p->sch.order.size());
+    info->fine = p->fine ? 1 : 0;
     info->kernel_local = p->cfg[0].kernel;
     info->kernel_remote = p->cfg[1].kernel;
     info->lanes_local = p->cfg[0].lanes;
@@ -703,7 +827,16 @@ extern "C" int spmv_plan_get_i32(const spmv_plan_t *p, int32_t which, int32_t *o
         case SPMV_I32_AR_PTR: src = &S.R_ptr; break;
         case SPMV_I32_AR_COLS: src = &S.R_col; break;
         case SPMV_I32_UNPACK_PERM: src = &S.unpack_perm; break;
-        case SPMV_I32_OP_ORDER: src = &p->sch.order; break;
+        case SPMV_I32_OP_ORDER: src = p->fine ? &p->fsch.order : &p->sch.order; break;
+        case SPMV_I32_OP_STREAM:
+            if (p->fine) {
+                src = &p->fsch.ostream;
+            } else {
+                for (int32_t t : p->sch.order)
+                    tmp.push_back(is_vertex(t) && vertex_type(t) == VType::GPU ? p->sch.stream[t] : -1);
+                src = &tmp;
+            }
+            break;
         case SPMV_I32_STREAM_MAP:
             tmp.assign(p->sch.stream, p->sch.stream + SPMV_N_VERTICES);
             src = &tmp;
