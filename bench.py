@@ -252,7 +252,7 @@ def serving_section(sp, torch, gen, n_req: int, rate: float, n_mats: int) -> dic
     return out
 
 
-def rules_section(sp, torch, A, P, r, x, sweep_res, replicas, ktune) -> dict:
+def rules_section(sp, torch, A, P, r, x, sweep_res, replicas, ktune, live=True) -> dict:
     """Design rules from the exhaustive sweep (Sec. IV), the Table V
     experiment on those times (classes and tree from tree-search subsets,
     accuracy over the whole space), and one live tree search on the device."""
@@ -276,6 +276,11 @@ def rules_section(sp, torch, A, P, r, x, sweep_res, replicas, ktune) -> dict:
         res = sp.spmv_mcts_run_table(P, t_all, iterations=it, seed=1)
         acc = rules.class_accuracy(space, t_all, res["index"])
         table_v[str(it or len(space))] = round(acc["accuracy"], 3)
+    out = {"n_classes": len(classes), "classes": classes, "leaves": dr["mln"],
+           "depth": int(dr["tree"].get_depth()) if dr["tree"] is not None else 0,
+           "n_features": len(dr["names"]), "rules_top3": top, "table_v_accuracy": table_v}
+    if not live:
+        return out
     # live search: rollouts timed on the device over cold replicas
     plans = [sp.spmv_plan_create(A, P, r, None, None, 2, ktune) for _ in range(replicas)]
     try:
@@ -289,21 +294,79 @@ def rules_section(sp, torch, A, P, r, x, sweep_res, replicas, ktune) -> dict:
             ys.append(torch.empty(n, dtype=torch.float64, device="cuda"))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        live = sp.spmv_mcts_run(plans, xs, ys, torch.cuda.current_stream(), iterations=200,
-                                seed=2)
+        found = sp.spmv_mcts_run(plans, xs, ys, torch.cuda.current_stream(), iterations=200,
+                                 seed=2)
         wall = time.perf_counter() - t0
     finally:
         for p in plans:
             sp.spmv_plan_destroy(p)
-    best_live = int(live["index"][int(np.argmin(live["time"]))])
-    return {"n_classes": len(classes), "classes": classes, "leaves": dr["mln"],
-            "depth": int(dr["tree"].get_depth()) if dr["tree"] is not None else 0,
-            "n_features": len(dr["names"]), "rules_top3": top, "table_v_accuracy": table_v,
-            "live_search": {"iterations": int(live["index"].size), "wall_s": round(wall, 2),
-                            "best_us": round(float(live["time"].min()) * 1e6, 2),
+    best_live = int(found["index"][int(np.argmin(found["time"]))])
+    return {**out,
+            "live_search": {"iterations": int(found["index"].size), "wall_s": round(wall, 2),
+                            "best_us": round(float(found["time"].min()) * 1e6, 2),
                             "best_index": best_live,
                             "best_class_in_sweep": int(y[best_live]),
                             "sweep_fastest_us": round(float(t_all.min()) * 1e6, 2)}}
+
+
+def fine_section(sp, torch, A, P, r, x, replicas, ktune, coarse_best, iterations=400) -> dict:
+    """The fine-grained program (per-peer Pack / copies / waits, Sec. III-A):
+    a device-timed tree search over its DAG, then the best fine program and
+    the best coarse plan re-measured side by side on the same cold replicas."""
+    plans = [sp.spmv_plan_create(A, P, r, None, None, 2, ktune) for _ in range(replicas)]
+    try:
+        info = sp.spmv_plan_info(plans[0])
+        lo, n = info["lo"], info["n_loc"]
+        halo = sp.spmv_plan_get_i32(plans[0], sp.SPMV_I32_HALO_COLS).astype(np.int64)
+        xs, ys = [], []
+        for p in plans:
+            sp.spmv_plan_inbox(p)[:] = x[halo]
+            xs.append(torch.from_numpy(np.ascontiguousarray(x[lo:lo + n])).cuda())
+            ys.append(torch.empty(n, dtype=torch.float64, device="cuda"))
+        stream = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = sp.spmv_mcts_run_seq(plans, xs, ys, stream, fine=True, iterations=iterations, seed=7)
+        wall = time.perf_counter() - t0
+        k = int(np.argmin(res["time"]))
+        ops, sts = res["ops"][k], res["streams"][k]
+        for p in plans:
+            sp.spmv_plan_set_fine(p, ops, sts)
+        t_fine = sp.spmv_plan_time(plans, xs, ys, stream, 0.01, 5)
+        c_ops, c_map = sp.spmv_plan_space_get(P, 2, coarse_best)
+        for p in plans:
+            sp.spmv_plan_reorder(p, c_ops, c_map, 2)
+        t_coarse = sp.spmv_plan_time(plans, xs, ys, stream, 0.01, 5)
+        count = sp.spmv_fine_count(plans[0], 2)
+    finally:
+        for p in plans:
+            sp.spmv_plan_destroy(p)
+    return {"n_tokens": int(ops.size), "programs": count, "iterations": int(res["time"].size),
+            "wall_s": round(wall, 2),
+            "search_best_us": round(float(res["time"].min()) * 1e6, 2),
+            "search_median_us": round(float(np.median(res["time"])) * 1e6, 2),
+            "best_fine_us": round(float(np.median(t_fine)) * 1e6, 2),
+            "best_coarse_us": round(float(np.median(t_coarse)) * 1e6, 2),
+            "best_fine_order": [sp.spmv_op_name(int(t)) + (f"@{int(s)}" if s >= 0 else "")
+                                for t, s in zip(ops, sts)]}
+
+
+def paper_section(sp, torch, gen, tuner) -> dict:
+    """The paper's own workload (Sec. IV: banded 150,000 x 150,000, 10
+    entries per row in half-bandwidth 37,500, P = 4): every plan of rank 1's
+    share timed cold, and the design-rule pipeline on those times."""
+    w = gen.WORKLOADS["banded_150k_p4r1"]
+    A = w["build"]()
+    P, r = w["nranks"], w["rank"]
+    x = w["x"](A.n_cols)
+    R0 = replicas_for(A, P, r, {}, sp)
+    t0 = time.perf_counter()
+    res = tuner.sweep_plans(A, P, r, x, 2, {}, t_measure=0.01, n_measure=1, replicas=R0)
+    wall = time.perf_counter() - t0
+    out = {"workload": w["desc"], "replicas": R0, "sweep_s": round(wall, 1),
+           "plan_sweep": tuner.sweep_summary(res)}
+    out["design_rules"] = rules_section(sp, torch, A, P, r, x, res, R0, {}, live=False)
+    return out
 
 
 def main() -> int:
@@ -354,7 +417,7 @@ def main() -> int:
     x = w["x"](A.n_cols)
 
     ops = smap = None
-    sweep = design = None
+    sweep = design = fine = None
     if args.plan == "auto" and P > 1:
         from paper_2203_02530_amd import tune as tuner
         ktune = {"lanes_local": args.lanes, "rows_local": args.rows, "kernel_local": args.kernel,
@@ -370,6 +433,7 @@ def main() -> int:
         sweep = tuner.sweep_summary(res)
         if not args.no_rules:
             design = rules_section(sp, torch, A, P, r, x, res, R0, ktune)
+            fine = fine_section(sp, torch, A, P, r, x, R0, ktune, best)
         sweep["chosen_index"] = best
         ops, smap = sp.spmv_plan_space_get(P, 2, best)
     elif args.plan not in ("auto", "default"):
@@ -473,6 +537,10 @@ def main() -> int:
         batched = batched_section(sp, torch, gen, args.batch_shares, reps=4)
     if args.serve_requests > 0:
         serving = serving_section(sp, torch, gen, args.serve_requests, 5000.0, 128)
+    paper = None
+    if args.plan == "auto" and not args.no_rules:
+        from paper_2203_02530_amd import tune as tuner
+        paper = paper_section(sp, torch, gen, tuner)
 
     out = {
         "metric": "rank-share SpMV GB/s vs HBM peak; batched req/s + p50/p99 latency vs plain",
@@ -511,6 +579,8 @@ def main() -> int:
         "in_plan_event_us": {k: round(float(v), 3) for k, v in in_plan_us.items()},
         "plan_sweep": sweep,
         "design_rules": design,
+        "fine_grained": fine,
+        "paper_workload": paper,
         "plan_order": plan_order,
         "plan_streams": plan_streams,
         "gflops": round(2.0 * (info["nnz_local"] + info["nnz_remote"]) / (ms_step * 1e-3) / 1e9, 3),
