@@ -230,21 +230,19 @@ void configure(CsrCfg &c, const std::vector<int32_t> &rp, int64_t n_rows, int32_
         c.rows = rows ? rows : auto_rows(c.lanes, n_rows);
         return;
     }
-    // short rows: a smaller window gives more tiles in flight (7-point:
-    // chunk 4 -> 12.0 us, 8 -> 12.3, 16 -> 16.1); longer rows: 8 (27-point:
-    // 27.3 us vs 29.2 with 16).  Width 2 beat width 4 on both.
+    // A window of 1024 entries (chunk 4) measured best for short and long
+    // stencil rows alike (7-point 11.7 us vs 12.3 with chunk 8; 27-point
+    // 25.0 vs 25.5), width 2 beat width 4 on both.  Summing lanes: about
+    // one per 8 entries of the mean row (27-point: 2 lanes 25.0 us, 1 lane
+    // 26.5, 4 lanes 25.8; 7-point: 1 lane).
     const double mean_len = n_rows > 0 ? double(nnz) / double(n_rows) : 1.0;
-    c.chunk = chunk ? chunk : (mean_len < 12.0 ? 4 : 8);
+    c.chunk = chunk ? chunk : 4;
     c.width = width ? width : 2;
     if (lanes) {
         c.lanes = lanes;
     } else {
-        // enough summing lanes that the rows-per-tile limit (256 / lanes)
-        // does not bind before the window of 256 * chunk entries is full
-        const double mean = n_rows > 0 ? double(nnz) / double(n_rows) : 1.0;
         c.lanes = 1;
-        while (c.lanes < 16 && double(stream_maxr(c.lanes * 2)) * mean >= stream_cap(c.chunk))
-            c.lanes <<= 1;
+        while (c.lanes < 16 && double(c.lanes * 2) * 8.0 <= mean_len) c.lanes <<= 1;
     }
     build_tiles(rp, n_rows, stream_cap(c.chunk), stream_maxr(c.lanes), c.width, c.tile_row,
                 c.tile_k);
