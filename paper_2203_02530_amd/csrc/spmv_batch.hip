@@ -456,7 +456,10 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
     if (e != hipSuccess) return fail(hip_error(e, "hipHostMalloc(batch table)"));
     std::memset(b->h_xy, 0, size_t(2 * n) * sizeof(void *));
     hipStream_t plan_st[1];
-    if ((rc = pool_streams(dev, 1, plan_st, &b->cs_send, &b->cs_recv))) return fail(rc);
+    hipStream_t send_k[kCopyStreams], recv_k[kCopyStreams];
+    if ((rc = pool_streams(dev, 1, plan_st, send_k, recv_k))) return fail(rc);
+    b->cs_send = send_k[0];
+    b->cs_recv = recv_k[0];
     for (hipEvent_t *ev : {&b->ev_a, &b->ev_s, &b->ev_r}) {
         e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
         if (e != hipSuccess) return fail(hip_error(e, "hipEventCreate(batch)"));

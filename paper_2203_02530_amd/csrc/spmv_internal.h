@@ -232,6 +232,10 @@ hipError_t launch_serve(int npt, int vw, const ServeDev *d_desc, const int32_t *
 
 // Per-device stream pool shared by all plans and batches (spmv_plan.cpp):
 // plan streams 0..n_plan-1 and the send / receive copy streams.
+// Copy streams per direction in the per-device pool (per-peer copies of a
+// fine-grained program round-robin over them).
+constexpr int kCopyStreams = 4;
+// send / recv: [kCopyStreams] out.
 int pool_streams(int device, int32_t n_plan, hipStream_t *plan_st, hipStream_t *send,
                  hipStream_t *recv);
 
@@ -284,6 +288,7 @@ struct spmv_plan {
     int32_t n_st = 0;           // plan streams owned
     int32_t n_streams_max = 1;  // as requested at creation
     hipStream_t cs_send = nullptr, cs_recv = nullptr;
+    hipStream_t cs_send_k[spmv::kCopyStreams] = {}, cs_recv_k[spmv::kCopyStreams] = {};
     hipEvent_t ev_start = nullptr, ev_send = nullptr, ev_recv = nullptr;
     hipEvent_t ev_rec[SPMV_N_VERTICES] = {};
     hipEvent_t ev_join[SPMV_MAX_STREAMS] = {};

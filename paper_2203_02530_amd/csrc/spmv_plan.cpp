@@ -27,7 +27,7 @@ namespace spmv {
 // ordering that an exec on the same thread did not already have.  The pool
 // lives until the process ends.
 struct StreamPool {
-    std::array<hipStream_t, SPMV_MAX_STREAMS + 2> st{};
+    std::array<hipStream_t, SPMV_MAX_STREAMS + 2 * kCopyStreams> st{};
 };
 
 int pool_streams(int device, int32_t n_plan, hipStream_t *plan_st, hipStream_t *send,
@@ -37,14 +37,22 @@ int pool_streams(int device, int32_t n_plan, hipStream_t *plan_st, hipStream_t *
     static std::map<int, StreamPool> pools;
     std::lock_guard<std::mutex> lock(mu);
     StreamPool &pool = pools[device];
-    for (int32_t i = 0; i < n_plan + 2; ++i) {
-        const int32_t slot = i < n_plan ? i : SPMV_MAX_STREAMS + (i - n_plan);
+    auto get = [&](int32_t slot) -> int {
         if (!pool.st[size_t(slot)])
             SPMV_HIP(hipStreamCreateWithFlags(&pool.st[size_t(slot)], hipStreamNonBlocking));
+        return SPMV_OK;
+    };
+    for (int32_t i = 0; i < n_plan; ++i) {
+        if (int rc = get(i)) return rc;
+        plan_st[i] = pool.st[size_t(i)];
     }
-    for (int32_t i = 0; i < n_plan; ++i) plan_st[i] = pool.st[size_t(i)];
-    *send = pool.st[SPMV_MAX_STREAMS];
-    *recv = pool.st[SPMV_MAX_STREAMS + 1];
+    // copy streams: [0] the coarse program's, all kCopyStreams for per-peer copies
+    for (int32_t k = 0; k < kCopyStreams; ++k) {
+        if (int rc = get(SPMV_MAX_STREAMS + k)) return rc;
+        if (int rc = get(SPMV_MAX_STREAMS + kCopyStreams + k)) return rc;
+        send[k] = pool.st[size_t(SPMV_MAX_STREAMS + k)];
+        recv[k] = pool.st[size_t(SPMV_MAX_STREAMS + kCopyStreams + k)];
+    }
     return SPMV_OK;
 }
 
@@ -143,7 +151,9 @@ int allocate_and_upload(spmv_plan *p)
     std::memset(p->h_outbox, 0, std::max<size_t>(n_send * 8, 8));
 
     p->n_st = std::max<int32_t>(std::max(p->sch.n_streams_used, p->n_streams_max), 1);
-    if (int rc = pool_streams(p->device, p->n_st, p->st, &p->cs_send, &p->cs_recv)) return rc;
+    if (int rc = pool_streams(p->device, p->n_st, p->st, p->cs_send_k, p->cs_recv_k)) return rc;
+    p->cs_send = p->cs_send_k[0];
+    p->cs_recv = p->cs_recv_k[0];
     SPMV_HIP(hipEventCreateWithFlags(&p->ev_start, hipEventDisableTiming));
     SPMV_HIP(hipEventCreateWithFlags(&p->ev_send, hipEventDisableTiming));
     SPMV_HIP(hipEventCreateWithFlags(&p->ev_recv, hipEventDisableTiming));
@@ -483,16 +493,21 @@ int exec_fine(spmv_plan_t *p, const double *x, double *y, hipStream_t caller)
                 SPMV_HIP(launch_pack(x, p->d_send_idx + so, p->d_sendbuf + so, sn, s));
                 break;
             case SPMV_OP_YL: SPMV_HIP(launch_product(p, 0, x, y, nullptr, s)); break;
-            case SPMV_OP_POST_SEND:
+            case SPMV_OP_POST_SEND: {
+                // each peer's copy on its own copy stream, like concurrent sends
+                const hipStream_t cs = p->cs_send_k[size_t(q) % kCopyStreams];
                 SPMV_HIP(hipMemcpyAsync(p->h_outbox + so, p->d_sendbuf + so, size_t(sn) * 8,
-                                        hipMemcpyDeviceToHost, p->cs_send));
-                SPMV_HIP(hipEventRecord(p->ev_psend[size_t(q)], p->cs_send));
+                                        hipMemcpyDeviceToHost, cs));
+                SPMV_HIP(hipEventRecord(p->ev_psend[size_t(q)], cs));
                 break;
-            case SPMV_OP_POST_RECV:
+            }
+            case SPMV_OP_POST_RECV: {
+                const hipStream_t cs = p->cs_recv_k[size_t(q) % kCopyStreams];
                 SPMV_HIP(hipMemcpyAsync(p->d_recvbuf + ro, p->h_inbox + ro, size_t(rn) * 8,
-                                        hipMemcpyHostToDevice, p->cs_recv));
-                SPMV_HIP(hipEventRecord(p->ev_precv[size_t(q)], p->cs_recv));
+                                        hipMemcpyHostToDevice, cs));
+                SPMV_HIP(hipEventRecord(p->ev_precv[size_t(q)], cs));
                 break;
+            }
             case SPMV_OP_WAIT_SEND: SPMV_HIP(hipEventSynchronize(p->ev_psend[size_t(q)])); break;
             case SPMV_OP_WAIT_RECV: SPMV_HIP(hipEventSynchronize(p->ev_precv[size_t(q)])); break;
             case SPMV_OP_YR: {
