@@ -77,6 +77,8 @@ def replicas_for(A, P, r, tune, sp) -> int:
 
 
 def kernel_variant(info: dict) -> str:
+    if info["kernel_local"] == 2 and info["form_local"] == 3:
+        return "k_sell16<%d>" % (info["chunk_local"] // 8)
     if info["kernel_local"] == 2 and info["form_local"] == 2:
         return "k_sell<%d>" % info["chunk_local"]
     if info["kernel_local"] == 2:
@@ -391,6 +393,9 @@ def main() -> int:
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--kernel", type=int, default=0, help="0 auto, 1 vector CSR, 2 stream CSR")
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--form", type=int, default=0,
+                    help="stream form: 0 auto, 1 packed tiles, 2 sliced ELL, 3 sliced ELL with "
+                         "16-bit column offsets")
     ap.add_argument("--xcd-remap", type=int, default=0)
     ap.add_argument("--fuse-unpack", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -427,7 +432,7 @@ def main() -> int:
     if args.plan == "auto" and P > 1:
         from paper_2203_02530_amd import tune as tuner
         ktune = {"lanes_local": args.lanes, "rows_local": args.rows, "kernel_local": args.kernel,
-                 "chunk_local": args.chunk}
+                 "chunk_local": args.chunk, "form": args.form}
         # rank plans under the timed loop's conditions: cold replicas
         R0 = args.replicas or replicas_for(A, P, r, ktune, sp)
         res = tuner.sweep_plans(A, P, r, x, 2, ktune, t_measure=args.sweep_measure, n_measure=1,
@@ -446,7 +451,7 @@ def main() -> int:
         ops, smap = sp.spmv_plan_space_get(P, 2, int(args.plan))
     tune = {"flags": 0, "lanes_local": args.lanes, "lanes_remote": 0,
             "rows_local": args.rows, "kernel_local": args.kernel, "chunk_local": args.chunk,
-            "xcd_remap": args.xcd_remap, "fuse_unpack": args.fuse_unpack}
+            "xcd_remap": args.xcd_remap, "fuse_unpack": args.fuse_unpack, "form": args.form}
 
     first = sp.spmv_plan_create(A, P, r, ops, smap, 2, tune)
     info = sp.spmv_plan_info(first)

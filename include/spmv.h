@@ -149,9 +149,16 @@ typedef struct {
                               rows, entries stored column-major per slice,
                               each row an fma chain; taken only when padding
                               stays within 15%, else packed tiles; chunk =
-                              entries per batch of loads: 4, 8, 16), 0 =
+                              entries per batch of loads: 4, 8, 16),
+                              3 = sliced ELL whose y_L columns are stored as
+                              16-bit offsets from the row, 8 per lane per
+                              16-byte load (taken when every slice has one
+                              width and every |col - row| <= 32767, else
+                              form 2; y_R takes form 2; chunk 8 or 16), 0 =
                               auto: sliced when every slice of 64 rows has
-                              the same width of at most 8, else packed.
+                              the same width of at most 8 (y_L in form 3
+                              when its offsets fit), else packed.  Every
+                              form gives the same bits for y.
                               Plans in sliced form cannot join a batch.     */
 } spmv_tune_t;
 
@@ -186,6 +193,7 @@ typedef struct {
                               at end adds the remote partial sums            */
     int32_t n_tiles_local, n_tiles_remote;  /* packed stream tiles (0: none) */
     int32_t form_local;    /* y_L stream form: 1 packed tiles, 2 sliced ELL,
+                              3 sliced ELL with 16-bit column offsets,
                               0 vector CSR                                   */
     int32_t form_remote;   /* same for y_R                                   */
     int32_t n_slices_local, n_slices_remote;  /* sliced-ELL slices (0: none) */

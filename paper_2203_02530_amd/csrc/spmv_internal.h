@@ -178,6 +178,9 @@ struct CsrDev {
     const int32_t *sell_ptr = nullptr;
     int32_t n_slices = 0, sell_u = 0;
     int32_t sell_width = 0;        // > 0: every slice this wide (sell_ptr unused)
+    // form 3: `col` holds 16-bit column offsets from the row (grouped 8 per
+    // lane, see build_sell16) in off_bytes bytes
+    uint32_t off_bytes = 0;
 };
 
 // Entries of padding after col/val on the device (vector loads of the
@@ -210,6 +213,21 @@ bool build_sell(const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
                 const std::vector<double> &val, int64_t n_rows, double max_ratio,
                 std::vector<int32_t> &ptr, std::vector<int32_t> &scol, std::vector<double> &sval,
                 int32_t &max_width, bool &uniform);
+// Sliced-ELL product with 16-bit row-relative columns (form 3, one width
+// for every slice): entries in groups of 8 per lane, 8 * `sell_u` entries
+// per batch of loads.
+hipError_t launch_sell16(const CsrDev &A, const double *x, double *out, int xcd_remap,
+                         hipStream_t s);
+// Padding marker of the 16-bit column offsets (never a valid offset).
+constexpr int16_t kPad16 = -32768;
+// The columns of a uniform-width sliced layout as offsets from the row:
+// entry v of row r = 64 s + l (column c) is stored as int16 (c - r) at
+// ((s * G + v / 8) * 64 + l) * 8 + v % 8, G = ceil(width / 8), so that a
+// lane reads 8 entries of its row with one 16-byte load and a wave's load
+// is 1 KiB contiguous; padding holds kPad16.  Returns false, leaving `off`
+// empty, when some |c - r| exceeds 32767 or 32-bit byte offsets overflow.
+bool build_sell16(const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
+                  int64_t n_rows, int32_t width, std::vector<int16_t> &off);
 // Cut [0, n_rows) into CSR-stream tiles (host).
 void build_tiles(const std::vector<int32_t> &rp, int64_t n_rows, int cap, int maxr, int vw,
                  std::vector<int32_t> &tile_row, std::vector<int32_t> &tile_k);
@@ -250,8 +268,10 @@ struct CsrCfg {
     int32_t kernel = SPMV_KERNEL_VECTOR;
     int32_t lanes = 1, rows = 1;   // vector CSR
     int32_t chunk = 8, width = 2;  // stream CSR (lanes = summing lanes)
-    int32_t form = 1;              // stream: 1 packed tiles, 2 sliced ELL
-    std::vector<int32_t> sell_ptr, sell_col;   // form 2, host copies for upload
+    int32_t form = 1;              // stream: 1 packed tiles, 2 sliced ELL,
+                                   // 3 sliced ELL with 16-bit column offsets
+    std::vector<int32_t> sell_ptr, sell_col;   // forms 2/3, host copies for upload
+    std::vector<int16_t> sell_off;             // form 3 (sell_col then empty)
     std::vector<double> sell_val;
     int32_t sell_width = 0;
     bool sell_uniform = false;

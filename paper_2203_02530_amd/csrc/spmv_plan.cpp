@@ -96,15 +96,22 @@ int allocate_and_upload(spmv_plan *p)
     };
     const size_t n_halo = S.halo.size(), n_send = S.send_idx.size(), n_rr = S.R_rows.size();
     const size_t pad = kEntryPad;
-    // col/val of each product: the CSR arrays, or the sliced layout (form 2)
-    auto sliced = [&](int side) { return p->cfg[side].form == 2; };
+    // col/val of each product: the CSR arrays, or the sliced layout (form
+    // 2), whose columns form 3 replaces by 16-bit offsets
+    auto sliced = [&](int side) { return p->cfg[side].form >= 2; };
     auto colsz = [&](int side) {
+        if (p->cfg[side].form == 3) return p->cfg[side].sell_off.size() * 2;
         return (sliced(side) ? p->cfg[side].sell_col.size()
                              : (side == 0 ? S.L_col.size() : S.R_col.size())) * 4;
     };
     auto coldata = [&](int side) -> const void * {
+        if (p->cfg[side].form == 3) return p->cfg[side].sell_off.data();
         return sliced(side) ? p->cfg[side].sell_col.data()
                             : (side == 0 ? S.L_col.data() : S.R_col.data());
+    };
+    auto valsz = [&](int side) {
+        return (sliced(side) ? p->cfg[side].sell_val.size()
+                             : (side == 0 ? S.L_val.size() : S.R_val.size())) * 8;
     };
     auto valdata = [&](int side) -> const void * {
         return sliced(side) ? p->cfg[side].sell_val.data()
@@ -124,8 +131,8 @@ int allocate_and_upload(spmv_plan *p)
         {(void **)&p->d_tile_k[1], p->cfg[1].tile_k.size() * 4, p->cfg[1].tile_k.data(), 0},
         {(void **)&p->d_sell_ptr[0], p->cfg[0].sell_ptr.size() * 4, p->cfg[0].sell_ptr.data(), 0},
         {(void **)&p->d_sell_ptr[1], p->cfg[1].sell_ptr.size() * 4, p->cfg[1].sell_ptr.data(), 0},
-        {(void **)&p->dL_val, colsz(0) * 2, valdata(0), pad * 8},
-        {(void **)&p->dR_val, colsz(1) * 2, valdata(1), pad * 8},
+        {(void **)&p->dL_val, valsz(0), valdata(0), pad * 8},
+        {(void **)&p->dR_val, valsz(1), valdata(1), pad * 8},
         {(void **)&p->d_sendbuf, n_send * 8, nullptr, 0},
         {(void **)&p->d_recvbuf, n_halo * 8, nullptr, 0},
         {(void **)&p->d_xhalo, n_halo * 8, nullptr, 0},
@@ -259,14 +266,19 @@ void configure(CsrCfg &c, const std::vector<int32_t> &rp, int64_t n_rows, int32_
     c.form = form;   // 0 = automatic, resolved by select_sell
 }
 
-// Sliced ELL for a stream product when its form asks for it (2) and its
-// rows are even enough (padding within kSellMaxRatio), or when the form is
-// automatic (0) and moreover every slice has one width of at most
+// Sliced ELL for a stream product when its form asks for it (2 or 3) and
+// its rows are even enough (padding within kSellMaxRatio), or when the form
+// is automatic (0) and moreover every slice has one width of at most
 // kAutoSellWidth; otherwise packed tiles stay.  U (entries per batch of
 // loads) is the chunk when given, else the smallest of 4, 8, 16 that covers
-// the widest slice (16 beyond).
+// the widest slice (16 beyond).  Form 3 (and the automatic choice, once
+// sliced) stores the columns as 16-bit offsets from the row when the
+// product's columns index the rows' own vector (y_L: `row_relative`), every
+// slice has one width and every offset fits; else form 2 stays.  Its U is
+// 8 or 16 (a chunk of 4 or 8 gives 8).
 void select_sell(CsrCfg &c, const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
-                 const std::vector<double> &val, int64_t n_rows, int32_t chunk)
+                 const std::vector<double> &val, int64_t n_rows, int32_t chunk,
+                 bool row_relative)
 {
     const bool ask = c.kernel == SPMV_KERNEL_STREAM && c.form != 1;
     const bool ok = ask && build_sell(rp, col, val, n_rows, kSellMaxRatio, c.sell_ptr,
@@ -278,11 +290,19 @@ void select_sell(CsrCfg &c, const std::vector<int32_t> &rp, const std::vector<in
         c.sell_val.clear();
         return;
     }
+    const int32_t asked = c.form;
     c.form = 2;
     c.chunk = chunk ? chunk : c.sell_width <= 4 ? 4 : c.sell_width <= 8 ? 8 : 16;
     c.lanes = 1;
     c.tile_row.clear();
     c.tile_k.clear();
+    if (row_relative && c.sell_uniform && (asked == 3 || asked == 0) &&
+        build_sell16(rp, col, n_rows, c.sell_width, c.sell_off)) {
+        c.form = 3;
+        c.sell_col.clear();
+        c.sell_col.shrink_to_fit();
+        c.chunk = chunk ? (chunk <= 8 ? 8 : 16) : (c.sell_width <= 8 ? 8 : 16);
+    }
 }
 
 hipError_t launch_product(const spmv_plan *p, int side, const double *x, double *out,
@@ -290,12 +310,16 @@ hipError_t launch_product(const spmv_plan *p, int side, const double *x, double 
 {
     CsrDev A = side == 0 ? local_csr(p) : remote_csr(p);
     const CsrCfg &c = p->cfg[side];
-    if (c.kernel == SPMV_KERNEL_STREAM && c.form == 2) {
+    if (c.kernel == SPMV_KERNEL_STREAM && c.form >= 2) {
         A.sell_ptr = p->d_sell_ptr[side];
         A.n_slices = int32_t(c.sell_ptr.size()) - 1;
         A.sell_u = c.chunk;
         A.sell_width = c.sell_uniform ? c.sell_width : 0;
-        A.nnz_alloc = int64_t(c.sell_col.size()) + kEntryPad;
+        A.nnz_alloc = int64_t(c.sell_val.size()) + kEntryPad;
+        if (c.form == 3) {
+            A.off_bytes = uint32_t((c.sell_off.size() + 2 * kEntryPad) * 2);
+            return launch_sell16(A, x, out, p->xcd_remap, s);
+        }
         return launch_sell(A, x, out, acc, p->xcd_remap, s);
     }
     if (c.kernel == SPMV_KERNEL_STREAM) {
@@ -338,7 +362,7 @@ int create_plan(Build build_share_fn, int32_t nranks, const int32_t *op_order, i
         return set_error(SPMV_EINVAL, "width must be 0, 2 or 4");
     if (t.xcd_remap < 0 || t.xcd_remap > 2 || t.fuse_unpack < 0 || t.fuse_unpack > 1)
         return set_error(SPMV_EINVAL, "tune field out of range");
-    if (t.form < 0 || t.form > 2) return set_error(SPMV_EINVAL, "form must be 0, 1 or 2");
+    if (t.form < 0 || t.form > 3) return set_error(SPMV_EINVAL, "form must be 0, 1, 2 or 3");
 
     std::vector<int32_t> def_ops;
     int32_t def_map[SPMV_N_VERTICES];
@@ -374,8 +398,9 @@ int create_plan(Build build_share_fn, int32_t nranks, const int32_t *op_order, i
               t.chunk_local, t.width, t.form);
     configure(p->cfg[1], S.R_ptr, int64_t(S.R_rows.size()), t.kernel_remote, t.lanes_remote,
               t.rows_remote, t.chunk_remote, t.width, t.form);
-    select_sell(p->cfg[0], S.L_ptr, S.L_col, S.L_val, S.n_loc, t.chunk_local);
-    select_sell(p->cfg[1], S.R_ptr, S.R_col, S.R_val, int64_t(S.R_rows.size()), t.chunk_remote);
+    select_sell(p->cfg[0], S.L_ptr, S.L_col, S.L_val, S.n_loc, t.chunk_local, true);
+    select_sell(p->cfg[1], S.R_ptr, S.R_col, S.R_val, int64_t(S.R_rows.size()), t.chunk_remote,
+                false);
     p->xcd_remap = t.xcd_remap ? t.xcd_remap : 1;
     p->fuse_unpack = t.fuse_unpack == 1;
     p->host_only = (t.flags & SPMV_F_HOST_ONLY) != 0;
@@ -809,7 +834,7 @@ extern "C" int spmv_plan_info(const spmv_plan_t *p, spmv_info_t *info)
         return c.kernel == SPMV_KERNEL_STREAM && c.form == 1 ? int32_t(c.tile_row.size()) - 1 : 0;
     };
     auto slices = [](const CsrCfg &c) {
-        return c.kernel == SPMV_KERNEL_STREAM && c.form == 2 ? int32_t(c.sell_ptr.size()) - 1 : 0;
+        return c.kernel == SPMV_KERNEL_STREAM && c.form >= 2 ? int32_t(c.sell_ptr.size()) - 1 : 0;
     };
     info->n_tiles_local = tiles(p->cfg[0]);
     info->n_tiles_remote = tiles(p->cfg[1]);

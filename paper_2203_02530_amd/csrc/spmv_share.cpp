@@ -299,4 +299,30 @@ bool build_sell(const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
     return true;
 }
 
+bool build_sell16(const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
+                  int64_t n_rows, int32_t width, std::vector<int16_t> &off)
+{
+    off.clear();
+    const int64_t n_slices = (n_rows + 63) / 64, G = (int64_t(width) + 7) / 8;
+    const int64_t total = n_slices * G * 512;
+    if ((total + 64) * 2 >= (int64_t(1) << 32)) return false;
+    off.assign(size_t(total), kPad16);
+    for (int64_t r = 0; r < n_rows; ++r) {
+        const int64_t s = r / 64, l = r % 64;
+        if (rp[size_t(r) + 1] - rp[size_t(r)] > width) {
+            off.clear();
+            return false;
+        }
+        for (int64_t k = rp[size_t(r)]; k < rp[size_t(r) + 1]; ++k) {
+            const int64_t v = k - rp[size_t(r)], d = int64_t(col[size_t(k)]) - r;
+            if (d <= int64_t(kPad16) || d > 32767) {
+                off.clear();
+                return false;
+            }
+            off[size_t(((s * G + v / 8) * 64 + l) * 8 + v % 8)] = int16_t(d);
+        }
+    }
+    return true;
+}
+
 }  // namespace spmv

@@ -64,17 +64,20 @@ __device__ __forceinline__ void load_vec(__amdgpu_buffer_rsrc_t rc, __amdgpu_buf
 }
 
 // The two halves of load_vec, so that a caller can issue all columns first.
+// Columns are read with the default cache policy, values as streaming
+// (non-temporal) data: streaming the columns too measured 3-4% slower on
+// the 7- and 27-point shares.
 template <int VW>
 __device__ __forceinline__ void load_cols(__amdgpu_buffer_rsrc_t rc, uint32_t e, int32_t *c)
 {
     const uint32_t oc = e == kNoEntry ? kOff : e * 4u;
     if constexpr (VW == 2) {
-        const auto cc = __builtin_amdgcn_raw_buffer_load_b64(rc, oc, 0, 2);
+        const auto cc = __builtin_amdgcn_raw_buffer_load_b64(rc, oc, 0, 0);
         c[0] = int32_t(cc[0]);
         c[1] = int32_t(cc[1]);
     } else {
         static_assert(VW == 4, "VW must be 2 or 4");
-        const auto cc = __builtin_amdgcn_raw_buffer_load_b128(rc, oc, 0, 2);
+        const auto cc = __builtin_amdgcn_raw_buffer_load_b128(rc, oc, 0, 0);
 #pragma unroll
         for (int j = 0; j < 4; ++j) c[j] = int32_t(cc[j]);
     }

@@ -451,9 +451,11 @@ def test_power_law_share_structure():
 
 def test_sliced_form_choice_on_host():
     """Automatic form: sliced ELL when every slice of 64 rows has one width
-    of at most 8 (7-point share, its one-entry remote rows), packed tiles
-    otherwise (27-point rows, uneven power-law rows); explicit form 2 takes
-    the sliced layout whenever padding stays within 15%."""
+    of at most 8 (7-point share, its one-entry remote rows), with y_L's
+    columns as 16-bit offsets from the row when they fit (form 3), packed
+    tiles otherwise (27-point rows, uneven power-law rows); explicit form 2
+    takes the sliced layout whenever padding stays within 15%, form 3 moreover
+    needs one width and offsets within 16 bits (else form 2), for y_L only."""
     def info(A, P, r, **tune):
         p = sp.spmv_plan_create(A, P, r, tune={"flags": sp.SPMV_F_HOST_ONLY, **tune})
         try:
@@ -461,19 +463,35 @@ def test_sliced_form_choice_on_host():
         finally:
             sp.spmv_plan_destroy(p)
     i = info(gen.laplacian_3d7(32), 4, 1)
-    assert (i["form_local"], i["form_remote"]) == (2, 2)
+    assert (i["form_local"], i["form_remote"]) == (3, 2)
     assert i["n_slices_local"] == (i["n_loc"] + 63) // 64 and i["n_tiles_local"] == 0
     assert i["n_slices_remote"] == (i["n_remote_rows"] + 63) // 64
     assert i["chunk_local"] == 8 and i["chunk_remote"] == 4
+    i = info(gen.laplacian_3d7(32), 4, 1, form=2)
+    assert (i["form_local"], i["form_remote"]) == (2, 2) and i["chunk_local"] == 8
     i = info(gen.stencil_3d27(20, seed=3), 4, 1)
     assert i["form_local"] == 1 and i["n_slices_local"] == 0 and i["n_tiles_local"] > 0
     i = info(gen.stencil_3d27(20, seed=3), 4, 1, form=2)
     assert i["form_local"] == 2 and i["chunk_local"] == 16
+    # slices of unequal widths (padding to one width > 15% on the small grid)
+    i = info(gen.stencil_3d27(20, seed=3), 4, 1, form=3)
+    assert i["form_local"] == 2
+    i = info(gen.stencil_3d27(40, seed=3), 4, 1, form=3)
+    assert i["form_local"] == 3 and i["chunk_local"] == 16 and i["form_remote"] == 2
+    i = info(gen.stencil_3d27(40, seed=3), 4, 1, form=3, chunk_local=4)
+    assert i["form_local"] == 3 and i["chunk_local"] == 8
+    # offsets up to 40,000 do not fit 16 bits: the 32-bit sliced form stays
+    i = info(gen.banded_uniform(90000, 4, 40000, seed=2), 1, 0, form=3)
+    assert i["form_local"] == 2
+    i = info(gen.banded_uniform(90000, 4, 30000, seed=2), 1, 0, form=3)
+    assert i["form_local"] == 3
     i = info(gen.power_law(20000, seed=3), 4, 1, form=2)
     assert i["form_local"] == 1                      # padding far beyond 15%
+    i = info(gen.power_law(20000, seed=3), 4, 1, form=3)
+    assert i["form_local"] == 1
     i = info(gen.laplacian_3d7(32), 4, 1, form=1)
     assert i["form_local"] == 1 and i["n_tiles_local"] > 0
     i = info(gen.laplacian_3d7(32), 4, 1, kernel_local=1)
     assert i["form_local"] == 0
     with pytest.raises(sp.SpmvError):
-        info(gen.laplacian_3d7(8), 4, 1, form=3)
+        info(gen.laplacian_3d7(8), 4, 1, form=4)

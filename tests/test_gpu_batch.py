@@ -127,11 +127,13 @@ def test_batch_rejects_mixed_configs():
     p3 = sp.spmv_plan_create(A, 2, 1, tune={"kernel_local": 1})
     p4 = sp.spmv_plan_create(A, 2, 1, tune={**TUNE, "form": 2})     # sliced: no tiles
     assert sp.spmv_plan_info(p4)["form_local"] == 2
+    p5 = sp.spmv_plan_create(A, 2, 1, tune={**TUNE, "form": 3})
+    assert sp.spmv_plan_info(p5)["form_local"] == 3
     try:
-        for bad in ([p1, p2], [p1, p3], [p1, p4]):
+        for bad in ([p1, p2], [p1, p3], [p1, p4], [p1, p5]):
             with pytest.raises(sp.SpmvError) as e:
                 sp.spmv_batch_create(bad)
             assert e.value.code == sp.SPMV_EINVAL
     finally:
-        for p in (p1, p2, p3, p4):
+        for p in (p1, p2, p3, p4, p5):
             sp.spmv_plan_destroy(p)

@@ -141,6 +141,75 @@ def test_sliced_form(chunk):
         assert np.array_equal(bits(res["y"]), bits(ref["y"]))
 
 
+def _expected_form(split, ask):
+    """The sliced form a y_L product takes (host rule): 2 when padding each
+    slice of 64 rows to its widest row stays within 15% of the entries; 3
+    (when asked for, or automatic) when one width for every slice fits that
+    too and every column lies within 32767 of its row."""
+    rp, col = np.asarray(split["L_ptr"]), np.asarray(split["L_col"])
+    lens = np.diff(rp)
+    n = lens.size
+    if not n:
+        return 3 if ask in (0, 3) else 2
+    widths = np.array([lens[i:i + 64].max() for i in range(0, n, 64)])
+    budget = 1.15 * max(int(rp[-1]), 1)
+    if 64 * int(widths.sum()) > budget:
+        return 1
+    uniform = 64 * int(widths.max()) * widths.size <= budget
+    rows = np.repeat(np.arange(n), lens)
+    fits = rows.size == 0 or int(np.abs(col - rows).max()) <= 32767
+    if ask == 0:
+        return (3 if fits else 2) if uniform and widths.max() <= 8 else 1
+    return 3 if ask == 3 and uniform and fits else 2
+
+
+@pytest.mark.parametrize("chunk", [0, 8, 16])
+def test_sliced16_form(chunk):
+    """Sliced ELL with 16-bit row-relative columns against the oracle, and
+    bit for bit against the 32-bit sliced form (same entry order): stencils,
+    a ragged last slice, offsets close to the 16-bit limit, and the fall
+    back to 32-bit columns when offsets exceed it or slices differ in
+    width."""
+    log(f"sliced16 form chunk={chunk}")
+    cases = [(gen.laplacian_3d7(48), 4, 1, 3),
+             (gen.stencil_3d27(40, seed=5), 4, 1, 6),
+             (gen.laplacian_2d5(37, 29), 1, 0, 12),               # 1073 rows: ragged last slice
+             (gen.banded_uniform(90000, 4, 30000, seed=2), 1, 0, 4),   # offsets up to 30,000
+             (gen.banded_uniform(90000, 4, 40000, seed=2), 1, 0, 5),   # beyond 16 bits: form 2
+             (gen.stencil_3d27(20, seed=3), 4, 1, 7),              # uneven widths: form 2
+             (gen.banded_uniform(60000, 10, 15000, seed=8), 4, 3, 9)]
+    for A, P, r, seed in cases:
+        x = gen.x_normal(A.n_cols, seed)
+        ref = oracle.share_reference(A, P, r, x)
+        split = oracle.split(A, P, r)
+        tune = {"kernel_local": 2, "kernel_remote": 2, "chunk_local": chunk,
+                "chunk_remote": chunk}
+        ops, smap = sp.spmv_plan_space_get(P, 2, 5) if P > 1 else (None, None)
+        res, _ = run_share(A, P, r, x, ops, smap, tune={**tune, "form": 3}, ref=ref)
+        assert_share_parity(res, ref)
+        assert res["info"]["form_local"] == _expected_form(split, 3), (A.n_rows, P, r)
+        two, _ = run_share(A, P, r, x, ops, smap, tune={**tune, "form": 2}, ref=ref)
+        assert two["info"]["form_local"] in (1, 2)
+        if two["info"]["form_local"] == 2:
+            assert np.array_equal(bits(res["y"]), bits(two["y"]))
+    for A, P, r in [(gen.laplacian_3d7(32), 4, 1), (gen.laplacian_2d5(64), 1, 0)]:
+        x = gen.x_integer(A.n_cols, 9)
+        res, ref = run_share(A, P, r, x, tune={"kernel_local": 2, "chunk_local": chunk, "form": 3})
+        assert res["info"]["form_local"] == 3
+        assert np.array_equal(bits(res["y"]), bits(ref["y"]))
+
+
+def test_automatic_form_rule():
+    """The automatic choice follows the host rule on every parity case."""
+    for A, P, r in [(gen.laplacian_3d7(32), 4, 1), (gen.stencil_3d27(40, seed=5), 4, 1),
+                    (gen.banded_uniform(90000, 4, 40000, seed=2), 1, 0),
+                    (gen.power_law(30000, seed=17), 4, 2)]:
+        x = gen.x_normal(A.n_cols, 1)
+        res, ref = run_share(A, P, r, x)
+        assert_share_parity(res, ref)
+        assert res["info"]["form_local"] == _expected_form(oracle.split(A, P, r), 0)
+
+
 def test_sliced_form_all_plans_identical_and_not_batched():
     import torch
     A = gen.stencil_3d27(24, seed=7)
