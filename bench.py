@@ -37,7 +37,8 @@ MALL_BYTES = 256 << 20         # Infinity Cache
 # known size), keyed by workload and kernel variant; a variant that is not
 # listed (or a kernel changed since) reports null.
 MEASURED_TRAFFIC = {
-    ("laplace3d_128_p4r1", "k_sell<8>"): 54_290_000,
+    ("laplace3d_128_p4r1", "k_sell16<1>"): 47_989_707,
+    ("stencil27_150_p8r3", "k_csr_stream<4,2,2>"): 142_241_301,
 }
 
 
@@ -528,6 +529,7 @@ def main() -> int:
                for name, op in (("yL", sp.SPMV_OP_YL), ("pack", sp.SPMV_OP_PACK),
                                 ("unpack", sp.SPMV_OP_UNPACK), ("yR", sp.SPMV_OP_YR))}
     achieved = B["yL"] / (kern_us["yL"] * 1e-6) / 1e9
+    traffic = MEASURED_TRAFFIC.get((args.workload, kernel_variant(info)))
     in_plan_us = {"pack": in_plan[sp.SPMV_OP_PACK], "yL": in_plan[sp.SPMV_OP_YL],
                   "unpack": in_plan[sp.SPMV_OP_UNPACK], "yR": in_plan[sp.SPMV_OP_YR],
                   "combine": in_plan[sp.SPMV_N_VERTICES],
@@ -581,7 +583,9 @@ def main() -> int:
         "roofline": {"bound": "hbm", "kernel": "y_L " + kernel_variant(info),
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": MEASURED_TRAFFIC.get((args.workload, kernel_variant(info))),
+                     "traffic": traffic,
+                     "traffic_gbs": (round(traffic / (kern_us["yL"] * 1e-6) / 1e9, 1)
+                                     if traffic else None),
                      "bytes_per_launch": B["yL"], "avg_us": round(kern_us["yL"], 3),
                      "launches": launches},
         "kernel_us": {k: round(float(v), 3) for k, v in kern_us.items()},
