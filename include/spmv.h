@@ -302,8 +302,11 @@ int spmv_plan_destroy(spmv_plan_t *plan);
  *
  *   x_local  device [n_loc] owned x entries (read only)
  *   y_local  device [n_loc] result; must not alias x_local
- *   stream   ordering anchor: the plan streams wait for work already issued
- *            to `stream` at start, and `stream` waits for the plan at end
+ *   stream   ordering anchor and plan stream 0: the plan's stream-0 steps
+ *            run on `stream` itself, after work already issued to it; the
+ *            other plan streams wait for that work at start, and `stream`
+ *            waits for them at end (a one-stream plan records no start or
+ *            end events)
  *
  * The halo values are read from the plan's pinned inbox, which the caller
  * fills beforehand (spmv_plan_inbox) with x at the halo columns, in halo

@@ -480,6 +480,15 @@ inline hipError_t prof_end(spmv_plan *p, int slot, hipStream_t s)
 
 namespace {
 
+// The streams an exec runs its plan streams on: plan stream 0 is the
+// caller's stream itself (so a one-stream plan needs no start or end
+// events), the others come from the device pool.
+void plan_streams(const spmv_plan_t *p, hipStream_t caller, int32_t n_used, hipStream_t *st)
+{
+    st[0] = caller;
+    for (int32_t i = 1; i < n_used; ++i) st[i] = p->st[i];
+}
+
 // One exec of a fine-grained order (per-peer Pack, copies and waits; see
 // spmv_fine.cpp).  Per-op profiling is not kept in this mode.
 int exec_fine(spmv_plan_t *p, const double *x, double *y, hipStream_t caller)
@@ -492,27 +501,30 @@ int exec_fine(spmv_plan_t *p, const double *x, double *y, hipStream_t caller)
     for (size_t k = 0; k < F.order.size(); ++k)
         if (tok_kind(F.order[k]) == 0 && tok_op(F.order[k]) == SPMV_OP_PACK)
             pack_stream[size_t(tok_peer(F.order[k]))] = F.ostream[k];
+    hipStream_t st[SPMV_MAX_STREAMS];
+    plan_streams(p, caller, n_used, st);
     bool combine = false;
     for (size_t k = 0; k < F.order.size(); ++k) {
         const int32_t t = F.order[k], kind = tok_kind(t), op = tok_op(t), q = tok_peer(t);
         if (kind == SPMV_SYNC_CER) {
-            SPMV_HIP(hipEventRecord(p->ev_pack[size_t(q)], p->st[pack_stream[size_t(q)]]));
+            SPMV_HIP(hipEventRecord(p->ev_pack[size_t(q)], st[pack_stream[size_t(q)]]));
             continue;
         }
         if (kind == SPMV_SYNC_CES) {
             SPMV_HIP(hipEventSynchronize(p->ev_pack[size_t(q)]));
             continue;
         }
-        const hipStream_t s = F.ostream[k] >= 0 ? p->st[F.ostream[k]] : nullptr;
+        const hipStream_t s = F.ostream[k] >= 0 ? st[F.ostream[k]] : nullptr;
         const int64_t so = q >= 0 ? S.send_off[size_t(q)] : 0;
         const int64_t sn = q >= 0 ? S.send_off[size_t(q) + 1] - so : 0;
         const int64_t ro = q >= 0 ? S.recv_off[size_t(q)] : 0;
         const int64_t rn = q >= 0 ? S.recv_off[size_t(q) + 1] - ro : 0;
         switch (op) {
             case SPMV_OP_START:
-                SPMV_HIP(hipEventRecord(p->ev_start, caller));
-                for (int32_t i = 0; i < n_used; ++i)
-                    SPMV_HIP(hipStreamWaitEvent(p->st[i], p->ev_start, 0));
+                // plan stream 0 is the caller's stream: only the others wait
+                if (n_used > 1) SPMV_HIP(hipEventRecord(p->ev_start, caller));
+                for (int32_t i = 1; i < n_used; ++i)
+                    SPMV_HIP(hipStreamWaitEvent(st[i], p->ev_start, 0));
                 break;
             case SPMV_OP_PACK:
                 SPMV_HIP(launch_pack(x, p->d_send_idx + so, p->d_sendbuf + so, sn, s));
@@ -548,8 +560,8 @@ int exec_fine(spmv_plan_t *p, const double *x, double *y, hipStream_t caller)
                 break;
             }
             case SPMV_OP_END:
-                for (int32_t i = 0; i < n_used; ++i) {
-                    SPMV_HIP(hipEventRecord(p->ev_join[i], p->st[i]));
+                for (int32_t i = 1; i < n_used; ++i) {
+                    SPMV_HIP(hipEventRecord(p->ev_join[i], st[i]));
                     SPMV_HIP(hipStreamWaitEvent(caller, p->ev_join[i], 0));
                 }
                 if (combine) SPMV_HIP(launch_combine(p->dR_rows, p->d_part, y, n_rr, caller));
@@ -582,12 +594,14 @@ extern "C" int spmv_exec(spmv_plan_t *p, const double *x, double *y, void *strea
     bool ran[SPMV_N_VERTICES + 1] = {};
     bool combine = false;
     const int32_t n_used = std::max<int32_t>(p->sch.n_streams_used, 1);
+    hipStream_t st[SPMV_MAX_STREAMS];
+    plan_streams(p, caller, n_used, st);
 
     for (int32_t tok : p->sch.order) {
         if (is_sync(tok)) {
             const int32_t kind = sync_kind(tok), v = sync_operand(tok);
             if (kind == SPMV_SYNC_CER) {
-                SPMV_HIP(hipEventRecord(p->ev_rec[v], p->st[smap[v]]));
+                SPMV_HIP(hipEventRecord(p->ev_rec[v], st[smap[v]]));
             } else {
                 // the wait acts on the records of v's GPU predecessors
                 const int32_t u = v == SPMV_OP_POST_SEND ? SPMV_OP_PACK
@@ -597,18 +611,19 @@ extern "C" int spmv_exec(spmv_plan_t *p, const double *x, double *y, void *strea
                 if (kind == SPMV_SYNC_CES)
                     SPMV_HIP(hipEventSynchronize(p->ev_rec[u]));
                 else
-                    SPMV_HIP(hipStreamWaitEvent(p->st[smap[v]], p->ev_rec[u], 0));
+                    SPMV_HIP(hipStreamWaitEvent(st[smap[v]], p->ev_rec[u], 0));
             }
             continue;
         }
         switch (tok) {
             case SPMV_OP_START:
-                SPMV_HIP(hipEventRecord(p->ev_start, caller));
-                for (int32_t i = 0; i < n_used; ++i)
-                    SPMV_HIP(hipStreamWaitEvent(p->st[i], p->ev_start, 0));
+                // plan stream 0 is the caller's stream: only the others wait
+                if (n_used > 1) SPMV_HIP(hipEventRecord(p->ev_start, caller));
+                for (int32_t i = 1; i < n_used; ++i)
+                    SPMV_HIP(hipStreamWaitEvent(st[i], p->ev_start, 0));
                 break;
             case SPMV_OP_PACK: {
-                hipStream_t s = p->st[smap[tok]];
+                hipStream_t s = st[smap[tok]];
                 SPMV_HIP(prof_begin(p, tok, s));
                 SPMV_HIP(launch_pack(x, p->d_send_idx, p->d_sendbuf, n_send, s));
                 SPMV_HIP(prof_end(p, tok, s));
@@ -616,7 +631,7 @@ extern "C" int spmv_exec(spmv_plan_t *p, const double *x, double *y, void *strea
                 break;
             }
             case SPMV_OP_YL: {
-                hipStream_t s = p->st[smap[tok]];
+                hipStream_t s = st[smap[tok]];
                 SPMV_HIP(prof_begin(p, tok, s));
                 SPMV_HIP(launch_product(p, 0, x, y, nullptr, s));
                 SPMV_HIP(prof_end(p, tok, s));
@@ -645,7 +660,7 @@ extern "C" int spmv_exec(spmv_plan_t *p, const double *x, double *y, void *strea
             case SPMV_OP_WAIT_RECV: SPMV_HIP(hipEventSynchronize(p->ev_recv)); break;
             case SPMV_OP_UNPACK: {
                 if (p->fuse_unpack) break;
-                hipStream_t s = p->st[smap[tok]];
+                hipStream_t s = st[smap[tok]];
                 SPMV_HIP(prof_begin(p, tok, s));
                 SPMV_HIP(launch_unpack(p->d_recvbuf, p->d_perm, p->d_xhalo, n_halo, s));
                 SPMV_HIP(prof_end(p, tok, s));
@@ -653,7 +668,7 @@ extern "C" int spmv_exec(spmv_plan_t *p, const double *x, double *y, void *strea
                 break;
             }
             case SPMV_OP_YR: {
-                hipStream_t s = p->st[smap[tok]];
+                hipStream_t s = st[smap[tok]];
                 const double *xh = p->fuse_unpack ? p->d_recvbuf : p->d_xhalo;
                 SPMV_HIP(prof_begin(p, tok, s));
                 if (p->fused_combine)
@@ -666,8 +681,8 @@ extern "C" int spmv_exec(spmv_plan_t *p, const double *x, double *y, void *strea
                 break;
             }
             case SPMV_OP_END:
-                for (int32_t i = 0; i < n_used; ++i) {
-                    SPMV_HIP(hipEventRecord(p->ev_join[i], p->st[i]));
+                for (int32_t i = 1; i < n_used; ++i) {
+                    SPMV_HIP(hipEventRecord(p->ev_join[i], st[i]));
                     SPMV_HIP(hipStreamWaitEvent(caller, p->ev_join[i], 0));
                 }
                 if (combine) {
