@@ -38,7 +38,8 @@ MALL_BYTES = 256 << 20         # Infinity Cache
 # listed (or a kernel changed since) reports null.
 MEASURED_TRAFFIC = {
     ("laplace3d_128_p4r1", "k_sell16<1>"): 47_989_707,
-    ("stencil27_150_p8r3", "k_csr_stream<4,2,2>"): 142_241_301,
+    ("stencil27_150_p8r3", "k_csr_stream<4,2,2,false>"): 142_241_301,
+    ("stencil27_150_p8r3", "k_csr_stream<4,2,2,true>"): 120_284_162,
 }
 
 
@@ -83,7 +84,8 @@ def kernel_variant(info: dict) -> str:
     if info["kernel_local"] == 2 and info["form_local"] == 2:
         return "k_sell<%d>" % info["chunk_local"]
     if info["kernel_local"] == 2:
-        return "k_csr_stream<%d,%d,%d>" % (info["chunk_local"], info["width"], info["lanes_local"])
+        return "k_csr_stream<%d,%d,%d,%s>" % (info["chunk_local"], info["width"], info["lanes_local"],
+                                              "true" if info["form_local"] == 4 else "false")
     return "k_csr_vector_buf<%d,%d>" % (info["lanes_local"], info["rows_local"])
 
 

@@ -154,12 +154,16 @@ typedef struct {
                               16-bit offsets from the row, 8 per lane per
                               16-byte load (taken when every slice has one
                               width and every |col - row| <= 32767, else
-                              form 2; y_R takes form 2; chunk 8 or 16), 0 =
-                              auto: sliced when every slice of 64 rows has
-                              the same width of at most 8 (y_L in form 3
-                              when its offsets fit), else packed.  Every
+                              form 2; y_R takes form 2; chunk 8 or 16),
+                              4 = packed tiles whose y_L columns are stored
+                              as 16-bit offsets from the first row of their
+                              tile (taken when every offset fits, else form
+                              1; y_R takes form 1), 0 = auto: sliced when
+                              every slice of 64 rows has the same width of
+                              at most 8, else packed, y_L with 16-bit
+                              offsets (forms 3, 4) when they fit.  Every
                               form gives the same bits for y.
-                              Plans in sliced form cannot join a batch.     */
+                              Only form 1 plans can join a batch.         */
 } spmv_tune_t;
 
 #define SPMV_F_HOST_ONLY  1  /* build metadata only: no device resources;
@@ -194,6 +198,7 @@ typedef struct {
     int32_t n_tiles_local, n_tiles_remote;  /* packed stream tiles (0: none) */
     int32_t form_local;    /* y_L stream form: 1 packed tiles, 2 sliced ELL,
                               3 sliced ELL with 16-bit column offsets,
+                              4 packed tiles with 16-bit column offsets,
                               0 vector CSR                                   */
     int32_t form_remote;   /* same for y_R                                   */
     int32_t n_slices_local, n_slices_remote;  /* sliced-ELL slices (0: none) */

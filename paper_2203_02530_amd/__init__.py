@@ -373,10 +373,10 @@ _I32_LEN = {
     SPMV_I32_AR_COLS: lambda i: i["nnz_remote"], SPMV_I32_UNPACK_PERM: lambda i: i["n_halo"],
     SPMV_I32_OP_ORDER: lambda i: i["n_ops"], SPMV_I32_STREAM_MAP: lambda i: SPMV_N_VERTICES,
     SPMV_I32_OP_STREAM: lambda i: i["n_ops"],
-    SPMV_I32_TILE_ROW_L: lambda i: i["n_tiles_local"] + 1 if i["form_local"] == 1 else 0,
-    SPMV_I32_TILE_K_L: lambda i: i["n_tiles_local"] + 1 if i["form_local"] == 1 else 0,
-    SPMV_I32_TILE_ROW_R: lambda i: i["n_tiles_remote"] + 1 if i["form_remote"] == 1 else 0,
-    SPMV_I32_TILE_K_R: lambda i: i["n_tiles_remote"] + 1 if i["form_remote"] == 1 else 0,
+    SPMV_I32_TILE_ROW_L: lambda i: i["n_tiles_local"] + 1 if i["form_local"] in (1, 4) else 0,
+    SPMV_I32_TILE_K_L: lambda i: i["n_tiles_local"] + 1 if i["form_local"] in (1, 4) else 0,
+    SPMV_I32_TILE_ROW_R: lambda i: i["n_tiles_remote"] + 1 if i["form_remote"] in (1, 4) else 0,
+    SPMV_I32_TILE_K_R: lambda i: i["n_tiles_remote"] + 1 if i["form_remote"] in (1, 4) else 0,
 }
 _F64_LEN = {
     SPMV_F64_AL_VAL: lambda i: i["nnz_local"], SPMV_F64_AR_VAL: lambda i: i["nnz_remote"],

@@ -181,6 +181,9 @@ struct CsrDev {
     // form 3: `col` holds 16-bit column offsets from the row (grouped 8 per
     // lane, see build_sell16) in off_bytes bytes
     uint32_t off_bytes = 0;
+    // form 4: `col` holds int16 offsets of each column from the first row of
+    // the entry's tile (see build_tile16)
+    bool col16 = false;
 };
 
 // Entries of padding after col/val on the device (vector loads of the
@@ -228,6 +231,12 @@ constexpr int16_t kPad16 = -32768;
 // empty, when some |c - r| exceeds 32767 or 32-bit byte offsets overflow.
 bool build_sell16(const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
                   int64_t n_rows, int32_t width, std::vector<int16_t> &off);
+// The columns of a product cut into stream tiles as int16 offsets from the
+// first row of each entry's tile: off[k] = col[k] - tile_row[t] for k in
+// [tile_k[t], tile_k[t+1]).  Returns false, leaving `off` empty, when an
+// offset does not fit 16 bits.
+bool build_tile16(const std::vector<int32_t> &col, const std::vector<int32_t> &tile_row,
+                  const std::vector<int32_t> &tile_k, std::vector<int16_t> &off);
 // Cut [0, n_rows) into CSR-stream tiles (host).
 void build_tiles(const std::vector<int32_t> &rp, int64_t n_rows, int cap, int maxr, int vw,
                  std::vector<int32_t> &tile_row, std::vector<int32_t> &tile_k);
@@ -269,9 +278,11 @@ struct CsrCfg {
     int32_t lanes = 1, rows = 1;   // vector CSR
     int32_t chunk = 8, width = 2;  // stream CSR (lanes = summing lanes)
     int32_t form = 1;              // stream: 1 packed tiles, 2 sliced ELL,
-                                   // 3 sliced ELL with 16-bit column offsets
+                                   // 3 sliced ELL with 16-bit column offsets,
+                                   // 4 packed tiles with 16-bit column offsets
     std::vector<int32_t> sell_ptr, sell_col;   // forms 2/3, host copies for upload
     std::vector<int16_t> sell_off;             // form 3 (sell_col then empty)
+    std::vector<int16_t> tile_off;             // form 4
     std::vector<double> sell_val;
     int32_t sell_width = 0;
     bool sell_uniform = false;

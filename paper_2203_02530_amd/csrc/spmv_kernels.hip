@@ -177,12 +177,13 @@ __global__ __launch_bounds__(kBlock) void k_csr_vector_buf(
 }
 
 // Single-share stream-CSR product: one block per tile (see spmv_stream.h).
-template <int NPT, int VW, int SL>
+template <int NPT, int VW, int SL, bool C16>
 __global__ __launch_bounds__(kBlock) void k_csr_stream(StreamArgs A, int remap)
 {
     __shared__ double s_p[kBlock * NPT];
     __shared__ int32_t s_rp[kBlock / SL + 1];
-    stream_tile<NPT, VW, SL>(A, tile_of_block(int(blockIdx.x), int(gridDim.x), remap), s_p, s_rp);
+    stream_tile<NPT, VW, SL, C16>(A, tile_of_block(int(blockIdx.x), int(gridDim.x), remap), s_p,
+                                  s_rp);
 }
 
 // Sliced-ELL product: one wave per slice of 64 rows; lane l owns row
@@ -392,8 +393,12 @@ hipError_t launch_stream_t(const CsrDev &A, const double *x, double *out, double
     a.acc = acc;
     a.nnz_alloc = uint32_t(A.nnz_alloc);
     a.n_x = uint32_t(A.n_x);
-    hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL>), dim3(unsigned(A.n_tiles)), dim3(kBlock), 0, s,
-                       a, remap);
+    if (A.col16)
+        hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, true>), dim3(unsigned(A.n_tiles)),
+                           dim3(kBlock), 0, s, a, remap);
+    else
+        hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, false>), dim3(unsigned(A.n_tiles)),
+                           dim3(kBlock), 0, s, a, remap);
     return hipGetLastError();
 }
 

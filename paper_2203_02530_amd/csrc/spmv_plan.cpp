@@ -98,14 +98,16 @@ int allocate_and_upload(spmv_plan *p)
     const size_t pad = kEntryPad;
     // col/val of each product: the CSR arrays, or the sliced layout (form
     // 2), whose columns form 3 replaces by 16-bit offsets
-    auto sliced = [&](int side) { return p->cfg[side].form >= 2; };
+    auto sliced = [&](int side) { return p->cfg[side].form == 2 || p->cfg[side].form == 3; };
     auto colsz = [&](int side) {
         if (p->cfg[side].form == 3) return p->cfg[side].sell_off.size() * 2;
+        if (p->cfg[side].form == 4) return p->cfg[side].tile_off.size() * 2;
         return (sliced(side) ? p->cfg[side].sell_col.size()
                              : (side == 0 ? S.L_col.size() : S.R_col.size())) * 4;
     };
     auto coldata = [&](int side) -> const void * {
         if (p->cfg[side].form == 3) return p->cfg[side].sell_off.data();
+        if (p->cfg[side].form == 4) return p->cfg[side].tile_off.data();
         return sliced(side) ? p->cfg[side].sell_col.data()
                             : (side == 0 ? S.L_col.data() : S.R_col.data());
     };
@@ -280,7 +282,7 @@ void select_sell(CsrCfg &c, const std::vector<int32_t> &rp, const std::vector<in
                  const std::vector<double> &val, int64_t n_rows, int32_t chunk,
                  bool row_relative)
 {
-    const bool ask = c.kernel == SPMV_KERNEL_STREAM && c.form != 1;
+    const bool ask = c.kernel == SPMV_KERNEL_STREAM && c.form != 1 && c.form != 4;
     const bool ok = ask && build_sell(rp, col, val, n_rows, kSellMaxRatio, c.sell_ptr,
                                       c.sell_col, c.sell_val, c.sell_width, c.sell_uniform);
     if (!ok || (c.form == 0 && !(c.sell_uniform && c.sell_width <= kAutoSellWidth))) {
@@ -305,12 +307,21 @@ void select_sell(CsrCfg &c, const std::vector<int32_t> &rp, const std::vector<in
     }
 }
 
+// Form 4 for y_L in packed tiles when asked for (4) or automatic (0):
+// columns as int16 offsets from the first row of each tile, when they fit;
+// else the 32-bit columns stay (form 1).
+void select_tile16(CsrCfg &c, const std::vector<int32_t> &col, int32_t asked)
+{
+    if (c.kernel != SPMV_KERNEL_STREAM || c.form != 1 || (asked != 0 && asked != 4)) return;
+    if (build_tile16(col, c.tile_row, c.tile_k, c.tile_off)) c.form = 4;
+}
+
 hipError_t launch_product(const spmv_plan *p, int side, const double *x, double *out,
                           double *acc, hipStream_t s)
 {
     CsrDev A = side == 0 ? local_csr(p) : remote_csr(p);
     const CsrCfg &c = p->cfg[side];
-    if (c.kernel == SPMV_KERNEL_STREAM && c.form >= 2) {
+    if (c.kernel == SPMV_KERNEL_STREAM && (c.form == 2 || c.form == 3)) {
         A.sell_ptr = p->d_sell_ptr[side];
         A.n_slices = int32_t(c.sell_ptr.size()) - 1;
         A.sell_u = c.chunk;
@@ -326,6 +337,7 @@ hipError_t launch_product(const spmv_plan *p, int side, const double *x, double 
         A.tile_row = p->d_tile_row[side];
         A.tile_k = p->d_tile_k[side];
         A.n_tiles = int32_t(c.tile_row.size()) - 1;
+        A.col16 = c.form == 4;
         return launch_csr_stream(A, x, out, acc, c.chunk, c.width, c.lanes, p->xcd_remap, s);
     }
     return launch_csr(A, x, out, acc, c.lanes, c.rows, p->xcd_remap, p->use_buffer, s);
@@ -362,7 +374,7 @@ int create_plan(Build build_share_fn, int32_t nranks, const int32_t *op_order, i
         return set_error(SPMV_EINVAL, "width must be 0, 2 or 4");
     if (t.xcd_remap < 0 || t.xcd_remap > 2 || t.fuse_unpack < 0 || t.fuse_unpack > 1)
         return set_error(SPMV_EINVAL, "tune field out of range");
-    if (t.form < 0 || t.form > 3) return set_error(SPMV_EINVAL, "form must be 0, 1, 2 or 3");
+    if (t.form < 0 || t.form > 4) return set_error(SPMV_EINVAL, "form must be 0 to 4");
 
     std::vector<int32_t> def_ops;
     int32_t def_map[SPMV_N_VERTICES];
@@ -399,6 +411,7 @@ int create_plan(Build build_share_fn, int32_t nranks, const int32_t *op_order, i
     configure(p->cfg[1], S.R_ptr, int64_t(S.R_rows.size()), t.kernel_remote, t.lanes_remote,
               t.rows_remote, t.chunk_remote, t.width, t.form);
     select_sell(p->cfg[0], S.L_ptr, S.L_col, S.L_val, S.n_loc, t.chunk_local, true);
+    select_tile16(p->cfg[0], S.L_col, t.form);
     select_sell(p->cfg[1], S.R_ptr, S.R_col, S.R_val, int64_t(S.R_rows.size()), t.chunk_remote,
                 false);
     p->xcd_remap = t.xcd_remap ? t.xcd_remap : 1;
@@ -846,10 +859,14 @@ extern "C" int spmv_plan_info(const spmv_plan_t *p, spmv_info_t *info)
     info->chunk_remote = p->cfg[1].chunk;
     info->width = p->cfg[0].kernel == SPMV_KERNEL_STREAM ? p->cfg[0].width : p->cfg[1].width;
     auto tiles = [](const CsrCfg &c) {
-        return c.kernel == SPMV_KERNEL_STREAM && c.form == 1 ? int32_t(c.tile_row.size()) - 1 : 0;
+        return c.kernel == SPMV_KERNEL_STREAM && (c.form == 1 || c.form == 4)
+                   ? int32_t(c.tile_row.size()) - 1
+                   : 0;
     };
     auto slices = [](const CsrCfg &c) {
-        return c.kernel == SPMV_KERNEL_STREAM && c.form >= 2 ? int32_t(c.sell_ptr.size()) - 1 : 0;
+        return c.kernel == SPMV_KERNEL_STREAM && (c.form == 2 || c.form == 3)
+                   ? int32_t(c.sell_ptr.size()) - 1
+                   : 0;
     };
     info->n_tiles_local = tiles(p->cfg[0]);
     info->n_tiles_remote = tiles(p->cfg[1]);

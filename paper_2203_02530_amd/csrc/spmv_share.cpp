@@ -325,4 +325,21 @@ bool build_sell16(const std::vector<int32_t> &rp, const std::vector<int32_t> &co
     return true;
 }
 
+bool build_tile16(const std::vector<int32_t> &col, const std::vector<int32_t> &tile_row,
+                  const std::vector<int32_t> &tile_k, std::vector<int16_t> &off)
+{
+    off.assign(col.size(), 0);
+    for (size_t t = 0; t + 1 < tile_row.size(); ++t) {
+        for (int64_t k = tile_k[t]; k < tile_k[t + 1]; ++k) {
+            const int64_t d = int64_t(col[size_t(k)]) - tile_row[t];
+            if (d < -32767 || d > 32767) {
+                off.clear();
+                return false;
+            }
+            off[size_t(k)] = int16_t(d);
+        }
+    }
+    return true;
+}
+
 }  // namespace spmv

@@ -83,6 +83,28 @@ __device__ __forceinline__ void load_cols(__amdgpu_buffer_rsrc_t rc, uint32_t e,
     }
 }
 
+// The same for 16-bit column offsets from a base row (the tile's first
+// row): VW offsets in one 4- or 8-byte load at byte 2e.
+template <int VW>
+__device__ __forceinline__ void load_cols16(__amdgpu_buffer_rsrc_t rc, uint32_t e, int32_t base_row,
+                                            int32_t *c)
+{
+    const uint32_t oc = e == kNoEntry ? kOff : e * 2u;
+    if constexpr (VW == 2) {
+        const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rc, oc, 0, 0);
+        c[0] = base_row + int32_t(int16_t(uint16_t(w & 0xFFFFu)));
+        c[1] = base_row + (int32_t(w) >> 16);
+    } else {
+        static_assert(VW == 4, "VW must be 2 or 4");
+        const auto w = __builtin_amdgcn_raw_buffer_load_b64(rc, oc, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            c[2 * j] = base_row + int32_t(int16_t(uint16_t(uint32_t(w[j]) & 0xFFFFu)));
+            c[2 * j + 1] = base_row + (int32_t(w[j]) >> 16);
+        }
+    }
+}
+
 template <int VW>
 __device__ __forceinline__ void load_vals(__amdgpu_buffer_rsrc_t rv, uint32_t e, double *a)
 {
@@ -104,6 +126,8 @@ __device__ __forceinline__ double load_x(__amdgpu_buffer_rsrc_t rx, uint32_t off
 
 // Operands of one stream-CSR product.  out[r] = row sum (acc == nullptr) or
 // acc[rows[r]] += row sum.  nnz_alloc = entries incl. padding, n_x = |x|.
+// With 16-bit columns (C16), col holds int16 offsets of each entry's column
+// from the first row of its tile.
 struct StreamArgs {
     const int32_t *tile_row, *tile_k, *rp, *col, *rows;
     const double *val, *x;
@@ -126,7 +150,7 @@ struct TileRegs {
 // Stage 1: the tile's bounds, its window's columns and values, then its row
 // pointers.  The two load groups are independent, so their memory latencies
 // overlap (the row pointers wait in registers until the LDS stage).
-template <int NPT, int VW>
+template <int NPT, int VW, bool C16 = false>
 __device__ __forceinline__ void tile_load(const StreamArgs &A, __amdgpu_buffer_rsrc_t r_col,
                                           __amdgpu_buffer_rsrc_t r_val, int t,
                                           TileRegs<NPT, VW> &T)
@@ -142,7 +166,10 @@ __device__ __forceinline__ void tile_load(const StreamArgs &A, __amdgpu_buffer_r
 #pragma unroll
     for (int v = 0; v < T.NV; ++v) {
         const int e = T.base + (v * kBlock + tid) * VW;
-        load_cols<VW>(r_col, e < T.k1 ? uint32_t(e) : kNoEntry, T.c[v]);
+        if constexpr (C16)
+            load_cols16<VW>(r_col, e < T.k1 ? uint32_t(e) : kNoEntry, T.r0, T.c[v]);
+        else
+            load_cols<VW>(r_col, e < T.k1 ? uint32_t(e) : kNoEntry, T.c[v]);
     }
 #pragma unroll
     for (int v = 0; v < T.NV; ++v) {
@@ -216,13 +243,13 @@ __device__ __forceinline__ void tile_reduce(const StreamArgs &A, const TileRegs<
 // One tile.  s_p: LDS[kBlock * NPT] doubles, s_rp: LDS[kBlock / SL + 1] ints.
 // Block-uniform control flow; the caller separates consecutive tiles with a
 // barrier (LDS is reused).
-template <int NPT, int VW, int SL>
+template <int NPT, int VW, int SL, bool C16 = false>
 __device__ __forceinline__ void stream_tile(const StreamArgs &A, int t, double *s_p, int32_t *s_rp)
 {
     constexpr int CAP = kBlock * NPT;
     constexpr int NV = NPT / VW;
     static_assert(NPT % VW == 0, "NPT must be a multiple of VW");
-    const auto r_col = rsrc(A.col, A.nnz_alloc * 4u);
+    const auto r_col = rsrc(A.col, A.nnz_alloc * (C16 ? 2u : 4u));
     const auto r_val = rsrc(A.val, A.nnz_alloc * 8u);
     const auto r_x = rsrc(A.x, A.n_x * 8u);
     const int r0 = A.tile_row[t], r1 = A.tile_row[t + 1];
@@ -240,7 +267,12 @@ __device__ __forceinline__ void stream_tile(const StreamArgs &A, int t, double *
                 const int e = w0 + (v * kBlock + tid) * VW;
                 int32_t c[VW];
                 double a[VW];
-                load_vec<VW>(r_col, r_val, e < k1 ? uint32_t(e) : kNoEntry, c, a);
+                if constexpr (C16) {
+                    load_cols16<VW>(r_col, e < k1 ? uint32_t(e) : kNoEntry, r0, c);
+                    load_vals<VW>(r_val, e < k1 ? uint32_t(e) : kNoEntry, a);
+                } else {
+                    load_vec<VW>(r_col, r_val, e < k1 ? uint32_t(e) : kNoEntry, c, a);
+                }
 #pragma unroll
                 for (int j = 0; j < VW; ++j) {
                     const bool ok = e + j >= k0 && e + j < k1;
@@ -264,7 +296,7 @@ __device__ __forceinline__ void stream_tile(const StreamArgs &A, int t, double *
     }
 
     TileRegs<NPT, VW> T;
-    tile_load<NPT, VW>(A, r_col, r_val, t, T);
+    tile_load<NPT, VW, C16>(A, r_col, r_val, t, T);
     tile_gather<NPT, VW>(r_x, T);
     tile_reduce<NPT, VW, SL>(A, T, s_p, s_rp);
 }

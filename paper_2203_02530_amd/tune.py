@@ -131,6 +131,7 @@ def sweep_summary(results) -> dict:
 DEFAULT_CANDIDATES = (
     [{"kernel_local": 2, "form": 3, "chunk_local": c} for c in (8, 16)] +
     [{"kernel_local": 2, "form": 2, "chunk_local": c} for c in (4, 8, 16)] +
+    [{"kernel_local": 2, "form": 4, "chunk_local": c, "width": 2} for c in (4, 8, 16)] +
     [{"kernel_local": 2, "form": 1, "chunk_local": c, "width": 2} for c in (4, 8, 16)] +
     [{"kernel_local": 2, "form": 1, "chunk_local": c, "width": 2, "lanes_local": l}
      for c in (4, 8) for l in (1, 2, 4)] +

@@ -453,9 +453,11 @@ def test_sliced_form_choice_on_host():
     """Automatic form: sliced ELL when every slice of 64 rows has one width
     of at most 8 (7-point share, its one-entry remote rows), with y_L's
     columns as 16-bit offsets from the row when they fit (form 3), packed
-    tiles otherwise (27-point rows, uneven power-law rows); explicit form 2
-    takes the sliced layout whenever padding stays within 15%, form 3 moreover
-    needs one width and offsets within 16 bits (else form 2), for y_L only."""
+    tiles otherwise (27-point rows, uneven power-law rows), y_L's columns
+    as 16-bit offsets from each tile's first row when they fit (form 4);
+    explicit form 2 takes the sliced layout whenever padding stays within
+    15%, form 3 moreover needs one width and offsets within 16 bits (else
+    form 2), for y_L only; form 4 needs the tile offsets to fit (else 1)."""
     def info(A, P, r, **tune):
         p = sp.spmv_plan_create(A, P, r, tune={"flags": sp.SPMV_F_HOST_ONLY, **tune})
         try:
@@ -470,7 +472,17 @@ def test_sliced_form_choice_on_host():
     i = info(gen.laplacian_3d7(32), 4, 1, form=2)
     assert (i["form_local"], i["form_remote"]) == (2, 2) and i["chunk_local"] == 8
     i = info(gen.stencil_3d27(20, seed=3), 4, 1)
-    assert i["form_local"] == 1 and i["n_slices_local"] == 0 and i["n_tiles_local"] > 0
+    assert i["form_local"] == 4 and i["n_slices_local"] == 0 and i["n_tiles_local"] > 0
+    i = info(gen.stencil_3d27(20, seed=3), 4, 1, form=1)
+    assert i["form_local"] == 1 and i["n_tiles_local"] > 0
+    i = info(gen.laplacian_3d7(32), 4, 1, form=4)
+    assert i["form_local"] == 4 and i["n_tiles_local"] > 0 and i["form_remote"] == 1
+    i = info(gen.power_law(20000, seed=3), 4, 1, form=4)
+    assert i["form_local"] == 4                      # 5,000 local columns: all fit
+    i = info(gen.power_law(200000, seed=3), 2, 1, form=4)
+    assert i["form_local"] == 1                      # columns far from the rows'
+    i = info(gen.power_law(200000, seed=3), 2, 1)
+    assert i["form_local"] == 1
     i = info(gen.stencil_3d27(20, seed=3), 4, 1, form=2)
     assert i["form_local"] == 2 and i["chunk_local"] == 16
     # slices of unequal widths (padding to one width > 15% on the small grid)
@@ -494,4 +506,4 @@ def test_sliced_form_choice_on_host():
     i = info(gen.laplacian_3d7(32), 4, 1, kernel_local=1)
     assert i["form_local"] == 0
     with pytest.raises(sp.SpmvError):
-        info(gen.laplacian_3d7(8), 4, 1, form=4)
+        info(gen.laplacian_3d7(8), 4, 1, form=5)

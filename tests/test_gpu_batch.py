@@ -129,11 +129,13 @@ def test_batch_rejects_mixed_configs():
     assert sp.spmv_plan_info(p4)["form_local"] == 2
     p5 = sp.spmv_plan_create(A, 2, 1, tune={**TUNE, "form": 3})
     assert sp.spmv_plan_info(p5)["form_local"] == 3
+    p6 = sp.spmv_plan_create(A, 2, 1, tune={**TUNE, "form": 4})
+    assert sp.spmv_plan_info(p6)["form_local"] == 4
     try:
-        for bad in ([p1, p2], [p1, p3], [p1, p4], [p1, p5]):
+        for bad in ([p1, p2], [p1, p3], [p1, p4], [p1, p5], [p1, p6]):
             with pytest.raises(sp.SpmvError) as e:
                 sp.spmv_batch_create(bad)
             assert e.value.code == sp.SPMV_EINVAL
     finally:
-        for p in (p1, p2, p3, p4, p5):
+        for p in (p1, p2, p3, p4, p5, p6):
             sp.spmv_plan_destroy(p)

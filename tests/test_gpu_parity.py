@@ -142,25 +142,71 @@ def test_sliced_form(chunk):
 
 
 def _expected_form(split, ask):
-    """The sliced form a y_L product takes (host rule): 2 when padding each
+    """The stream form a y_L product takes (host rule): 2 when padding each
     slice of 64 rows to its widest row stays within 15% of the entries; 3
     (when asked for, or automatic) when one width for every slice fits that
-    too and every column lies within 32767 of its row."""
+    too and every column lies within 32767 of its row; packed tiles
+    otherwise, 4 (asked for, or automatic) when every column lies within
+    16 bits of its tile's first row (decided here with the 256-row margin
+    of a tile: the cases below stay clear of the edge)."""
     rp, col = np.asarray(split["L_ptr"]), np.asarray(split["L_col"])
     lens = np.diff(rp)
     n = lens.size
+    rows = np.repeat(np.arange(n), lens)
+    dmax = int(np.abs(col - rows).max()) if rows.size else 0
+    tile_fits = dmax <= 32767 - 256
+    assert tile_fits or dmax > 32767 + 256
+    packed = 4 if ask in (0, 4) and tile_fits else 1
+    if ask in (1, 4):
+        return packed
     if not n:
         return 3 if ask in (0, 3) else 2
     widths = np.array([lens[i:i + 64].max() for i in range(0, n, 64)])
     budget = 1.15 * max(int(rp[-1]), 1)
     if 64 * int(widths.sum()) > budget:
-        return 1
+        return packed
     uniform = 64 * int(widths.max()) * widths.size <= budget
-    rows = np.repeat(np.arange(n), lens)
-    fits = rows.size == 0 or int(np.abs(col - rows).max()) <= 32767
+    fits = dmax <= 32767
     if ask == 0:
-        return (3 if fits else 2) if uniform and widths.max() <= 8 else 1
+        return (3 if fits else 2) if uniform and widths.max() <= 8 else packed
     return 3 if ask == 3 and uniform and fits else 2
+
+
+@pytest.mark.parametrize("chunk,width,lanes", [(0, 0, 0), (4, 2, 1), (8, 4, 2), (16, 2, 4)])
+def test_packed16_form(chunk, width, lanes):
+    """Packed tiles with 16-bit columns relative to each tile's first row
+    against the oracle, and bit for bit against 32-bit packed tiles (same
+    tiles, same order): stencils, banded rows with offsets near the 16-bit
+    limit, rows longer than a window, and the fall back to 32-bit columns."""
+    log(f"packed16 form chunk={chunk} width={width} lanes={lanes}")
+    cases = [(gen.stencil_3d27(30, seed=5), 4, 2, 6),
+             (gen.laplacian_3d7(48), 4, 1, 3),
+             (gen.banded_uniform(90000, 4, 32000, seed=2), 1, 0, 4),   # offsets up to 32,000
+             (gen.banded_uniform(2000, 1500, 2000, seed=7), 1, 0, 8),  # rows longer than a window
+             (gen.banded_uniform(90000, 4, 40000, seed=2), 1, 0, 5),   # beyond 16 bits: form 1
+             (gen.power_law(30000, seed=17), 4, 2, 18),
+             (gen.laplacian_2d5(37, 29), 1, 0, 12)]
+    for A, P, r, seed in cases:
+        x = gen.x_normal(A.n_cols, seed)
+        ref = oracle.share_reference(A, P, r, x)
+        split = oracle.split(A, P, r)
+        tune = {"kernel_local": 2, "kernel_remote": 2, "chunk_local": chunk,
+                "chunk_remote": chunk, "width": width, "lanes_local": lanes}
+        ops, smap = sp.spmv_plan_space_get(P, 2, 7) if P > 1 else (None, None)
+        res, _ = run_share(A, P, r, x, ops, smap, tune={**tune, "form": 4}, ref=ref)
+        assert_share_parity(res, ref)
+        assert res["info"]["form_local"] == _expected_form(split, 4), (A.n_rows, P, r)
+        one, _ = run_share(A, P, r, x, ops, smap, tune={**tune, "form": 1}, ref=ref)
+        assert one["info"]["form_local"] == 1
+        assert np.array_equal(bits(res["y"]), bits(one["y"]))
+    for A, P, r in [(gen.laplacian_3d7(32), 4, 1), (gen.stencil_3d27(20, seed=3), 2, 1)]:
+        x = gen.x_integer(A.n_cols, 9)
+        res, ref = run_share(A, P, r, x, tune={"kernel_local": 2, "form": 4})
+        assert res["info"]["form_local"] == 4
+        if A.n_rows == 32 ** 3:
+            assert np.array_equal(bits(res["y"]), bits(ref["y"]))
+        else:
+            assert_share_parity(res, ref)
 
 
 @pytest.mark.parametrize("chunk", [0, 8, 16])
@@ -203,7 +249,7 @@ def test_automatic_form_rule():
     """The automatic choice follows the host rule on every parity case."""
     for A, P, r in [(gen.laplacian_3d7(32), 4, 1), (gen.stencil_3d27(40, seed=5), 4, 1),
                     (gen.banded_uniform(90000, 4, 40000, seed=2), 1, 0),
-                    (gen.power_law(30000, seed=17), 4, 2)]:
+                    (gen.power_law(30000, seed=17), 4, 2), (gen.power_law(200000, seed=3), 2, 1)]:
         x = gen.x_normal(A.n_cols, 1)
         res, ref = run_share(A, P, r, x)
         assert_share_parity(res, ref)
