@@ -108,6 +108,60 @@ def time_op(sp, torch, plans, op, xs, ys, launches: int) -> float:
     return e0.elapsed_time(e1) * 1e3 / launches
 
 
+def probe_ceiling(sp, torch, nbytes: int, launches: int = 200) -> dict:
+    """Achievable read bandwidth at the size of one y_L launch: the read
+    probe over cold buffers of `nbytes` (rotated past twice the MALL), best
+    of a few grid sizes."""
+    nbytes = max(16, nbytes // 16 * 16)
+    K = max(2, math.ceil(2 * MALL_BYTES / nbytes))
+    bufs = [torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+            for _ in range(K)]
+    part = torch.empty(1 << 16, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.Stream()
+    best = None
+    for blocks in (1024, 2048, 4096, 8192):
+        with torch.cuda.stream(stream):
+            for i in range(2 * K):
+                sp.spmv_hbm_probe(0, bufs[i % K], part, nbytes, blocks, stream)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for i in range(launches):
+                sp.spmv_hbm_probe(0, bufs[i % K], part, nbytes, blocks, stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / launches
+        if best is None or us < best[1]:
+            best = (blocks, us)
+    del bufs
+    gbs = nbytes / (best[1] * 1e-6) / 1e9
+    return {"bytes": nbytes, "blocks": best[0], "us": round(best[1], 3),
+            "read_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def cpu_plain(A, P, r, x, bytes_per_step: float, budget_s: float = 5.0) -> dict:
+    """A plain FP64 CSR product of the same rows on the host (scipy's
+    single-threaded CSR kernel), beside the oracle: the ordinary CPU way to
+    compute this share."""
+    import scipy.sparse as sps
+    q, m = divmod(A.n_rows, P)
+    lo, hi = r * q + min(r, m), (r + 1) * q + min(r + 1, m)
+    k0, k1 = int(A.row_ptr[lo]), int(A.row_ptr[hi])
+    M = sps.csr_matrix((A.val[k0:k1], A.col_idx[k0:k1], A.row_ptr[lo:hi + 1] - k0),
+                       shape=(hi - lo, A.n_cols))
+    M @ x
+    times = []
+    t_start = time.perf_counter()
+    while len(times) < 5 or (time.perf_counter() - t_start < budget_s and len(times) < 200):
+        t0 = time.perf_counter()
+        M @ x
+        times.append(time.perf_counter() - t0)
+    t = float(np.median(times))
+    return {"value": round(bytes_per_step / t / 1e9, 3), "unit": "GB/s", "cores": 1,
+            "kind": "scipy.sparse CSR product", "sample": f"{len(times)} products, median "
+            f"{t * 1e3:.2f} ms each"}
+
+
 def cpu_baseline(A, P, r, x, bytes_per_step: float, budget_s: float = 12.0) -> dict:
     """The oracle (Dot2 over every owned row, OpenMP) timed on the host."""
     import oracle
@@ -396,6 +450,7 @@ def main() -> int:
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--kernel", type=int, default=0, help="0 auto, 1 vector CSR, 2 stream CSR")
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--width", type=int, default=0, help="stream CSR entries per load (0 auto)")
     ap.add_argument("--form", type=int, default=0,
                     help="stream form: 0 auto, 1 packed tiles, 2 sliced ELL, 3 sliced ELL with "
                          "16-bit column offsets")
@@ -435,7 +490,7 @@ def main() -> int:
     if args.plan == "auto" and P > 1:
         from paper_2203_02530_amd import tune as tuner
         ktune = {"lanes_local": args.lanes, "rows_local": args.rows, "kernel_local": args.kernel,
-                 "chunk_local": args.chunk, "form": args.form}
+                 "chunk_local": args.chunk, "form": args.form, "width": args.width}
         # rank plans under the timed loop's conditions: cold replicas
         R0 = args.replicas or replicas_for(A, P, r, ktune, sp)
         res = tuner.sweep_plans(A, P, r, x, 2, ktune, t_measure=args.sweep_measure, n_measure=1,
@@ -454,7 +509,8 @@ def main() -> int:
         ops, smap = sp.spmv_plan_space_get(P, 2, int(args.plan))
     tune = {"flags": 0, "lanes_local": args.lanes, "lanes_remote": 0,
             "rows_local": args.rows, "kernel_local": args.kernel, "chunk_local": args.chunk,
-            "xcd_remap": args.xcd_remap, "fuse_unpack": args.fuse_unpack, "form": args.form}
+            "xcd_remap": args.xcd_remap, "fuse_unpack": args.fuse_unpack, "form": args.form,
+            "width": args.width}
 
     first = sp.spmv_plan_create(A, P, r, ops, smap, 2, tune)
     info = sp.spmv_plan_info(first)
@@ -530,8 +586,11 @@ def main() -> int:
     kern_us = {name: time_op(sp, torch, plans, op, xs, ys, launches)
                for name, op in (("yL", sp.SPMV_OP_YL), ("pack", sp.SPMV_OP_PACK),
                                 ("unpack", sp.SPMV_OP_UNPACK), ("yR", sp.SPMV_OP_YR))}
+    # the same launches on one replica: its arrays stay in the MALL
+    warm_yl_us = time_op(sp, torch, plans[:1], sp.SPMV_OP_YL, xs[:1], ys[:1], launches)
     achieved = B["yL"] / (kern_us["yL"] * 1e-6) / 1e9
     traffic = MEASURED_TRAFFIC.get((args.workload, kernel_variant(info)))
+    ceiling = probe_ceiling(sp, torch, traffic or B["yL"])
     in_plan_us = {"pack": in_plan[sp.SPMV_OP_PACK], "yL": in_plan[sp.SPMV_OP_YL],
                   "unpack": in_plan[sp.SPMV_OP_UNPACK], "yR": in_plan[sp.SPMV_OP_YR],
                   "combine": in_plan[sp.SPMV_N_VERTICES],
@@ -541,9 +600,10 @@ def main() -> int:
     plan_order = [sp.spmv_op_name(int(t)) for t in sp.spmv_plan_get_i32(first, sp.SPMV_I32_OP_ORDER)]
     plan_streams = {sp.spmv_op_name(v): int(m) for v, m in enumerate(
         sp.spmv_plan_get_i32(first, sp.SPMV_I32_STREAM_MAP)) if m >= 0}
-    cpu = None
+    cpu = plain = None
     if not args.no_cpu:
         cpu = cpu_baseline(A, P, r, x, float(B["total"]))
+        plain = cpu_plain(A, P, r, x, float(B["total"]))
     for p in plans:
         sp.spmv_plan_destroy(p)
     plans = []
@@ -591,6 +651,12 @@ def main() -> int:
                      "bytes_per_launch": B["yL"], "avg_us": round(kern_us["yL"], 3),
                      "launches": launches},
         "kernel_us": {k: round(float(v), 3) for k, v in kern_us.items()},
+        "yL_warm": {"avg_us": round(warm_yl_us, 3),
+                    "achieved": round(B["yL"] / (warm_yl_us * 1e-6) / 1e9, 1)},
+        "hbm_probe": {**ceiling,
+                      "yL_moved_over_probe": (round(traffic / (kern_us["yL"] * 1e-6) / 1e9
+                                                    / ceiling["read_gbs"], 3)
+                                              if traffic else None)},
         "kernel_gbs": {k: round(B[k] / (kern_us[k] * 1e-6) / 1e9, 1) for k in kern_us
                        if kern_us[k] > 0 and B[k] > 0},
         "in_plan_event_us": {k: round(float(v), 3) for k, v in in_plan_us.items()},
@@ -602,6 +668,7 @@ def main() -> int:
         "plan_streams": plan_streams,
         "gflops": round(2.0 * (info["nnz_local"] + info["nnz_remote"]) / (ms_step * 1e-3) / 1e9, 3),
         "cpu_baseline": cpu,
+        "cpu_plain": plain,
         "batched": batched,
         "serving": serving,
     }
