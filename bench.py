@@ -212,6 +212,8 @@ def batched_section(sp, torch, gen, n_shares: int, reps: int) -> dict:
     try:
         full = sp.spmv_batch_create(plans, {"use_graph": 1})
         full_st = sp.spmv_batch_create(plans, {"use_graph": 2})
+        by_cs = {k: sp.spmv_batch_create(plans, {"use_graph": 2, "copy_streams": k})
+                 for k in (2, 4)}
         dev = sp.spmv_batch_create(plans, {"staging": 1})
         try:
             finfo = sp.spmv_batch_info(full)
@@ -227,6 +229,8 @@ def batched_section(sp, torch, gen, n_shares: int, reps: int) -> dict:
 
             t_graph = timed(lambda: sp.spmv_batch_exec(full, xs, ys, stream), reps)
             t_streams = timed(lambda: sp.spmv_batch_exec(full_st, xs, ys, stream), reps)
+            t_cs = {k: timed(lambda: sp.spmv_batch_exec(bk, xs, ys, stream), reps)
+                    for k, bk in by_cs.items()}
             t_batch = min(t_graph, t_streams)
             t_dev = timed(lambda: sp.spmv_batch_exec(dev, xs, ys, stream), reps * 4)
 
@@ -237,13 +241,17 @@ def batched_section(sp, torch, gen, n_shares: int, reps: int) -> dict:
         finally:
             sp.spmv_batch_destroy(full)
             sp.spmv_batch_destroy(full_st)
+            for bk in by_cs.values():
+                sp.spmv_batch_destroy(bk)
             sp.spmv_batch_destroy(dev)
         B = finfo["device_bytes"]
         out.update({
             "shares": n_shares, "work_items": finfo["n_items"], "grid": finfo["n_blocks"],
             "ms_per_batch": round(t_batch * 1e3, 3),
             "ms_per_batch_graph": round(t_graph * 1e3, 3),
-            "ms_per_batch_two_copy_streams": round(t_streams * 1e3, 3),
+            "ms_per_batch_stream_launches": round(t_streams * 1e3, 3),
+            "ms_per_batch_by_copy_streams": {"1": round(t_streams * 1e3, 3),
+                                             **{str(k): round(v * 1e3, 3) for k, v in t_cs.items()}},
             "ms_per_batch_device_phase": round(t_dev * 1e3, 3),
             "ms_sequential_execs": round(t_seq * 1e3, 3),
             "speedup_vs_sequential": round(t_seq / t_batch, 3),

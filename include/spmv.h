@@ -542,18 +542,24 @@ int spmv_mcts_run_seq(spmv_plan_t *const *plans, int32_t n_plans, const double *
  * matrices and sizes) together: every GPU step of every share goes into one
  * of three grouped persistent kernels (Pack + y_L | Unpack | y_R), whose work
  * lists hold the stream-CSR tiles and gather ranges of all shares, balanced
- * over the blocks longest-first; the halo staging of all shares becomes copy
- * nodes.  The paper's host-blocking synchronisations (CER/CES before
- * PostSend, WaitRecv before y_R) become graph edges: Pack+y_L -> send copies;
- * receive copies -> Unpack -> y_R; Pack+y_L -> y_R.  The whole batch is one
- * hipGraph launch.  A share's y is bit-identical to spmv_exec of its plan:
- * the same tiles are summed by the same device code.
+ * over the blocks longest-first; the halo staging of all shares becomes
+ * copies on one copy stream per direction (or copy nodes of a hipGraph).
+ * The paper's host-blocking synchronisations (CER/CES before PostSend,
+ * WaitRecv before y_R) become device-side dependencies: Pack+y_L -> send
+ * copies; receive copies -> Unpack -> y_R; Pack+y_L -> y_R.  The whole batch
+ * is three kernel launches and the copies (or one hipGraph launch), with
+ * one host synchronisation at the end.  A share's y is bit-identical to
+ * spmv_exec of its plan: the same tiles are summed by the same device code.
  */
 typedef struct spmv_batch spmv_batch_t;   /* opaque */
 
 typedef struct {
     int32_t blocks_per_cu;  /* persistent grid = 256 * blocks_per_cu, 0 = 8  */
-    int32_t use_graph;      /* 0 = auto (graph), 1 = hipGraph, 2 = stream launches */
+    int32_t use_graph;      /* 0 = auto (stream launches when the halo is
+                               staged: the graph's copy nodes run one after
+                               another and measured 1.3-1.5x slower; the
+                               graph otherwise), 1 = hipGraph, 2 = stream
+                               launches                                      */
     int32_t xcd_affinity;   /* 0 = auto (on when >= 8 shares), 1 = on: the work
                                of share s runs on XCD s mod 8, 2 = off        */
     int32_t staging;        /* 0 = halo staged through the plans' pinned
@@ -561,7 +567,13 @@ typedef struct {
                                (no copies: for timing the grouped kernels;
                                y_R then uses whatever the receive buffers
                                hold)                                          */
-    int32_t reserved[4];
+    int32_t copy_streams;   /* stream launches (use_graph = 2): copy streams
+                               per direction, share i's copies on stream
+                               i mod copy_streams; 0 = auto (1: concurrent
+                               copies of one direction measured slower; the
+                               graph chains each direction's copies too),
+                               1..4                                           */
+    int32_t reserved[3];
 } spmv_batch_opts_t;
 
 typedef struct {

@@ -92,7 +92,7 @@ class spmv_tune_t(ctypes.Structure):
 class spmv_batch_opts_t(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("xcd_affinity", ctypes.c_int32), ("staging", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("copy_streams", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class spmv_batch_info_t(ctypes.Structure):

@@ -195,8 +195,10 @@ struct spmv_batch {
     int64_t n_items[3] = {};
     void **h_xy = nullptr;          // pinned [2n]: x pointers then y pointers
 
-    hipStream_t cs_send = nullptr, cs_recv = nullptr;
-    hipEvent_t ev_a = nullptr, ev_s = nullptr, ev_r = nullptr;
+    int32_t n_cs = 1;                                   // copy streams per direction
+    hipStream_t cs_send_k[kCopyStreams] = {}, cs_recv_k[kCopyStreams] = {};
+    hipEvent_t ev_a = nullptr, ev_s = nullptr, ev_r = nullptr, ev_f = nullptr;
+    hipEvent_t ev_sk[kCopyStreams] = {}, ev_rk[kCopyStreams] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int64_t dev_bytes = 0, link_bytes = 0;
@@ -209,8 +211,12 @@ void batch_release(spmv_batch *b)
     if (!b) return;
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    for (hipEvent_t e : {b->ev_a, b->ev_s, b->ev_r})
+    for (hipEvent_t e : {b->ev_a, b->ev_s, b->ev_r, b->ev_f})
         if (e) (void)hipEventDestroy(e);
+    for (int k = 0; k < kCopyStreams; ++k) {
+        if (b->ev_sk[k]) (void)hipEventDestroy(b->ev_sk[k]);
+        if (b->ev_rk[k]) (void)hipEventDestroy(b->ev_rk[k]);
+    }
     if (b->arena) (void)hipFree(b->arena);
     if (b->h_xy) (void)hipHostFree(b->h_xy);
     delete b;
@@ -250,6 +256,57 @@ void assign(const std::vector<Item> &items, const std::vector<int64_t> &cost, in
 
 int64_t tile_cost(const std::vector<int32_t> &tk, size_t t) { return int64_t(tk[t + 1] - tk[t]) + 64; }
 
+// One batch on stream s: the pointer table, the receive copies (forked
+// onto the copy streams right away: they need nothing from this batch),
+// Pack + y_L, the send copies behind it, Unpack once every receive copy is
+// in, y_R, and the join of the send copies (stream launches).
+int issue(spmv_batch *b, hipStream_t s)
+{
+    auto launch = [&](int ph) -> hipError_t {
+        if (b->n_items[ph] == 0) return hipSuccess;
+        hipLaunchKernelGGL(b->fn, dim3(unsigned(b->n_blocks)), dim3(kBlock), 0, s, b->d_sh,
+                           b->d_x, b->d_y, b->d_items[ph], b->d_blk[ph]);
+        return hipGetLastError();
+    };
+    SPMV_HIP(hipMemcpyAsync(b->d_x, b->h_xy, size_t(2 * b->n) * sizeof(void *),
+                            hipMemcpyHostToDevice, s));
+    SPMV_HIP(hipEventRecord(b->ev_f, s));
+    for (int32_t k = 0; k < b->n_cs; ++k) SPMV_HIP(hipStreamWaitEvent(b->cs_recv_k[k], b->ev_f, 0));
+    // receive copies need nothing from this batch: issue them first, on
+    // n_cs streams, then Pack + y_L, then the send copies behind it
+    const int32_t K = b->n_cs;
+    if (b->staging) {
+        for (int32_t i = 0; i < b->n; ++i) {
+            const spmv_plan *p = b->plans[size_t(i)];
+            const size_t nh = p->share.halo.size() * 8;
+            if (nh)
+                SPMV_HIP(hipMemcpyAsync(p->d_recvbuf, p->h_inbox, nh, hipMemcpyHostToDevice,
+                                        b->cs_recv_k[i % K]));
+        }
+    }
+    SPMV_HIP(launch(0));
+    SPMV_HIP(hipEventRecord(b->ev_a, s));
+    for (int32_t k = 0; k < K; ++k) SPMV_HIP(hipStreamWaitEvent(b->cs_send_k[k], b->ev_a, 0));
+    if (b->staging) {
+        for (int32_t i = 0; i < b->n; ++i) {
+            const spmv_plan *p = b->plans[size_t(i)];
+            const size_t ns = p->share.send_idx.size() * 8;
+            if (ns)
+                SPMV_HIP(hipMemcpyAsync(p->h_outbox, p->d_sendbuf, ns, hipMemcpyDeviceToHost,
+                                        b->cs_send_k[i % K]));
+        }
+    }
+    for (int32_t k = 0; k < K; ++k) {
+        SPMV_HIP(hipEventRecord(b->ev_sk[k], b->cs_send_k[k]));
+        SPMV_HIP(hipEventRecord(b->ev_rk[k], b->cs_recv_k[k]));
+        SPMV_HIP(hipStreamWaitEvent(s, b->ev_rk[k], 0));
+    }
+    SPMV_HIP(launch(1));
+    SPMV_HIP(launch(2));
+    for (int32_t k = 0; k < K; ++k) SPMV_HIP(hipStreamWaitEvent(s, b->ev_sk[k], 0));
+    return SPMV_OK;
+}
+
 int build_graph(spmv_batch *b)
 {
     SPMV_HIP(hipGraphCreate(&b->graph, 0));
@@ -271,21 +328,29 @@ int build_graph(spmv_batch *b)
     };
     hipGraphNode_t n_a = nullptr, n_b = nullptr, n_c = nullptr;
     if (int rc = kernel_node(0, &n_t, 1, &n_a)) return rc;
+    // the copies of each direction form one chain: concurrent copies of one
+    // direction share the host link and measured slower (64 power-law
+    // shares: 31.7 ms per batch with one copy stream per direction, 40.9
+    // with two, 49.4 with four)
     std::vector<hipGraphNode_t> recv;
+    hipGraphNode_t prev_send = n_a, prev_recv = nullptr;
     for (spmv_plan *p : b->staging ? b->plans : std::vector<spmv_plan *>{}) {
         const size_t ns = p->share.send_idx.size() * 8, nh = p->share.halo.size() * 8;
         if (ns) {
             hipGraphNode_t n;
-            SPMV_HIP(hipGraphAddMemcpyNode1D(&n, b->graph, &n_a, 1, p->h_outbox, p->d_sendbuf, ns,
-                                             hipMemcpyDeviceToHost));
+            SPMV_HIP(hipGraphAddMemcpyNode1D(&n, b->graph, &prev_send, 1, p->h_outbox,
+                                             p->d_sendbuf, ns, hipMemcpyDeviceToHost));
+            prev_send = n;
         }
         if (nh) {
             hipGraphNode_t n;
-            SPMV_HIP(hipGraphAddMemcpyNode1D(&n, b->graph, nullptr, 0, p->d_recvbuf, p->h_inbox, nh,
+            SPMV_HIP(hipGraphAddMemcpyNode1D(&n, b->graph, prev_recv ? &prev_recv : nullptr,
+                                             prev_recv ? 1 : 0, p->d_recvbuf, p->h_inbox, nh,
                                              hipMemcpyHostToDevice));
-            recv.push_back(n);
+            prev_recv = n;
         }
     }
+    if (prev_recv) recv.push_back(prev_recv);
     std::vector<hipGraphNode_t> deps_c{n_a};
     if (b->n_items[1] > 0) {
         if (int rc = kernel_node(1, recv.data(), recv.size(), &n_b)) return rc;
@@ -310,7 +375,8 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
     spmv_batch_opts_t o{};
     if (opts) o = *opts;
     if (o.blocks_per_cu < 0 || o.blocks_per_cu > 32 || o.use_graph < 0 || o.use_graph > 2 ||
-        o.xcd_affinity < 0 || o.xcd_affinity > 2 || o.staging < 0 || o.staging > 1)
+        o.xcd_affinity < 0 || o.xcd_affinity > 2 || o.staging < 0 || o.staging > 1 ||
+        o.copy_streams < 0 || o.copy_streams > kCopyStreams)
         return set_error(SPMV_EINVAL, "batch option out of range");
     const int npt = plans[0] ? plans[0]->cfg[0].chunk : 0;
     const int vw = plans[0] ? plans[0]->cfg[0].width : 0;
@@ -340,9 +406,14 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
     b->device = dev;
     b->fn = grouped_fn(npt, vw);
     b->n_blocks = kCUs * (o.blocks_per_cu ? o.blocks_per_cu : 8);
-    b->use_graph = o.use_graph != 2;
+    // automatic: stream launches when the halo is staged (the graph runs its
+    // copy nodes one after another: 46 ms per batch of 64 power-law shares
+    // against 31-37 ms with one copy stream per direction), the graph when
+    // only the grouped kernels run
+    b->use_graph = o.use_graph == 1 || (o.use_graph == 0 && o.staging == 1);
     b->xcd_aff = o.xcd_affinity == 1 || (o.xcd_affinity == 0 && n >= kXcds);
     b->staging = o.staging == 0;
+    b->n_cs = o.copy_streams ? o.copy_streams : 1;
 
     // descriptors and work items
     std::vector<ShareDev> sh(static_cast<size_t>(n));
@@ -458,11 +529,19 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
     hipStream_t plan_st[1];
     hipStream_t send_k[kCopyStreams], recv_k[kCopyStreams];
     if ((rc = pool_streams(dev, 1, plan_st, send_k, recv_k))) return fail(rc);
-    b->cs_send = send_k[0];
-    b->cs_recv = recv_k[0];
-    for (hipEvent_t *ev : {&b->ev_a, &b->ev_s, &b->ev_r}) {
+    for (int k = 0; k < kCopyStreams; ++k) {
+        b->cs_send_k[k] = send_k[k];
+        b->cs_recv_k[k] = recv_k[k];
+    }
+    for (hipEvent_t *ev : {&b->ev_a, &b->ev_s, &b->ev_r, &b->ev_f}) {
         e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
         if (e != hipSuccess) return fail(hip_error(e, "hipEventCreate(batch)"));
+    }
+    for (int k = 0; k < b->n_cs; ++k) {
+        for (hipEvent_t *ev : {&b->ev_sk[k], &b->ev_rk[k]}) {
+            e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+            if (e != hipSuccess) return fail(hip_error(e, "hipEventCreate(batch)"));
+        }
     }
     if (b->use_graph && (rc = build_graph(b))) return fail(rc);
     *out = b;
@@ -488,32 +567,7 @@ extern "C" int spmv_batch_exec(spmv_batch_t *b, const double *const *x, double *
         SPMV_HIP(hipStreamSynchronize(s));
         return SPMV_OK;
     }
-    auto launch = [&](int ph) -> hipError_t {
-        if (b->n_items[ph] == 0) return hipSuccess;
-        hipLaunchKernelGGL(b->fn, dim3(unsigned(b->n_blocks)), dim3(kBlock), 0, s, b->d_sh,
-                           b->d_x, b->d_y, b->d_items[ph], b->d_blk[ph]);
-        return hipGetLastError();
-    };
-    SPMV_HIP(hipMemcpyAsync(b->d_x, b->h_xy, size_t(2 * b->n) * sizeof(void *),
-                            hipMemcpyHostToDevice, s));
-    SPMV_HIP(launch(0));
-    SPMV_HIP(hipEventRecord(b->ev_a, s));
-    SPMV_HIP(hipStreamWaitEvent(b->cs_send, b->ev_a, 0));
-    for (spmv_plan *p : b->staging ? b->plans : std::vector<spmv_plan *>{}) {
-        const size_t ns = p->share.send_idx.size() * 8, nh = p->share.halo.size() * 8;
-        if (ns)
-            SPMV_HIP(hipMemcpyAsync(p->h_outbox, p->d_sendbuf, ns, hipMemcpyDeviceToHost,
-                                    b->cs_send));
-        if (nh)
-            SPMV_HIP(hipMemcpyAsync(p->d_recvbuf, p->h_inbox, nh, hipMemcpyHostToDevice,
-                                    b->cs_recv));
-    }
-    SPMV_HIP(hipEventRecord(b->ev_s, b->cs_send));
-    SPMV_HIP(hipEventRecord(b->ev_r, b->cs_recv));
-    SPMV_HIP(hipStreamWaitEvent(s, b->ev_r, 0));
-    SPMV_HIP(launch(1));
-    SPMV_HIP(launch(2));
-    SPMV_HIP(hipStreamWaitEvent(s, b->ev_s, 0));
+    if (int rc = issue(b, s)) return rc;
     SPMV_HIP(hipStreamSynchronize(s));
     return SPMV_OK;
 }

@@ -74,7 +74,9 @@ def _check(plans, ys, refs, solo):
 
 @pytest.mark.parametrize("opts", [{"use_graph": 1}, {"use_graph": 2},
                                   {"use_graph": 1, "xcd_affinity": 1, "blocks_per_cu": 2},
-                                  {"use_graph": 2, "xcd_affinity": 2, "blocks_per_cu": 1}])
+                                  {"use_graph": 2, "xcd_affinity": 2, "blocks_per_cu": 1},
+                                  {"use_graph": 2, "copy_streams": 1},
+                                  {"use_graph": 2, "copy_streams": 3}])
 def test_batch_bit_identical_to_solo(opts):
     import torch
     log(f"batch opts {opts}")
