@@ -298,7 +298,7 @@ void select_sell(CsrCfg &c, const std::vector<int32_t> &rp, const std::vector<in
     c.lanes = 1;
     c.tile_row.clear();
     c.tile_k.clear();
-    if (row_relative && c.sell_uniform && (asked == 3 || asked == 0) &&
+    if (row_relative && c.sell_uniform && c.sell_width > 0 && (asked == 3 || asked == 0) &&
         build_sell16(rp, col, n_rows, c.sell_width, c.sell_off)) {
         c.form = 3;
         c.sell_col.clear();

@@ -505,5 +505,13 @@ def test_sliced_form_choice_on_host():
     assert i["form_local"] == 1 and i["n_tiles_local"] > 0
     i = info(gen.laplacian_3d7(32), 4, 1, kernel_local=1)
     assert i["form_local"] == 0
+    # an empty local block (every entry remote): the 32-bit sliced form
+    n = 256
+    rows = np.arange(n)
+    C = gen.CSR(n, n, np.arange(n + 1, dtype=np.int32), ((rows + n // 2) % n).astype(np.int32),
+                np.ones(n))
+    assert info(C, 2, 1)["form_local"] == 2
+    assert info(C, 2, 1, form=3)["form_local"] == 2
+    assert info(C, 2, 1, form=4)["form_local"] == 4
     with pytest.raises(sp.SpmvError):
         info(gen.laplacian_3d7(8), 4, 1, form=5)

@@ -160,13 +160,13 @@ def _expected_form(split, ask):
     if ask in (1, 4):
         return packed
     if not n:
-        return 3 if ask in (0, 3) else 2
+        return 2                             # no rows: width 0 keeps 32-bit columns
     widths = np.array([lens[i:i + 64].max() for i in range(0, n, 64)])
     budget = 1.15 * max(int(rp[-1]), 1)
     if 64 * int(widths.sum()) > budget:
         return packed
     uniform = 64 * int(widths.max()) * widths.size <= budget
-    fits = dmax <= 32767
+    fits = dmax <= 32767 and int(widths.max()) > 0
     if ask == 0:
         return (3 if fits else 2) if uniform and widths.max() <= 8 else packed
     return 3 if ask == 3 and uniform and fits else 2
@@ -437,6 +437,16 @@ def test_empty_share_and_empty_rows():
         for r in range(P):
             res, ref = run_share(B, P, r, x)
             assert_share_parity(res, ref)
+    # every entry remote: empty local blocks over owned rows, in every form
+    n = 256
+    rows = np.arange(n)
+    C = gen.CSR(n, n, np.arange(n + 1, dtype=np.int32), ((rows + n // 2) % n).astype(np.int32),
+                np.linspace(-1.0, 1.0, n))
+    x = gen.x_normal(n, 3)
+    for form in (0, 1, 2, 3, 4):
+        res, ref = run_share(C, 2, 1, x, tune={"kernel_local": 2, "form": form})
+        assert res["info"]["nnz_local"] == 0
+        assert_share_parity(res, ref)
 
 
 def test_long_rows():
