@@ -449,6 +449,42 @@ def test_empty_share_and_empty_rows():
         assert_share_parity(res, ref)
 
 
+@pytest.mark.parametrize("plan_index", [332, 1500, 71, 1190, 2003])
+def test_exec_orders_after_pending_caller_work(plan_index):
+    """The exec runs after work still pending on the caller's stream (its
+    plan stream 0 is that stream; other plan streams wait at start) and
+    returns with y complete: x is written by an asynchronous copy on a side
+    stream just before the exec, y read without a further synchronisation."""
+    import torch
+    A = gen.laplacian_3d7(48)
+    P, r = 4, 1
+    x = gen.x_normal(A.n_cols, 77)
+    ref = oracle.share_reference(A, P, r, x)
+    ops, smap = sp.spmv_plan_space_get(P, 2, plan_index)
+    plan = sp.spmv_plan_create(A, P, r, ops, smap, 2)
+    try:
+        info = sp.spmv_plan_info(plan)
+        lo, n = info["lo"], info["n_loc"]
+        sp.spmv_plan_inbox(plan)[:] = ref["inbox"]
+        src = torch.from_numpy(np.ascontiguousarray(x[lo:lo + n])).cuda()
+        big = torch.empty(1 << 26, dtype=torch.float64, device="cuda")
+        xd = torch.zeros(n, dtype=torch.float64, device="cuda")
+        yd = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+        side = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            for _ in range(4):
+                big.mul_(1.0)               # ~2 GB of traffic queued ahead of x
+            xd.copy_(src)
+            sp.spmv_exec(plan, xd, yd, side)
+            y = yd.cpu().numpy()            # no synchronisation in between
+        assert info["n_streams"] >= 1
+        ok = oracle.within_tolerance(y, ref["y"], ref["absax"], 1e-12)
+        assert ok.all(), np.flatnonzero(~ok)[:10]
+    finally:
+        sp.spmv_plan_destroy(plan)
+
+
 def test_long_rows():
     """Rows far longer than a wavefront (up to 10^4 entries)."""
     A = gen.power_law(40000, mean_len=200.0, sigma=1.2, max_len=10000, seed=44)
