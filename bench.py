@@ -585,6 +585,17 @@ def main() -> int:
         ms += sp.spmv_plan_get_f64(p, sp.SPMV_F64_OP_MS)
         cnt += sp.spmv_plan_get_f64(p, sp.SPMV_F64_OP_COUNT)
     in_plan = np.where(cnt > 0, ms / np.maximum(cnt, 1), 0.0) * 1e3
+    # host timeline of the same plan (where the host waits), its own pass
+    for p in plans:
+        sp.spmv_plan_set_profile(p, False, host=True)
+        sp.spmv_plan_reset_times(p)
+    for i in range(min(args.steps, 200)):
+        sp.spmv_exec(plans[i % R], xs[i % R], ys[i % R], stream)
+    torch.cuda.synchronize()
+    h_us = sum(sp.spmv_plan_get_f64(p, sp.SPMV_F64_HOST_US) for p in plans)
+    h_n = sum(float(sp.spmv_plan_get_f64(p, sp.SPMV_F64_HOST_COUNT)[0]) for p in plans)
+    for p in plans:
+        sp.spmv_plan_set_profile(p, False)
     B = step_bytes(info)
     value = B["total"] / (ms_step * 1e-3) / 1e9
 
@@ -668,6 +679,8 @@ def main() -> int:
         "kernel_gbs": {k: round(B[k] / (kern_us[k] * 1e-6) / 1e9, 1) for k in kern_us
                        if kern_us[k] > 0 and B[k] > 0},
         "in_plan_event_us": {k: round(float(v), 3) for k, v in in_plan_us.items()},
+        "host_timeline_us": [[name, round(float(t) / max(h_n, 1.0), 2)]
+                             for name, t in zip(plan_order, h_us)],
         "plan_sweep": sweep,
         "design_rules": design,
         "fine_grained": fine,

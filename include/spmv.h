@@ -241,6 +241,11 @@ typedef struct {
                                     per op since the last reset (SPMV_F_PROFILE;
                                     index SPMV_N_VERTICES = combine step)      */
 #define SPMV_F64_OP_COUNT     6  /* [SPMV_N_VERTICES + 1] timed launches       */
+#define SPMV_F64_HOST_US      7  /* [n_ops] summed microseconds from an exec's
+                                    entry to the return of each token's host
+                                    call, in order (host timeline, profile
+                                    mode 2); cleared when the order changes  */
+#define SPMV_F64_HOST_COUNT   8  /* [1] execs summed in SPMV_F64_HOST_US      */
 
 /* ------------------------------------------------------------ plans */
 
@@ -369,10 +374,12 @@ int spmv_plan_info(const spmv_plan_t *plan, spmv_info_t *info);
 int spmv_plan_get_i32(const spmv_plan_t *plan, int32_t which, int32_t *out, int64_t n);
 /* Copy FP64 data `which` (SPMV_F64_*) into host out[0..n) (synchronous). */
 int spmv_plan_get_f64(spmv_plan_t *plan, int32_t which, double *out, int64_t n);
-/* Zero the per-op timing accumulators of a SPMV_F_PROFILE plan. */
+/* Zero the timing accumulators (per-op event times and host timeline). */
 int spmv_plan_reset_times(spmv_plan_t *plan);
-/* Switch per-op timing (SPMV_F_PROFILE) on (on != 0) or off for later
- * executions; timing adds two event records per GPU step and copy. */
+/* Profiling of later executions, a bit mask: 1 = per-op GPU timing with HIP
+ * events (as SPMV_F_PROFILE; two event records per GPU step and copy), 2 =
+ * host timeline (a steady-clock read after each token: where the host waits
+ * and for how long); 0 = off.  SPMV_EINVAL outside 0..3. */
 int spmv_plan_set_profile(spmv_plan_t *plan, int32_t on);
 
 /* Pinned host buffers owned by the plan: the inbox [n_halo] the caller

@@ -72,7 +72,8 @@ SPMV_KERNEL_VECTOR, SPMV_KERNEL_STREAM = 1, 2
  SPMV_I32_STREAM_MAP, SPMV_I32_TILE_ROW_L, SPMV_I32_TILE_K_L, SPMV_I32_TILE_ROW_R,
  SPMV_I32_TILE_K_R, SPMV_I32_OP_STREAM) = range(17)
 (SPMV_F64_AL_VAL, SPMV_F64_AR_VAL, SPMV_F64_SENDBUF, SPMV_F64_RECVBUF,
- SPMV_F64_X_HALO, SPMV_F64_OP_MS, SPMV_F64_OP_COUNT) = range(7)
+ SPMV_F64_X_HALO, SPMV_F64_OP_MS, SPMV_F64_OP_COUNT, SPMV_F64_HOST_US,
+ SPMV_F64_HOST_COUNT) = range(9)
 
 
 # ------------------------------------------------------------ structs
@@ -383,6 +384,7 @@ _F64_LEN = {
     SPMV_F64_SENDBUF: lambda i: i["n_send"], SPMV_F64_RECVBUF: lambda i: i["n_halo"],
     SPMV_F64_X_HALO: lambda i: i["n_halo"], SPMV_F64_OP_MS: lambda i: SPMV_N_VERTICES + 1,
     SPMV_F64_OP_COUNT: lambda i: SPMV_N_VERTICES + 1,
+    SPMV_F64_HOST_US: lambda i: i["n_ops"], SPMV_F64_HOST_COUNT: lambda i: 1,
 }
 
 
@@ -400,8 +402,9 @@ def spmv_plan_get_f64(plan, which: int) -> np.ndarray:
     return out[:n]
 
 
-def spmv_plan_set_profile(plan, on: bool = True) -> None:
-    _check(_lib.spmv_plan_set_profile(plan, 1 if on else 0))
+def spmv_plan_set_profile(plan, on: bool = True, host: bool = False) -> None:
+    """Per-op GPU event timing (``on``) and the host timeline (``host``)."""
+    _check(_lib.spmv_plan_set_profile(plan, (1 if on else 0) | (2 if host else 0)))
 
 
 def spmv_plan_reset_times(plan) -> None:

@@ -332,4 +332,9 @@ struct spmv_plan {
     hipEvent_t ev_b[SPMV_N_VERTICES + 1] = {}, ev_e[SPMV_N_VERTICES + 1] = {};
     double ms[SPMV_N_VERTICES + 1] = {};
     double cnt[SPMV_N_VERTICES + 1] = {};
+    // host timeline: summed microseconds from an exec's entry to the end of
+    // each token's host call, over host_n execs (reset when the order changes)
+    bool host_times = false;
+    std::vector<double> host_us;
+    double host_n = 0.0;
 };

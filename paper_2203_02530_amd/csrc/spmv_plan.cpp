@@ -493,6 +493,34 @@ inline hipError_t prof_end(spmv_plan *p, int slot, hipStream_t s)
 
 namespace {
 
+// Host timeline of one exec (profiling mode 2): marks the end of each
+// token's host call, relative to the exec's entry.
+struct HostMarks {
+    spmv_plan_t *p;
+    std::chrono::steady_clock::time_point t0;
+    size_t k = 0;
+    HostMarks(spmv_plan_t *plan, size_t n_tokens) : p(plan)
+    {
+        if (!p->host_times) return;
+        if (p->host_us.size() != n_tokens) {
+            p->host_us.assign(n_tokens, 0.0);
+            p->host_n = 0.0;
+        }
+        t0 = std::chrono::steady_clock::now();
+    }
+    void mark()
+    {
+        if (p->host_times && k < p->host_us.size())
+            p->host_us[k] += std::chrono::duration<double, std::micro>(
+                                 std::chrono::steady_clock::now() - t0).count();
+        ++k;
+    }
+    void done()
+    {
+        if (p->host_times) p->host_n += 1.0;
+    }
+};
+
 // The streams an exec runs its plan streams on: plan stream 0 is the
 // caller's stream itself (so a one-stream plan needs no start or end
 // events), the others come from the device pool.
@@ -516,15 +544,18 @@ int exec_fine(spmv_plan_t *p, const double *x, double *y, hipStream_t caller)
             pack_stream[size_t(tok_peer(F.order[k]))] = F.ostream[k];
     hipStream_t st[SPMV_MAX_STREAMS];
     plan_streams(p, caller, n_used, st);
+    HostMarks hm(p, F.order.size());
     bool combine = false;
     for (size_t k = 0; k < F.order.size(); ++k) {
         const int32_t t = F.order[k], kind = tok_kind(t), op = tok_op(t), q = tok_peer(t);
         if (kind == SPMV_SYNC_CER) {
             SPMV_HIP(hipEventRecord(p->ev_pack[size_t(q)], st[pack_stream[size_t(q)]]));
+            hm.mark();
             continue;
         }
         if (kind == SPMV_SYNC_CES) {
             SPMV_HIP(hipEventSynchronize(p->ev_pack[size_t(q)]));
+            hm.mark();
             continue;
         }
         const hipStream_t s = F.ostream[k] >= 0 ? st[F.ostream[k]] : nullptr;
@@ -582,7 +613,9 @@ int exec_fine(spmv_plan_t *p, const double *x, double *y, hipStream_t caller)
                 break;
             default: return set_error(SPMV_EPLAN, "unexpected token in fine-grained schedule");
         }
+        hm.mark();
     }
+    hm.done();
     return SPMV_OK;
 }
 
@@ -609,6 +642,7 @@ extern "C" int spmv_exec(spmv_plan_t *p, const double *x, double *y, void *strea
     const int32_t n_used = std::max<int32_t>(p->sch.n_streams_used, 1);
     hipStream_t st[SPMV_MAX_STREAMS];
     plan_streams(p, caller, n_used, st);
+    HostMarks hm(p, p->sch.order.size());
 
     for (int32_t tok : p->sch.order) {
         if (is_sync(tok)) {
@@ -626,6 +660,7 @@ extern "C" int spmv_exec(spmv_plan_t *p, const double *x, double *y, void *strea
                 else
                     SPMV_HIP(hipStreamWaitEvent(st[smap[v]], p->ev_rec[u], 0));
             }
+            hm.mark();
             continue;
         }
         switch (tok) {
@@ -708,7 +743,9 @@ extern "C" int spmv_exec(spmv_plan_t *p, const double *x, double *y, void *strea
                 break;
             default: return set_error(SPMV_EPLAN, "unexpected token in schedule");
         }
+        hm.mark();
     }
+    hm.done();
     if (p->profile) {
         for (int i = 0; i <= SPMV_N_VERTICES; ++i) {
             if (!ran[i]) continue;
@@ -766,6 +803,8 @@ extern "C" int spmv_plan_reorder(spmv_plan_t *p, const int32_t *op_order, int32_
                                          " streams, the plan owns " + std::to_string(p->n_st));
     p->sch = std::move(sch);
     p->fine = false;
+    p->host_us.clear();
+    p->host_n = 0.0;
     p->fused_combine = fuses_combine(p->sch);
     return SPMV_OK;
 }
@@ -803,6 +842,8 @@ extern "C" int spmv_plan_set_fine(spmv_plan_t *p, const int32_t *op_order,
     }
     p->fsch = std::move(f);
     p->fine = true;
+    p->host_us.clear();
+    p->host_n = 0.0;
     p->fused_combine = pos_l < pos_r && p->fsch.ostream[size_t(pos_l)] == p->fsch.ostream[size_t(pos_r)];
     return SPMV_OK;
 }
@@ -941,6 +982,17 @@ extern "C" int spmv_plan_get_f64(spmv_plan_t *p, int32_t which, double *out, int
             break;
         case SPMV_F64_OP_MS: host = p->ms; len = SPMV_N_VERTICES + 1; break;
         case SPMV_F64_OP_COUNT: host = p->cnt; len = SPMV_N_VERTICES + 1; break;
+        case SPMV_F64_HOST_US: {
+            const size_t n_ops = p->fine ? p->fsch.order.size() : p->sch.order.size();
+            if (p->host_us.size() != n_ops) {
+                p->host_us.assign(n_ops, 0.0);
+                p->host_n = 0.0;
+            }
+            host = p->host_us.data();
+            len = int64_t(n_ops);
+            break;
+        }
+        case SPMV_F64_HOST_COUNT: host = &p->host_n; len = 1; break;
         default: return set_error(SPMV_EINVAL, "unknown f64 selector");
     }
     if (n < len) return set_error(SPMV_EINVAL, "output too small: need " + std::to_string(len));
@@ -957,7 +1009,8 @@ extern "C" int spmv_plan_set_profile(spmv_plan_t *p, int32_t on)
 {
     if (!p) return set_error(SPMV_EINVAL, "plan is NULL");
     if (p->host_only) return set_error(SPMV_ESTATE, "plan was created host-only");
-    if (on && !p->ev_b[0]) {
+    if (on < 0 || on > 3) return set_error(SPMV_EINVAL, "profile mode must be 0 to 3");
+    if ((on & 1) && !p->ev_b[0]) {
         int dev = 0;
         SPMV_HIP(hipGetDevice(&dev));
         if (dev != p->device) SPMV_HIP(hipSetDevice(p->device));
@@ -967,7 +1020,8 @@ extern "C" int spmv_plan_set_profile(spmv_plan_t *p, int32_t on)
         }
         if (dev != p->device) SPMV_HIP(hipSetDevice(dev));
     }
-    p->profile = on != 0;
+    p->profile = (on & 1) != 0;
+    p->host_times = (on & 2) != 0;
     return SPMV_OK;
 }
 
@@ -976,6 +1030,8 @@ extern "C" int spmv_plan_reset_times(spmv_plan_t *p)
     if (!p) return set_error(SPMV_EINVAL, "plan is NULL");
     std::fill(p->ms, p->ms + SPMV_N_VERTICES + 1, 0.0);
     std::fill(p->cnt, p->cnt + SPMV_N_VERTICES + 1, 0.0);
+    std::fill(p->host_us.begin(), p->host_us.end(), 0.0);
+    p->host_n = 0.0;
     return SPMV_OK;
 }
 

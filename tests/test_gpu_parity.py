@@ -508,6 +508,22 @@ def test_profile_counters():
             assert cnt[op] == 3 and ms[op] > 0
         sp.spmv_plan_reset_times(plan)
         assert sp.spmv_plan_get_f64(plan, sp.SPMV_F64_OP_COUNT).sum() == 0
+        # host timeline: one cumulative mark per token, in order
+        sp.spmv_plan_set_profile(plan, False, host=True)
+        for _ in range(4):
+            res, _ = run_share(A, 4, 1, x, plan=plan)
+        assert_share_parity(res, oracle.share_reference(A, 4, 1, x))
+        n_ops = sp.spmv_plan_info(plan)["n_ops"]
+        hus = sp.spmv_plan_get_f64(plan, sp.SPMV_F64_HOST_US)
+        assert hus.size == n_ops
+        assert sp.spmv_plan_get_f64(plan, sp.SPMV_F64_HOST_COUNT)[0] == 4
+        assert np.all(hus > 0) and np.all(np.diff(hus) >= 0)
+        assert sp.spmv_plan_get_f64(plan, sp.SPMV_F64_OP_COUNT).sum() == 0   # events off
+        ops, smap = sp.spmv_plan_space_get(4, 2, 9)
+        sp.spmv_plan_reorder(plan, ops, smap, 2)                               # clears it
+        assert sp.spmv_plan_get_f64(plan, sp.SPMV_F64_HOST_COUNT)[0] == 0
+        with pytest.raises(sp.SpmvError):
+            sp._check(sp._lib.spmv_plan_set_profile(plan, 4))
     finally:
         sp.spmv_plan_destroy(plan)
 
