@@ -322,7 +322,6 @@ struct spmv_plan {
     hipStream_t cs_send_k[spmv::kCopyStreams] = {}, cs_recv_k[spmv::kCopyStreams] = {};
     hipEvent_t ev_start = nullptr, ev_send = nullptr, ev_recv = nullptr;
     hipEvent_t ev_rec[SPMV_N_VERTICES] = {};
-    hipEvent_t ev_join[SPMV_MAX_STREAMS] = {};
     // fine-grained mode: the order is fsch over fdag (per-peer vertices)
     bool fine = false;
     spmv::FineDag fdag;
