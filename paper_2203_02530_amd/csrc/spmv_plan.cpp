@@ -248,8 +248,9 @@ void configure(CsrCfg &c, const std::vector<int32_t> &rp, int64_t n_rows, int32_
     // A window of 1024 entries (chunk 4) measured best for short and long
     // stencil rows alike (7-point 11.7 us vs 12.3 with chunk 8; 27-point
     // 25.0 vs 25.5), width 2 beat width 4 on both.  Summing lanes: about
-    // one per 8 entries of the mean row (27-point: 2 lanes 25.0 us, 1 lane
-    // 26.5, 4 lanes 25.8; 7-point: 1 lane).
+    // one per 7 entries of the mean row (27-point, 25.8 entries: 2 lanes
+    // 25.0 us, 1 lane 26.5, 4 lanes 25.8; power-law remote rows, 15.3
+    // entries: 2 lanes 65 us, 1 lane 70.8; 7-point: 1 lane).
     const double mean_len = n_rows > 0 ? double(nnz) / double(n_rows) : 1.0;
     c.chunk = chunk ? chunk : 4;
     c.width = width ? width : 2;
@@ -257,7 +258,7 @@ void configure(CsrCfg &c, const std::vector<int32_t> &rp, int64_t n_rows, int32_
         c.lanes = lanes;
     } else {
         c.lanes = 1;
-        while (c.lanes < 16 && double(c.lanes * 2) * 8.0 <= mean_len) c.lanes <<= 1;
+        while (c.lanes < 16 && double(c.lanes) * 14.0 <= mean_len) c.lanes <<= 1;
     }
     build_tiles(rp, n_rows, stream_cap(c.chunk), stream_maxr(c.lanes), c.width, c.tile_row,
                 c.tile_k);
