@@ -138,6 +138,10 @@ def test_batch_rejects_mixed_configs():
             with pytest.raises(sp.SpmvError) as e:
                 sp.spmv_batch_create(bad)
             assert e.value.code == sp.SPMV_EINVAL
+        for opts in ({"copy_streams": 5}, {"copy_streams": -1}, {"use_graph": 3}):
+            with pytest.raises(sp.SpmvError) as e:
+                sp.spmv_batch_create([p1], opts)
+            assert e.value.code == sp.SPMV_EINVAL
     finally:
         for p in (p1, p2, p3, p4, p5, p6):
             sp.spmv_plan_destroy(p)
