@@ -53,7 +53,12 @@ def test_two_neighbour_count_closed_form():
     A, P, r = SHARES[0]
     p = _plan(A, P, r)
     try:
+        from math import factorial as f
+        # 16 tokens between start and end: two send chains of 5, the receive
+        # part (two chains of 2 then yR: 4!/(2!2!) = 6 orders) and yL
+        closed = f(16) // (f(5) * f(5) * f(5) * f(1)) * 6
         orders = ofine.count_orders(ofine.fine_dag(oracle.split(A, P, r), r))
+        assert orders == closed == 72_648_576
         assert sp.spmv_fine_count(p, 2) == orders * 8 == 581_188_608
     finally:
         sp.spmv_plan_destroy(p)
