@@ -222,7 +222,10 @@ void worker_loop(spmv_server *s)
         Slot *free_slot = nullptr;
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            while (!s->pending.empty() &&
+            // after a device error nothing more is admitted: the caller sees
+            // the error from drain/submit, and destroy must not wait for
+            // requests that can no longer complete
+            while (!s->worker_error && !s->pending.empty() &&
                    s->inflight + int32_t(s->admitted.size()) < s->o.max_inflight) {
                 Req &r = s->reqs[size_t(s->pending.front())];
                 if (s->resident + s->arena.used + r.bytes > s->o.budget_bytes) break;
@@ -238,7 +241,7 @@ void worker_loop(spmv_server *s)
                     free_slot = &sl;
                     break;
                 }
-            if (free_slot && !s->admitted.empty()) {
+            if (free_slot && !s->admitted.empty() && !s->worker_error) {
                 const size_t k = std::min<size_t>(s->admitted.size(), size_t(s->o.max_batch));
                 batch.assign(s->admitted.begin(), s->admitted.begin() + long(k));
                 for (int64_t id : batch) batch_reqs.push_back(s->reqs[size_t(id)]);
@@ -266,7 +269,8 @@ void worker_loop(spmv_server *s)
         bool busy = false;
         for (const Slot &sl : s->slots) busy |= sl.busy;
         std::unique_lock<std::mutex> lk(s->mu);
-        if (s->stop && s->pending.empty() && s->admitted.empty() && !busy) break;
+        if (s->stop && !busy && (s->worker_error || (s->pending.empty() && s->admitted.empty())))
+            break;
         if (busy || !s->pending.empty() || Clock::now() - idle_since < std::chrono::milliseconds(2)) {
             lk.unlock();
             std::this_thread::yield();   // keep completion latency low while work is around
