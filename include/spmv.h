@@ -152,7 +152,8 @@ typedef struct {
                               entries per batch of loads: 4, 8, 16),
                               3 = sliced ELL whose y_L columns are stored as
                               16-bit offsets from the row, 8 per lane per
-                              16-byte load (taken when every slice has one
+                              16-byte load, and values in pairs, 2 per lane
+                              per 16-byte load (taken when every slice has one
                               width and every |col - row| <= 32767, else
                               form 2; y_R takes form 2; chunk 8 or 16),
                               4 = packed tiles whose y_L columns are stored

@@ -217,8 +217,8 @@ bool build_sell(const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
                 std::vector<int32_t> &ptr, std::vector<int32_t> &scol, std::vector<double> &sval,
                 int32_t &max_width, bool &uniform);
 // Sliced-ELL product with 16-bit row-relative columns (form 3, one width
-// for every slice): entries in groups of 8 per lane, 8 * `sell_u` entries
-// per batch of loads.
+// for every slice, values in pairs: see pair_values): entries in groups of
+// 8 per lane, 8 * `sell_u` entries per batch of loads.
 hipError_t launch_sell16(const CsrDev &A, const double *x, double *out, int xcd_remap,
                          hipStream_t s);
 // Padding marker of the 16-bit column offsets (never a valid offset).
@@ -237,6 +237,12 @@ bool build_sell16(const std::vector<int32_t> &rp, const std::vector<int32_t> &co
 // offset does not fit 16 bits.
 bool build_tile16(const std::vector<int32_t> &col, const std::vector<int32_t> &tile_row,
                   const std::vector<int32_t> &tile_k, std::vector<int16_t> &off);
+// Reorder the values of a uniform-width sliced layout (entry v of row
+// 64 s + l at 64 w s + 64 v + l) into pairs: entries 2p and 2p + 1 of row l
+// at 64 w s + 128 p + 2 l (+ 1), and the last entry of an odd width at
+// 64 w s + 64 (w - 1) + l, so that a lane reads two entries with one
+// 16-byte load.
+void pair_values(std::vector<double> &val, int64_t n_slices, int32_t width);
 // Cut [0, n_rows) into CSR-stream tiles (host).
 void build_tiles(const std::vector<int32_t> &rp, int64_t n_rows, int cap, int maxr, int vw,
                  std::vector<int32_t> &tile_row, std::vector<int32_t> &tile_k);

@@ -262,10 +262,12 @@ struct Sell16Args {
 // Sliced ELL with the columns stored as 16-bit offsets from the row: per
 // group of 8 entries a lane issues one 16-byte load (a wave reads 1 KiB
 // contiguous), so a 7-entry stencil row costs 16 bytes of column data
-// instead of 28.  Values, x gathers and the fma chain are those of k_sell,
-// in the same entry order, so both forms give the same bits.  One wave per
-// block (64-thread blocks measured 2% faster than 256 on the 7-point share);
-// the offsets are read with the default cache policy and the values as
+// instead of 28; the values of a slice are stored in pairs, one 16-byte
+// load per two entries of a row (9.03 vs 9.40 us with one 8-byte load per
+// entry on the 7-point share).  x gathers and the fma chain are those of
+// k_sell, in the same entry order, so both forms give the same bits.  One
+// wave per block (64-thread blocks measured 2% faster than 256); the
+// offsets are read with the default cache policy and the values as
 // streaming (non-temporal) data, which measured 0.2-0.3 us faster than
 // streaming both.
 __device__ __forceinline__ void unpack16(const uint32_t w, int32_t &lo, int32_t &hi)
@@ -307,18 +309,28 @@ __global__ __launch_bounds__(64) void k_sell16(Sell16Args A, int remap)
                 d[8 * h + 2 * k + 1] = in ? hi : int32_t(kPad16);
             }
         }
+        // values in pairs: one 16-byte load per two entries of a row, and
+        // the odd last entry of an odd-width row on its own
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int v = g0 * 8 + u;
-            a[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-                r_val, v < w ? uint32_t(voff + v * 64 + lane) * 8u : kOff, 0, 2));
+        for (int j = 0; j < U / 2; ++j) {
+            const int v = g0 * 8 + 2 * j;
+            const auto q = __builtin_amdgcn_raw_buffer_load_b128(
+                r_val, v + 1 < w ? uint32_t(voff + (v >> 1) * 128 + lane * 2) * 8u : kOff, 0, 2);
+            a[2 * j] = __builtin_bit_cast(double, (uint64_t(q[1]) << 32) | q[0]);
+            a[2 * j + 1] = __builtin_bit_cast(double, (uint64_t(q[3]) << 32) | q[2]);
         }
+        const int tail_u = (w & 1) ? (w - 1) - g0 * 8 : -1;
+        const double tail = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+            r_val, tail_u >= 0 && tail_u < U ? uint32_t(voff + (w - 1) * 64 + lane) * 8u : kOff, 0,
+            2));
 #pragma unroll
         for (int u = 0; u < U; ++u)
             xv[u] = load_x(r_x, d[u] != kPad16 ? uint32_t(r + d[u]) * 8u : kOff);
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (d[u] != kPad16) s = fma(a[u], xv[u], s);
+        for (int u = 0; u < U; ++u) {
+            const double av = u == tail_u ? tail : a[u];
+            if (d[u] != kPad16) s = fma(av, xv[u], s);
+        }
     }
     if (r < A.n_rows) A.out[r] = s;
 }

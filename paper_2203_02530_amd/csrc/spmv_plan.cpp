@@ -300,6 +300,7 @@ void select_sell(CsrCfg &c, const std::vector<int32_t> &rp, const std::vector<in
         c.form = 3;
         c.sell_col.clear();
         c.sell_col.shrink_to_fit();
+        pair_values(c.sell_val, int64_t(c.sell_ptr.size()) - 1, c.sell_width);
         c.chunk = chunk ? (chunk <= 8 ? 8 : 16) : (c.sell_width <= 8 ? 8 : 16);
     }
 }

@@ -325,6 +325,22 @@ bool build_sell16(const std::vector<int32_t> &rp, const std::vector<int32_t> &co
     return true;
 }
 
+void pair_values(std::vector<double> &val, int64_t n_slices, int32_t width)
+{
+    const int64_t w = width, even = w & ~int64_t(1);
+    std::vector<double> out(val.size(), 0.0);
+    for (int64_t sl = 0; sl < n_slices; ++sl) {
+        const int64_t base = sl * 64 * w;
+        for (int64_t v = 0; v < w; ++v)
+            for (int64_t l = 0; l < 64; ++l) {
+                const int64_t dst = v < even ? base + (v >> 1) * 128 + 2 * l + (v & 1)
+                                             : base + (w - 1) * 64 + l;
+                out[size_t(dst)] = val[size_t(base + v * 64 + l)];
+            }
+    }
+    val.swap(out);
+}
+
 bool build_tile16(const std::vector<int32_t> &col, const std::vector<int32_t> &tile_row,
                   const std::vector<int32_t> &tile_k, std::vector<int16_t> &off)
 {
