@@ -471,6 +471,8 @@ def main() -> int:
                     help="rank shares in the batched section (0 = skip it)")
     ap.add_argument("--serve-requests", type=int, default=20000,
                     help="requests in the serving section (0 = skip it)")
+    ap.add_argument("--tune-kernel", action="store_true",
+                    help="also time the y_L kernel variants of the autotuner on this share")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only launch the dominant kernel back-to-back and the copy probe of "
                          "known size (for hardware-counter runs), print their timings")
@@ -626,6 +628,14 @@ def main() -> int:
     for p in plans:
         sp.spmv_plan_destroy(p)
     plans = []
+    kernel_tune = None
+    if args.tune_kernel:
+        from paper_2203_02530_amd import tune as tuner
+        t0 = time.perf_counter()
+        best, res = tuner.tune_kernel(A, P, r, x, launches=max(10 * R, 200))
+        kernel_tune = {"wall_s": round(time.perf_counter() - t0, 1), "best": best,
+                       "auto_variant": kernel_variant(info),
+                       "results": [{"tune": d["tune"], "us": round(d["us"], 3)} for d in res]}
     batched = serving = None
     if args.batch_shares > 0:
         batched = batched_section(sp, torch, gen, args.batch_shares, reps=4)
@@ -684,6 +694,7 @@ def main() -> int:
         "plan_sweep": sweep,
         "design_rules": design,
         "fine_grained": fine,
+        "kernel_tune": kernel_tune,
         "paper_workload": paper,
         "plan_order": plan_order,
         "plan_streams": plan_streams,

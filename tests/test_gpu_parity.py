@@ -449,6 +449,26 @@ def test_empty_share_and_empty_rows():
         assert_share_parity(res, ref)
 
 
+def test_kernel_autotuner():
+    """The kernel autotuner times every candidate and returns the fastest;
+    the tune it returns computes y within tolerance."""
+    from paper_2203_02530_amd import tune as tuner
+    A = gen.laplacian_3d7(48)
+    P, r = 4, 1
+    x = gen.x_normal(A.n_cols, 81)
+    cands = [{"kernel_local": 2, "form": 3, "chunk_local": 8},
+             {"kernel_local": 2, "form": 2, "chunk_local": 8},
+             {"kernel_local": 2, "form": 4, "chunk_local": 4, "width": 2},
+             {"kernel_local": 2, "form": 1, "chunk_local": 4, "width": 2},
+             {"kernel_local": 1, "lanes_local": 8, "rows_local": 4}]
+    best, res = tuner.tune_kernel(A, P, r, x, candidates=cands, launches=20)
+    assert [d["tune"] for d in res] == cands
+    assert all(d["us"] > 0 for d in res)
+    assert best == min(res, key=lambda d: d["us"])["tune"]
+    out, ref = run_share(A, P, r, x, tune=best)
+    assert_share_parity(out, ref)
+
+
 @pytest.mark.parametrize("plan_index", [332, 1500, 71, 1190, 2003])
 def test_exec_orders_after_pending_caller_work(plan_index):
     """The exec runs after work still pending on the caller's stream (its
