@@ -576,3 +576,42 @@ def test_full_stencil27_150_p8_rank3():
     info = res["info"]
     assert info["n_loc"] == 421875 and info["n_halo"] == 45151
     assert_share_parity(res, ref)
+
+
+def test_full_powerlaw_4m_p16_rank5_and_batch():
+    """The power-law 4M-row share (rank 5 of 16) at full size against the
+    oracle's rank-local definition, every row checked, alone and in a batch
+    of two full shares in the batch launch configuration the benchmark
+    times (bit-identical to the solo execs)."""
+    import torch
+    tune = {"kernel_local": 2, "kernel_remote": 2, "chunk_local": 8, "chunk_remote": 8,
+            "width": 2, "form": 1}
+    shares, plans, refs, xs, ys = [], [], [], [], []
+    try:
+        for seed in (4000, 4001):
+            log(f"full power-law 4M share seed {seed}")
+            d = gen.power_law_share(4_000_000, 16, 5, seed=seed)
+            x = gen.x_normal(d["n_global"], seed + 100)
+            ref = oracle.share_reference_local(d["local"], d["n_global"], 16, 5, d["send_idx"],
+                                               d["send_off"], x)
+            plan = sp.spmv_plan_create_local(d["local"], d["n_global"], 16, 5, d["send_idx"],
+                                             d["send_off"], tune=tune)
+            plans.append(plan)
+            res, _ = run_share(None, 16, 5, x, ref=ref, plan=plan)
+            assert res["info"]["n_loc"] == 250_000
+            assert_share_parity(res, ref)
+            info = res["info"]
+            lo, n = info["lo"], info["n_loc"]
+            xs.append(torch.from_numpy(np.ascontiguousarray(x[lo:lo + n])).cuda())
+            ys.append(torch.full((n,), float("nan"), dtype=torch.float64, device="cuda"))
+            refs.append(res["y"])
+        b = sp.spmv_batch_create(plans)
+        try:
+            sp.spmv_batch_exec(b, xs, ys, torch.cuda.current_stream())
+            for y, solo in zip(ys, refs):
+                assert np.array_equal(bits(y.cpu().numpy()), bits(solo))
+        finally:
+            sp.spmv_batch_destroy(b)
+    finally:
+        for p in plans:
+            sp.spmv_plan_destroy(p)
