@@ -78,6 +78,28 @@ def test_batched_equals_plain_and_oracle():
         assert oracle.within_tolerance(y_b[i], ref, ax).all(), i
 
 
+def test_largest_pool_matrices():
+    """The largest matrices of the serving pool's recipe (10^6 and 3*10^5
+    rows, 5..27 entries per row in half-bandwidth 2000) at full size: 40
+    requests arriving at once, batched and plain bit-identical, every
+    request within tolerance of the oracle."""
+    mats = [gen.banded_random(1_000_000, seed=5001), gen.banded_random(300_000, seed=5002)]
+    arr, ids, xs, ys, xnp = _trace(mats, 40, 1e9, 3)
+    log("serve largest batched")
+    _, _, st_b, y_b = _serve(mats, arr, ids, xs, ys, {"mode": 0})
+    for y in ys:
+        y.fill_(float("nan"))
+    log("serve largest plain")
+    _, _, st_p, y_p = _serve(mats, arr, ids, xs, ys, {"mode": 1})
+    assert st_b["completed"] == st_p["completed"] == 40
+    assert st_b["mean_batch"] > 1.0
+    for i in range(40):
+        assert np.array_equal(bits(y_b[i]), bits(y_p[i])), i
+        A = mats[ids[i]]
+        ref, ax = oracle.spmv_dot2(A.row_ptr, A.col_idx, A.val, xnp[i])
+        assert oracle.within_tolerance(y_b[i], ref, ax).all(), i
+
+
 def test_budget_bounds_device_bytes():
     """A budget that fits the matrices plus only a few requests at a time:
     all requests still complete, and buffers in use never exceed the room."""
