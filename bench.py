@@ -480,7 +480,8 @@ def main() -> int:
 
     if args.gpus != 1:
         print(f"bench.py measures one rank share on one GPU; --gpus {args.gpus} is not "
-              "supported (the multi-GPU exchange is a design, not part of this build)",
+              "supported (the library runs one rank's share per GPU; the multi-GPU "
+              "exchange is not implemented)",
               file=sys.stderr)
         return 2
 
