@@ -188,7 +188,8 @@ typedef struct {
     int64_t n_remote_rows; /* owned rows with at least one remote entry     */
     int64_t device_bytes;  /* device memory owned by the plan               */
     int32_t nranks, rank;
-    int32_t n_streams;     /* plan streams (excluding the two copy streams) */
+    int32_t n_streams;     /* plan streams (stream 0 = the caller's; copy
+                              streams not counted)                          */
     int32_t n_ops;         /* tokens in the canonical operation order        */
     int32_t kernel_local, kernel_remote;   /* 1 = vector CSR, 2 = stream CSR */
     int32_t lanes_local, lanes_remote, rows_local, rows_remote;
@@ -255,8 +256,10 @@ typedef struct {
  * blocks (rank q owns rows [q*floor(n/P) + min(q, n mod P), ...)), split it
  * into A_L / A_R (Sec. III-A), derive the halo set and the send lists,
  * validate the operation order, and allocate and upload everything the exec
- * needs: device CSRs, send/receive buffers, pinned inbox/outbox, the plan
- * streams, two private copy streams and the events.
+ * needs: device CSRs, send/receive buffers, pinned inbox/outbox and the
+ * events.  Plan streams other than stream 0 (which is the caller's stream
+ * at exec time) and the copy streams come from a per-device pool shared by
+ * all plans.
  *
  *   csr        host, borrowed; validated (SPMV_ECSR on any defect)
  *   nranks     >= 1; rank in [0, nranks)
