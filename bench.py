@@ -424,6 +424,46 @@ def fine_section(sp, torch, A, P, r, x, replicas, ktune, coarse_best, iterations
                                 for t, s in zip(ops, sts)]}
 
 
+def ranks_section(sp, torch, A, P, x, ops, smap, tune, steps: int = 100) -> dict:
+    """Every rank's share of the same matrix, one after another on this GPU,
+    with the chosen plan: step time and y_L per rank, and the max over ranks
+    that the paper's protocol reports (Sec. III-C3)."""
+    out = []
+    for q in range(P):
+        first = sp.spmv_plan_create(A, P, q, ops, smap, 2, tune)
+        info = sp.spmv_plan_info(first)
+        R = max(1, math.ceil(2 * MALL_BYTES / max(info["device_bytes"] + 16 * info["n_loc"], 1)))
+        plans = [first] + [sp.spmv_plan_create(A, P, q, ops, smap, 2, tune) for _ in range(R - 1)]
+        try:
+            lo, n = info["lo"], info["n_loc"]
+            halo = sp.spmv_plan_get_i32(first, sp.SPMV_I32_HALO_COLS).astype(np.int64)
+            xs, ys = [], []
+            for p in plans:
+                sp.spmv_plan_inbox(p)[:] = x[halo]
+                xs.append(torch.from_numpy(np.ascontiguousarray(x[lo:lo + n])).cuda())
+                ys.append(torch.empty(n, dtype=torch.float64, device="cuda"))
+            stream = torch.cuda.current_stream()
+            for i in range(2 * R):
+                sp.spmv_exec(plans[i % R], xs[i % R], ys[i % R], stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(steps):
+                sp.spmv_exec(plans[i % R], xs[i % R], ys[i % R], stream)
+            torch.cuda.synchronize()
+            step_us = (time.perf_counter() - t0) / steps * 1e6
+            yl_us = time_op(sp, torch, plans, sp.SPMV_OP_YL, xs, ys, max(10 * R, 200))
+            B = step_bytes(info)
+            out.append({"rank": q, "n_loc": n, "n_halo": info["n_halo"],
+                        "form_local": info["form_local"], "step_us": round(step_us, 2),
+                        "yL_us": round(yl_us, 3),
+                        "yL_frac": round(B["yL"] / (yl_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)})
+        finally:
+            for p in plans:
+                sp.spmv_plan_destroy(p)
+    return {"ranks": out, "max_step_us": max(d["step_us"] for d in out),
+            "max_rank": max(out, key=lambda d: d["step_us"])["rank"]}
+
+
 def paper_section(sp, torch, gen, tuner) -> dict:
     """The paper's own workload (Sec. IV: banded 150,000 x 150,000, 10
     entries per row in half-bandwidth 37,500, P = 4): every plan of rank 1's
@@ -471,6 +511,9 @@ def main() -> int:
                     help="rank shares in the batched section (0 = skip it)")
     ap.add_argument("--serve-requests", type=int, default=20000,
                     help="requests in the serving section (0 = skip it)")
+    ap.add_argument("--all-ranks", type=int, default=1,
+                    help="also run every rank's share of the matrix with the chosen plan "
+                         "and report the max over ranks (1 = yes)")
     ap.add_argument("--tune-kernel", action="store_true",
                     help="also time the y_L kernel variants of the autotuner on this share")
     ap.add_argument("--kernel-only", action="store_true",
@@ -642,6 +685,9 @@ def main() -> int:
         batched = batched_section(sp, torch, gen, args.batch_shares, reps=4)
     if args.serve_requests > 0:
         serving = serving_section(sp, torch, gen, args.serve_requests, 5000.0, 128)
+    all_ranks = None
+    if P > 1 and not args.kernel_only and args.all_ranks:
+        all_ranks = ranks_section(sp, torch, A, P, x, ops, smap, tune)
     paper = None
     if args.plan == "auto" and not args.no_rules:
         from paper_2203_02530_amd import tune as tuner
@@ -696,6 +742,7 @@ def main() -> int:
         "design_rules": design,
         "fine_grained": fine,
         "kernel_tune": kernel_tune,
+        "all_ranks": all_ranks,
         "paper_workload": paper,
         "plan_order": plan_order,
         "plan_streams": plan_streams,
