@@ -261,6 +261,20 @@ def power_law_share(n: int = 4_000_000, nranks: int = 16, rank: int = 5,
                 send_idx=np.concatenate(send).astype(np.int32), send_off=send_off.astype(np.int32))
 
 
+def three_diagonals(n: int, d: int, seed: int = 0) -> CSR:
+    """Rows with the columns i - d, i, i + d (those inside [0, n)), values
+    N(0,1): offsets of exactly d from the row, for 16-bit boundary cases."""
+    rng = np.random.default_rng(seed)
+    i = np.arange(n)
+    cols = np.stack([i - d, i, i + d], axis=1)
+    valid = (cols >= 0) & (cols < n)
+    counts = valid.sum(axis=1)
+    rp = np.zeros(n + 1, np.int32)
+    np.cumsum(counts, out=rp[1:])
+    c = cols[valid].astype(np.int32)
+    return CSR(n, n, rp, c, rng.standard_normal(c.size))
+
+
 def banded_random(n: int, lo_len: int = 5, hi_len: int = 27, half_bw: int = 2000,
                   seed: int = 5000) -> CSR:
     """Row length uniform in {lo_len..hi_len}, columns distinct inside

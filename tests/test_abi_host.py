@@ -505,6 +505,14 @@ def test_sliced_form_choice_on_host():
     assert i["form_local"] == 1 and i["n_tiles_local"] > 0
     i = info(gen.laplacian_3d7(32), 4, 1, kernel_local=1)
     assert i["form_local"] == 0
+    # the 16-bit boundary: offsets of exactly +-32767 fit the sliced form,
+    # +-32768 do not (-32768 marks padding); tiles add up to 255 rows
+    def tri(d):
+        return gen.three_diagonals(200000, d)
+    assert info(tri(32767), 1, 0, form=3)["form_local"] == 3
+    assert info(tri(32768), 1, 0, form=3)["form_local"] == 2
+    assert info(tri(32767 - 255), 1, 0, form=4)["form_local"] == 4
+    assert info(tri(32768), 1, 0, form=4)["form_local"] == 1
     # an empty local block (every entry remote): the 32-bit sliced form
     n = 256
     rows = np.arange(n)

@@ -245,6 +245,22 @@ def test_sliced16_form(chunk):
         assert np.array_equal(bits(res["y"]), bits(ref["y"]))
 
 
+def test_sixteen_bit_boundary():
+    """Offsets of exactly +-32767 from the row in the 16-bit sliced form, and
+    of +-32512 (plus up to 255 rows within a tile) in 16-bit packed tiles:
+    oracle parity and the bits of the 32-bit forms; +-32768 falls back."""
+    for d, form, other, expect in ((32767, 3, 2, 3), (32768, 3, 2, 2),
+                                   (32767 - 255, 4, 1, 4), (32768, 4, 1, 1)):
+        A = gen.three_diagonals(200000, d, seed=d)
+        x = gen.x_normal(A.n_cols, 5)
+        log(f"16-bit boundary d={d} form={form}")
+        res, ref = run_share(A, 1, 0, x, tune={"kernel_local": 2, "form": form})
+        assert res["info"]["form_local"] == expect
+        assert_share_parity(res, ref)
+        base, _ = run_share(A, 1, 0, x, tune={"kernel_local": 2, "form": other}, ref=ref)
+        assert np.array_equal(bits(res["y"]), bits(base["y"]))
+
+
 def test_automatic_form_rule():
     """The automatic choice follows the host rule on every parity case."""
     for A, P, r in [(gen.laplacian_3d7(32), 4, 1), (gen.stencil_3d27(40, seed=5), 4, 1),
