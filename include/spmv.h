@@ -164,7 +164,7 @@ typedef struct {
                               at most 8, else packed, y_L with 16-bit
                               offsets (forms 3, 4) when they fit.  Every
                               form gives the same bits for y.
-                              Only form 1 plans can join a batch.         */
+                              Plans in forms 1 and 4 can join a batch.    */
 } spmv_tune_t;
 
 #define SPMV_F_HOST_ONLY  1  /* build metadata only: no device resources;
@@ -601,8 +601,9 @@ typedef struct {
 /*
  * Build a batch over `n` plans (borrowed: they must outlive the batch and are
  * not executed meanwhile).  Every plan must be a device plan whose y_L and
- * y_R use the stream-CSR kernel with one common chunk and width (the lanes
- * per row may differ).  SPMV_EINVAL otherwise.
+ * y_R use the stream-CSR kernel in packed tiles (y_L with 32- or 16-bit
+ * columns, forms 1 and 4) with one common chunk and width (the lanes per
+ * row may differ).  SPMV_EINVAL otherwise.
  */
 int spmv_batch_create(spmv_plan_t *const *plans, int32_t n, const spmv_batch_opts_t *opts,
                       spmv_batch_t **out);

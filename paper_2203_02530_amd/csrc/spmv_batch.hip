@@ -31,23 +31,24 @@ struct ShareDev {
     const int32_t *send_idx, *perm;
     double *sendbuf, *recvbuf, *xhalo;
     uint32_t L_nnz_alloc, R_nnz_alloc, n_loc, n_halo;
-    int32_t L_lanes, R_lanes, fuse_unpack, pad;
+    int32_t L_lanes, R_lanes, fuse_unpack;
+    int32_t L_col16;   // A_L columns as int16 offsets from each tile's first row
 };
 
 struct Item {
     int32_t kind, share, a, n;   // tile a, or gather range [a, a + n)
 };
 
-template <int NPT, int VW>
+template <int NPT, int VW, bool C16 = false>
 __device__ __forceinline__ void tile_sl(int sl, const StreamArgs &A, int t, double *s_p,
                                         int32_t *s_rp)
 {
     switch (sl) {
-        case 1: stream_tile<NPT, VW, 1>(A, t, s_p, s_rp); break;
-        case 2: stream_tile<NPT, VW, 2>(A, t, s_p, s_rp); break;
-        case 4: stream_tile<NPT, VW, 4>(A, t, s_p, s_rp); break;
-        case 8: stream_tile<NPT, VW, 8>(A, t, s_p, s_rp); break;
-        default: stream_tile<NPT, VW, 16>(A, t, s_p, s_rp); break;
+        case 1: stream_tile<NPT, VW, 1, C16>(A, t, s_p, s_rp); break;
+        case 2: stream_tile<NPT, VW, 2, C16>(A, t, s_p, s_rp); break;
+        case 4: stream_tile<NPT, VW, 4, C16>(A, t, s_p, s_rp); break;
+        case 8: stream_tile<NPT, VW, 8, C16>(A, t, s_p, s_rp); break;
+        default: stream_tile<NPT, VW, 16, C16>(A, t, s_p, s_rp); break;
     }
 }
 
@@ -83,7 +84,10 @@ __global__ __launch_bounds__(kBlock) void k_grouped(const ShareDev *__restrict__
             A.acc = nullptr;
             A.nnz_alloc = S.L_nnz_alloc;
             A.n_x = S.n_loc;
-            tile_sl<NPT, VW>(S.L_lanes, A, it.a, s_p, s_rp);
+            if (S.L_col16)
+                tile_sl<NPT, VW, true>(S.L_lanes, A, it.a, s_p, s_rp);
+            else
+                tile_sl<NPT, VW, false>(S.L_lanes, A, it.a, s_p, s_rp);
         } else {
             StreamArgs A;
             A.tile_row = S.R_tile_row;
@@ -388,7 +392,8 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
                                               " is host-only or on another device");
         for (int side = 0; side < 2; ++side)
             if (p->cfg[side].kernel != SPMV_KERNEL_STREAM || p->cfg[side].chunk != npt ||
-                p->cfg[side].width != vw || p->cfg[side].form != 1)
+                p->cfg[side].width != vw ||
+                !(p->cfg[side].form == 1 || (side == 0 && p->cfg[side].form == 4)))
                 return set_error(SPMV_EINVAL, "plan " + std::to_string(i) +
                                                   ": batched shares need packed-tile stream-CSR "
                                                   "products with one common chunk and width");
@@ -447,7 +452,7 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
         d.L_lanes = p->cfg[0].lanes;
         d.R_lanes = p->cfg[1].lanes;
         d.fuse_unpack = p->fuse_unpack ? 1 : 0;
-        d.pad = 0;
+        d.L_col16 = p->cfg[0].form == 4 ? 1 : 0;
         const int64_t n_send = int64_t(S.send_idx.size()), n_halo = int64_t(S.halo.size());
         for (int64_t a = 0; a < n_send; a += gather_len) {
             const int32_t len = int32_t(std::min<int64_t>(gather_len, n_send - a));

@@ -101,6 +101,32 @@ def test_batch_bit_identical_to_solo(opts):
             sp.spmv_plan_destroy(p)
 
 
+@pytest.mark.parametrize("use_graph", [1, 2])
+def test_batch_with_16bit_tiles(use_graph):
+    """Shares whose local product uses packed tiles with 16-bit columns (and
+    shares whose columns do not fit, in 32-bit tiles) in one batch."""
+    import torch
+    shares = _shares()
+    plans, xs, ys, refs, solo = _setup(shares, tune={**TUNE, "form": 4})
+    try:
+        forms = [sp.spmv_plan_info(p)["form_local"] for p in plans]
+        assert 4 in forms
+        b = sp.spmv_batch_create(plans, {"use_graph": use_graph})
+        try:
+            for rep in range(2):
+                for y in ys:
+                    if y is not None:
+                        y.fill_(float("nan"))
+                torch.cuda.synchronize()
+                sp.spmv_batch_exec(b, xs, ys, torch.cuda.current_stream())
+                _check(plans, ys, refs, solo)
+        finally:
+            sp.spmv_batch_destroy(b)
+    finally:
+        for p in plans:
+            sp.spmv_plan_destroy(p)
+
+
 def test_batch_same_alone_and_in_mix():
     """A share's bits do not depend on which other shares are batched with it."""
     import torch
@@ -134,7 +160,8 @@ def test_batch_rejects_mixed_configs():
     p6 = sp.spmv_plan_create(A, 2, 1, tune={**TUNE, "form": 4})
     assert sp.spmv_plan_info(p6)["form_local"] == 4
     try:
-        for bad in ([p1, p2], [p1, p3], [p1, p4], [p1, p5], [p1, p6]):
+        sp.spmv_batch_destroy(sp.spmv_batch_create([p1, p6]))   # 16-bit tiles may join
+        for bad in ([p1, p2], [p1, p3], [p1, p4], [p1, p5]):
             with pytest.raises(sp.SpmvError) as e:
                 sp.spmv_batch_create(bad)
             assert e.value.code == sp.SPMV_EINVAL
