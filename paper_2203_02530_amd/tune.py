@@ -1,6 +1,6 @@
 """Autotuner over the paper's design space and the kernel variants.
 
-Two searches, both timed on the device by the library itself:
+Three searches, all timed on the device by the library itself:
 
 * :func:`sweep_plans` -- every (operation order, stream map) of the SpMV DAG
   (the design space of Sec. III-B/C, enumerated by the library), timed with
@@ -12,6 +12,9 @@ Two searches, both timed on the device by the library itself:
   tiles: window chunk, load width, summing lanes; sliced ELL: entries per
   batch of loads; vector CSR: lanes per row, rows per lane group), timed
   with HIP events around back-to-back launches over cold replicas.
+* :func:`tune_batch` -- the options of a batch of shares (stream launches
+  or one graph, copy streams, persistent blocks per CU, XCD affinity),
+  timed over whole batches.
 
 Results can be appended to a JSONL cache keyed by the matrix digest, so an
 interrupted sweep resumes where it stopped.
@@ -25,7 +28,8 @@ import os
 
 import numpy as np
 
-from . import (SPMV_OP_YL, spmv_op_launch, spmv_plan_create, spmv_plan_destroy,
+from . import (SPMV_OP_YL, spmv_batch_create, spmv_batch_destroy, spmv_batch_exec,
+               spmv_op_launch, spmv_plan_create, spmv_plan_destroy,
                spmv_plan_get_i32, spmv_plan_inbox, spmv_plan_info, spmv_plan_reorder,
                spmv_plan_space_count, spmv_plan_space_get, spmv_plan_time, SPMV_I32_HALO_COLS)
 
@@ -177,3 +181,37 @@ def tune_kernel(A, nranks: int, rank: int, x: np.ndarray, candidates=DEFAULT_CAN
             log(json.dumps(results[-1]))
     best = min(results, key=lambda d: d["us"])
     return best["tune"], results
+
+
+DEFAULT_BATCH_CANDIDATES = (
+    [{"use_graph": 2, "copy_streams": k, "blocks_per_cu": b} for k in (1, 2) for b in (4, 8, 16)] +
+    [{"use_graph": 1, "blocks_per_cu": b} for b in (8,)] +
+    [{"use_graph": 2, "copy_streams": 1, "blocks_per_cu": 8, "xcd_affinity": 2}])
+
+
+def tune_batch(plans, xs, ys, candidates=DEFAULT_BATCH_CANDIDATES, reps: int = 3, log=None):
+    """Search the batch options (stream launches or one graph, copy streams
+    per direction, persistent blocks per CU, XCD affinity) for a set of
+    plans by timing whole batches (halo staging included).  Returns (best
+    options, all results); every candidate computes the same bits."""
+    import time
+    import torch
+    stream = torch.cuda.current_stream()
+    results = []
+    for opts in candidates:
+        b = spmv_batch_create(plans, opts)
+        try:
+            spmv_batch_exec(b, xs, ys, stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                spmv_batch_exec(b, xs, ys, stream)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / reps * 1e3
+        finally:
+            spmv_batch_destroy(b)
+        results.append({"opts": dict(opts), "ms": ms})
+        if log:
+            log(json.dumps(results[-1]))
+    best = min(results, key=lambda d: d["ms"])
+    return best["opts"], results

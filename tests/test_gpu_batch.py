@@ -127,6 +127,25 @@ def test_batch_with_16bit_tiles(use_graph):
             sp.spmv_plan_destroy(p)
 
 
+def test_batch_autotuner():
+    """The batch autotuner times every candidate; every candidate gives the
+    solo bits, and the options it returns are the fastest."""
+    from paper_2203_02530_amd import tune as tuner
+    shares = _shares()
+    plans, xs, ys, refs, solo = _setup(shares)
+    try:
+        cands = [{"use_graph": 2, "copy_streams": 1, "blocks_per_cu": 4},
+                 {"use_graph": 2, "copy_streams": 2, "blocks_per_cu": 8},
+                 {"use_graph": 1, "blocks_per_cu": 8}]
+        best, res = tuner.tune_batch(plans, xs, ys, candidates=cands, reps=2)
+        assert [d["opts"] for d in res] == cands and all(d["ms"] > 0 for d in res)
+        assert best == min(res, key=lambda d: d["ms"])["opts"]
+        _check(plans, ys, refs, solo)
+    finally:
+        for p in plans:
+            sp.spmv_plan_destroy(p)
+
+
 def test_batch_same_alone_and_in_mix():
     """A share's bits do not depend on which other shares are batched with it."""
     import torch
