@@ -165,6 +165,49 @@ constexpr int kCUs = 256;
 
 }  // namespace
 
+// Small batches: the descriptors come in the kernel arguments.
+template <int NPT, int VW>
+__global__ __launch_bounds__(kBlock) void k_serve_inline(const ServeInline a)
+{
+    __shared__ double s_p[kBlock * NPT];
+    __shared__ int32_t s_rp[kBlock + 1];
+    const int total = a.pref[a.n_req];
+    for (int g = int(blockIdx.x); g < total; g += int(gridDim.x)) {
+        int lo = 0;   // largest s with pref[s] <= g
+        for (int s = 1; s < a.n_req; ++s)
+            if (a.pref[s] <= g) lo = s;
+        const ServeDev &S = a.d[lo];
+        StreamArgs A;
+        A.tile_row = S.tile_row;
+        A.tile_k = S.tile_k;
+        A.rp = S.rp;
+        A.col = S.col;
+        A.rows = nullptr;
+        A.val = S.val;
+        A.x = S.x;
+        A.out = S.y;
+        A.acc = nullptr;
+        A.nnz_alloc = S.nnz_alloc;
+        A.n_x = S.n;
+        tile_sl<NPT, VW>(S.lanes, A, g - a.pref[lo], s_p, s_rp);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_serve_inline(int npt, int vw, const ServeInline &a, hipStream_t s)
+{
+    if (a.n_req < 1 || a.n_req > kServeInline) return hipErrorInvalidValue;
+    const int total = a.pref[a.n_req];
+    if (total <= 0) return hipSuccess;
+    const unsigned grid = unsigned(std::min(total, kCUs * 8));
+    void (*fn)(const ServeInline) = nullptr;
+    if (vw == 2) fn = npt == 4 ? k_serve_inline<4, 2> : npt == 8 ? k_serve_inline<8, 2> : npt == 16 ? k_serve_inline<16, 2> : nullptr;
+    if (vw == 4) fn = npt == 4 ? k_serve_inline<4, 4> : npt == 8 ? k_serve_inline<8, 4> : npt == 16 ? k_serve_inline<16, 4> : nullptr;
+    if (!fn) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_serve(int npt, int vw, const ServeDev *d_desc, const int32_t *d_pref, int n_req,
                         int total_tiles, hipStream_t s)
 {

@@ -262,6 +262,15 @@ struct ServeDev {
 // tile of request s (pref[n_req] = total).  Grid-stride over tiles.
 hipError_t launch_serve(int npt, int vw, const ServeDev *d_desc, const int32_t *d_pref,
                         int n_req, int total_tiles, hipStream_t s);
+// The same for a batch of at most kServeInline requests whose descriptors
+// travel in the kernel arguments (no copy of them ahead of the launch).
+constexpr int kServeInline = 8;
+struct ServeInline {
+    ServeDev d[kServeInline];
+    int32_t pref[kServeInline + 1];
+    int32_t n_req;
+};
+hipError_t launch_serve_inline(int npt, int vw, const ServeInline &a, hipStream_t s);
 
 // Per-device stream pool shared by all plans and batches (spmv_plan.cpp):
 // plan streams 0..n_plan-1 and the send / receive copy streams.

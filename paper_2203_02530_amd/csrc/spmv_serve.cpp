@@ -166,7 +166,11 @@ int launch_batch(spmv_server *s, Slot &sl, const std::vector<int64_t> &ids,
         d.n_tiles = int32_t(p->cfg[0].tile_row.size()) - 1;
         pref[i + 1] = pref[i] + d.n_tiles;
     }
-    SPMV_HIP(hipMemcpyAsync(sl.d_desc, sl.h_stage, s->stage_bytes, hipMemcpyHostToDevice, sl.st));
+    // A small batch passes its descriptors in the kernel arguments; a larger one
+    // copies them to the slot's device buffer ahead of the launch.
+    const bool inline_desc = n <= kServeInline;
+    if (!inline_desc)
+        SPMV_HIP(hipMemcpyAsync(sl.d_desc, sl.h_stage, s->stage_bytes, hipMemcpyHostToDevice, sl.st));
     for (int i = 0; i < n; ++i) {
         const Req &r = rq[size_t(i)];
         const int64_t nl = s->mats[size_t(r.mat)]->share.n_loc;
@@ -174,7 +178,15 @@ int launch_batch(spmv_server *s, Slot &sl, const std::vector<int64_t> &ids,
             SPMV_HIP(hipMemcpyAsync(const_cast<double *>(desc[i].x), r.xh, size_t(nl) * 8,
                                     hipMemcpyHostToDevice, sl.st));
     }
-    SPMV_HIP(launch_serve(s->o.chunk, 2, sl.d_desc, sl.d_pref, n, pref[n], sl.st));
+    if (inline_desc) {
+        ServeInline a{};
+        for (int i = 0; i < n; ++i) a.d[i] = desc[i];
+        for (int i = 0; i <= n; ++i) a.pref[i] = pref[i];
+        a.n_req = n;
+        SPMV_HIP(launch_serve_inline(s->o.chunk, 2, a, sl.st));
+    } else {
+        SPMV_HIP(launch_serve(s->o.chunk, 2, sl.d_desc, sl.d_pref, n, pref[n], sl.st));
+    }
     for (int i = 0; i < n; ++i) {
         const Req &r = rq[size_t(i)];
         const int64_t nl = s->mats[size_t(r.mat)]->share.n_loc;

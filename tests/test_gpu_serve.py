@@ -78,6 +78,29 @@ def test_batched_equals_plain_and_oracle():
         assert oracle.within_tolerance(y_b[i], ref, ax).all(), i
 
 
+def test_large_batches_copy_descriptors():
+    """Batches of at most eight requests take their descriptors in the kernel
+    arguments, larger ones copy them to the device first: 256 requests that
+    arrive at once make batches of up to 64 (the copied form), the plain mode
+    serves each alone (the inline form), and both agree bit for bit and with
+    the oracle."""
+    mats = _pool(k=8, seed=2)
+    arr, ids, xs, ys, xnp = _trace(mats, 256, 1e9, 4)
+    log("serve large batches")
+    _, _, st_b, y_b = _serve(mats, arr, ids, xs, ys, {"mode": 0, "max_batch": 64})
+    for y in ys:
+        y.fill_(float("nan"))
+    log("serve large batches, plain")
+    _, _, st_p, y_p = _serve(mats, arr, ids, xs, ys, {"mode": 1})
+    assert st_b["completed"] == st_p["completed"] == 256
+    assert st_b["mean_batch"] > 8.0, st_b
+    for i in range(256):
+        assert np.array_equal(bits(y_b[i]), bits(y_p[i])), i
+        A = mats[ids[i]]
+        ref, ax = oracle.spmv_dot2(A.row_ptr, A.col_idx, A.val, xnp[i])
+        assert oracle.within_tolerance(y_b[i], ref, ax).all(), i
+
+
 def test_largest_pool_matrices():
     """The largest matrices of the serving pool's recipe (10^6 and 3*10^5
     rows, 5..27 entries per row in half-bandwidth 2000) at full size: 40
