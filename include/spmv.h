@@ -162,8 +162,17 @@ typedef struct {
                               1; y_R takes form 1), 0 = auto: sliced when
                               every slice of 64 rows has the same width of
                               at most 8, else packed, y_L with 16-bit
-                              offsets (forms 3, 4) when they fit.  Every
-                              form gives the same bits for y.
+                              offsets (forms 3, 4) when they fit.
+                              5 = y_R in column slabs: the halo cut into 8
+                              equal column ranges, one per XCD, so the x
+                              values a slab gathers stay in one XCD's L2;
+                              each slab in packed tiles writes a partial sum
+                              per row, and a second kernel adds a row's 8
+                              partial sums in slab order (lanes_remote at
+                              most 4; y_L takes the automatic form; without
+                              remote rows y_R stays in form 1).  Every form
+                              but 5 gives the same bits for y; form 5 gives
+                              bits of its own, the same under every plan.
                               Plans in forms 1 and 4 can join a batch.    */
 } spmv_tune_t;
 
@@ -201,7 +210,7 @@ typedef struct {
     int32_t form_local;    /* y_L stream form: 1 packed tiles, 2 sliced ELL,
                               3 sliced ELL with 16-bit column offsets,
                               4 packed tiles with 16-bit column offsets,
-                              0 vector CSR                                   */
+                              5 column slabs (y_R), 0 vector CSR            */
     int32_t form_remote;   /* same for y_R                                   */
     int32_t n_slices_local, n_slices_remote;  /* sliced-ELL slices (0: none) */
     int32_t fine;          /* 1 while a fine-grained order is in force       */

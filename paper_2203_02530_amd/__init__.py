@@ -365,6 +365,17 @@ def spmv_plan_info(plan) -> dict:
     return info.as_dict()
 
 
+def _tiles_r(i):
+    # form 5 keeps the 8 column slabs' tiles one after another, each with
+    # its closing entry
+    if i["form_remote"] == 5:
+        return i["n_tiles_remote"] + SLABS
+    return i["n_tiles_remote"] + 1 if i["form_remote"] in (1, 4) else 0
+
+
+SLABS = 8   # column slabs of form 5, one per XCD
+
+
 _I32_LEN = {
     SPMV_I32_HALO_COLS: lambda i: i["n_halo"], SPMV_I32_RECV_OFF: lambda i: i["nranks"] + 1,
     SPMV_I32_SEND_IDX: lambda i: i["n_send"], SPMV_I32_SEND_OFF: lambda i: i["nranks"] + 1,
@@ -376,8 +387,8 @@ _I32_LEN = {
     SPMV_I32_OP_STREAM: lambda i: i["n_ops"],
     SPMV_I32_TILE_ROW_L: lambda i: i["n_tiles_local"] + 1 if i["form_local"] in (1, 4) else 0,
     SPMV_I32_TILE_K_L: lambda i: i["n_tiles_local"] + 1 if i["form_local"] in (1, 4) else 0,
-    SPMV_I32_TILE_ROW_R: lambda i: i["n_tiles_remote"] + 1 if i["form_remote"] in (1, 4) else 0,
-    SPMV_I32_TILE_K_R: lambda i: i["n_tiles_remote"] + 1 if i["form_remote"] in (1, 4) else 0,
+    SPMV_I32_TILE_ROW_R: lambda i: _tiles_r(i),
+    SPMV_I32_TILE_K_R: lambda i: _tiles_r(i),
 }
 _F64_LEN = {
     SPMV_F64_AL_VAL: lambda i: i["nnz_local"], SPMV_F64_AR_VAL: lambda i: i["nnz_remote"],

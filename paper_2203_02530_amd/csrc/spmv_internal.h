@@ -206,6 +206,36 @@ hipError_t launch_sell(const CsrDev &A, const double *x, double *out, double *ac
                        int xcd_remap, hipStream_t s);
 int stream_cap(int npt);
 int stream_maxr(int sum_lanes);
+
+// Form 5 (y_R): the halo's columns cut into kSlabs equal ranges, one per
+// XCD.  Slab k is a CSR over all compressed remote rows holding the entries
+// whose halo index lies in range k, cut into packed stream tiles; the blocks
+// of slab k run on XCD k (blocks are dealt to the XCDs round-robin), so the
+// x values slab k gathers stay in that XCD's L2.  Each slab writes one
+// partial sum per row; a second kernel adds the kSlabs partial sums of a row
+// in slab order and stores the result (out[i]) or adds it (acc[rows[i]]).
+constexpr int kSlabs = 8;
+struct SlabDev {
+    const int32_t *rp;          // [kSlabs * (n_rows + 1)], slab k at k * (n_rows + 1)
+    const int32_t *col;         // slab k's entries from nnz_off[k]
+    const double *val;
+    const int32_t *tile_row, *tile_k;   // slab k's tiles from tile_off[k]
+    const int32_t *rows;
+    const double *x;
+    double *part;               // [kSlabs * n_rows]
+    double *out, *acc;
+    int32_t n_rows, chunk, width, lanes;
+    int64_t nnz_off[kSlabs + 1], tile_off[kSlabs + 1];   // tile_off: n_tiles + 1 each
+    int64_t nnz_alloc, n_x;
+};
+hipError_t launch_slabs(const SlabDev &A, hipStream_t s);
+// Builds the slabs from a CSR over n_rows rows whose columns index an
+// n_x-entry vector; each slab's entries start at a multiple of 4.
+void build_slabs(const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
+                 const std::vector<double> &val, int64_t n_rows, int64_t n_x, int cap, int maxr,
+                 int vw, std::vector<int32_t> &s_rp, std::vector<int32_t> &s_col,
+                 std::vector<double> &s_val, std::vector<int32_t> &tile_row,
+                 std::vector<int32_t> &tile_k, int64_t *nnz_off, int64_t *tile_off);
 // Sliced ELL with slices of 64 rows (one wave): entry v of row 64 s + l is
 // stored at ptr[s] + 64 v + l, a slice as wide as its longest row (or every
 // slice as wide as the longest row, `uniform`, when that padding fits too),
@@ -294,7 +324,8 @@ struct CsrCfg {
     int32_t chunk = 8, width = 2;  // stream CSR (lanes = summing lanes)
     int32_t form = 1;              // stream: 1 packed tiles, 2 sliced ELL,
                                    // 3 sliced ELL with 16-bit column offsets,
-                                   // 4 packed tiles with 16-bit column offsets
+                                   // 4 packed tiles with 16-bit column offsets,
+                                   // 5 column slabs (y_R)
     std::vector<int32_t> sell_ptr, sell_col;   // forms 2/3, host copies for upload
     std::vector<int16_t> sell_off;             // form 3 (sell_col then empty)
     std::vector<int16_t> tile_off;             // form 4
@@ -302,6 +333,11 @@ struct CsrCfg {
     int32_t sell_width = 0;
     bool sell_uniform = false;
     std::vector<int32_t> tile_row, tile_k;
+    // form 5: sell_ptr holds the slabs' row pointers, tile_row/tile_k their
+    // tiles (concatenated), slab_col/slab_val their entries
+    std::vector<int32_t> slab_col;
+    std::vector<double> slab_val;
+    int64_t slab_nnz[kSlabs + 1] = {}, slab_tiles[kSlabs + 1] = {};
 };
 }  // namespace spmv
 
@@ -323,6 +359,7 @@ struct spmv_plan {
     double *dR_val = nullptr;
     int32_t *d_send_idx = nullptr, *d_perm = nullptr;
     double *d_sendbuf = nullptr, *d_recvbuf = nullptr, *d_xhalo = nullptr, *d_part = nullptr;
+    double *d_slab_part = nullptr;   // form 5: [kSlabs * n_remote_rows]
     int32_t *d_tile_row[2] = {}, *d_tile_k[2] = {};
     int32_t *d_sell_ptr[2] = {};
 

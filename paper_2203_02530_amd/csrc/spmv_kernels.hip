@@ -576,4 +576,110 @@ hipError_t launch_csr(const CsrDev &A, const double *x, double *out, double *acc
     }
 }
 
+namespace {
+
+static_assert(kSlabs == kXcds, "one column slab per XCD");
+
+struct SlabArgs {
+    StreamArgs s[kSlabs];
+    int32_t n_tiles[kSlabs];
+};
+
+// Column slabs: block b works on slab b % kSlabs, which the hardware's
+// round-robin dealing of blocks places on XCD b % kSlabs, and takes that
+// slab's tile b / kSlabs.  Each slab writes its row sums to its own part of
+// the partial-sum array.
+template <int NPT, int VW, int SL>
+__global__ __launch_bounds__(kBlock) void k_csr_slabs(const SlabArgs a)
+{
+    __shared__ double s_p[kBlock * NPT];
+    __shared__ int32_t s_rp[kBlock / SL + 1];
+    const int k = int(blockIdx.x) % kSlabs, q = int(blockIdx.x) / kSlabs;
+    if (q >= a.n_tiles[k]) return;   // whole block, before any barrier
+    stream_tile<NPT, VW, SL, false>(a.s[k], q, s_p, s_rp);
+}
+
+// y_R of row i = the slab partial sums added in slab order; stored, or added
+// into y at the row's local index.
+__global__ __launch_bounds__(kBlock) void k_slab_sum(const double *__restrict__ part, int64_t n,
+                                                     const int32_t *__restrict__ rows,
+                                                     double *__restrict__ out,
+                                                     double *__restrict__ acc)
+{
+    const int64_t stride = int64_t(gridDim.x) * kBlock;
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+        double s = part[i];
+#pragma unroll
+        for (int k = 1; k < kSlabs; ++k) s += part[k * n + i];
+        if (acc)
+            acc[rows[i]] += s;
+        else
+            out[i] = s;
+    }
+}
+
+template <int NPT, int VW, int SL>
+hipError_t launch_slabs_t(const SlabDev &A, hipStream_t s)
+{
+    SlabArgs a;
+    int64_t most = 0;
+    for (int k = 0; k < kSlabs; ++k) {
+        StreamArgs &t = a.s[k];
+        t.tile_row = A.tile_row + A.tile_off[k];
+        t.tile_k = A.tile_k + A.tile_off[k];
+        t.rp = A.rp + int64_t(k) * (A.n_rows + 1);
+        t.col = A.col + A.nnz_off[k];
+        t.rows = nullptr;
+        t.val = A.val + A.nnz_off[k];
+        t.x = A.x;
+        t.out = A.part + int64_t(k) * A.n_rows;
+        t.acc = nullptr;
+        t.nnz_alloc = uint32_t(A.nnz_alloc - A.nnz_off[k]);
+        t.n_x = uint32_t(A.n_x);
+        a.n_tiles[k] = int32_t(A.tile_off[k + 1] - A.tile_off[k] - 1);
+        most = std::max<int64_t>(most, a.n_tiles[k]);
+    }
+    if (most > 0)
+        hipLaunchKernelGGL((k_csr_slabs<NPT, VW, SL>), dim3(unsigned(most * kSlabs)),
+                           dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_slab_sum, dim3(grid_for(A.n_rows)), dim3(kBlock), 0, s, A.part,
+                       int64_t(A.n_rows), A.rows, A.out, A.acc);
+    return hipGetLastError();
+}
+
+template <int NPT, int VW>
+hipError_t launch_slabs_v(const SlabDev &A, hipStream_t s)
+{
+    switch (A.lanes) {
+        case 1: return launch_slabs_t<NPT, VW, 1>(A, s);
+        case 2: return launch_slabs_t<NPT, VW, 2>(A, s);
+        case 4: return launch_slabs_t<NPT, VW, 4>(A, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_slabs(const SlabDev &A, hipStream_t s)
+{
+    if (A.n_rows <= 0) return hipSuccess;
+    if (A.width == 2) {
+        switch (A.chunk) {
+            case 4: return launch_slabs_v<4, 2>(A, s);
+            case 8: return launch_slabs_v<8, 2>(A, s);
+            case 16: return launch_slabs_v<16, 2>(A, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (A.width == 4) {
+        switch (A.chunk) {
+            case 4: return launch_slabs_v<4, 4>(A, s);
+            case 8: return launch_slabs_v<8, 4>(A, s);
+            case 16: return launch_slabs_v<16, 4>(A, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
 }  // namespace spmv

@@ -98,22 +98,26 @@ int allocate_and_upload(spmv_plan *p)
     // 2), whose columns form 3 replaces by 16-bit offsets
     auto sliced = [&](int side) { return p->cfg[side].form == 2 || p->cfg[side].form == 3; };
     auto colsz = [&](int side) {
+        if (p->cfg[side].form == 5) return p->cfg[side].slab_col.size() * 4;
         if (p->cfg[side].form == 3) return p->cfg[side].sell_off.size() * 2;
         if (p->cfg[side].form == 4) return p->cfg[side].tile_off.size() * 2;
         return (sliced(side) ? p->cfg[side].sell_col.size()
                              : (side == 0 ? S.L_col.size() : S.R_col.size())) * 4;
     };
     auto coldata = [&](int side) -> const void * {
+        if (p->cfg[side].form == 5) return p->cfg[side].slab_col.data();
         if (p->cfg[side].form == 3) return p->cfg[side].sell_off.data();
         if (p->cfg[side].form == 4) return p->cfg[side].tile_off.data();
         return sliced(side) ? p->cfg[side].sell_col.data()
                             : (side == 0 ? S.L_col.data() : S.R_col.data());
     };
     auto valsz = [&](int side) {
+        if (p->cfg[side].form == 5) return p->cfg[side].slab_val.size() * 8;
         return (sliced(side) ? p->cfg[side].sell_val.size()
                              : (side == 0 ? S.L_val.size() : S.R_val.size())) * 8;
     };
     auto valdata = [&](int side) -> const void * {
+        if (p->cfg[side].form == 5) return p->cfg[side].slab_val.data();
         return sliced(side) ? p->cfg[side].sell_val.data()
                             : (side == 0 ? S.L_val.data() : S.R_val.data());
     };
@@ -137,6 +141,7 @@ int allocate_and_upload(spmv_plan *p)
         {(void **)&p->d_recvbuf, n_halo * 8, nullptr, 0},
         {(void **)&p->d_xhalo, n_halo * 8, nullptr, 0},
         {(void **)&p->d_part, n_rr * 8, nullptr, 0},
+        {(void **)&p->d_slab_part, p->cfg[1].form == 5 ? kSlabs * n_rr * 8 : 0, nullptr, 0},
     };
     size_t total = 0;
     for (const Item &it : items) total += align_up(std::max<size_t>(it.bytes + it.pad, 1));
@@ -314,11 +319,60 @@ void select_tile16(CsrCfg &c, const std::vector<int32_t> &col, int32_t asked)
     if (build_tile16(col, c.tile_row, c.tile_k, c.tile_off)) c.form = 4;
 }
 
+// Form 5 for y_R when asked for: column slabs (see SlabDev), each with
+// packed stream tiles; summing lanes by the mean row length within a slab
+// (at most 4).  Without remote rows the packed form stays.  Returns whether
+// the slabs were built.
+bool select_slabs(CsrCfg &c, const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
+                  const std::vector<double> &val, int64_t n_rows, int64_t n_x, int32_t lanes)
+{
+    if (c.kernel != SPMV_KERNEL_STREAM || c.form != 5) return false;
+    if (n_rows <= 0 || n_x <= 0) {
+        c.form = 1;
+        return false;
+    }
+    const double mean = double(rp[size_t(n_rows)]) / double(kSlabs * n_rows);
+    if (lanes) {
+        c.lanes = lanes;
+    } else {
+        c.lanes = 1;
+        while (c.lanes < 4 && double(c.lanes) * 14.0 <= mean) c.lanes <<= 1;
+    }
+    build_slabs(rp, col, val, n_rows, n_x, stream_cap(c.chunk), stream_maxr(c.lanes), c.width,
+                c.sell_ptr, c.slab_col, c.slab_val, c.tile_row, c.tile_k, c.slab_nnz,
+                c.slab_tiles);
+    return true;
+}
+
 hipError_t launch_product(const spmv_plan *p, int side, const double *x, double *out,
                           double *acc, hipStream_t s)
 {
     CsrDev A = side == 0 ? local_csr(p) : remote_csr(p);
     const CsrCfg &c = p->cfg[side];
+    if (c.kernel == SPMV_KERNEL_STREAM && c.form == 5) {
+        SlabDev D;
+        D.rp = p->d_sell_ptr[side];
+        D.col = A.col;
+        D.val = A.val;
+        D.tile_row = p->d_tile_row[side];
+        D.tile_k = p->d_tile_k[side];
+        D.rows = A.rows;
+        D.x = x;
+        D.part = p->d_slab_part;
+        D.out = out;
+        D.acc = acc;
+        D.n_rows = A.n_rows;
+        D.chunk = c.chunk;
+        D.width = c.width;
+        D.lanes = c.lanes;
+        for (int k = 0; k <= kSlabs; ++k) {
+            D.nnz_off[k] = c.slab_nnz[k];
+            D.tile_off[k] = c.slab_tiles[k];
+        }
+        D.nnz_alloc = int64_t(c.slab_col.size()) + kEntryPad;
+        D.n_x = A.n_x;
+        return launch_slabs(D, s);
+    }
     if (c.kernel == SPMV_KERNEL_STREAM && (c.form == 2 || c.form == 3)) {
         A.sell_ptr = p->d_sell_ptr[side];
         A.n_slices = int32_t(c.sell_ptr.size()) - 1;
@@ -372,7 +426,9 @@ int create_plan(Build build_share_fn, int32_t nranks, const int32_t *op_order, i
         return set_error(SPMV_EINVAL, "width must be 0, 2 or 4");
     if (t.xcd_remap < 0 || t.xcd_remap > 2 || t.fuse_unpack < 0 || t.fuse_unpack > 1)
         return set_error(SPMV_EINVAL, "tune field out of range");
-    if (t.form < 0 || t.form > 4) return set_error(SPMV_EINVAL, "form must be 0 to 4");
+    if (t.form < 0 || t.form > 5) return set_error(SPMV_EINVAL, "form must be 0 to 5");
+    if (t.form == 5 && t.lanes_remote > 4)
+        return set_error(SPMV_EINVAL, "column slabs sum with at most 4 lanes per row");
 
     std::vector<int32_t> def_ops;
     int32_t def_map[SPMV_N_VERTICES];
@@ -404,14 +460,18 @@ int create_plan(Build build_share_fn, int32_t nranks, const int32_t *op_order, i
             return set_error(SPMV_EINVAL, "stream CSR needs arrays below 4 GiB");
         }
     }
+    // form 5 concerns y_R only; y_L then takes the automatic form
+    const int32_t form_l = t.form == 5 ? 0 : t.form;
     configure(p->cfg[0], S.L_ptr, S.n_loc, t.kernel_local, t.lanes_local, t.rows_local,
-              t.chunk_local, t.width, t.form);
+              t.chunk_local, t.width, form_l);
     configure(p->cfg[1], S.R_ptr, int64_t(S.R_rows.size()), t.kernel_remote, t.lanes_remote,
               t.rows_remote, t.chunk_remote, t.width, t.form);
     select_sell(p->cfg[0], S.L_ptr, S.L_col, S.L_val, S.n_loc, t.chunk_local, true);
-    select_tile16(p->cfg[0], S.L_col, t.form);
-    select_sell(p->cfg[1], S.R_ptr, S.R_col, S.R_val, int64_t(S.R_rows.size()), t.chunk_remote,
-                false);
+    select_tile16(p->cfg[0], S.L_col, form_l);
+    if (!select_slabs(p->cfg[1], S.R_ptr, S.R_col, S.R_val, int64_t(S.R_rows.size()),
+                      int64_t(S.halo.size()), t.lanes_remote))
+        select_sell(p->cfg[1], S.R_ptr, S.R_col, S.R_val, int64_t(S.R_rows.size()),
+                    t.chunk_remote, false);
     p->xcd_remap = t.xcd_remap ? t.xcd_remap : 1;
     p->fuse_unpack = t.fuse_unpack == 1;
     p->host_only = (t.flags & SPMV_F_HOST_ONLY) != 0;
@@ -916,6 +976,8 @@ extern "C" int spmv_plan_info(const spmv_plan_t *p, spmv_info_t *info)
     info->chunk_remote = p->cfg[1].chunk;
     info->width = p->cfg[0].kernel == SPMV_KERNEL_STREAM ? p->cfg[0].width : p->cfg[1].width;
     auto tiles = [](const CsrCfg &c) {
+        if (c.kernel == SPMV_KERNEL_STREAM && c.form == 5)
+            return int32_t(c.slab_tiles[kSlabs] - kSlabs);   // every slab's tiles
         return c.kernel == SPMV_KERNEL_STREAM && (c.form == 1 || c.form == 4)
                    ? int32_t(c.tile_row.size()) - 1
                    : 0;

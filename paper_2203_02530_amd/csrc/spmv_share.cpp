@@ -255,6 +255,45 @@ void build_tiles(const std::vector<int32_t> &rp, int64_t n_rows, int cap, int ma
     tile_k.push_back(n_rows > 0 ? rp[size_t(n_rows)] : (rp.empty() ? 0 : rp[0]));
 }
 
+void build_slabs(const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
+                 const std::vector<double> &val, int64_t n_rows, int64_t n_x, int cap, int maxr,
+                 int vw, std::vector<int32_t> &s_rp, std::vector<int32_t> &s_col,
+                 std::vector<double> &s_val, std::vector<int32_t> &tile_row,
+                 std::vector<int32_t> &tile_k, int64_t *nnz_off, int64_t *tile_off)
+{
+    const int64_t w = std::max<int64_t>((n_x + kSlabs - 1) / kSlabs, 1);
+    s_rp.assign(size_t(kSlabs * (n_rows + 1)), 0);
+    s_col.clear();
+    s_val.clear();
+    tile_row.clear();
+    tile_k.clear();
+    std::vector<int32_t> rk, tr, tk;
+    for (int k = 0; k < kSlabs; ++k) {
+        while (s_col.size() % 4) {   // each slab starts 16-byte aligned
+            s_col.push_back(0);
+            s_val.push_back(0.0);
+        }
+        nnz_off[k] = int64_t(s_col.size());
+        tile_off[k] = int64_t(tile_row.size());
+        // a row's entries in slab k are contiguous: its columns ascend
+        rk.assign(size_t(n_rows + 1), 0);
+        for (int64_t r = 0; r < n_rows; ++r) {
+            for (int64_t j = rp[size_t(r)]; j < rp[size_t(r) + 1]; ++j)
+                if (col[size_t(j)] / w == k) {
+                    s_col.push_back(col[size_t(j)]);
+                    s_val.push_back(val[size_t(j)]);
+                }
+            rk[size_t(r) + 1] = int32_t(int64_t(s_col.size()) - nnz_off[k]);
+        }
+        std::copy(rk.begin(), rk.end(), s_rp.begin() + k * (n_rows + 1));
+        build_tiles(rk, n_rows, cap, maxr, vw, tr, tk);
+        tile_row.insert(tile_row.end(), tr.begin(), tr.end());
+        tile_k.insert(tile_k.end(), tk.begin(), tk.end());
+    }
+    nnz_off[kSlabs] = int64_t(s_col.size());
+    tile_off[kSlabs] = int64_t(tile_row.size());
+}
+
 bool build_sell(const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
                 const std::vector<double> &val, int64_t n_rows, double max_ratio,
                 std::vector<int32_t> &ptr, std::vector<int32_t> &scol, std::vector<double> &sval,

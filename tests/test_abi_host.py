@@ -449,6 +449,51 @@ def test_power_law_share_structure():
         sp.spmv_plan_destroy(p)
 
 
+def test_column_slab_form_on_host():
+    """Form 5: y_R in 8 column slabs, each a full set of packed tiles over
+    every remote row (the concatenated tile arrays hold 8 runs from row 0 to
+    the last remote row); y_L takes the automatic form; summing lanes at
+    most 4; no remote rows or the vector kernel leave the packed or vector
+    form."""
+    def info(A, P, r, **tune):
+        p = sp.spmv_plan_create(A, P, r, tune={"flags": sp.SPMV_F_HOST_ONLY, **tune})
+        try:
+            i = sp.spmv_plan_info(p)
+            tr = tk = None
+            if i["form_remote"] == 5:
+                tr = sp.spmv_plan_get_i32(p, sp.SPMV_I32_TILE_ROW_R)
+                tk = sp.spmv_plan_get_i32(p, sp.SPMV_I32_TILE_K_R)
+            return i, tr, tk
+        finally:
+            sp.spmv_plan_destroy(p)
+    A = gen.power_law(20000, seed=3)
+    i0, _, _ = info(A, 4, 1)
+    i, tr, tk = info(A, 4, 1, form=5)
+    assert i["form_remote"] == 5 and i["form_local"] == i0["form_local"]
+    assert i["lanes_remote"] == 1            # about 2 entries per row per slab
+    n_rr = i["n_remote_rows"]
+    starts = np.flatnonzero(tr == 0)
+    ends = np.flatnonzero(tr == n_rr)
+    assert starts.size == 8 and ends.size == 8 and starts[0] == 0
+    assert np.array_equal(starts[1:], ends[:-1] + 1) and ends[-1] == tr.size - 1
+    assert tr.size == i["n_tiles_remote"] + 8
+    total = 0
+    for a, b in zip(starts, ends):
+        assert np.all(np.diff(tr[a:b + 1]) > 0) and np.all(np.diff(tk[a:b + 1]) >= 0)
+        assert tk[a] == 0
+        total += int(tk[b])
+    assert total == i["nnz_remote"]          # every remote entry in one slab
+    # lanes beyond 4 are refused; no remote rows: packed; vector kernel: 0
+    with pytest.raises(sp.SpmvError):
+        sp.spmv_plan_create(A, 4, 1, tune={"flags": sp.SPMV_F_HOST_ONLY, "form": 5,
+                                           "lanes_remote": 8})
+    assert info(A, 4, 1, form=5, lanes_remote=2)[0]["lanes_remote"] == 2
+    assert info(gen.laplacian_3d7(8), 1, 0, form=5)[0]["form_remote"] == 1
+    assert info(A, 4, 1, form=5, kernel_remote=1)[0]["form_remote"] == 0
+    with pytest.raises(sp.SpmvError):
+        sp.spmv_plan_create(A, 4, 1, tune={"flags": sp.SPMV_F_HOST_ONLY, "form": 6})
+
+
 def test_sliced_form_choice_on_host():
     """Automatic form: sliced ELL when every slice of 64 rows has one width
     of at most 8 (7-point share, its one-entry remote rows), with y_L's
@@ -522,4 +567,4 @@ def test_sliced_form_choice_on_host():
     assert info(C, 2, 1, form=3)["form_local"] == 2
     assert info(C, 2, 1, form=4)["form_local"] == 4
     with pytest.raises(sp.SpmvError):
-        info(gen.laplacian_3d7(8), 4, 1, form=5)
+        info(gen.laplacian_3d7(8), 4, 1, form=6)

@@ -209,6 +209,56 @@ def test_packed16_form(chunk, width, lanes):
             assert_share_parity(res, ref)
 
 
+def _dense_remote_rows(n=40000, dense=(20000, 20001, 29999), seed=4):
+    """A diagonal matrix whose listed rows also hold every column of the
+    first half: on two ranks those rows carry 20,000 remote entries, 2,500
+    in each column slab (longer than any window)."""
+    rng = np.random.default_rng(seed)
+    cols, ptr = [], [0]
+    for i in range(n):
+        c = np.arange(n // 2, dtype=np.int32) if i in dense else np.empty(0, np.int32)
+        c = np.union1d(c, [i]).astype(np.int32)
+        cols.append(c)
+        ptr.append(ptr[-1] + c.size)
+    col = np.concatenate(cols)
+    return gen.CSR(n, n, np.asarray(ptr, np.int32), col, rng.standard_normal(col.size))
+
+
+@pytest.mark.parametrize("chunk,width,lanes", [(0, 0, 0), (4, 2, 1), (8, 4, 2), (16, 2, 4)])
+def test_column_slab_form(chunk, width, lanes):
+    """y_R in column slabs (form 5) against the oracle on power-law,
+    stencil and banded shares and on rows far longer than a window; every
+    plan gives the same bits, whether y_R adds into y itself or a combine
+    step adds its partial sums; integer data are exact."""
+    log(f"column slabs chunk={chunk} width={width} lanes={lanes}")
+    cases = [(gen.power_law(60000, seed=21), 4, 2, 31),
+             (gen.power_law(30000, seed=17), 16, 5, 32),
+             (gen.stencil_3d27(30, seed=5), 4, 2, 33),
+             (gen.banded_random(50000, seed=9), 3, 1, 34),
+             (_dense_remote_rows(), 2, 1, 35),
+             (gen.laplacian_2d5(37, 29), 3, 2, 36)]
+    tune = {"kernel_remote": 2, "chunk_remote": chunk, "width": width, "lanes_remote": lanes,
+            "form": 5}
+    for A, P, r, seed in cases:
+        x = gen.x_normal(A.n_cols, seed)
+        ref = oracle.share_reference(A, P, r, x)
+        ys, fused = [], set()
+        for idx in (7, 468, 1190, 2003):
+            ops, smap = sp.spmv_plan_space_get(P, 2, idx)
+            res, _ = run_share(A, P, r, x, ops, smap, tune=tune, ref=ref)
+            assert res["info"]["form_remote"] == 5, (A.n_rows, P, r)
+            assert_share_parity(res, ref)
+            ys.append(bits(res["y"]))
+            fused.add(res["info"]["fused_combine"])
+        assert fused == {0, 1}
+        for y in ys[1:]:
+            assert np.array_equal(ys[0], y)
+    A = gen.laplacian_3d7(32)   # integer entries: every sum exact
+    res, ref = run_share(A, 4, 2, gen.x_integer(A.n_cols, 9), tune=tune)
+    assert res["info"]["form_remote"] == 5
+    assert np.array_equal(bits(res["y"]), bits(ref["y"]))
+
+
 @pytest.mark.parametrize("chunk", [0, 8, 16])
 def test_sliced16_form(chunk):
     """Sliced ELL with 16-bit row-relative columns against the oracle, and
