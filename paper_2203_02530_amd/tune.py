@@ -10,8 +10,9 @@ Three searches, all timed on the device by the library itself:
   is uploaded once per replica; samples rotate over cold replicas.
 * :func:`tune_kernel` -- the product kernel variant (stream CSR in packed
   tiles: window chunk, load width, summing lanes; sliced ELL: entries per
-  batch of loads; vector CSR: lanes per row, rows per lane group), timed
-  with HIP events around back-to-back launches over cold replicas.
+  batch of loads; vector CSR: lanes per row, rows per lane group; for y_R
+  also column slabs), timed with HIP events around back-to-back launches
+  over cold replicas.
 * :func:`tune_batch` -- the options of a batch of shares (stream launches
   or one graph, copy streams, persistent blocks per CU, XCD affinity),
   timed over whole batches.
@@ -28,7 +29,7 @@ import os
 
 import numpy as np
 
-from . import (SPMV_OP_YL, spmv_batch_create, spmv_batch_destroy, spmv_batch_exec,
+from . import (SPMV_OP_YL, SPMV_OP_YR, spmv_batch_create, spmv_batch_destroy, spmv_batch_exec,
                spmv_op_launch, spmv_plan_create, spmv_plan_destroy,
                spmv_plan_get_i32, spmv_plan_inbox, spmv_plan_info, spmv_plan_reorder,
                spmv_plan_space_count, spmv_plan_space_get, spmv_plan_time, SPMV_I32_HALO_COLS)
@@ -142,12 +143,24 @@ DEFAULT_CANDIDATES = (
     [{"kernel_local": 1, "lanes_local": l, "rows_local": r} for l in (8, 32) for r in (4, 8)])
 
 
+# y_R variants: packed tiles with 1, 2 or 4 summing lanes, the sliced form
+# (taken only where its padding stays small), column slabs with 1 or 2 lanes.
+DEFAULT_REMOTE_CANDIDATES = (
+    [{"kernel_remote": 2, "form": 1, "lanes_remote": l} for l in (1, 2, 4)] +
+    [{"kernel_remote": 2, "form": 2}] +
+    [{"kernel_remote": 2, "form": 5, "lanes_remote": l} for l in (1, 2)])
+
+
 def tune_kernel(A, nranks: int, rank: int, x: np.ndarray, candidates=DEFAULT_CANDIDATES,
-                launches: int = 100, log=None):
-    """Search kernel variants for y_L (both CSR kernels: stream chunk / width
-    / summing lanes, vector lanes / rows) by timing back-to-back launches
-    over cold replicas.  Returns (best tune dict, all results)."""
+                launches: int = 100, log=None, op: int = SPMV_OP_YL):
+    """Search kernel variants for one product (y_L by default: both CSR
+    kernels, stream chunk / width / summing lanes, vector lanes / rows; with
+    op = SPMV_OP_YR and DEFAULT_REMOTE_CANDIDATES the forms of y_R) by timing
+    back-to-back launches of that op over cold replicas.  Returns (best tune
+    dict, all results)."""
     import torch
+    if op not in (SPMV_OP_YL, SPMV_OP_YR):
+        raise ValueError("tune_kernel times y_L or y_R")
     results = []
     stream = torch.cuda.Stream()
     for tune in candidates:
@@ -164,12 +177,12 @@ def tune_kernel(A, nranks: int, rank: int, x: np.ndarray, candidates=DEFAULT_CAN
             torch.cuda.synchronize()
             with torch.cuda.stream(stream):
                 for i in range(2 * R):
-                    spmv_op_launch(plans[i % R], SPMV_OP_YL, xs[i % R], ys[i % R], stream)
+                    spmv_op_launch(plans[i % R], op, xs[i % R], ys[i % R], stream)
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
                 for i in range(launches):
-                    spmv_op_launch(plans[i % R], SPMV_OP_YL, xs[i % R], ys[i % R], stream)
+                    spmv_op_launch(plans[i % R], op, xs[i % R], ys[i % R], stream)
                 e1.record(stream)
             torch.cuda.synchronize()
             us = e0.elapsed_time(e1) * 1e3 / launches

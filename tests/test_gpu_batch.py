@@ -191,3 +191,19 @@ def test_batch_rejects_mixed_configs():
     finally:
         for p in (p1, p2, p3, p4, p5, p6):
             sp.spmv_plan_destroy(p)
+    # y_R in column slabs cannot join a batch; the same share with y_R in
+    # packed tiles (and y_L in 16-bit tiles either way) can
+    B = gen.power_law(20000, seed=3)
+    q4 = sp.spmv_plan_create(B, 4, 1, tune={**TUNE, "form": 4})
+    q5 = sp.spmv_plan_create(B, 4, 1, tune={**TUNE, "form": 5})
+    try:
+        i4, i5 = sp.spmv_plan_info(q4), sp.spmv_plan_info(q5)
+        assert (i4["form_local"], i4["form_remote"]) == (4, 1)
+        assert (i5["form_local"], i5["form_remote"]) == (4, 5)
+        sp.spmv_batch_destroy(sp.spmv_batch_create([q4]))
+        with pytest.raises(sp.SpmvError) as e:
+            sp.spmv_batch_create([q5])
+        assert e.value.code == sp.SPMV_EINVAL
+    finally:
+        sp.spmv_plan_destroy(q4)
+        sp.spmv_plan_destroy(q5)

@@ -535,6 +535,28 @@ def test_kernel_autotuner():
     assert_share_parity(out, ref)
 
 
+def test_remote_autotuner():
+    """The same search over y_R's forms (packed tiles with 1, 2, 4 lanes,
+    sliced, column slabs with 1, 2 lanes) on a power-law share whose halo
+    is larger than one XCD's L2: every candidate timed, the fastest
+    returned, its plan within tolerance of the oracle."""
+    from paper_2203_02530_amd import tune as tuner
+    A = gen.power_law(1_000_000, seed=44)
+    P, r = 8, 3
+    x = gen.x_normal(A.n_cols, 82)
+    cands = list(tuner.DEFAULT_REMOTE_CANDIDATES)
+    best, res = tuner.tune_kernel(A, P, r, x, candidates=cands, launches=20, op=sp.SPMV_OP_YR)
+    assert [d["tune"] for d in res] == cands
+    assert all(d["us"] > 0 for d in res)
+    assert best == min(res, key=lambda d: d["us"])["tune"]
+    log("remote autotuner: " + ", ".join(f'{d["tune"]["form"]}/{d["tune"].get("lanes_remote", 0)}'
+                                          f' {d["us"]:.1f} us' for d in res))
+    out, ref = run_share(A, P, r, x, tune=best)
+    assert_share_parity(out, ref)
+    with pytest.raises(ValueError):
+        tuner.tune_kernel(A, P, r, x, candidates=cands[:1], op=sp.SPMV_OP_PACK)
+
+
 @pytest.mark.parametrize("plan_index", [332, 1500, 71, 1190, 2003])
 def test_exec_orders_after_pending_caller_work(plan_index):
     """The exec runs after work still pending on the caller's stream (its
