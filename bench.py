@@ -484,6 +484,40 @@ def ranks_section(sp, torch, A, P, x, ops, smap, tune, steps: int = 100) -> dict
             "max_rank": max(out, key=lambda d: d["step_us"])["rank"]}
 
 
+def slabs_section(sp, torch, gen, launches: int = 200) -> dict:
+    """y_R of the 4M-row power-law share (P = 16, rank 5; its dominant
+    kernel, random gathers from a 19 MB halo) in packed tiles (the
+    automatic form) and in column slabs (form 5), each timed over cold
+    replicas with events around back-to-back launches."""
+    w = gen.WORKLOADS["powerlaw_4m_p16r5"]
+    A = w["build"]()
+    P, r = w["nranks"], w["rank"]
+    x = w["x"](A.n_cols)
+    out = {"workload": w["desc"]}
+    for name, tune in (("packed", {}), ("slabs", {"form": 5})):
+        R = replicas_for(A, P, r, tune, sp)
+        plans = [sp.spmv_plan_create(A, P, r, None, None, 2, tune) for _ in range(R)]
+        try:
+            info = sp.spmv_plan_info(plans[0])
+            lo, n = info["lo"], info["n_loc"]
+            xs = [torch.from_numpy(np.ascontiguousarray(x[lo:lo + n])).cuda() for _ in plans]
+            ys = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in plans]
+            us = time_op(sp, torch, plans, sp.SPMV_OP_YR, xs, ys, launches)
+        finally:
+            for p in plans:
+                sp.spmv_plan_destroy(p)
+        out[name] = {"yR_us": round(us, 3), "form_remote": info["form_remote"],
+                     "lanes_remote": info["lanes_remote"], "tiles": info["n_tiles_remote"],
+                     "replicas": R}
+    nr, h = info["nnz_remote"], info["n_halo"]
+    yr_bytes = 12 * nr + 24 * info["n_remote_rows"] + 8 * h
+    out["yR_bytes"] = int(yr_bytes)
+    for name in ("packed", "slabs"):
+        out[name]["yR_gbs"] = round(yr_bytes / (out[name]["yR_us"] * 1e-6) / 1e9, 1)
+    out["speedup"] = round(out["packed"]["yR_us"] / out["slabs"]["yR_us"], 3)
+    return out
+
+
 def paper_section(sp, torch, gen, tuner) -> dict:
     """The paper's own workload (Sec. IV: banded 150,000 x 150,000, 10
     entries per row in half-bandwidth 37,500, P = 4): every plan of rank 1's
@@ -531,6 +565,9 @@ def main() -> int:
                     help="rank shares in the batched section (0 = skip it)")
     ap.add_argument("--serve-requests", type=int, default=20000,
                     help="requests in the serving section (0 = skip it)")
+    ap.add_argument("--slabs", type=int, default=1,
+                    help="time y_R of the power-law share in packed tiles and in column "
+                         "slabs (1 = yes)")
     ap.add_argument("--all-ranks", type=int, default=1,
                     help="also run every rank's share of the matrix with the chosen plan "
                          "and report the max over ranks (1 = yes)")
@@ -718,6 +755,10 @@ def main() -> int:
     if P > 1 and not args.kernel_only and args.all_ranks:
         progress("every rank's share")
         all_ranks = ranks_section(sp, torch, A, P, x, ops, smap, tune)
+    slabs = None
+    if args.slabs and not args.kernel_only:
+        progress("column slabs")
+        slabs = slabs_section(sp, torch, gen)
     paper = None
     if args.plan == "auto" and not args.no_rules:
         from paper_2203_02530_amd import tune as tuner
@@ -774,6 +815,7 @@ def main() -> int:
         "fine_grained": fine,
         "kernel_tune": kernel_tune,
         "all_ranks": all_ranks,
+        "remote_slabs": slabs,
         "paper_workload": paper,
         "plan_order": plan_order,
         "plan_streams": plan_streams,
