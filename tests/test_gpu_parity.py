@@ -253,6 +253,17 @@ def test_column_slab_form(chunk, width, lanes):
         assert fused == {0, 1}
         for y in ys[1:]:
             assert np.array_equal(ys[0], y)
+        # y_R reading the receive buffer directly, and the fine-grained
+        # program: the same bits
+        fu, _ = run_share(A, P, r, x, tune={**tune, "fuse_unpack": 1}, ref=ref)
+        assert fu["info"]["form_remote"] == 5 and np.array_equal(ys[0], bits(fu["y"]))
+        plan = sp.spmv_plan_create(A, P, r, None, None, 2, tune)
+        try:
+            sp.spmv_plan_set_fine(plan)
+            fi, _ = run_share(A, P, r, x, ref=ref, plan=plan)
+            assert fi["info"]["fine"] == 1 and np.array_equal(ys[0], bits(fi["y"]))
+        finally:
+            sp.spmv_plan_destroy(plan)
     A = gen.laplacian_3d7(32)   # integer entries: every sum exact
     res, ref = run_share(A, 4, 2, gen.x_integer(A.n_cols, 9), tune=tune)
     assert res["info"]["form_remote"] == 5
