@@ -332,15 +332,29 @@ bool select_slabs(CsrCfg &c, const std::vector<int32_t> &rp, const std::vector<i
         return false;
     }
     const double mean = double(rp[size_t(n_rows)]) / double(kSlabs * n_rows);
+    const int32_t lanes_packed = c.lanes;
     if (lanes) {
         c.lanes = lanes;
     } else {
         c.lanes = 1;
         while (c.lanes < 4 && double(c.lanes) * 14.0 <= mean) c.lanes <<= 1;
     }
+    std::vector<int32_t> tile_row, tile_k;
     build_slabs(rp, col, val, n_rows, n_x, stream_cap(c.chunk), stream_maxr(c.lanes), c.width,
-                c.sell_ptr, c.slab_col, c.slab_val, c.tile_row, c.tile_k, c.slab_nnz,
-                c.slab_tiles);
+                c.sell_ptr, c.slab_col, c.slab_val, tile_row, tile_k, c.slab_nnz, c.slab_tiles);
+    // the stream kernel addresses the values through 32-bit byte offsets;
+    // the slabs' alignment padding can push a share at the limit past it
+    constexpr int64_t kMax = (int64_t(1) << 32) - 64;
+    if ((int64_t(c.slab_val.size()) + kEntryPad) * 8 >= kMax) {
+        c.form = 1;
+        c.lanes = lanes_packed;
+        c.sell_ptr.clear();
+        c.slab_col.clear();
+        c.slab_val.clear();
+        return false;
+    }
+    c.tile_row.swap(tile_row);
+    c.tile_k.swap(tile_k);
     return true;
 }
 
