@@ -206,7 +206,8 @@ typedef struct {
     int32_t xcd_remap, fuse_unpack;
     int32_t fused_combine; /* 1: y_R adds into y itself; 0: a combine step
                               at end adds the remote partial sums            */
-    int32_t n_tiles_local, n_tiles_remote;  /* packed stream tiles (0: none) */
+    int32_t n_tiles_local, n_tiles_remote;  /* packed stream tiles (0: none;
+                              form 5: the tiles of all 8 slabs)            */
     int32_t form_local;    /* y_L stream form: 1 packed tiles, 2 sliced ELL,
                               3 sliced ELL with 16-bit column offsets,
                               4 packed tiles with 16-bit column offsets,
@@ -235,7 +236,11 @@ typedef struct {
 #define SPMV_I32_TILE_ROW_L  12  /* [n_tiles_local+1] stream-CSR tile rows of
                                     A_L: tile t = rows [row[t], row[t+1])     */
 #define SPMV_I32_TILE_K_L    13  /* [n_tiles_local+1] first entry of each tile */
-#define SPMV_I32_TILE_ROW_R  14  /* same for A_R (compressed rows)            */
+#define SPMV_I32_TILE_ROW_R  14  /* same for A_R (compressed rows); in column
+                                    slabs (form 5) the 8 slabs' arrays one
+                                    after another, each closed by its own
+                                    last entry: n_tiles_remote + 8 in all,
+                                    entries counted within the slab         */
 #define SPMV_I32_TILE_K_R    15
 #define SPMV_I32_OP_STREAM   16  /* [n_ops] canonical stream of each position of
                                     the order in force, -1 for tokens that
