@@ -107,6 +107,25 @@ __global__ __launch_bounds__(kBlock) void k_grouped(const ShareDev *__restrict__
     }
 }
 
+// Tile t of one request: y = A x over the request's matrix.
+template <int NPT, int VW>
+__device__ __forceinline__ void serve_tile(const ServeDev &S, int t, double *s_p, int32_t *s_rp)
+{
+    StreamArgs A;
+    A.tile_row = S.tile_row;
+    A.tile_k = S.tile_k;
+    A.rp = S.rp;
+    A.col = S.col;
+    A.rows = nullptr;
+    A.val = S.val;
+    A.x = S.x;
+    A.out = S.y;
+    A.acc = nullptr;
+    A.nnz_alloc = S.nnz_alloc;
+    A.n_x = S.n;
+    tile_sl<NPT, VW>(S.lanes, A, t, s_p, s_rp);
+}
+
 // Serving: grid-stride over the tiles of a batch of requests (each request
 // one resident single-rank matrix); request s owns global tiles
 // [pref[s], pref[s+1]).
@@ -126,20 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_serve(const ServeDev *__restrict__ d
             else
                 hi = mid;
         }
-        const ServeDev &S = d[lo];
-        StreamArgs A;
-        A.tile_row = S.tile_row;
-        A.tile_k = S.tile_k;
-        A.rp = S.rp;
-        A.col = S.col;
-        A.rows = nullptr;
-        A.val = S.val;
-        A.x = S.x;
-        A.out = S.y;
-        A.acc = nullptr;
-        A.nnz_alloc = S.nnz_alloc;
-        A.n_x = S.n;
-        tile_sl<NPT, VW>(S.lanes, A, g - pref[lo], s_p, s_rp);
+        serve_tile<NPT, VW>(d[lo], g - pref[lo], s_p, s_rp);
         __syncthreads();
     }
 }
@@ -176,20 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_inline(const ServeInline a)
         int lo = 0;   // largest s with pref[s] <= g
         for (int s = 1; s < a.n_req; ++s)
             if (a.pref[s] <= g) lo = s;
-        const ServeDev &S = a.d[lo];
-        StreamArgs A;
-        A.tile_row = S.tile_row;
-        A.tile_k = S.tile_k;
-        A.rp = S.rp;
-        A.col = S.col;
-        A.rows = nullptr;
-        A.val = S.val;
-        A.x = S.x;
-        A.out = S.y;
-        A.acc = nullptr;
-        A.nnz_alloc = S.nnz_alloc;
-        A.n_x = S.n;
-        tile_sl<NPT, VW>(S.lanes, A, g - a.pref[lo], s_p, s_rp);
+        serve_tile<NPT, VW>(a.d[lo], g - a.pref[lo], s_p, s_rp);
         __syncthreads();
     }
 }
