@@ -236,7 +236,8 @@ def test_column_slab_form(chunk, width, lanes):
              (gen.stencil_3d27(30, seed=5), 4, 2, 33),
              (gen.banded_random(50000, seed=9), 3, 1, 34),
              (_dense_remote_rows(), 2, 1, 35),
-             (gen.laplacian_2d5(37, 29), 3, 2, 36)]
+             (gen.laplacian_2d5(37, 29), 3, 2, 36),
+             (gen.laplacian_2d5(5, 4), 2, 1, 37)]   # a 5-entry halo: slabs 5-7 empty
     tune = {"kernel_remote": 2, "chunk_remote": chunk, "width": width, "lanes_remote": lanes,
             "form": 5}
     for A, P, r, seed in cases:
