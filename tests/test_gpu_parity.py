@@ -521,10 +521,11 @@ def test_empty_share_and_empty_rows():
     C = gen.CSR(n, n, np.arange(n + 1, dtype=np.int32), ((rows + n // 2) % n).astype(np.int32),
                 np.linspace(-1.0, 1.0, n))
     x = gen.x_normal(n, 3)
-    for form in (0, 1, 2, 3, 4):
+    for form in (0, 1, 2, 3, 4, 5):
         res, ref = run_share(C, 2, 1, x, tune={"kernel_local": 2, "form": form})
         assert res["info"]["nnz_local"] == 0
         assert_share_parity(res, ref)
+    assert res["info"]["form_remote"] == 5
 
 
 def test_kernel_autotuner():
