@@ -63,8 +63,19 @@ def step_convolution(a_sorted: np.ndarray, r: int) -> np.ndarray:
     a = np.asarray(a_sorted, np.float64)
     if a.size < 2 * r:
         return np.zeros(0)
-    kernel = np.concatenate([np.ones(r), -np.ones(r)])   # np.convolve flips it
-    return np.convolve(a, kernel, mode="valid")
+    # Each window is summed in a fixed order: start from 0, add the r
+    # samples after the gap left to right, then subtract the r samples up to
+    # it left to right.  Every output is then the same floating-point
+    # expression whatever the array length, so measured (non-integer) times
+    # give reproducible peaks; an FFT or a library convolution may reorder
+    # the additions and move a peak by one rounding.
+    m = a.size - 2 * r + 1
+    c = np.zeros(m)
+    for k in range(r, 2 * r):
+        c += a[k:k + m]
+    for k in range(r):
+        c -= a[k:k + m]
+    return c
 
 
 def class_labels(times, radius: int | None = None, percentile: float = 98.0) -> dict:

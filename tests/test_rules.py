@@ -89,6 +89,31 @@ def test_conv_matches_oracle():
         assert rules.step_convolution(a, r).tolist() == c
 
 
+def _timing_like(n, seed):
+    """Float times shaped like a plan sweep: a few levels 45-100 us apart by
+    uneven steps, with noise of about a microsecond (no sum is exact)."""
+    rng = np.random.default_rng(seed)
+    levels = rng.choice([45.3e-6, 52.1e-6, 71.7e-6, 98.9e-6], size=n, p=[0.1, 0.3, 0.5, 0.1])
+    return levels + rng.normal(0.0, 1.1e-6, size=n) + rng.random(n) * 1e-7
+
+
+@pytest.mark.parametrize("n,seed", [(50, 11), (400, 12), (2016, 13), (2016, 14)])
+def test_conv_and_labels_match_oracle_on_float_times(n, seed):
+    """On measured-like float times the window sums are the same floating
+    point expressions on both sides (bit-identical), so peaks, prominences,
+    bounds and labels agree exactly."""
+    t = _timing_like(n, seed)
+    r = orules.radius(n)
+    a = np.sort(t, kind="stable")
+    c, _ = orules.step_conv(a.tolist(), r)
+    got = rules.step_convolution(a, r)
+    assert np.array_equal(got.view(np.int64), np.asarray(c, np.float64).view(np.int64))
+    lab_lib = rules.class_labels(t)
+    lab, bounds = orules.labels(t.tolist())
+    assert lab_lib["bounds"].tolist() == bounds
+    assert lab_lib["labels"].tolist() == lab
+
+
 def test_features_match_oracle_full_space():
     space = rules.plan_space(4, 2)
     X, names = rules.features(space)
