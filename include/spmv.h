@@ -140,9 +140,13 @@ typedef struct {
     int32_t width;         /* stream: entries per load, 0 = auto, 2 or 4     */
     int32_t xcd_remap;     /* 0 = auto, 1 = contiguous row tiles per XCD,
                               2 = plain round-robin block order             */
-    int32_t fuse_unpack;   /* 0 = explicit Unpack kernel, 1 = y_R reads the
-                              receive buffer directly (valid because the
-                              receive layout equals the halo order)          */
+    int32_t fuse_unpack;   /* 0 = auto: y_R reads the receive buffer in
+                              place whenever the unpack permutation is the
+                              identity (always here: the receive layout
+                              equals the halo order), so no Unpack kernel
+                              runs; 1 = fused (SPMV_EINVAL if the permutation
+                              is not the identity); 2 = the explicit Unpack
+                              kernel                                         */
     int32_t flags;         /* SPMV_F_* below                               */
     int32_t form;          /* stream: 1 = packed tiles (rows cut to fill
                               each window), 2 = sliced ELL (a wave per 64
@@ -215,6 +219,7 @@ typedef struct {
     int32_t form_remote;   /* same for y_R                                   */
     int32_t n_slices_local, n_slices_remote;  /* sliced-ELL slices (0: none) */
     int32_t fine;          /* 1 while a fine-grained order is in force       */
+    int32_t device;        /* HIP device of the plan's memory (-1 host-only) */
 } spmv_info_t;
 
 /* Integer metadata selectors for spmv_plan_get_i32. */
@@ -251,8 +256,8 @@ typedef struct {
 #define SPMV_F64_AR_VAL       1  /* [nnz_remote]                              */
 #define SPMV_F64_SENDBUF      2  /* [n_send] device send buffer after Pack    */
 #define SPMV_F64_RECVBUF      3  /* [n_halo] device receive buffer            */
-#define SPMV_F64_X_HALO       4  /* [n_halo] x_R after Unpack (equals RECVBUF
-                                    when fuse_unpack = 1)                     */
+#define SPMV_F64_X_HALO       4  /* [n_halo] x_R after Unpack (the receive
+                                    buffer itself when Unpack is fused)       */
 #define SPMV_F64_OP_MS        5  /* [SPMV_N_VERTICES + 1] summed milliseconds
                                     per op since the last reset (SPMV_F_PROFILE;
                                     index SPMV_N_VERTICES = combine step)      */

@@ -155,7 +155,7 @@ class spmv_info_t(ctypes.Structure):
             "lanes_local", "lanes_remote", "rows_local", "rows_remote", "chunk_local",
             "chunk_remote", "width", "xcd_remap", "fuse_unpack", "fused_combine",
             "n_tiles_local", "n_tiles_remote", "form_local", "form_remote",
-            "n_slices_local", "n_slices_remote", "fine")]
+            "n_slices_local", "n_slices_remote", "fine", "device")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -243,6 +243,58 @@ def _addr(a) -> int:
     return int(a.data_ptr())
 
 
+# Per plan: (n_loc, device), cached at the first check and dropped when the
+# plan is destroyed (a later plan may reuse the handle's address).
+_PLAN_META: dict = {}
+# Per batch: the (n_loc, device) of each share, recorded at creation.
+_BATCH_META: dict = {}
+
+
+def _plan_meta(plan):
+    m = _PLAN_META.get(plan)
+    if m is None:
+        info = spmv_plan_info(plan)
+        m = (int(info["n_loc"]), int(info["device"]))
+        _PLAN_META[plan] = m
+    return m
+
+
+def _dev_vec(a, n: int, device: int, name: str) -> int:
+    """Address of a device vector of at least n FP64 entries, checked: a
+    contiguous float64 torch CUDA tensor on `device`, or None when n == 0.
+    A plain int is taken as a raw device address the caller vouches for
+    (the library cannot inspect it).  Anything else -- a host array, a CPU
+    tensor, another dtype, a strided view, too few entries, another device
+    -- raises before any launch."""
+    if a is None:
+        if n > 0:
+            raise ValueError(f"{name} is None but the plan has {n} rows")
+        return 0
+    if isinstance(a, int):
+        return a
+    if isinstance(a, np.ndarray):
+        raise TypeError(f"{name} is a host numpy array; pass a device tensor")
+    if torch is None or not isinstance(a, torch.Tensor):
+        raise TypeError(f"{name} must be a torch CUDA tensor, got {type(a).__name__}")
+    if not a.is_cuda:
+        raise ValueError(f"{name} is on {a.device}, not on a GPU")
+    if a.dtype != torch.float64:
+        raise TypeError(f"{name} has dtype {a.dtype}; the library computes in float64")
+    if not a.is_contiguous():
+        raise ValueError(f"{name} is not contiguous")
+    if a.numel() < n:
+        raise ValueError(f"{name} has {a.numel()} entries, the plan needs {n}")
+    if device >= 0 and a.device.index != device:
+        raise ValueError(f"{name} is on cuda:{a.device.index}, the plan on cuda:{device}")
+    return int(a.data_ptr())
+
+
+def _plan_vecs(plan, x, y, need_x: bool = True, need_y: bool = True):
+    n, dev = _plan_meta(plan)
+    return (_dev_vec(x, n if need_x else 0, dev, "x") if (need_x or x is not None) else 0,
+            _dev_vec(y, n if need_y else 0, dev, "y") if (need_y or y is not None) else 0)
+
+
 def _stream_handle(stream) -> int:
     if stream is None:
         return 0
@@ -310,17 +362,23 @@ def spmv_plan_create_local(local, n_global: int, nranks: int, rank: int, send_id
 
 
 def spmv_plan_destroy(plan) -> None:
+    _PLAN_META.pop(plan, None)
     _check(_lib.spmv_plan_destroy(plan))
 
 
 def spmv_exec(plan, x, y, stream=None) -> None:
-    """y = (A x) over the plan's rows; x, y device arrays of n_loc FP64."""
-    _check(_lib.spmv_exec(plan, _addr(x), _addr(y), _stream_handle(stream)))
+    """y = (A x) over the plan's rows; x, y contiguous float64 CUDA tensors
+    of at least n_loc entries on the plan's device (checked)."""
+    xa, ya = _plan_vecs(plan, x, y)
+    _check(_lib.spmv_exec(plan, xa, ya, _stream_handle(stream)))
 
 
 def spmv_op_launch(plan, op: int, x=None, y=None, stream=None) -> None:
-    """Launch one GPU op of the plan asynchronously on ``stream``."""
-    _check(_lib.spmv_op_launch(plan, op, _addr(x), _addr(y), _stream_handle(stream)))
+    """Launch one GPU op of the plan asynchronously on ``stream``; x is
+    checked for Pack and y_L, y for y_L and y_R."""
+    xa, ya = _plan_vecs(plan, x, y, need_x=op in (SPMV_OP_PACK, SPMV_OP_YL),
+                        need_y=op in (SPMV_OP_YL, SPMV_OP_YR))
+    _check(_lib.spmv_op_launch(plan, op, xa, ya, _stream_handle(stream)))
 
 
 def _smap_array(stream_map):
@@ -351,12 +409,21 @@ def spmv_plan_time(plans, xs, ys, stream=None, t_measure: float = 0.01,
         plans, xs, ys = [plans], [xs], [ys]
     n = len(plans)
     pa = (ctypes.c_void_p * n)(*plans)
-    xa = (ctypes.c_void_p * n)(*[_addr(v) or None for v in xs])
-    ya = (ctypes.c_void_p * n)(*[_addr(v) or None for v in ys])
+    xa, ya = _vec_tables(plans, xs, ys)
     out = np.empty(n_measure, np.float64)
     _check(_lib.spmv_plan_time(pa, n, xa, ya, _stream_handle(stream), t_measure, n_measure,
                                out.ctypes.data))
     return out
+
+
+def _vec_tables(plans, xs, ys):
+    """ctypes tables of the checked x / y addresses of each plan."""
+    if len(xs) != len(plans) or len(ys) != len(plans):
+        raise ValueError("need one x and one y per plan")
+    n = len(plans)
+    pairs = [_plan_vecs(p, x, y) for p, x, y in zip(plans, xs, ys)]
+    return ((ctypes.c_void_p * n)(*[a or None for a, _ in pairs]),
+            (ctypes.c_void_p * n)(*[b or None for _, b in pairs]))
 
 
 def spmv_plan_info(plan) -> dict:
@@ -511,8 +578,7 @@ def spmv_mcts_run(plans, xs, ys, stream=None, iterations: int = 0, seed: int = 0
         plans, xs, ys = [plans], [xs], [ys]
     n = len(plans)
     pa = (ctypes.c_void_p * n)(*plans)
-    xa = (ctypes.c_void_p * n)(*[_addr(v) or None for v in xs])
-    ya = (ctypes.c_void_p * n)(*[_addr(v) or None for v in ys])
+    xa, ya = _vec_tables(plans, xs, ys)
     o, keep = _mcts_opts(iterations, seed, c, n_streams, n_measure, t_measure, rand)
     nranks = spmv_plan_info(plans[0])["nranks"]
     cap = int(iterations) if iterations > 0 else spmv_plan_space_count(nranks, max(n_streams, 1))
@@ -533,8 +599,7 @@ def spmv_mcts_run_seq(plans, xs=None, ys=None, stream=None, fine: bool = False, 
         ys = [ys] if ys is not None else None
     n = len(plans)
     pa = (ctypes.c_void_p * n)(*plans)
-    xa = (ctypes.c_void_p * n)(*[_addr(v) or None for v in xs]) if xs else None
-    ya = (ctypes.c_void_p * n)(*[_addr(v) or None for v in ys]) if ys else None
+    xa, ya = _vec_tables(plans, xs, ys) if xs and ys else (None, None)
     o, keep = _mcts_opts(iterations, seed, c, n_streams, n_measure, t_measure, rand)
     if fine:
         max_ops = len(spmv_fine_tokens(plans[0]))
@@ -631,14 +696,23 @@ def spmv_batch_create(plans, opts: dict | None = None):
         setattr(o, k, v)
     out = ctypes.c_void_p()
     _check(_lib.spmv_batch_create(arr, len(plans), ctypes.byref(o), ctypes.byref(out)))
+    _BATCH_META[out.value] = [_plan_meta(p) for p in plans]
     return out.value
 
 
 def spmv_batch_exec(batch, xs, ys, stream=None) -> None:
-    """xs, ys: sequences of device arrays (one per share)."""
+    """xs, ys: sequences of device tensors, one per share, each checked
+    like spmv_exec's against its share."""
+    meta = _BATCH_META.get(batch)
+    if meta is None:
+        raise ValueError("unknown batch handle")
+    if len(xs) != len(meta) or len(ys) != len(meta):
+        raise ValueError(f"the batch has {len(meta)} shares; got {len(xs)} x and {len(ys)} y")
     n = len(xs)
-    xa = (ctypes.c_void_p * n)(*[_addr(v) or None for v in xs])
-    ya = (ctypes.c_void_p * n)(*[_addr(v) or None for v in ys])
+    xa = (ctypes.c_void_p * n)(*[_dev_vec(v, m[0], m[1], f"x[{i}]") or None
+                                 for i, (v, m) in enumerate(zip(xs, meta))])
+    ya = (ctypes.c_void_p * n)(*[_dev_vec(v, m[0], m[1], f"y[{i}]") or None
+                                 for i, (v, m) in enumerate(zip(ys, meta))])
     _check(_lib.spmv_batch_exec(batch, xa, ya, _stream_handle(stream)))
 
 
@@ -649,6 +723,7 @@ def spmv_batch_info(batch) -> dict:
 
 
 def spmv_batch_destroy(batch) -> None:
+    _BATCH_META.pop(batch, None)
     _check(_lib.spmv_batch_destroy(batch))
 
 

@@ -242,6 +242,7 @@ struct spmv_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int64_t dev_bytes = 0, link_bytes = 0;
+    bool pool_held = false;         // holds one acquisition of the stream pool
 };
 
 namespace {
@@ -259,6 +260,7 @@ void batch_release(spmv_batch *b)
     }
     if (b->arena) (void)hipFree(b->arena);
     if (b->h_xy) (void)hipHostFree(b->h_xy);
+    if (b->pool_held) pool_release(b->device);
     delete b;
 }
 
@@ -570,6 +572,7 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
     hipStream_t plan_st[1];
     hipStream_t send_k[kCopyStreams], recv_k[kCopyStreams];
     if ((rc = pool_streams(dev, 1, plan_st, send_k, recv_k))) return fail(rc);
+    b->pool_held = true;
     for (int k = 0; k < kCopyStreams; ++k) {
         b->cs_send_k[k] = send_k[k];
         b->cs_recv_k[k] = recv_k[k];

@@ -310,6 +310,9 @@ constexpr int kCopyStreams = 4;
 // send / recv: [kCopyStreams] out.
 int pool_streams(int device, int32_t n_plan, hipStream_t *plan_st, hipStream_t *send,
                  hipStream_t *recv);
+// Give back one acquisition of the device's pool; the last one destroys
+// its streams.
+void pool_release(int device);
 
 }  // namespace spmv
 
@@ -347,6 +350,7 @@ struct spmv_plan {
     spmv::CsrCfg cfg[2];           // [0] = y_L, [1] = y_R
     int32_t xcd_remap = 1;
     bool fuse_unpack = false, fused_combine = false, host_only = false, profile = false;
+    bool pool_held = false;        // holds one acquisition of the stream pool
     bool use_buffer = true;
     int device = 0;
 

@@ -25,18 +25,24 @@ namespace spmv {
 // streams would be multiplexed over the few hardware queues and add latency),
 // and since an exec ends with all its work finished, sharing adds no
 // ordering that an exec on the same thread did not already have.  The pool
-// lives until the process ends.
+// counts its users (plans and batches); when the last one is released the
+// streams are destroyed, so a process that destroys its objects leaves no
+// HIP object of this library behind for the runtime's teardown at exit.
 struct StreamPool {
     std::array<hipStream_t, SPMV_MAX_STREAMS + 2 * kCopyStreams> st{};
+    int64_t users = 0;
 };
+
+namespace {
+std::mutex g_pool_mu;
+std::map<int, StreamPool> g_pools;
+}  // namespace
 
 int pool_streams(int device, int32_t n_plan, hipStream_t *plan_st, hipStream_t *send,
                  hipStream_t *recv)
 {
-    static std::mutex mu;
-    static std::map<int, StreamPool> pools;
-    std::lock_guard<std::mutex> lock(mu);
-    StreamPool &pool = pools[device];
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    StreamPool &pool = g_pools[device];
     auto get = [&](int32_t slot) -> int {
         if (!pool.st[size_t(slot)])
             SPMV_HIP(hipStreamCreateWithFlags(&pool.st[size_t(slot)], hipStreamNonBlocking));
@@ -53,7 +59,21 @@ int pool_streams(int device, int32_t n_plan, hipStream_t *plan_st, hipStream_t *
         send[k] = pool.st[size_t(SPMV_MAX_STREAMS + k)];
         recv[k] = pool.st[size_t(SPMV_MAX_STREAMS + kCopyStreams + k)];
     }
+    ++pool.users;   // only a successful acquisition is counted
     return SPMV_OK;
+}
+
+void pool_release(int device)
+{
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    auto it = g_pools.find(device);
+    if (it == g_pools.end() || it->second.users <= 0) return;
+    if (--it->second.users > 0) return;
+    for (hipStream_t &st : it->second.st)
+        if (st) {
+            (void)hipStreamDestroy(st);
+            st = nullptr;
+        }
 }
 
 namespace {
@@ -78,6 +98,7 @@ void release(spmv_plan *p)
     if (p->arena) (void)hipFree(p->arena);
     if (p->h_inbox) (void)hipHostFree(p->h_inbox);
     if (p->h_outbox) (void)hipHostFree(p->h_outbox);
+    if (p->pool_held) pool_release(p->device);
     delete p;
 }
 
@@ -139,7 +160,7 @@ int allocate_and_upload(spmv_plan *p)
         {(void **)&p->dR_val, valsz(1), valdata(1), pad * 8},
         {(void **)&p->d_sendbuf, n_send * 8, nullptr, 0},
         {(void **)&p->d_recvbuf, n_halo * 8, nullptr, 0},
-        {(void **)&p->d_xhalo, n_halo * 8, nullptr, 0},
+        {(void **)&p->d_xhalo, p->fuse_unpack ? 0 : n_halo * 8, nullptr, 0},
         {(void **)&p->d_part, n_rr * 8, nullptr, 0},
         {(void **)&p->d_slab_part, p->cfg[1].form == 5 ? kSlabs * n_rr * 8 : 0, nullptr, 0},
     };
@@ -164,6 +185,7 @@ int allocate_and_upload(spmv_plan *p)
 
     p->n_st = std::max<int32_t>(std::max(p->sch.n_streams_used, p->n_streams_max), 1);
     if (int rc = pool_streams(p->device, p->n_st, p->st, p->cs_send_k, p->cs_recv_k)) return rc;
+    p->pool_held = true;
     p->cs_send = p->cs_send_k[0];
     p->cs_recv = p->cs_recv_k[0];
     SPMV_HIP(hipEventCreateWithFlags(&p->ev_start, hipEventDisableTiming));
@@ -438,7 +460,7 @@ int create_plan(Build build_share_fn, int32_t nranks, const int32_t *op_order, i
         return set_error(SPMV_EINVAL, "stream CSR sums with at most 16 lanes per row");
     if (t.width != 0 && t.width != 2 && t.width != 4)
         return set_error(SPMV_EINVAL, "width must be 0, 2 or 4");
-    if (t.xcd_remap < 0 || t.xcd_remap > 2 || t.fuse_unpack < 0 || t.fuse_unpack > 1)
+    if (t.xcd_remap < 0 || t.xcd_remap > 2 || t.fuse_unpack < 0 || t.fuse_unpack > 2)
         return set_error(SPMV_EINVAL, "tune field out of range");
     if (t.form < 0 || t.form > 5) return set_error(SPMV_EINVAL, "form must be 0 to 5");
     if (t.form == 5 && t.lanes_remote > 4)
@@ -487,7 +509,18 @@ int create_plan(Build build_share_fn, int32_t nranks, const int32_t *op_order, i
         select_sell(p->cfg[1], S.R_ptr, S.R_col, S.R_val, int64_t(S.R_rows.size()),
                     t.chunk_remote, false);
     p->xcd_remap = t.xcd_remap ? t.xcd_remap : 1;
-    p->fuse_unpack = t.fuse_unpack == 1;
+    // y_R can read the receive buffer in place exactly when the unpack
+    // permutation is the identity (always, with the halo and the receive
+    // buffer both in ascending global column order); the explicit kernel
+    // stays available on request (fuse_unpack = 2)
+    bool identity = true;
+    for (size_t i = 0; i < S.unpack_perm.size() && identity; ++i)
+        identity = S.unpack_perm[i] == int32_t(i);
+    if (t.fuse_unpack == 1 && !identity) {
+        delete p;
+        return set_error(SPMV_EINVAL, "fuse_unpack = 1 needs the identity unpack permutation");
+    }
+    p->fuse_unpack = t.fuse_unpack == 1 || (t.fuse_unpack == 0 && identity);
     p->host_only = (t.flags & SPMV_F_HOST_ONLY) != 0;
     p->profile = (t.flags & SPMV_F_PROFILE) != 0;
     p->use_buffer = (t.flags & SPMV_F_NO_BUFFER) == 0;
@@ -1010,6 +1043,7 @@ extern "C" int spmv_plan_info(const spmv_plan_t *p, spmv_info_t *info)
     info->xcd_remap = p->xcd_remap;
     info->fuse_unpack = p->fuse_unpack;
     info->fused_combine = p->fused_combine;
+    info->device = p->host_only ? -1 : p->device;
     return SPMV_OK;
 }
 

@@ -326,6 +326,7 @@ void server_release(spmv_server *s)
         if (sl.ev) (void)hipEventDestroy(sl.ev);
         if (sl.st) (void)hipStreamDestroy(sl.st);
         if (sl.h_stage) (void)hipHostFree(sl.h_stage);
+        if (sl.d_desc) (void)hipFree(sl.d_desc);
     }
     if (s->arena_base) (void)hipFree(s->arena_base);
     for (spmv_plan *p : s->mats) spmv_plan_destroy(p);

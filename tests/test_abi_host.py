@@ -268,6 +268,59 @@ def test_host_only_plan_refuses_exec():
         sp.spmv_plan_destroy(p)
 
 
+def test_binding_rejects_bad_vectors_before_any_launch():
+    """The binding checks x / y before calling the library: host arrays,
+    CPU tensors, other dtypes, strided views, short tensors and missing
+    vectors raise; nothing reaches a kernel (the plan is host-only, so a
+    call that got through would return SPMV_ESTATE instead)."""
+    import torch
+    A = gen.laplacian_3d7(6)
+    p = sp.spmv_plan_create(A, 2, 1, tune=HOST_ONLY)
+    try:
+        info = sp.spmv_plan_info(p)
+        n = info["n_loc"]
+        assert info["device"] == -1
+        good_shape = torch.zeros(n, dtype=torch.float64)
+        bad = [(np.zeros(n), TypeError),                                   # host numpy
+               (good_shape, ValueError),                                   # CPU tensor
+               (torch.zeros(n, dtype=torch.float32), ValueError),          # CPU, fp32
+               ("not a tensor", TypeError),
+               (None, ValueError)]                                         # missing
+        for v, exc in bad:
+            with pytest.raises(exc):
+                sp.spmv_exec(p, v, 0)
+            with pytest.raises(exc):
+                sp.spmv_exec(p, 0, v)
+            with pytest.raises(exc):
+                sp.spmv_op_launch(p, sp.SPMV_OP_YL, v, 0)
+            with pytest.raises(exc):
+                sp.spmv_plan_time([p], [v], [0])
+        # the remaining checks need the tensor to be on a GPU; their order
+        # (device, dtype, contiguity, length) is exercised by the GPU tests
+        with pytest.raises(ValueError):
+            sp.spmv_plan_time([p], [0], [0, 0])
+        # raw integer addresses pass the binding: the library then refuses the
+        # host-only plan
+        with pytest.raises(sp.SpmvError) as e:
+            sp.spmv_exec(p, 1 << 20, 2 << 20)
+        assert e.value.code == sp.SPMV_ESTATE
+    finally:
+        sp.spmv_plan_destroy(p)
+
+
+def test_fused_unpack_is_the_default():
+    A = gen.laplacian_3d7(8)
+    for tune, fused in (({}, 1), ({"fuse_unpack": 1}, 1), ({"fuse_unpack": 2}, 0)):
+        p = sp.spmv_plan_create(A, 4, 1, tune={"flags": sp.SPMV_F_HOST_ONLY, **tune})
+        try:
+            assert sp.spmv_plan_info(p)["fuse_unpack"] == fused
+        finally:
+            sp.spmv_plan_destroy(p)
+    with pytest.raises(sp.SpmvError) as e:
+        sp.spmv_plan_create(A, 4, 1, tune={"flags": sp.SPMV_F_HOST_ONLY, "fuse_unpack": 3})
+    assert e.value.code == sp.SPMV_EINVAL
+
+
 def test_default_plan_fuses_combine():
     A = gen.laplacian_3d7(8)
     p = sp.spmv_plan_create(A, 2, 1, tune=HOST_ONLY)

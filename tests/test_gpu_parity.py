@@ -74,7 +74,7 @@ def test_lane_variants(lanes, rows):
     A = gen.power_law(30000, seed=17)
     x = gen.x_normal(A.n_cols, 18)
     log(f"power-law 30k lanes={lanes} rows={rows}")
-    for fuse, remap, flags in ((0, 1, 0), (1, 2, sp.SPMV_F_NO_BUFFER)):
+    for fuse, remap, flags in ((2, 1, 0), (1, 2, sp.SPMV_F_NO_BUFFER)):
         res, ref = run_share(A, 4, 2, x, tune={"kernel_local": 1, "kernel_remote": 1,
                                                "lanes_local": lanes, "lanes_remote": lanes,
                                                "rows_local": rows, "rows_remote": rows,
@@ -92,7 +92,7 @@ def test_stream_variants(chunk, width, lanes):
     for A, P, r, seed in [(gen.power_law(30000, seed=17), 4, 2, 18),
                           (gen.power_law(12000, mean_len=300.0, seed=44), 4, 1, 45)]:
         x = gen.x_normal(A.n_cols, seed)
-        for fuse, remap in ((0, 1), (1, 2)):
+        for fuse, remap in ((2, 1), (1, 2)):
             res, ref = run_share(A, P, r, x, tune={
                 "kernel_local": 2, "kernel_remote": 2, "chunk_local": chunk,
                 "chunk_remote": chunk, "width": width, "lanes_local": lanes,
@@ -254,9 +254,9 @@ def test_column_slab_form(chunk, width, lanes):
         assert fused == {0, 1}
         for y in ys[1:]:
             assert np.array_equal(ys[0], y)
-        # y_R reading the receive buffer directly, and the fine-grained
-        # program: the same bits
-        fu, _ = run_share(A, P, r, x, tune={**tune, "fuse_unpack": 1}, ref=ref)
+        # the explicit Unpack kernel (the default reads the receive buffer
+        # in place), and the fine-grained program: the same bits
+        fu, _ = run_share(A, P, r, x, tune={**tune, "fuse_unpack": 2}, ref=ref)
         assert fu["info"]["form_remote"] == 5 and np.array_equal(ys[0], bits(fu["y"]))
         plan = sp.spmv_plan_create(A, P, r, None, None, 2, tune)
         try:
@@ -413,6 +413,12 @@ def test_every_plan_bit_identical():
         else:
             assert np.array_equal(bits(res["y"]), first), i
             assert np.array_equal(bits(res["outbox"]), bits(ref["sendbuf"])), i
+        if i % 16 == 0:
+            # every 16th plan again with the explicit Unpack kernel
+            ex, _ = run_share(A, P, r, x, ops, smap, 2, ref=ref, tune={"fuse_unpack": 2})
+            assert ex["info"]["fuse_unpack"] == 0
+            assert np.array_equal(bits(ex["y"]), first), i
+    assert res["info"]["fuse_unpack"] == 1   # the default reads the receive buffer in place
     assert 0 < fused < n   # both the fused and the combine path were exercised
 
 
@@ -462,9 +468,14 @@ def test_three_streams_and_explicit_unpack():
            O.SPMV_OP_WAIT_RECV, O.SPMV_OP_UNPACK, O.SPMV_CER_AFTER(O.SPMV_OP_UNPACK),
            O.SPMV_CSWE_B4(O.SPMV_OP_YR), O.SPMV_OP_YR, O.SPMV_OP_WAIT_SEND, O.SPMV_OP_END]
     smap = {O.SPMV_OP_PACK: 0, O.SPMV_OP_YL: 1, O.SPMV_OP_UNPACK: 2, O.SPMV_OP_YR: 0}
-    res, _ = run_share(A, 4, 2, x, ops, smap, 3, ref=ref)
+    res, _ = run_share(A, 4, 2, x, ops, smap, 3, ref=ref, tune={"fuse_unpack": 2})
     assert res["info"]["n_streams"] == 3 and res["info"]["fused_combine"] == 0
+    assert res["info"]["fuse_unpack"] == 0
     assert_share_parity(res, ref)
+    # the same order with Unpack fused (the default): no kernel, same bits
+    fu, _ = run_share(A, 4, 2, x, ops, smap, 3, ref=ref)
+    assert fu["info"]["fuse_unpack"] == 1
+    assert np.array_equal(bits(fu["y"]), bits(res["y"]))
 
 
 def test_repeated_exec_new_x():
@@ -619,7 +630,7 @@ def test_long_rows():
 def test_profile_counters():
     A = gen.laplacian_3d7(24)
     x = gen.x_uniform(A.n_cols, 3)
-    plan = sp.spmv_plan_create(A, 4, 1, tune={"flags": sp.SPMV_F_PROFILE})
+    plan = sp.spmv_plan_create(A, 4, 1, tune={"flags": sp.SPMV_F_PROFILE, "fuse_unpack": 2})
     try:
         for _ in range(3):
             run_share(A, 4, 1, x, plan=plan)
@@ -716,3 +727,36 @@ def test_full_powerlaw_4m_p16_rank5_and_batch():
     finally:
         for p in plans:
             sp.spmv_plan_destroy(p)
+
+
+def test_full_paper_banded_150k_p4_rank1_sampled_plans():
+    """The paper's own input at full size (Sec. III: 150,000 rows, 10
+    entries per row in half-bandwidth 37,500, P = 4; rank 1), in the launch
+    configuration the benchmark times: the default plan against the oracle
+    on every row, then 24 plans spread over the space on the same uploaded
+    share (re-ordered in place), each bit-identical to the first and with an
+    exact outbox.  Its column offsets exceed 16 bits, so y_L runs packed tiles
+    with 32-bit columns here (the 6,000-row all-plans case runs another
+    form)."""
+    A = gen.banded_uniform(150_000, 10, 37_500, seed=100)
+    x = gen.x_normal(A.n_cols, 101)
+    P, r = 4, 1
+    log("full banded 150k P=4 r=1")
+    ref = oracle.share_reference(A, P, r, x)
+    res, _ = run_share(A, P, r, x, ref=ref, keep_plan=True)
+    plan = res.pop("plan")
+    try:
+        info = res["info"]
+        assert info["n_loc"] == 37_500 and info["form_local"] == 1
+        assert info["nnz_local"] + info["nnz_remote"] == 375_000
+        assert_share_parity(res, ref)
+        first = bits(res["y"])
+        n = sp.spmv_plan_space_count(P, 2)
+        for i in np.linspace(0, n - 1, 24).astype(int):
+            ops, smap = sp.spmv_plan_space_get(P, 2, int(i))
+            sp.spmv_plan_reorder(plan, ops, smap, 2)
+            got, _ = run_share(A, P, r, x, ref=ref, plan=plan)
+            assert np.array_equal(bits(got["y"]), first), i
+            assert np.array_equal(bits(got["outbox"]), bits(ref["sendbuf"])), i
+    finally:
+        sp.spmv_plan_destroy(plan)

@@ -157,3 +157,29 @@ def test_budget_rejections():
         assert e.value.code == sp.SPMV_EBUDGET
     finally:
         sp.spmv_server_destroy(srv)
+
+
+def test_create_destroy_returns_device_memory():
+    """Every device allocation of a server (request arena, per-slot stage
+    descriptors, resident plans) is released by destroy: free device memory
+    returns to its level after repeated create / start / destroy cycles."""
+    import torch
+    A = gen.banded_random(5000, seed=8)
+
+    def cycle():
+        srv = sp.spmv_server_create({"max_epochs": 32, "max_inflight": 4})
+        try:
+            sp.spmv_server_add_matrix(srv, A)
+            sp.spmv_server_start(srv)
+        finally:
+            sp.spmv_server_destroy(srv)
+
+    cycle()                                   # runtime pools warm up
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(16):
+        cycle()
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    # 16 cycles x 32 slots of descriptor buffers would be >= 512 allocations
+    assert free0 - free1 <= (2 << 20), (free0, free1)

@@ -213,8 +213,10 @@ def test_device_search_on_host_only_plans_is_an_error():
     plans = [sp.spmv_plan_create(A, 4, 1, None, None, 2, {"flags": sp.SPMV_F_HOST_ONLY})
              for _ in range(2)]
     try:
-        xs = [np.zeros(500) for _ in plans]
-        ys = [np.zeros(500) for _ in plans]
+        # raw addresses pass the binding's checks (host arrays would not);
+        # the library refuses the host-only plans before any launch
+        xs = [1 << 20 for _ in plans]
+        ys = [2 << 20 for _ in plans]
         with pytest.raises(sp.SpmvError) as e:
             sp.spmv_mcts_run(plans, xs, ys, None, iterations=5, seed=5, t_measure=0.001)
         assert e.value.code == sp.SPMV_ESTATE
