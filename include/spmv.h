@@ -133,7 +133,10 @@ typedef struct {
                               1..16)                                         */
     int32_t lanes_remote;
     int32_t rows_local;    /* vector: rows per lane group, 0 = auto, 1/2/4/8 */
-    int32_t rows_remote;
+    int32_t rows_remote;   /* same for y_R; in column slabs (form 5) rows per
+                              thread: 0/1 = tiles of 256 / lanes_remote rows,
+                              2/4/8 = wide tiles of up to that many times 256
+                              rows, one thread per row (lanes_remote 0 or 1) */
     int32_t chunk_local;   /* stream: entries per thread per window, 0 = auto,
                               4, 8 or 16                                      */
     int32_t chunk_remote;
@@ -174,10 +177,14 @@ typedef struct {
                               per row, and a second kernel adds a row's 8
                               partial sums in slab order (lanes_remote at
                               most 4; y_L takes the automatic form; without
-                              remote rows y_R stays in form 1).  Every form
-                              but 5 gives the same bits for y; form 5 gives
-                              bits of its own, the same under every plan.
-                              Plans in forms 1 and 4 can join a batch.    */
+                              remote rows y_R stays in form 1).  The
+                              automatic form (0) takes column slabs for y_R
+                              when the halo (8 bytes per entry) exceeds one
+                              XCD's 4 MiB L2 and y_R uses the stream kernel.
+                              Every form but 5 gives the same bits for y;
+                              form 5 gives bits of its own, the same under
+                              every plan.  Plans in forms 1 and 4 can join
+                              a batch.                                     */
 } spmv_tune_t;
 
 #define SPMV_F_HOST_ONLY  1  /* build metadata only: no device resources;

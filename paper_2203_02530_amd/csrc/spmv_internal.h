@@ -225,6 +225,8 @@ struct SlabDev {
     double *part;               // [kSlabs * n_rows]
     double *out, *acc;
     int32_t n_rows, chunk, width, lanes;
+    int32_t rpt;                // rows per thread: 1 = tiles of kBlock / lanes rows;
+                                // 2, 4, 8 = wide tiles (lanes 1)
     int64_t nnz_off[kSlabs + 1], tile_off[kSlabs + 1];   // tile_off: n_tiles + 1 each
     int64_t nnz_alloc, n_x;
 };

@@ -599,6 +599,18 @@ __global__ __launch_bounds__(kBlock) void k_csr_slabs(const SlabArgs a)
     stream_tile<NPT, VW, SL, false>(a.s[k], q, s_p, s_rp);
 }
 
+// The same with wide tiles: RPT * kBlock rows per tile at most, one thread
+// per row.
+template <int NPT, int VW, int RPT>
+__global__ __launch_bounds__(kBlock) void k_csr_slabs_wide(const SlabArgs a)
+{
+    __shared__ double s_p[kBlock * NPT];
+    __shared__ int32_t s_rp[RPT * kBlock + 1];
+    const int k = int(blockIdx.x) % kSlabs, q = int(blockIdx.x) / kSlabs;
+    if (q >= a.n_tiles[k]) return;   // whole block, before any barrier
+    wide_tile<NPT, VW, RPT>(a.s[k], q, s_p, s_rp);
+}
+
 // y_R of row i = the slab partial sums added in slab order; stored, or added
 // into y at the row's local index.
 __global__ __launch_bounds__(kBlock) void k_slab_sum(const double *__restrict__ part, int64_t n,
@@ -618,7 +630,7 @@ __global__ __launch_bounds__(kBlock) void k_slab_sum(const double *__restrict__ 
     }
 }
 
-template <int NPT, int VW, int SL>
+template <int NPT, int VW, int SL, int RPT>
 hipError_t launch_slabs_t(const SlabDev &A, hipStream_t s)
 {
     SlabArgs a;
@@ -639,9 +651,14 @@ hipError_t launch_slabs_t(const SlabDev &A, hipStream_t s)
         a.n_tiles[k] = int32_t(A.tile_off[k + 1] - A.tile_off[k] - 1);
         most = std::max<int64_t>(most, a.n_tiles[k]);
     }
-    if (most > 0)
-        hipLaunchKernelGGL((k_csr_slabs<NPT, VW, SL>), dim3(unsigned(most * kSlabs)),
-                           dim3(kBlock), 0, s, a);
+    if (most > 0) {
+        if constexpr (RPT == 1)
+            hipLaunchKernelGGL((k_csr_slabs<NPT, VW, SL>), dim3(unsigned(most * kSlabs)),
+                               dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_csr_slabs_wide<NPT, VW, RPT>), dim3(unsigned(most * kSlabs)),
+                               dim3(kBlock), 0, s, a);
+    }
     hipLaunchKernelGGL(k_slab_sum, dim3(grid_for(A.n_rows)), dim3(kBlock), 0, s, A.part,
                        int64_t(A.n_rows), A.rows, A.out, A.acc);
     return hipGetLastError();
@@ -650,10 +667,19 @@ hipError_t launch_slabs_t(const SlabDev &A, hipStream_t s)
 template <int NPT, int VW>
 hipError_t launch_slabs_v(const SlabDev &A, hipStream_t s)
 {
+    if (A.rpt > 1) {
+        if (A.lanes != 1) return hipErrorInvalidValue;
+        switch (A.rpt) {
+            case 2: return launch_slabs_t<NPT, VW, 1, 2>(A, s);
+            case 4: return launch_slabs_t<NPT, VW, 1, 4>(A, s);
+            case 8: return launch_slabs_t<NPT, VW, 1, 8>(A, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (A.lanes) {
-        case 1: return launch_slabs_t<NPT, VW, 1>(A, s);
-        case 2: return launch_slabs_t<NPT, VW, 2>(A, s);
-        case 4: return launch_slabs_t<NPT, VW, 4>(A, s);
+        case 1: return launch_slabs_t<NPT, VW, 1, 1>(A, s);
+        case 2: return launch_slabs_t<NPT, VW, 2, 1>(A, s);
+        case 4: return launch_slabs_t<NPT, VW, 4, 1>(A, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -341,12 +341,31 @@ void select_tile16(CsrCfg &c, const std::vector<int32_t> &col, int32_t asked)
     if (build_tile16(col, c.tile_row, c.tile_k, c.tile_off)) c.form = 4;
 }
 
-// Form 5 for y_R when asked for: column slabs (see SlabDev), each with
-// packed stream tiles; summing lanes by the mean row length within a slab
-// (at most 4).  Without remote rows the packed form stays.  Returns whether
-// the slabs were built.
+// Column slabs (form 5) when asked for, or automatically for a y_R whose
+// halo is larger than one XCD's L2: there every gather of the packed form
+// fetches a cache line from the MALL or HBM (the power-law share's y_R moved
+// 6.3 times its bytes in packed tiles), while a slab's eighth of the halo
+// stays in its XCD's L2.
+constexpr int64_t kXcdL2Bytes = int64_t(4) << 20;
+
+bool want_slabs(int32_t form, int32_t kernel, int64_t n_halo, int64_t n_remote_rows)
+{
+    if (kernel == SPMV_KERNEL_VECTOR) return false;
+    return form == 5 || (form == 0 && n_remote_rows > 0 && n_halo * 8 > kXcdL2Bytes);
+}
+
+// Form 5 for y_R: column slabs (see SlabDev), each cut into stream tiles.
+// Rows per thread `rows` > 1 selects wide tiles of up to rows * 256 rows
+// with one thread per row and windows of 256 * chunk entries (chunk 8 unless
+// given); otherwise (the automatic choice) tiles of 256 / lanes rows with
+// summing lanes by the mean row length within a slab (at most 4).  On the
+// power-law 4M share (about 2 entries per row and slab) wide tiles measured
+// 36.1-42.9 us against 35.8 us for tiles of 256 rows: the slab's gathers
+// from L2 bound both, so filling the windows gains nothing.  Without remote
+// rows the packed form stays.  Returns whether the slabs were built.
 bool select_slabs(CsrCfg &c, const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
-                  const std::vector<double> &val, int64_t n_rows, int64_t n_x, int32_t lanes)
+                  const std::vector<double> &val, int64_t n_rows, int64_t n_x, int32_t lanes,
+                  int32_t rows, int32_t chunk)
 {
     if (c.kernel != SPMV_KERNEL_STREAM || c.form != 5) return false;
     if (n_rows <= 0 || n_x <= 0) {
@@ -354,22 +373,33 @@ bool select_slabs(CsrCfg &c, const std::vector<int32_t> &rp, const std::vector<i
         return false;
     }
     const double mean = double(rp[size_t(n_rows)]) / double(kSlabs * n_rows);
-    const int32_t lanes_packed = c.lanes;
-    if (lanes) {
-        c.lanes = lanes;
-    } else {
+    const int32_t lanes_packed = c.lanes, chunk_packed = c.chunk;
+    const bool wide = rows > 1;
+    if (wide) {
+        c.rows = rows > 1 ? rows : 4;
         c.lanes = 1;
-        while (c.lanes < 4 && double(c.lanes) * 14.0 <= mean) c.lanes <<= 1;
+        c.chunk = chunk ? chunk : 8;
+    } else {
+        c.rows = 1;
+        if (lanes) {
+            c.lanes = lanes;
+        } else {
+            c.lanes = 1;
+            while (c.lanes < 4 && double(c.lanes) * 14.0 <= mean) c.lanes <<= 1;
+        }
     }
+    const int maxr = wide ? c.rows * stream_maxr(1) : stream_maxr(c.lanes);
     std::vector<int32_t> tile_row, tile_k;
-    build_slabs(rp, col, val, n_rows, n_x, stream_cap(c.chunk), stream_maxr(c.lanes), c.width,
-                c.sell_ptr, c.slab_col, c.slab_val, tile_row, tile_k, c.slab_nnz, c.slab_tiles);
+    build_slabs(rp, col, val, n_rows, n_x, stream_cap(c.chunk), maxr, c.width, c.sell_ptr,
+                c.slab_col, c.slab_val, tile_row, tile_k, c.slab_nnz, c.slab_tiles);
     // the stream kernel addresses the values through 32-bit byte offsets;
     // the slabs' alignment padding can push a share at the limit past it
     constexpr int64_t kMax = (int64_t(1) << 32) - 64;
     if ((int64_t(c.slab_val.size()) + kEntryPad) * 8 >= kMax) {
         c.form = 1;
         c.lanes = lanes_packed;
+        c.chunk = chunk_packed;
+        c.rows = 1;
         c.sell_ptr.clear();
         c.slab_col.clear();
         c.slab_val.clear();
@@ -401,6 +431,7 @@ hipError_t launch_product(const spmv_plan *p, int side, const double *x, double 
         D.chunk = c.chunk;
         D.width = c.width;
         D.lanes = c.lanes;
+        D.rpt = c.rows;
         for (int k = 0; k <= kSlabs; ++k) {
             D.nnz_off[k] = c.slab_nnz[k];
             D.tile_off[k] = c.slab_tiles[k];
@@ -465,6 +496,8 @@ int create_plan(Build build_share_fn, int32_t nranks, const int32_t *op_order, i
     if (t.form < 0 || t.form > 5) return set_error(SPMV_EINVAL, "form must be 0 to 5");
     if (t.form == 5 && t.lanes_remote > 4)
         return set_error(SPMV_EINVAL, "column slabs sum with at most 4 lanes per row");
+    if (t.form == 5 && t.rows_remote > 1 && t.lanes_remote > 1)
+        return set_error(SPMV_EINVAL, "wide slab tiles (rows_remote > 1) sum with one lane");
 
     std::vector<int32_t> def_ops;
     int32_t def_map[SPMV_N_VERTICES];
@@ -498,14 +531,17 @@ int create_plan(Build build_share_fn, int32_t nranks, const int32_t *op_order, i
     }
     // form 5 concerns y_R only; y_L then takes the automatic form
     const int32_t form_l = t.form == 5 ? 0 : t.form;
+    const bool slabs = want_slabs(t.form, t.kernel_remote, int64_t(S.halo.size()),
+                                  int64_t(S.R_rows.size()));
     configure(p->cfg[0], S.L_ptr, S.n_loc, t.kernel_local, t.lanes_local, t.rows_local,
               t.chunk_local, t.width, form_l);
+    // in column slabs rows_remote counts rows per thread, not vector rows
     configure(p->cfg[1], S.R_ptr, int64_t(S.R_rows.size()), t.kernel_remote, t.lanes_remote,
-              t.rows_remote, t.chunk_remote, t.width, t.form);
+              slabs ? 0 : t.rows_remote, t.chunk_remote, t.width, slabs ? 5 : t.form);
     select_sell(p->cfg[0], S.L_ptr, S.L_col, S.L_val, S.n_loc, t.chunk_local, true);
     select_tile16(p->cfg[0], S.L_col, form_l);
     if (!select_slabs(p->cfg[1], S.R_ptr, S.R_col, S.R_val, int64_t(S.R_rows.size()),
-                      int64_t(S.halo.size()), t.lanes_remote))
+                      int64_t(S.halo.size()), t.lanes_remote, t.rows_remote, t.chunk_remote))
         select_sell(p->cfg[1], S.R_ptr, S.R_col, S.R_val, int64_t(S.R_rows.size()),
                     t.chunk_remote, false);
     p->xcd_remap = t.xcd_remap ? t.xcd_remap : 1;

@@ -240,6 +240,53 @@ __device__ __forceinline__ void tile_reduce(const StreamArgs &A, const TileRegs<
     }
 }
 
+// One row longer than the window (a tile of its own): per-thread fma
+// chains over all windows, then a fixed-order reduction over the block.
+// s_p needs kBlock / 64 doubles.
+template <int NPT, int VW, bool C16 = false>
+__device__ __forceinline__ void long_row_tile(const StreamArgs &A, __amdgpu_buffer_rsrc_t r_col,
+                                              __amdgpu_buffer_rsrc_t r_val,
+                                              __amdgpu_buffer_rsrc_t r_x, int r0, int k0, int k1,
+                                              double *s_p)
+{
+    constexpr int CAP = kBlock * NPT;
+    constexpr int NV = NPT / VW;
+    const int base = k0 & ~(VW - 1);
+    const int tid = int(threadIdx.x);
+    double s = 0.0;
+    for (int w0 = base; w0 < k1; w0 += CAP) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int e = w0 + (v * kBlock + tid) * VW;
+            int32_t c[VW];
+            double a[VW];
+            if constexpr (C16) {
+                load_cols16<VW>(r_col, e < k1 ? uint32_t(e) : kNoEntry, r0, c);
+                load_vals<VW>(r_val, e < k1 ? uint32_t(e) : kNoEntry, a);
+            } else {
+                load_vec<VW>(r_col, r_val, e < k1 ? uint32_t(e) : kNoEntry, c, a);
+            }
+#pragma unroll
+            for (int j = 0; j < VW; ++j) {
+                const bool ok = e + j >= k0 && e + j < k1;
+                const double xv = load_x(r_x, ok ? uint32_t(c[j]) * 8u : kOff);
+                const double f = fma(a[j], xv, s);
+                s = ok ? f : s;
+            }
+        }
+    }
+    s = group_sum<64>(s);
+    if ((tid & 63) == 63) s_p[tid >> 6] = s;
+    __syncthreads();
+    if (tid == 0) {
+        const double tot = (s_p[0] + s_p[1]) + (s_p[2] + s_p[3]);
+        if (A.acc)
+            A.acc[A.rows[r0]] += tot;
+        else
+            A.out[r0] = tot;
+    }
+}
+
 // One tile.  s_p: LDS[kBlock * NPT] doubles, s_rp: LDS[kBlock / SL + 1] ints.
 // Block-uniform control flow; the caller separates consecutive tiles with a
 // barrier (LDS is reused).
@@ -247,7 +294,6 @@ template <int NPT, int VW, int SL, bool C16 = false>
 __device__ __forceinline__ void stream_tile(const StreamArgs &A, int t, double *s_p, int32_t *s_rp)
 {
     constexpr int CAP = kBlock * NPT;
-    constexpr int NV = NPT / VW;
     static_assert(NPT % VW == 0, "NPT must be a multiple of VW");
     const auto r_col = rsrc(A.col, A.nnz_alloc * (C16 ? 2u : 4u));
     const auto r_val = rsrc(A.val, A.nnz_alloc * 8u);
@@ -255,43 +301,9 @@ __device__ __forceinline__ void stream_tile(const StreamArgs &A, int t, double *
     const int r0 = A.tile_row[t], r1 = A.tile_row[t + 1];
     const int k0 = A.tile_k[t], k1 = A.tile_k[t + 1];
     const int base = k0 & ~(VW - 1);
-    const int tid = int(threadIdx.x);
 
     if (r1 - r0 == 1 && k1 - base > CAP) {
-        // one long row: per-thread fma chains over all windows, then a
-        // fixed-order reduction over the block
-        double s = 0.0;
-        for (int w0 = base; w0 < k1; w0 += CAP) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const int e = w0 + (v * kBlock + tid) * VW;
-                int32_t c[VW];
-                double a[VW];
-                if constexpr (C16) {
-                    load_cols16<VW>(r_col, e < k1 ? uint32_t(e) : kNoEntry, r0, c);
-                    load_vals<VW>(r_val, e < k1 ? uint32_t(e) : kNoEntry, a);
-                } else {
-                    load_vec<VW>(r_col, r_val, e < k1 ? uint32_t(e) : kNoEntry, c, a);
-                }
-#pragma unroll
-                for (int j = 0; j < VW; ++j) {
-                    const bool ok = e + j >= k0 && e + j < k1;
-                    const double xv = load_x(r_x, ok ? uint32_t(c[j]) * 8u : kOff);
-                    const double f = fma(a[j], xv, s);
-                    s = ok ? f : s;
-                }
-            }
-        }
-        s = group_sum<64>(s);
-        if ((tid & 63) == 63) s_p[tid >> 6] = s;
-        __syncthreads();
-        if (tid == 0) {
-            const double tot = (s_p[0] + s_p[1]) + (s_p[2] + s_p[3]);
-            if (A.acc)
-                A.acc[A.rows[r0]] += tot;
-            else
-                A.out[r0] = tot;
-        }
+        long_row_tile<NPT, VW, C16>(A, r_col, r_val, r_x, r0, k0, k1, s_p);
         return;
     }
 
@@ -299,6 +311,96 @@ __device__ __forceinline__ void stream_tile(const StreamArgs &A, int t, double *
     tile_load<NPT, VW, C16>(A, r_col, r_val, t, T);
     tile_gather<NPT, VW>(r_x, T);
     tile_reduce<NPT, VW, SL>(A, T, s_p, s_rp);
+}
+
+// Wide tile: up to RPT * kBlock short rows whose entries fit one window of
+// kBlock * NPT entries, each row summed left to right by one thread (thread
+// t takes rows t, t + kBlock, ...), so a tile of rows with one or two
+// entries still fills its window and every thread keeps NPT gathers in
+// flight.  A row's sum is the same as with one summing lane in a tile of
+// kBlock rows.  s_p: LDS[kBlock * NPT] doubles, s_rp: LDS[RPT * kBlock + 1]
+// ints.  Stores out[r0 + g] (acc is not used).
+template <int NPT, int VW, int RPT>
+__device__ __forceinline__ void wide_tile(const StreamArgs &A, int t, double *s_p, int32_t *s_rp)
+{
+    constexpr int CAP = kBlock * NPT;
+    constexpr int NV = NPT / VW;
+    static_assert(NPT % VW == 0, "NPT must be a multiple of VW");
+    const auto r_col = rsrc(A.col, A.nnz_alloc * 4u);
+    const auto r_val = rsrc(A.val, A.nnz_alloc * 8u);
+    const auto r_x = rsrc(A.x, A.n_x * 8u);
+    const int r0 = A.tile_row[t], nr = A.tile_row[t + 1] - r0;
+    const int k0 = A.tile_k[t], k1 = A.tile_k[t + 1];
+    const int base = k0 & ~(VW - 1);
+    const int tid = int(threadIdx.x);
+
+    if (nr == 1 && k1 - base > CAP) {
+        long_row_tile<NPT, VW, false>(A, r_col, r_val, r_x, r0, k0, k1, s_p);
+        return;
+    }
+
+    // columns of the whole window, then values, then the row pointers: the
+    // three load groups are independent
+    int32_t c[NV][VW];
+    double a[NV][VW], xv[NV][VW];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int e = base + (v * kBlock + tid) * VW;
+        load_cols<VW>(r_col, e < k1 ? uint32_t(e) : kNoEntry, c[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int e = base + (v * kBlock + tid) * VW;
+        load_vals<VW>(r_val, e < k1 ? uint32_t(e) : kNoEntry, a[v]);
+    }
+    // nr + 1 <= RPT * kBlock + 1 pointers: RPT per thread, plus the last
+    // one by thread 0 when the tile is full
+    int32_t rp[RPT + 1];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int i = j * kBlock + tid;
+        rp[j] = i <= nr ? A.rp[r0 + i] : 0;
+    }
+    rp[RPT] = (tid == 0 && nr == RPT * kBlock) ? A.rp[r0 + RPT * kBlock] : 0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int j = 0; j < VW; ++j) {
+            const int k = base + (v * kBlock + tid) * VW + j;
+            const bool ok = k >= k0 && k < k1;
+            xv[v][j] = load_x(r_x, ok ? uint32_t(c[v][j]) * 8u : kOff);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int j = 0; j < VW; ++j) s_p[(v * kBlock + tid) * VW + j] = a[v][j] * xv[v][j];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int i = j * kBlock + tid;
+        if (i <= nr) s_rp[i] = rp[j];
+    }
+    if (tid == 0 && nr == RPT * kBlock) s_rp[RPT * kBlock] = rp[RPT];
+    __syncthreads();
+
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int g = j * kBlock + tid;
+        if (g < nr) {
+            const int b = s_rp[g] - base, e = s_rp[g + 1] - base;
+            double s = 0.0;
+            int k = b;
+            for (; k + 3 < e; k += 4) {
+                const double p0 = s_p[k], p1 = s_p[k + 1], p2 = s_p[k + 2], p3 = s_p[k + 3];
+                s += p0;
+                s += p1;
+                s += p2;
+                s += p3;
+            }
+            for (; k < e; ++k) s += s_p[k];
+            A.out[r0 + g] = s;
+        }
+    }
 }
 
 }  // namespace spmv

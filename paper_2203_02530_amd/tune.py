@@ -144,11 +144,15 @@ DEFAULT_CANDIDATES = (
 
 
 # y_R variants: packed tiles with 1, 2 or 4 summing lanes, the sliced form
-# (taken only where its padding stays small), column slabs with 1 or 2 lanes.
+# (taken only where its padding stays small), column slabs in tiles of 256 /
+# lanes rows (1 or 2 lanes) and in wide tiles (2, 4 or 8 rows per thread,
+# windows of 1,024 to 4,096 entries).
 DEFAULT_REMOTE_CANDIDATES = (
     [{"kernel_remote": 2, "form": 1, "lanes_remote": l} for l in (1, 2, 4)] +
     [{"kernel_remote": 2, "form": 2}] +
-    [{"kernel_remote": 2, "form": 5, "lanes_remote": l} for l in (1, 2)])
+    [{"kernel_remote": 2, "form": 5, "lanes_remote": l, "rows_remote": 1} for l in (1, 2)] +
+    [{"kernel_remote": 2, "form": 5, "lanes_remote": 1, "rows_remote": r, "chunk_remote": c}
+     for r in (2, 4, 8) for c in (4, 8, 16)])
 
 
 def tune_kernel(A, nranks: int, rank: int, x: np.ndarray, candidates=DEFAULT_CANDIDATES,

@@ -522,8 +522,10 @@ def test_column_slab_form_on_host():
     A = gen.power_law(20000, seed=3)
     i0, _, _ = info(A, 4, 1)
     i, tr, tk = info(A, 4, 1, form=5)
+    assert i0["form_remote"] == 1            # a halo far inside one XCD's L2
     assert i["form_remote"] == 5 and i["form_local"] == i0["form_local"]
-    assert i["lanes_remote"] == 1            # about 2 entries per row per slab
+    # about 2 entries per row per slab: one summing lane, tiles of 256 rows
+    assert (i["lanes_remote"], i["rows_remote"]) == (1, 1)
     n_rr = i["n_remote_rows"]
     starts = np.flatnonzero(tr == 0)
     ends = np.flatnonzero(tr == n_rr)
@@ -536,15 +538,74 @@ def test_column_slab_form_on_host():
         assert tk[a] == 0
         total += int(tk[b])
     assert total == i["nnz_remote"]          # every remote entry in one slab
+    assert np.diff(tr).max() <= 256
+    # wide tiles (rows per thread > 1): up to rows * 256 rows, windows of
+    # 256 * chunk entries (8 unless given), one summing lane; explicit rows
+    # per thread with lanes > 1 are refused
+    i4, tr4, tk4 = info(A, 4, 1, form=5, rows_remote=4)
+    assert (i4["lanes_remote"], i4["rows_remote"], i4["chunk_remote"]) == (1, 4, 8)
+    for a, b in zip(np.flatnonzero(tr4 == 0), np.flatnonzero(tr4 == n_rr)):
+        rows, ents = np.diff(tr4[a:b + 1]), np.diff(tk4[a:b + 1])
+        assert rows.max() <= 4 * 256 and np.all((ents <= 8 * 256) | (rows == 1))
+    assert i4["n_tiles_remote"] < i["n_tiles_remote"]
+    i8, _, _ = info(A, 4, 1, form=5, rows_remote=8, chunk_remote=16)
+    assert (i8["rows_remote"], i8["chunk_remote"]) == (8, 16)
+    with pytest.raises(sp.SpmvError):
+        sp.spmv_plan_create(A, 4, 1, tune={"flags": sp.SPMV_F_HOST_ONLY, "form": 5,
+                                           "lanes_remote": 2, "rows_remote": 2})
     # lanes beyond 4 are refused; no remote rows: packed; vector kernel: 0
     with pytest.raises(sp.SpmvError):
         sp.spmv_plan_create(A, 4, 1, tune={"flags": sp.SPMV_F_HOST_ONLY, "form": 5,
                                            "lanes_remote": 8})
-    assert info(A, 4, 1, form=5, lanes_remote=2)[0]["lanes_remote"] == 2
+    i2 = info(A, 4, 1, form=5, lanes_remote=2)[0]
+    assert (i2["lanes_remote"], i2["rows_remote"]) == (2, 1)
     assert info(gen.laplacian_3d7(8), 1, 0, form=5)[0]["form_remote"] == 1
     assert info(A, 4, 1, form=5, kernel_remote=1)[0]["form_remote"] == 0
     with pytest.raises(sp.SpmvError):
         sp.spmv_plan_create(A, 4, 1, tune={"flags": sp.SPMV_F_HOST_ONLY, "form": 6})
+
+
+def _wide_halo_share(n_half, seed=0):
+    """Two ranks; each of rank 0's rows has one entry on its diagonal and
+    one in rank 1's block, at distinct columns: rank 0's halo has n_half
+    entries."""
+    rng = np.random.default_rng(seed)
+    n = 2 * n_half
+    far = n_half + rng.permutation(n_half)
+    ptr = [np.arange(0, 2 * n_half + 1, 2, dtype=np.int32),
+           2 * n_half + np.arange(1, n_half + 1, dtype=np.int32)]
+    col = np.empty(2 * n_half, np.int32)
+    col[0::2] = np.arange(n_half)
+    col[1::2] = far
+    col = np.concatenate([col, np.arange(n_half, n, dtype=np.int32)])
+    return gen.CSR(n, n, np.concatenate(ptr).astype(np.int32), col,
+                   rng.standard_normal(col.size))
+
+
+def test_column_slabs_automatic_beyond_one_l2():
+    """The automatic form takes column slabs for y_R exactly when the halo
+    (8 bytes per entry) is larger than one XCD's 4 MiB L2; an explicit
+    form 1 keeps packed tiles; the vector kernel never slabs."""
+    for n_half, slabs in ((524_288, False), (524_289, True)):
+        A = _wide_halo_share(n_half)
+        p = sp.spmv_plan_create(A, 2, 0, tune=HOST_ONLY)
+        try:
+            i = sp.spmv_plan_info(p)
+            assert i["n_halo"] == n_half
+            # one entry per row: below the limit the automatic sliced form
+            assert i["form_remote"] == (5 if slabs else 2), n_half
+            if slabs:   # one entry per row: one summing lane
+                assert (i["lanes_remote"], i["rows_remote"]) == (1, 1)
+        finally:
+            sp.spmv_plan_destroy(p)
+    A = _wide_halo_share(600_000)
+    for tune, form in (({"form": 1}, 1), ({"form": 2}, 2), ({"kernel_remote": 1}, 0),
+                       ({"form": 5}, 5)):
+        p = sp.spmv_plan_create(A, 2, 0, tune={"flags": sp.SPMV_F_HOST_ONLY, **tune})
+        try:
+            assert sp.spmv_plan_info(p)["form_remote"] == form, tune
+        finally:
+            sp.spmv_plan_destroy(p)
 
 
 def test_sliced_form_choice_on_host():

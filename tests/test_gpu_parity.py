@@ -224,13 +224,16 @@ def _dense_remote_rows(n=40000, dense=(20000, 20001, 29999), seed=4):
     return gen.CSR(n, n, np.asarray(ptr, np.int32), col, rng.standard_normal(col.size))
 
 
-@pytest.mark.parametrize("chunk,width,lanes", [(0, 0, 0), (4, 2, 1), (8, 4, 2), (16, 2, 4)])
-def test_column_slab_form(chunk, width, lanes):
-    """y_R in column slabs (form 5) against the oracle on power-law,
+@pytest.mark.parametrize("chunk,width,lanes,rows", [(0, 0, 0, 0), (4, 2, 1, 1), (8, 4, 2, 1),
+                                                    (16, 2, 4, 1), (4, 2, 1, 2), (8, 4, 0, 4),
+                                                    (16, 2, 1, 8), (16, 4, 0, 2)])
+def test_column_slab_form(chunk, width, lanes, rows):
+    """y_R in column slabs (form 5), in tiles of 256 / lanes rows and in
+    wide tiles (rows per thread > 1), against the oracle on power-law,
     stencil and banded shares and on rows far longer than a window; every
     plan gives the same bits, whether y_R adds into y itself or a combine
     step adds its partial sums; integer data are exact."""
-    log(f"column slabs chunk={chunk} width={width} lanes={lanes}")
+    log(f"column slabs chunk={chunk} width={width} lanes={lanes} rows={rows}")
     cases = [(gen.power_law(60000, seed=21), 4, 2, 31),
              (gen.power_law(30000, seed=17), 16, 5, 32),
              (gen.stencil_3d27(30, seed=5), 4, 2, 33),
@@ -239,7 +242,7 @@ def test_column_slab_form(chunk, width, lanes):
              (gen.laplacian_2d5(37, 29), 3, 2, 36),
              (gen.laplacian_2d5(5, 4), 2, 1, 37)]   # a 5-entry halo: slabs 5-7 empty
     tune = {"kernel_remote": 2, "chunk_remote": chunk, "width": width, "lanes_remote": lanes,
-            "form": 5}
+            "rows_remote": rows, "form": 5}
     for A, P, r, seed in cases:
         x = gen.x_normal(A.n_cols, seed)
         ref = oracle.share_reference(A, P, r, x)
@@ -727,6 +730,44 @@ def test_full_powerlaw_4m_p16_rank5_and_batch():
     finally:
         for p in plans:
             sp.spmv_plan_destroy(p)
+
+
+def test_full_powerlaw_4m_global_p16_rank5_column_slabs():
+    """Rank 5's share of the global 4M-row power-law matrix (16 ranks, the
+    whole matrix generated, so the send lists and the halo come from the
+    real partition), in the launch configuration the benchmark times: the
+    automatic form puts y_R in column slabs (its 19 MB halo exceeds one
+    XCD's L2).  Every row against the oracle, the outbox and
+    receive buffer bit-exact, then 8 plans spread over the space on the same
+    uploaded share, each bit-identical to the first; wide slab tiles
+    (rows_remote = 4) agree with the oracle too."""
+    w = gen.WORKLOADS["powerlaw_4m_p16r5"]
+    A = w["build"]()
+    x = w["x"](A.n_cols)
+    P, r = w["nranks"], w["rank"]
+    log("full global power-law 4M P=16 r=5, automatic form")
+    ref = oracle.share_reference(A, P, r, x)
+    res, _ = run_share(A, P, r, x, ref=ref, keep_plan=True)
+    plan = res.pop("plan")
+    try:
+        info = res["info"]
+        assert info["n_loc"] == 250_000 and info["form_remote"] == 5
+        assert info["rows_remote"] == 1 and info["lanes_remote"] == 1
+        assert info["n_halo"] * 8 > 4 << 20
+        assert_share_parity(res, ref)
+        first = bits(res["y"])
+        n = sp.spmv_plan_space_count(P, 2)
+        for i in np.linspace(0, n - 1, 8).astype(int):
+            ops, smap = sp.spmv_plan_space_get(P, 2, int(i))
+            sp.spmv_plan_reorder(plan, ops, smap, 2)
+            got, _ = run_share(A, P, r, x, ref=ref, plan=plan)
+            assert np.array_equal(bits(got["y"]), first), i
+    finally:
+        sp.spmv_plan_destroy(plan)
+    log("full global power-law 4M P=16 r=5, wide slab tiles")
+    res, _ = run_share(A, P, r, x, ref=ref, tune={"form": 5, "rows_remote": 4})
+    assert res["info"]["form_remote"] == 5 and res["info"]["rows_remote"] == 4
+    assert_share_parity(res, ref)
 
 
 def test_full_paper_banded_150k_p4_rank1_sampled_plans():
