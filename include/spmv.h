@@ -712,6 +712,38 @@ int spmv_server_run_trace(spmv_server_t *srv, int64_t n, const int32_t *matrix,
 int spmv_server_stats(spmv_server_t *srv, spmv_server_stats_t *stats);
 int spmv_server_destroy(spmv_server_t *srv);   /* drains, stops, frees; NULL-safe */
 
+/* ------------------------------------------------------------ no allocation */
+
+/* Bytes of the library's fixed per-device scratch array (64 MiB). */
+#define SPMV_STATIC_SCRATCH_BYTES (64ll << 20)
+
+/*
+ * spmv_exec for callers that cannot allocate device memory around their
+ * calls (a tight serving loop, a harness that forbids it): the same exec,
+ * with the same arguments, results and errors as spmv_exec, except that
+ * the per-exec intermediate data (send buffer, receive buffer, unpacked
+ * halo, remote partial sums, column-slab partial sums) lives in one fixed
+ * device array of the library instead of the plan's own buffers.  The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ *
+ * The array holds SPMV_STATIC_SCRATCH_BYTES on every GPU the library runs
+ * on, until the process ends; its device address is looked up on the first
+ * call on a device.  A plan whose exec needs more (8 bytes per send entry
+ * and per halo entry, 8 more per halo entry when Unpack is not fused, 8 per
+ * remote row, 64 per remote row in column slabs, each piece rounded up to
+ * 256 bytes) is refused with SPMV_EINVAL before anything runs.  Every call
+ * on one GPU uses the same array and leaves its last contents there (each
+ * piece is written in full before it is read, so no call depends on them):
+ * calls that overlap on one GPU (from several host threads) race and must
+ * not be issued.  The call is host-synchronous like spmv_exec, so calls
+ * from one thread never overlap.  spmv_plan_get_f64 keeps describing the
+ * plan's own buffers (the last spmv_exec), not the static array; the
+ * outbox receives the send buffer as with spmv_exec.
+ */
+int spmv_exec_static(spmv_plan_t *plan, const double *x_local, double *y_local, void *stream);
+/* SPMV_STATIC_SCRATCH_BYTES, as compiled into the library. */
+int64_t spmv_static_scratch_bytes(void);
+
 /* ------------------------------------------------------------ measurement */
 
 /*

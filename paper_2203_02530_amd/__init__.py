@@ -177,6 +177,8 @@ _proto("spmv_plan_create_ex", [_P, _I32, _I32, _P, _I32, _P, _I32, _P, _P])
 _proto("spmv_plan_create_local", [_P, _I64, _I32, _I32, _P, _P, _P, _I32, _P, _I32, _P, _P])
 _proto("spmv_plan_destroy", [_P])
 _proto("spmv_exec", [_P, _P, _P, _P])
+_proto("spmv_exec_static", [_P, _P, _P, _P])
+_proto("spmv_static_scratch_bytes", [], _I64)
 _proto("spmv_plan_info", [_P, _P])
 _proto("spmv_op_launch", [_P, _I32, _P, _P, _P])
 _proto("spmv_plan_reorder", [_P, _P, _I32, _P, _I32])
@@ -371,6 +373,17 @@ def spmv_exec(plan, x, y, stream=None) -> None:
     of at least n_loc entries on the plan's device (checked)."""
     xa, ya = _plan_vecs(plan, x, y)
     _check(_lib.spmv_exec(plan, xa, ya, _stream_handle(stream)))
+
+
+def spmv_exec_static(plan, x, y, stream=None) -> None:
+    """spmv_exec with the exec's intermediate data in the library's fixed
+    per-device scratch array (allocates nothing); same checks and results."""
+    xa, ya = _plan_vecs(plan, x, y)
+    _check(_lib.spmv_exec_static(plan, xa, ya, _stream_handle(stream)))
+
+
+def spmv_static_scratch_bytes() -> int:
+    return int(_lib.spmv_static_scratch_bytes())
 
 
 def spmv_op_launch(plan, op: int, x=None, y=None, stream=None) -> None:
