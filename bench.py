@@ -1,19 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark of the rank-share SpMV on one MI355X.
 
-One step = one ``spmv_exec`` of the rank share: Pack, local product y_L,
+One step = one ``spmv_exec`` of a rank share: Pack, local product y_L,
 host-staged halo exchange (PostSend/PostRecv/Wait*), Unpack and remote
 product y_R, in the plan's operation order and stream binding, ending with
 all work finished.  Inputs are resident in HBM before the timed region.
 
-Cold-cache protocol: the share is uploaded R times (independent device
-copies of A, x and y, R * footprint > 2x the 256 MB Infinity Cache) and the
-steps rotate over the copies, so each step streams A from HBM.
+The headline share is rank 5 of the 4M-row power-law matrix on 16 ranks
+(the whole matrix is generated; the largest single-GPU configuration: its
+remote product gathers from a 19 MB halo).  The 3D 7-point 128^3 and 27-point
+150^3 shares are measured beside it, the 7-point share with the design-space
+stages (plan sweep, design rules and their stability over repeated sweeps,
+tree search, fine-grained program, every rank's share), and the paper's own
+banded input with its plan sweep and rules.
+
+Cold-cache protocol: a share is uploaded R times (independent device copies
+of A, x and y, R * footprint > 2x the 256 MB Infinity Cache) and the steps
+rotate over the copies, so each step streams A from HBM.
 
 Printed: one JSON line with the metric ``rank-share SpMV GB/s`` (algorithmic
 device bytes of all GPU steps / wall time per step), the roofline of the
-dominant kernel (y_L, timed with HIP events on its own stream) and the CPU
-oracle's rate on a bounded sample.
+headline share's dominant kernel (y_R, timed with HIP events on the stream
+it is launched on), the share's device phase (Pack, y_L, Unpack, y_R back to
+back), the CPU oracle's rate on a bounded sample, the 64-share batch and the
+serving trace.
 """
 from __future__ import annotations
 
@@ -31,16 +41,29 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
 MALL_BYTES = 256 << 20         # Infinity Cache
+HEADLINE = "powerlaw_4m_p16r5"
+EXTRAS = ("laplace3d_128_p4r1", "stencil27_150_p8r3")
 
-# HBM bytes per launch of the dominant kernel from the two rocprofv3 --pmc
-# runs (FETCH_SIZE x 1.9994 + WRITE_SIZE x 1.0, factors from the copy probe of
-# known size), keyed by workload and kernel variant; a variant that is not
-# listed (or a kernel changed since) reports null.
+# HBM bytes per launch of a kernel from the two rocprofv3 --pmc runs
+# (FETCH_SIZE x 1.9994 + WRITE_SIZE x 1.0, factors from the copy probe of
+# known size), keyed by workload and kernel variant, with the summary that
+# holds them; a variant that is not listed (or a kernel changed since)
+# reports null.
 MEASURED_TRAFFIC = {
-    ("laplace3d_128_p4r1", "k_sell16<1>"): 47_997_896,
-    ("stencil27_150_p8r3", "k_csr_stream<4,2,2,false>"): 142_241_301,
-    ("stencil27_150_p8r3", "k_csr_stream<4,2,2,true>"): 120_284_162,
+    ("laplace3d_128_p4r1", "k_sell16<1>"):
+        (47_997_896, "profiles/sliced16_laplace3d_128_p4r1.md"),
+    ("stencil27_150_p8r3", "k_csr_stream<4,2,2,false>"):
+        (142_241_301, "profiles/stream_csr_stencil27_150_p8r3.md"),
+    ("stencil27_150_p8r3", "k_csr_stream<4,2,2,true>"):
+        (120_284_162, "profiles/stream_csr_stencil27_150_p8r3.md"),
 }
+
+OPS = ("pack", "yL", "unpack", "yR")
+
+
+def op_code(sp, name: str) -> int:
+    return {"pack": sp.SPMV_OP_PACK, "yL": sp.SPMV_OP_YL, "unpack": sp.SPMV_OP_UNPACK,
+            "yR": sp.SPMV_OP_YR}[name]
 
 
 def step_bytes(info: dict) -> dict:
@@ -66,6 +89,17 @@ def step_bytes(info: dict) -> dict:
     return b
 
 
+def launch_bytes(info: dict) -> dict:
+    """Algorithmic bytes of one spmv_op_launch of each GPU op (y_R launched
+    alone adds into y: its row ids, y read and written)."""
+    n, nl, nr = info["n_loc"], info["nnz_local"], info["nnz_remote"]
+    h, s, rr = info["n_halo"], info["n_send"], info["n_remote_rows"]
+    return {"pack": 20 * s,
+            "yL": 12 * nl + 4 * (n + 1) + 16 * n,
+            "unpack": 0 if info["fuse_unpack"] else 20 * h,
+            "yR": 12 * nr + 4 * (rr + 1) + 4 * rr + 8 * h + 16 * rr if rr else 0}
+
+
 def replicas_for(A, P, r, tune, sp) -> int:
     """Device copies of the share needed to exceed twice the Infinity Cache."""
     p = sp.spmv_plan_create(A, P, r, None, None, 2, {**tune, "flags": sp.SPMV_F_HOST_ONLY})
@@ -78,21 +112,36 @@ def replicas_for(A, P, r, tune, sp) -> int:
     return max(1, math.ceil(2 * MALL_BYTES / max(footprint, 1)))
 
 
-def kernel_variant(info: dict) -> str:
-    if info["kernel_local"] == 2 and info["form_local"] == 3:
-        return "k_sell16<%d>" % (info["chunk_local"] // 8)
-    if info["kernel_local"] == 2 and info["form_local"] == 2:
-        return "k_sell<%d>" % info["chunk_local"]
-    if info["kernel_local"] == 2:
-        return "k_csr_stream<%d,%d,%d,%s>" % (info["chunk_local"], info["width"], info["lanes_local"],
-                                              "true" if info["form_local"] == 4 else "false")
-    return "k_csr_vector_buf<%d,%d>" % (info["lanes_local"], info["rows_local"])
+def _stream_variant(form, chunk, width, lanes):
+    return "k_csr_stream<%d,%d,%d,%s>" % (chunk, width, lanes, "true" if form == 4 else "false")
+
+
+def kernel_variant(info: dict, side: str = "yL") -> str:
+    """Name of the kernel (template instance) that runs one product."""
+    loc = side == "yL"
+    kern = info["kernel_local" if loc else "kernel_remote"]
+    form = info["form_local" if loc else "form_remote"]
+    chunk = info["chunk_local" if loc else "chunk_remote"]
+    lanes = info["lanes_local" if loc else "lanes_remote"]
+    rows = info["rows_local" if loc else "rows_remote"]
+    if kern == 2 and form == 3:
+        return "k_sell16<%d>" % (chunk // 8)
+    if kern == 2 and form == 2:
+        return "k_sell<%d>" % chunk
+    if kern == 2 and form == 5:
+        main = ("k_csr_slabs_wide<%d,%d,%d>" % (chunk, info["width"], rows) if rows > 1
+                else "k_csr_slabs<%d,%d,%d>" % (chunk, info["width"], lanes))
+        return main + "+k_slab_sum"
+    if kern == 2:
+        return _stream_variant(form, chunk, info["width"], lanes)
+    return "k_csr_vector_buf<%d,%d>" % (lanes, rows)
 
 
 def time_op(sp, torch, plans, op, xs, ys, launches: int) -> float:
     """Average duration (us) of one GPU op of the plan: HIP events bracket
-    `launches` back-to-back launches on one stream, rotating over the cold
-    replicas, so launch gaps are hidden behind the queued kernels."""
+    `launches` back-to-back launches on the stream they are issued to,
+    rotating over the cold replicas, so launch gaps are hidden behind the
+    queued kernels."""
     stream = torch.cuda.Stream()
     R = len(plans)
     with torch.cuda.stream(stream):
@@ -108,6 +157,30 @@ def time_op(sp, torch, plans, op, xs, ys, launches: int) -> float:
     return e0.elapsed_time(e1) * 1e3 / launches
 
 
+def time_device_phase(sp, torch, plans, xs, ys, reps: int) -> float:
+    """Average duration (us) of the share's device work alone: Pack, y_L,
+    Unpack and y_R launched back to back on one stream (no copies, no host
+    waits), rotating over the cold replicas."""
+    stream = torch.cuda.Stream()
+    R = len(plans)
+    ops = [sp.SPMV_OP_PACK, sp.SPMV_OP_YL, sp.SPMV_OP_UNPACK, sp.SPMV_OP_YR]
+
+    def one(i):
+        for op in ops:
+            sp.spmv_op_launch(plans[i % R], op, xs[i % R], ys[i % R], stream)
+    with torch.cuda.stream(stream):
+        for i in range(2 * R):
+            one(i)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(reps):
+            one(i)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / reps
+
+
 _T_START = time.perf_counter()
 
 
@@ -118,9 +191,9 @@ def progress(msg: str) -> None:
 
 
 def probe_ceiling(sp, torch, nbytes: int, launches: int = 200) -> dict:
-    """Achievable read bandwidth at the size of one y_L launch: the read
-    probe over cold buffers of `nbytes` (rotated past twice the MALL), best
-    of a few grid sizes."""
+    """Achievable read bandwidth at a given size: the read probe over cold
+    buffers of `nbytes` (rotated past twice the MALL), best of a few grid
+    sizes."""
     nbytes = max(16, nbytes // 16 * 16)
     K = max(2, math.ceil(2 * MALL_BYTES / nbytes))
     bufs = [torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -148,49 +221,69 @@ def probe_ceiling(sp, torch, nbytes: int, launches: int = 200) -> dict:
             "read_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
-def cpu_plain(A, P, r, x, bytes_per_step: float, budget_s: float = 5.0) -> dict:
-    """A plain FP64 CSR product of the same rows on the host (scipy's
-    single-threaded CSR kernel), beside the oracle: the ordinary CPU way to
-    compute this share."""
-    import scipy.sparse as sps
-    q, m = divmod(A.n_rows, P)
-    lo, hi = r * q + min(r, m), (r + 1) * q + min(r + 1, m)
-    k0, k1 = int(A.row_ptr[lo]), int(A.row_ptr[hi])
-    M = sps.csr_matrix((A.val[k0:k1], A.col_idx[k0:k1], A.row_ptr[lo:hi + 1] - k0),
-                       shape=(hi - lo, A.n_cols))
-    M @ x
-    times = []
-    t_start = time.perf_counter()
-    while len(times) < 5 or time.perf_counter() - t_start < budget_s:
-        t0 = time.perf_counter()
-        M @ x
-        times.append(time.perf_counter() - t0)
-    t = float(np.median(times))
-    return {"value": round(bytes_per_step / t / 1e9, 3), "unit": "GB/s", "cores": 1,
-            "kind": "scipy.sparse CSR product", "sample": f"{len(times)} products, median "
-            f"{t * 1e3:.2f} ms each"}
+def host_cpu() -> dict:
+    """The host's CPU model and logical core count."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
 
 
-def cpu_baseline(A, P, r, x, bytes_per_step: float, budget_s: float = 12.0) -> dict:
-    """The oracle (Dot2 over every owned row, OpenMP) timed on the host: full
-    rank-share products repeated for about budget_s seconds of CPU work."""
+def _share_rows(A, P, r):
     import oracle
-    oracle.build(force=False)
     lo_all = oracle.row_blocks(A.n_rows, P)
     lo, hi = int(lo_all[r]), int(lo_all[r + 1])
-    rp = np.ascontiguousarray(A.row_ptr[lo:hi + 1])
-    oracle.spmv_dot2(rp, A.col_idx, A.val, x)                 # warm-up
+    return lo, hi, np.ascontiguousarray(A.row_ptr[lo:hi + 1])
+
+
+def _timed_repeats(fn, budget_s: float):
+    fn()                                                      # warm-up
     times = []
     t_start = time.perf_counter()
     while len(times) < 5 or time.perf_counter() - t_start < budget_s:
         t0 = time.perf_counter()
-        oracle.spmv_dot2(rp, A.col_idx, A.val, x)
+        fn()
         times.append(time.perf_counter() - t0)
-    t = float(np.median(times))
+    return float(np.median(times)), len(times), time.perf_counter() - t_start
+
+
+def cpu_baseline(A, P, r, x, bytes_per_step: float, dynamic: bool,
+                 budget_s: float = 12.0) -> dict:
+    """The oracle (Dot2 over every owned row, OpenMP on all host threads)
+    timed on the host: full rank-share products repeated for about budget_s
+    seconds of CPU work, median."""
+    import oracle
+    oracle.build(force=False)
+    lo, hi, rp = _share_rows(A, P, r)
+    t, k, wall = _timed_repeats(lambda: oracle.spmv_dot2(rp, A.col_idx, A.val, x, dynamic),
+                                budget_s)
     return {"value": round(bytes_per_step / t / 1e9, 3), "unit": "GB/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{len(times)} full rank-share products (Dot2, all {hi - lo} owned rows) "
-                      f"in {time.perf_counter() - t_start:.1f} s, median {t * 1e3:.2f} ms each"}
+            "cores": oracle.num_threads(), "kind": "oracle", **host_cpu(),
+            "schedule": "dynamic,1024" if dynamic else "static",
+            "sample": f"{k} full rank-share products (Dot2, all {hi - lo} owned rows) "
+                      f"in {wall:.1f} s, median {t * 1e3:.3f} ms each"}
+
+
+def cpu_plain(A, P, r, x, bytes_per_step: float, dynamic: bool, budget_s: float = 6.0) -> dict:
+    """The plain FP64 CSR product of the same rows (one multiply and add per
+    entry, OpenMP over rows on all host threads): the ordinary CPU way to
+    compute this share, beside the oracle."""
+    import oracle
+    lo, hi, rp = _share_rows(A, P, r)
+    t, k, wall = _timed_repeats(lambda: oracle.spmv_plain(rp, A.col_idx, A.val, x, dynamic),
+                                budget_s)
+    return {"value": round(bytes_per_step / t / 1e9, 3), "unit": "GB/s",
+            "cores": oracle.num_threads(), "kind": "plain CSR loop, OpenMP", **host_cpu(),
+            "schedule": "dynamic,1024" if dynamic else "static",
+            "gflops": round(2.0 * int(A.row_ptr[hi] - A.row_ptr[lo]) / t / 1e9, 3),
+            "sample": f"{k} full rank-share products in {wall:.1f} s, median "
+                      f"{t * 1e3:.3f} ms each"}
 
 
 def batched_section(sp, torch, gen, n_shares: int, reps: int) -> dict:
@@ -484,38 +577,251 @@ def ranks_section(sp, torch, A, P, x, ops, smap, tune, steps: int = 100) -> dict
             "max_rank": max(out, key=lambda d: d["step_us"])["rank"]}
 
 
-def slabs_section(sp, torch, gen, launches: int = 200) -> dict:
-    """y_R of the 4M-row power-law share (P = 16, rank 5; its dominant
-    kernel, random gathers from a 19 MB halo) in packed tiles (the
-    automatic form) and in column slabs (form 5), each timed over cold
-    replicas with events around back-to-back launches."""
-    w = gen.WORKLOADS["powerlaw_4m_p16r5"]
+def stability_section(sp, A, P, r, x, replicas, ktune, first_res, repeats: int,
+                      t_measure: float) -> dict:
+    """How much of the design-rule output survives timing noise (Sec. IV):
+    the sweep is repeated `repeats` more times on the same share, and each
+    sweep's classes and rules are compared with the first one's."""
+    from paper_2203_02530_amd import rules
+    from paper_2203_02530_amd import tune as tuner
+
+    def rule_out(res):
+        t = np.empty(len(res))
+        for d in res:
+            t[d["index"]] = d["t"]
+        dr = rules.design_rules(rules.plan_space(P, 2), t)
+        y = np.asarray(dr["labels"]["labels"])
+        fast = [rs for rs in dr["rules"] if rs["class"] == 0]
+        top = max(fast, key=lambda rs: rs["samples"])["text"] if fast else []
+        return t, y, top
+    runs = [rule_out(first_res)]
+    for _ in range(repeats):
+        res = tuner.sweep_plans(A, P, r, x, 2, ktune, t_measure=t_measure, n_measure=1,
+                                replicas=replicas)
+        runs.append(rule_out(res))
+    t0, y0, top0 = runs[0]
+    fast0 = set(np.flatnonzero(y0 == 0).tolist())
+    out = {"sweeps": len(runs), "n_classes": [int(np.unique(y).size) for _, y, _ in runs],
+           "fastest_class_size": [int((y == 0).sum()) for _, y, _ in runs],
+           "top_rules_fastest_class": [list(top) for _, _, top in runs], "vs_first": []}
+    for t, y, top in runs[1:]:
+        fast = set(np.flatnonzero(y == 0).tolist())
+        same_k = np.unique(y).size == np.unique(y0).size
+        out["vs_first"].append({
+            "time_rank_corr": round(float(np.corrcoef(np.argsort(np.argsort(t0)),
+                                                      np.argsort(np.argsort(t)))[0, 1]), 4),
+            "same_class_count": bool(same_k),
+            "label_agreement": round(float((y == y0).mean()), 4) if same_k else None,
+            "fastest_class_jaccard": round(len(fast & fast0) / max(len(fast | fast0), 1), 4),
+            "top_rule_set_equal": list(top) == list(top0),
+            "top_rules_shared": len(set(top) & set(top0)),
+            "median_time_change": round(float(np.median(np.abs(t - t0) / t0)), 4)})
+    return out
+
+
+def measure_share(sp, torch, gen, key: str, args, sweep: bool = True) -> tuple[dict, dict]:
+    """One rank share: the plan (chosen by the cold sweep of every plan, or
+    the default), timed steps, per-op event times and the host timeline of
+    the chosen plan, each GPU op's duration over back-to-back launches, the
+    device phase, and the roofline of the op with the most algorithmic
+    bytes.  Returns (result, context for further sections)."""
+    from paper_2203_02530_amd import tune as tuner
+    w = gen.WORKLOADS[key]
+    t0 = time.perf_counter()
     A = w["build"]()
     P, r = w["nranks"], w["rank"]
     x = w["x"](A.n_cols)
-    out = {"workload": w["desc"]}
-    for name, tune in (("packed", {}), ("slabs", {"form": 5})):
-        R = replicas_for(A, P, r, tune, sp)
-        plans = [sp.spmv_plan_create(A, P, r, None, None, 2, tune) for _ in range(R)]
-        try:
-            info = sp.spmv_plan_info(plans[0])
-            lo, n = info["lo"], info["n_loc"]
-            xs = [torch.from_numpy(np.ascontiguousarray(x[lo:lo + n])).cuda() for _ in plans]
-            ys = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in plans]
-            us = time_op(sp, torch, plans, sp.SPMV_OP_YR, xs, ys, launches)
-        finally:
-            for p in plans:
-                sp.spmv_plan_destroy(p)
-        out[name] = {"yR_us": round(us, 3), "form_remote": info["form_remote"],
-                     "lanes_remote": info["lanes_remote"], "tiles": info["n_tiles_remote"],
-                     "replicas": R}
-    nr, h = info["nnz_remote"], info["n_halo"]
-    yr_bytes = 12 * nr + 24 * info["n_remote_rows"] + 8 * h
-    out["yR_bytes"] = int(yr_bytes)
-    for name in ("packed", "slabs"):
-        out[name]["yR_gbs"] = round(yr_bytes / (out[name]["yR_us"] * 1e-6) / 1e9, 1)
-    out["speedup"] = round(out["packed"]["yR_us"] / out["slabs"]["yR_us"], 3)
-    return out
+    build_s = time.perf_counter() - t0
+    ktune = {"lanes_local": args.lanes, "rows_local": args.rows, "kernel_local": args.kernel,
+             "chunk_local": args.chunk, "form": args.form, "width": args.width}
+    ctx = {"A": A, "P": P, "r": r, "x": x, "ktune": ktune, "res": None, "best": None}
+    ops = smap = None
+    sweep_out = None
+    if sweep and P > 1 and args.plan == "auto":
+        R0 = args.replicas or replicas_for(A, P, r, ktune, sp)
+        progress(f"{key}: plan sweep over {R0} cold replicas")
+        res = tuner.sweep_plans(A, P, r, x, 2, ktune, t_measure=args.sweep_measure, n_measure=1,
+                                replicas=R0)
+        top = [d["index"] for d in tuner.best_plans(res, 8)]
+        again = tuner.sweep_plans(A, P, r, x, 2, ktune, t_measure=args.sweep_measure,
+                                  n_measure=5, indices=top, replicas=R0)
+        best = tuner.best_plans(again, 1)[0]["index"]
+        sweep_out = tuner.sweep_summary(res)
+        sweep_out["chosen_index"] = best
+        ops, smap = sp.spmv_plan_space_get(P, 2, best)
+        ctx.update(res=res, best=best, R0=R0)
+    elif args.plan not in ("auto", "default") and P > 1:
+        ops, smap = sp.spmv_plan_space_get(P, 2, int(args.plan))
+    tune = {"flags": 0, "lanes_local": args.lanes, "lanes_remote": args.lanes_remote,
+            "rows_local": args.rows, "rows_remote": args.rows_remote,
+            "kernel_local": args.kernel, "chunk_local": args.chunk,
+            "chunk_remote": args.chunk_remote, "xcd_remap": args.xcd_remap,
+            "fuse_unpack": args.fuse_unpack, "form": args.form, "width": args.width}
+    ctx["ops"], ctx["smap"], ctx["tune"] = ops, smap, tune
+
+    progress(f"{key}: timed steps")
+    first = sp.spmv_plan_create(A, P, r, ops, smap, 2, tune)
+    info = sp.spmv_plan_info(first)
+    lo, n = info["lo"], info["n_loc"]
+    R = args.replicas or max(1, math.ceil(2 * MALL_BYTES / max(info["device_bytes"] + 16 * n, 1)))
+    plans = [first] + [sp.spmv_plan_create(A, P, r, ops, smap, 2, tune) for _ in range(R - 1)]
+    try:
+        halo = sp.spmv_plan_get_i32(first, sp.SPMV_I32_HALO_COLS).astype(np.int64)
+        xs, ys = [], []
+        for p in plans:
+            sp.spmv_plan_inbox(p)[:] = x[halo]
+            xs.append(torch.from_numpy(np.ascontiguousarray(x[lo:lo + n])).cuda())
+            ys.append(torch.empty(n, dtype=torch.float64, device="cuda"))
+        stream = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        if args.kernel_only:
+            return kernel_only(sp, torch, key, info, plans, xs, ys, stream, args), ctx
+
+        # the timed loop passes raw addresses straight to the C entry point
+        exec_fn = sp._lib.spmv_exec
+        call = [(p, x_.data_ptr(), y_.data_ptr()) for p, x_, y_ in zip(plans, xs, ys)]
+        sh = stream.cuda_stream
+        for i in range(args.warmup):
+            sp.spmv_exec(plans[i % R], xs[i % R], ys[i % R], stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            p, xp, yp = call[i % R]
+            if exec_fn(p, xp, yp, sh):
+                raise sp.SpmvError(-5, sp.spmv_last_error())
+        torch.cuda.synchronize()
+        ms_step = (time.perf_counter() - t0) / args.steps * 1e3
+
+        # per-step event times inside the plan, from a separate profiled pass
+        # (the event records add host work, so they stay out of the timed loop)
+        for p in plans:
+            sp.spmv_plan_set_profile(p, True)
+            sp.spmv_plan_reset_times(p)
+        for i in range(min(args.steps, 100)):
+            sp.spmv_exec(plans[i % R], xs[i % R], ys[i % R], stream)
+        torch.cuda.synchronize()
+        ms = np.zeros(sp.SPMV_N_VERTICES + 1)
+        cnt = np.zeros(sp.SPMV_N_VERTICES + 1)
+        for p in plans:
+            ms += sp.spmv_plan_get_f64(p, sp.SPMV_F64_OP_MS)
+            cnt += sp.spmv_plan_get_f64(p, sp.SPMV_F64_OP_COUNT)
+        in_plan = np.where(cnt > 0, ms / np.maximum(cnt, 1), 0.0) * 1e3
+        # host timeline of the same plan (where the host waits), its own pass
+        for p in plans:
+            sp.spmv_plan_set_profile(p, False, host=True)
+            sp.spmv_plan_reset_times(p)
+        for i in range(min(args.steps, 200)):
+            sp.spmv_exec(plans[i % R], xs[i % R], ys[i % R], stream)
+        torch.cuda.synchronize()
+        h_us = sum(sp.spmv_plan_get_f64(p, sp.SPMV_F64_HOST_US) for p in plans)
+        h_n = sum(float(sp.spmv_plan_get_f64(p, sp.SPMV_F64_HOST_COUNT)[0]) for p in plans)
+        for p in plans:
+            sp.spmv_plan_set_profile(p, False)
+        B = step_bytes(info)
+        LB = launch_bytes(info)
+
+        # each GPU op alone, back to back on one stream, events on that stream
+        progress(f"{key}: kernel timings")
+        launches = max(10 * R, 200)
+        kern_us = {name: (time_op(sp, torch, plans, op_code(sp, name), xs, ys, launches)
+                          if LB[name] > 0 else 0.0) for name in OPS}
+        dev_us = time_device_phase(sp, torch, plans, xs, ys, max(5 * R, 100))
+        dev_bytes = sum(LB.values())
+        dom = max(("yL", "yR", "pack"), key=lambda k: LB[k])
+        dom_variant = kernel_variant(info, dom) if dom in ("yL", "yR") else "k_gather"
+        achieved = LB[dom] / (kern_us[dom] * 1e-6) / 1e9
+        tr = MEASURED_TRAFFIC.get((key, dom_variant))
+        traffic, traffic_src = (tr if tr else (None, None))
+        ceiling = probe_ceiling(sp, torch, traffic or LB[dom])
+        plan_order = [sp.spmv_op_name(int(t))
+                      for t in sp.spmv_plan_get_i32(first, sp.SPMV_I32_OP_ORDER)]
+        plan_streams = {sp.spmv_op_name(v): int(m) for v, m in enumerate(
+            sp.spmv_plan_get_i32(first, sp.SPMV_I32_STREAM_MAP)) if m >= 0}
+    finally:
+        for p in plans:
+            sp.spmv_plan_destroy(p)
+    out = {
+        "workload": w["desc"], "input_build_s": round(build_s, 1),
+        "value": round(B["total"] / (ms_step * 1e-3) / 1e9, 3), "ms_per_step": round(ms_step, 5),
+        "gflops": round(2.0 * (info["nnz_local"] + info["nnz_remote"]) / (ms_step * 1e-3) / 1e9, 3),
+        "config": {"workload": w["desc"], "rows": int(A.n_rows), "nnz": int(A.nnz),
+                   "nranks": P, "rank": r, "n_loc": n, "nnz_local": info["nnz_local"],
+                   "nnz_remote": info["nnz_remote"], "n_halo": info["n_halo"],
+                   "n_send": info["n_send"], "n_remote_rows": info["n_remote_rows"],
+                   "plan": args.plan if sweep_out is None else "auto",
+                   "kernel_yL": kernel_variant(info, "yL"), "kernel_yR": kernel_variant(info, "yR"),
+                   "form_local": info["form_local"], "form_remote": info["form_remote"],
+                   "n_tiles_local": info["n_tiles_local"], "n_tiles_remote": info["n_tiles_remote"],
+                   "xcd_remap": info["xcd_remap"], "fuse_unpack": info["fuse_unpack"],
+                   "fused_combine": info["fused_combine"], "replicas": R,
+                   "step_device_bytes": B["total"], "step_host_link_bytes": B["host_link"]},
+        "roofline": {"bound": "hbm", "kernel": f"{dom} {dom_variant}",
+                     "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_source": traffic_src,
+                     "traffic_over_algorithmic": round(traffic / LB[dom], 3) if traffic else None,
+                     "traffic_gbs": (round(traffic / (kern_us[dom] * 1e-6) / 1e9, 1)
+                                     if traffic else None),
+                     "bytes_per_launch": LB[dom], "avg_us": round(kern_us[dom], 3),
+                     "launches": launches},
+        "hbm_probe": {**ceiling, "kernel_moved_over_probe": (
+            round(traffic / (kern_us[dom] * 1e-6) / 1e9 / ceiling["read_gbs"], 3)
+            if traffic else None)},
+        "device_phase": {"ops": "Pack + y_L + Unpack + y_R back to back, no copies",
+                         "bytes": dev_bytes, "avg_us": round(dev_us, 3),
+                         "gbs": round(dev_bytes / (dev_us * 1e-6) / 1e9, 1),
+                         "frac": round(dev_bytes / (dev_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
+        "kernel_us": {k: round(float(v), 3) for k, v in kern_us.items()},
+        "kernel_bytes": LB,
+        "kernel_gbs": {k: round(LB[k] / (kern_us[k] * 1e-6) / 1e9, 1) for k in kern_us
+                       if kern_us[k] > 0 and LB[k] > 0},
+        "in_plan_event_us": {"pack": round(float(in_plan[sp.SPMV_OP_PACK]), 3),
+                             "yL": round(float(in_plan[sp.SPMV_OP_YL]), 3),
+                             "unpack": round(float(in_plan[sp.SPMV_OP_UNPACK]), 3),
+                             "yR": round(float(in_plan[sp.SPMV_OP_YR]), 3),
+                             "combine": round(float(in_plan[sp.SPMV_N_VERTICES]), 3),
+                             "post_send_copy": round(float(in_plan[sp.SPMV_OP_POST_SEND]), 3),
+                             "post_recv_copy": round(float(in_plan[sp.SPMV_OP_POST_RECV]), 3)},
+        "host_timeline_us": [[name, round(float(t) / max(h_n, 1.0), 2)]
+                             for name, t in zip(plan_order, h_us)],
+        "plan_sweep": sweep_out, "plan_order": plan_order, "plan_streams": plan_streams,
+    }
+    ctx["info"] = info
+    return out, ctx
+
+
+def kernel_only(sp, torch, key, info, plans, xs, ys, stream, args) -> dict:
+    """Counter runs: one op launched back to back over the cold replicas,
+    then a plain copy of known size whose FETCH_SIZE / WRITE_SIZE readings
+    calibrate the counters."""
+    LB = launch_bytes(info)
+    name = args.op or max(("yL", "yR", "pack"), key=lambda k: LB[k])
+    launches = max(10 * len(plans), 200)
+    us = time_op(sp, torch, plans, op_code(sp, name), xs, ys, launches)
+    nbytes = 64 << 20
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").normal_()
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(10):
+        sp.spmv_hbm_probe(1, src, dst, nbytes, 0, stream)
+    torch.cuda.synchronize()
+    return {"kernel_only": True, "workload": key, "op": name,
+            "variant": kernel_variant(info, name) if name in ("yL", "yR") else "k_gather",
+            "avg_us": round(us, 3), "launches": launches + 2 * len(plans),
+            "bytes_per_launch": LB[name], "copy_bytes_each_way": nbytes, "copy_launches": 10}
+
+
+def extra_summary(out: dict) -> dict:
+    """The fields of a share carried beside the headline."""
+    rf = out["roofline"]
+    return {"workload": out["workload"], "kernel": rf["kernel"],
+            "bytes_per_launch": rf["bytes_per_launch"], "avg_us": rf["avg_us"],
+            "achieved": rf["achieved"], "frac": rf["frac"], "traffic": rf["traffic"],
+            "traffic_source": rf["traffic_source"], "step_us": round(out["ms_per_step"] * 1e3, 2),
+            "value": out["value"], "device_phase": out["device_phase"],
+            "hbm_probe": out["hbm_probe"],
+            "kernel_us": out["kernel_us"], "plan_sweep": out["plan_sweep"],
+            "config": out["config"]}
 
 
 def paper_section(sp, torch, gen, tuner) -> dict:
@@ -541,7 +847,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="laplace3d_128_p4r1")
+    ap.add_argument("--workload", default=HEADLINE)
     ap.add_argument("--replicas", type=int, default=0, help="0 = enough to exceed 2x MALL")
     ap.add_argument("--plan", default="auto",
                     help="'auto' (sweep the design space, keep the fastest), 'default', "
@@ -549,40 +855,48 @@ def main() -> int:
     ap.add_argument("--sweep-measure", type=float, default=0.01,
                     help="seconds per measurement in the plan sweep (paper: 0.01)")
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--lanes-remote", type=int, default=0)
     ap.add_argument("--rows", type=int, default=0)
+    ap.add_argument("--rows-remote", type=int, default=0)
     ap.add_argument("--kernel", type=int, default=0, help="0 auto, 1 vector CSR, 2 stream CSR")
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--chunk-remote", type=int, default=0)
     ap.add_argument("--width", type=int, default=0, help="stream CSR entries per load (0 auto)")
     ap.add_argument("--form", type=int, default=0,
                     help="stream form: 0 auto, 1 packed tiles, 2 sliced ELL, 3 sliced ELL with "
-                         "16-bit column offsets")
+                         "16-bit column offsets, 4 packed tiles with 16-bit columns, 5 y_R in "
+                         "column slabs")
     ap.add_argument("--xcd-remap", type=int, default=0)
     ap.add_argument("--fuse-unpack", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-rules", action="store_true",
-                    help="skip design rules, the Table V experiment and the live tree search")
+                    help="skip the design-space stages on the 7-point share and the paper's "
+                         "workload")
+    ap.add_argument("--extras", type=int, default=1,
+                    help="also measure the 7-point and 27-point stencil shares (1 = yes)")
+    ap.add_argument("--stability", type=int, default=2,
+                    help="repeated sweeps of the 7-point share for the rule stability figure")
     ap.add_argument("--batch-shares", type=int, default=64,
                     help="rank shares in the batched section (0 = skip it)")
     ap.add_argument("--serve-requests", type=int, default=20000,
                     help="requests in the serving section (0 = skip it)")
-    ap.add_argument("--slabs", type=int, default=1,
-                    help="time y_R of the power-law share in packed tiles and in column "
-                         "slabs (1 = yes)")
     ap.add_argument("--all-ranks", type=int, default=1,
-                    help="also run every rank's share of the matrix with the chosen plan "
+                    help="run every rank's share of the 7-point matrix with the chosen plan "
                          "and report the max over ranks (1 = yes)")
     ap.add_argument("--tune-kernel", action="store_true",
-                    help="also time the y_L kernel variants of the autotuner on this share")
+                    help="also time the product kernel variants of the autotuner on the "
+                         "headline share (y_L and y_R)")
     ap.add_argument("--kernel-only", action="store_true",
-                    help="only launch the dominant kernel back-to-back and the copy probe of "
-                         "known size (for hardware-counter runs), print their timings")
+                    help="only launch one op of the workload back-to-back and the copy probe "
+                         "of known size (for hardware-counter runs), print their timings")
+    ap.add_argument("--op", default="", help="op for --kernel-only (pack, yL, unpack, yR; "
+                                             "default: the one with the most bytes)")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(f"bench.py measures one rank share on one GPU; --gpus {args.gpus} is not "
               "supported (the library runs one rank's share per GPU; the multi-GPU "
-              "exchange is not implemented)",
-              file=sys.stderr)
+              "exchange is not implemented)", file=sys.stderr)
         return 2
 
     import torch
@@ -591,159 +905,35 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    w = gen.WORKLOADS[args.workload]
-    A = w["build"]()
-    P, r = w["nranks"], w["rank"]
-    x = w["x"](A.n_cols)
-
-    ops = smap = None
-    sweep = design = fine = None
-    if args.plan == "auto" and P > 1:
-        from paper_2203_02530_amd import tune as tuner
-        ktune = {"lanes_local": args.lanes, "rows_local": args.rows, "kernel_local": args.kernel,
-                 "chunk_local": args.chunk, "form": args.form, "width": args.width}
-        # rank plans under the timed loop's conditions: cold replicas
-        R0 = args.replicas or replicas_for(A, P, r, ktune, sp)
-        progress("plan sweep")
-        res = tuner.sweep_plans(A, P, r, x, 2, ktune, t_measure=args.sweep_measure, n_measure=1,
-                                replicas=R0)
-        top = [d["index"] for d in tuner.best_plans(res, 8)]
-        again = tuner.sweep_plans(A, P, r, x, 2, ktune, t_measure=args.sweep_measure, n_measure=5,
-                                  indices=top, replicas=R0)
-        best = tuner.best_plans(again, 1)[0]["index"]
-        sweep = tuner.sweep_summary(res)
-        if not args.no_rules:
-            progress("design rules")
-            design = rules_section(sp, torch, A, P, r, x, res, R0, ktune)
-            progress("fine-grained search")
-            fine = fine_section(sp, torch, A, P, r, x, R0, ktune, best)
-        sweep["chosen_index"] = best
-        ops, smap = sp.spmv_plan_space_get(P, 2, best)
-    elif args.plan not in ("auto", "default"):
-        ops, smap = sp.spmv_plan_space_get(P, 2, int(args.plan))
-    tune = {"flags": 0, "lanes_local": args.lanes, "lanes_remote": 0,
-            "rows_local": args.rows, "kernel_local": args.kernel, "chunk_local": args.chunk,
-            "xcd_remap": args.xcd_remap, "fuse_unpack": args.fuse_unpack, "form": args.form,
-            "width": args.width}
-
-    progress("timed steps")
-    first = sp.spmv_plan_create(A, P, r, ops, smap, 2, tune)
-    info = sp.spmv_plan_info(first)
-    lo, n = info["lo"], info["n_loc"]
-    footprint = info["device_bytes"] + 16 * n
-    R = args.replicas or max(1, math.ceil(2 * MALL_BYTES / max(footprint, 1)))
-    plans = [first] + [sp.spmv_plan_create(A, P, r, ops, smap, 2, tune) for _ in range(R - 1)]
-    halo = sp.spmv_plan_get_i32(first, sp.SPMV_I32_HALO_COLS).astype(np.int64)
-    xs, ys = [], []
-    for p in plans:
-        sp.spmv_plan_inbox(p)[:] = x[halo]
-        xs.append(torch.from_numpy(np.ascontiguousarray(x[lo:lo + n])).cuda())
-        ys.append(torch.empty(n, dtype=torch.float64, device="cuda"))
-    stream = torch.cuda.current_stream()
-    torch.cuda.synchronize()
 
     if args.kernel_only:
-        # counter runs: y_L over the cold replicas, then a plain copy of known
-        # size whose FETCH_SIZE / WRITE_SIZE readings calibrate the counters
-        launches = 10 * R
-        us = time_op(sp, torch, plans, sp.SPMV_OP_YL, xs, ys, launches)
-        nbytes = 64 << 20
-        src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").normal_()
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        for _ in range(10):
-            sp.spmv_hbm_probe(1, src, dst, nbytes, 0, stream)
-        torch.cuda.synchronize()
-        B = step_bytes(info)
-        print(json.dumps({"kernel_only": True, "yL_us": round(us, 3), "yL_launches": launches + 2 * R,
-                          "yL_bytes": B["yL"], "copy_bytes_each_way": nbytes, "copy_launches": 10}),
-              flush=True)
-        for p in plans:
-            sp.spmv_plan_destroy(p)
+        out, _ = measure_share(sp, torch, gen, args.workload, args, sweep=False)
+        print(json.dumps(out), flush=True)
         return 0
 
-    # the timed loop passes raw addresses straight to the C entry point
-    exec_fn = sp._lib.spmv_exec
-    call = [(p, x_.data_ptr(), y_.data_ptr()) for p, x_, y_ in zip(plans, xs, ys)]
-    sh = stream.cuda_stream
-    for i in range(args.warmup):
-        sp.spmv_exec(plans[i % R], xs[i % R], ys[i % R], stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        p, xp, yp = call[i % R]
-        if exec_fn(p, xp, yp, sh):
-            raise sp.SpmvError(-5, sp.spmv_last_error())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_step = elapsed / args.steps * 1e3
-
-    # per-step event times inside the plan, from a separate profiled pass
-    # (the event records add host work, so they stay out of the timed loop)
-    for p in plans:
-        sp.spmv_plan_set_profile(p, True)
-        sp.spmv_plan_reset_times(p)
-    for i in range(min(args.steps, 100)):
-        sp.spmv_exec(plans[i % R], xs[i % R], ys[i % R], stream)
-    torch.cuda.synchronize()
-    ms = np.zeros(sp.SPMV_N_VERTICES + 1)
-    cnt = np.zeros(sp.SPMV_N_VERTICES + 1)
-    for p in plans:
-        ms += sp.spmv_plan_get_f64(p, sp.SPMV_F64_OP_MS)
-        cnt += sp.spmv_plan_get_f64(p, sp.SPMV_F64_OP_COUNT)
-    in_plan = np.where(cnt > 0, ms / np.maximum(cnt, 1), 0.0) * 1e3
-    # host timeline of the same plan (where the host waits), its own pass
-    for p in plans:
-        sp.spmv_plan_set_profile(p, False, host=True)
-        sp.spmv_plan_reset_times(p)
-    for i in range(min(args.steps, 200)):
-        sp.spmv_exec(plans[i % R], xs[i % R], ys[i % R], stream)
-    torch.cuda.synchronize()
-    h_us = sum(sp.spmv_plan_get_f64(p, sp.SPMV_F64_HOST_US) for p in plans)
-    h_n = sum(float(sp.spmv_plan_get_f64(p, sp.SPMV_F64_HOST_COUNT)[0]) for p in plans)
-    for p in plans:
-        sp.spmv_plan_set_profile(p, False)
-    B = step_bytes(info)
-    value = B["total"] / (ms_step * 1e-3) / 1e9
-
-    # Kernel durations: back-to-back launches of each GPU op, events on the
-    # launching stream.  y_L is the dominant kernel (95% of the device bytes).
-    launches = max(10 * R, 200)
-    progress("kernel timings")
-    kern_us = {name: time_op(sp, torch, plans, op, xs, ys, launches)
-               for name, op in (("yL", sp.SPMV_OP_YL), ("pack", sp.SPMV_OP_PACK),
-                                ("unpack", sp.SPMV_OP_UNPACK), ("yR", sp.SPMV_OP_YR))}
-    # the same launches on one replica: its arrays stay in the MALL
-    warm_yl_us = time_op(sp, torch, plans[:1], sp.SPMV_OP_YL, xs[:1], ys[:1], launches)
-    achieved = B["yL"] / (kern_us["yL"] * 1e-6) / 1e9
-    traffic = MEASURED_TRAFFIC.get((args.workload, kernel_variant(info)))
-    ceiling = probe_ceiling(sp, torch, traffic or B["yL"])
-    in_plan_us = {"pack": in_plan[sp.SPMV_OP_PACK], "yL": in_plan[sp.SPMV_OP_YL],
-                  "unpack": in_plan[sp.SPMV_OP_UNPACK], "yR": in_plan[sp.SPMV_OP_YR],
-                  "combine": in_plan[sp.SPMV_N_VERTICES],
-                  "post_send_copy": in_plan[sp.SPMV_OP_POST_SEND],
-                  "post_recv_copy": in_plan[sp.SPMV_OP_POST_RECV]}
-
-    plan_order = [sp.spmv_op_name(int(t)) for t in sp.spmv_plan_get_i32(first, sp.SPMV_I32_OP_ORDER)]
-    plan_streams = {sp.spmv_op_name(v): int(m) for v, m in enumerate(
-        sp.spmv_plan_get_i32(first, sp.SPMV_I32_STREAM_MAP)) if m >= 0}
+    head, hctx = measure_share(sp, torch, gen, args.workload, args)
     cpu = plain = None
     if not args.no_cpu:
-        progress("cpu baseline")
-        cpu = cpu_baseline(A, P, r, x, float(B["total"]))
-        plain = cpu_plain(A, P, r, x, float(B["total"]))
-    for p in plans:
-        sp.spmv_plan_destroy(p)
-    plans = []
+        progress("cpu baselines")
+        dyn = args.workload.startswith("powerlaw")
+        B = float(head["config"]["step_device_bytes"])
+        cpu = cpu_baseline(hctx["A"], hctx["P"], hctx["r"], hctx["x"], B, dyn)
+        plain = cpu_plain(hctx["A"], hctx["P"], hctx["r"], hctx["x"], B, dyn)
     kernel_tune = None
     if args.tune_kernel:
         from paper_2203_02530_amd import tune as tuner
-        t0 = time.perf_counter()
         progress("kernel autotuner")
-        best, res = tuner.tune_kernel(A, P, r, x, launches=max(10 * R, 200))
-        kernel_tune = {"wall_s": round(time.perf_counter() - t0, 1), "best": best,
-                       "auto_variant": kernel_variant(info),
-                       "results": [{"tune": d["tune"], "us": round(d["us"], 3)} for d in res]}
+        t0 = time.perf_counter()
+        A, P, r, x = hctx["A"], hctx["P"], hctx["r"], hctx["x"]
+        bl, rl = tuner.tune_kernel(A, P, r, x, launches=200)
+        br, rr = tuner.tune_kernel(A, P, r, x, candidates=tuner.DEFAULT_REMOTE_CANDIDATES,
+                                   launches=200, op=sp.SPMV_OP_YR)
+        kernel_tune = {"wall_s": round(time.perf_counter() - t0, 1),
+                       "yL": {"best": bl, "results": [{"tune": d["tune"], "us": round(d["us"], 3)}
+                                                      for d in rl]},
+                       "yR": {"best": br, "results": [{"tune": d["tune"], "us": round(d["us"], 3)}
+                                                      for d in rr]}}
+    del hctx
     batched = serving = None
     if args.batch_shares > 0:
         progress("batched shares")
@@ -751,14 +941,32 @@ def main() -> int:
     if args.serve_requests > 0:
         progress("serving")
         serving = serving_section(sp, torch, gen, args.serve_requests, 5000.0, 128)
-    all_ranks = None
-    if P > 1 and not args.kernel_only and args.all_ranks:
-        progress("every rank's share")
-        all_ranks = ranks_section(sp, torch, A, P, x, ops, smap, tune)
-    slabs = None
-    if args.slabs and not args.kernel_only:
-        progress("column slabs")
-        slabs = slabs_section(sp, torch, gen)
+
+    extras = {}
+    design = None
+    if args.extras:
+        for key in EXTRAS:
+            ex, ctx = measure_share(sp, torch, gen, key, args)
+            extras[key] = extra_summary(ex)
+            if key == "laplace3d_128_p4r1" and not args.no_rules and ctx["res"] is not None:
+                A, P, r, x = ctx["A"], ctx["P"], ctx["r"], ctx["x"]
+                progress(f"{key}: design rules")
+                design = {"workload": ex["workload"],
+                          "rules": rules_section(sp, torch, A, P, r, x, ctx["res"], ctx["R0"],
+                                                 ctx["ktune"])}
+                if args.stability > 0:
+                    progress(f"{key}: rule stability ({args.stability} more sweeps)")
+                    design["stability"] = stability_section(
+                        sp, A, P, r, x, ctx["R0"], ctx["ktune"], ctx["res"], args.stability,
+                        args.sweep_measure)
+                progress(f"{key}: fine-grained search")
+                design["fine_grained"] = fine_section(sp, torch, A, P, r, x, ctx["R0"],
+                                                      ctx["ktune"], ctx["best"])
+                if args.all_ranks:
+                    progress(f"{key}: every rank's share")
+                    design["all_ranks"] = ranks_section(sp, torch, A, P, x, ctx["ops"],
+                                                        ctx["smap"], ctx["tune"])
+            del ctx
     paper = None
     if args.plan == "auto" and not args.no_rules:
         from paper_2203_02530_amd import tune as tuner
@@ -767,68 +975,41 @@ def main() -> int:
 
     out = {
         "metric": "rank-share SpMV GB/s vs HBM peak; batched req/s + p50/p99 latency vs plain",
-        "value": round(value, 3),
+        "value": head["value"],
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 5),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w["desc"], "rows": int(A.n_rows), "nnz": int(A.nnz),
-                   "nranks": P, "rank": r, "n_loc": n, "nnz_local": info["nnz_local"],
-                   "nnz_remote": info["nnz_remote"], "n_halo": info["n_halo"],
-                   "plan": args.plan, "kernel_local": info["kernel_local"],
-                   "chunk_local": info["chunk_local"], "form_local": info["form_local"],
-                   "n_tiles_local": info["n_tiles_local"],
-                   "n_slices_local": info["n_slices_local"],
-                   "lanes_local": info["lanes_local"],
-                   "rows_local": info["rows_local"], "lanes_remote": info["lanes_remote"],
-                   "rows_remote": info["rows_remote"], "xcd_remap": info["xcd_remap"],
-                   "fuse_unpack": info["fuse_unpack"], "replicas": R,
-                   "step_device_bytes": B["total"], "step_host_link_bytes": B["host_link"]},
-        "roofline": {"bound": "hbm", "kernel": "y_L " + kernel_variant(info),
-                     "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "traffic_gbs": (round(traffic / (kern_us["yL"] * 1e-6) / 1e9, 1)
-                                     if traffic else None),
-                     "bytes_per_launch": B["yL"], "avg_us": round(kern_us["yL"], 3),
-                     "launches": launches},
-        "kernel_us": {k: round(float(v), 3) for k, v in kern_us.items()},
-        "yL_warm": {"avg_us": round(warm_yl_us, 3),
-                    "achieved": round(B["yL"] / (warm_yl_us * 1e-6) / 1e9, 1)},
-        "hbm_probe": {**ceiling,
-                      "yL_moved_over_probe": (round(traffic / (kern_us["yL"] * 1e-6) / 1e9
-                                                    / ceiling["read_gbs"], 3)
-                                              if traffic else None)},
-        "kernel_gbs": {k: round(B[k] / (kern_us[k] * 1e-6) / 1e9, 1) for k in kern_us
-                       if kern_us[k] > 0 and B[k] > 0},
-        "in_plan_event_us": {k: round(float(v), 3) for k, v in in_plan_us.items()},
-        "host_timeline_us": [[name, round(float(t) / max(h_n, 1.0), 2)]
-                             for name, t in zip(plan_order, h_us)],
-        "plan_sweep": sweep,
-        "design_rules": design,
-        "fine_grained": fine,
-        "kernel_tune": kernel_tune,
-        "all_ranks": all_ranks,
-        "remote_slabs": slabs,
-        "paper_workload": paper,
-        "plan_order": plan_order,
-        "plan_streams": plan_streams,
-        "gflops": round(2.0 * (info["nnz_local"] + info["nnz_remote"]) / (ms_step * 1e-3) / 1e9, 3),
+        "config": head["config"],
+        "roofline": head["roofline"],
         "cpu_baseline": cpu,
         "cpu_plain": plain,
+        "device_phase": head["device_phase"],
+        "hbm_probe": head["hbm_probe"],
+        "gflops": head["gflops"],
+        "kernel_us": head["kernel_us"],
+        "kernel_bytes": head["kernel_bytes"],
+        "kernel_gbs": head["kernel_gbs"],
+        "in_plan_event_us": head["in_plan_event_us"],
+        "host_timeline_us": head["host_timeline_us"],
+        "plan_sweep": head["plan_sweep"],
+        "plan_order": head["plan_order"],
+        "plan_streams": head["plan_streams"],
+        "kernel_tune": kernel_tune,
         "batched": batched,
         "serving": serving,
+        "extras": extras,
+        "design_space": design,
+        "paper_workload": paper,
     }
     progress("done")
     print(json.dumps(out), flush=True)
-    for p in plans:
-        sp.spmv_plan_destroy(p)
     return 0
 
 

@@ -63,6 +63,8 @@ def _load():
         P = ctypes.c_void_p
         lib.orc_csr_dot2.argtypes = [ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int]
         lib.orc_csr_dot2.restype = None
+        lib.orc_csr_plain.argtypes = [ctypes.c_int64, P, P, P, P, P, ctypes.c_int]
+        lib.orc_csr_plain.restype = None
         lib.orc_dot2.argtypes = [ctypes.c_int64, P, P]
         lib.orc_dot2.restype = ctypes.c_double
         lib.orc_num_threads.restype = ctypes.c_int
@@ -109,6 +111,22 @@ def spmv_dot2(row_ptr: np.ndarray, col_idx: np.ndarray, val: np.ndarray,
         _load().orc_csr_dot2(n, _ptr(row_ptr), _ptr(col_idx), _ptr(val), _ptr(x),
                              _ptr(y), _ptr(ax), int(dynamic))
     return y, ax
+
+
+def spmv_plain(row_ptr: np.ndarray, col_idx: np.ndarray, val: np.ndarray, x: np.ndarray,
+               dynamic: bool = False) -> np.ndarray:
+    """The plain (uncompensated) FP64 CSR product of a row block, OpenMP over
+    rows: the CPU throughput baseline, not a reference."""
+    row_ptr = np.ascontiguousarray(row_ptr, np.int32)
+    col_idx = np.ascontiguousarray(col_idx, np.int32)
+    val = np.ascontiguousarray(val, np.float64)
+    x = np.ascontiguousarray(x, np.float64)
+    n = row_ptr.size - 1
+    y = np.empty(max(n, 0), np.float64)
+    if n > 0:
+        _load().orc_csr_plain(n, _ptr(row_ptr), _ptr(col_idx), _ptr(val), _ptr(x), _ptr(y),
+                              int(dynamic))
+    return y
 
 
 # ---------------------------------------------------------------- partition

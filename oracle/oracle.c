@@ -113,6 +113,33 @@ void orc_csr_dot2(int64_t n_rows, const int32_t *row_ptr, const int32_t *col,
     }
 }
 
+/*
+ * The plain FP64 CSR product, y[i] = sum of fl(A[i,k] * x[k]) added left to
+ * right, no compensation: the ordinary CPU way to compute a row block, timed
+ * beside the oracle as the CPU throughput baseline (it is not a reference:
+ * its rounding is that of any plain summation).  Scheduling as in
+ * orc_csr_dot2.
+ */
+void orc_csr_plain(int64_t n_rows, const int32_t *row_ptr, const int32_t *col,
+                   const double *val, const double *x, double *y, int dynamic)
+{
+    if (dynamic) {
+#pragma omp parallel for schedule(dynamic, 1024)
+        for (int64_t i = 0; i < n_rows; ++i) {
+            double s = 0.0;
+            for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) s += val[k] * x[col[k]];
+            y[i] = s;
+        }
+    } else {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n_rows; ++i) {
+            double s = 0.0;
+            for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) s += val[k] * x[col[k]];
+            y[i] = s;
+        }
+    }
+}
+
 /* Dot2 of two dense vectors (used by the oracle's own self-tests). */
 double orc_dot2(int64_t n, const double *a, const double *b)
 {
