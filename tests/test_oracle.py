@@ -383,3 +383,50 @@ def test_plan_space_stream_canonical_and_valid():
                 if s not in seen:
                     assert s == len(seen)
                     seen.append(s)
+
+
+def test_power_law_share_model_matches_global_partition():
+    """The share-level power-law generator (used for the 64-share batch, where
+    building 64 global 4M-row matrices would not fit the run) against the
+    real partition of the global matrix of the same seed: both draw the same
+    row lengths, so every peer's total entries are equal, and the modelled
+    send-list sizes (a binomial count of hits in this rank's column block,
+    deduplicated) must match the send lists the split of the whole matrix
+    gives, peer by peer within 1% (the spread of a distinct count over
+    ~250,000 columns is ~0.2%); the halo size and the local / remote entry
+    counts within 1% too."""
+    import oracle
+    P, r, seed = 16, 5, 4000
+    A = gen.power_law(4_000_000, seed=seed)
+    g = oracle.split(A, P, r)
+    d = gen.power_law_share(4_000_000, P, r, seed=seed)
+    m = oracle.split_local(d["local"], d["n_global"], P, r, d["send_idx"], d["send_off"])
+    gs, ms = np.diff(g["send_off"]), np.diff(d["send_off"])
+    assert gs[r] == 0 and ms[r] == 0
+    others = [q for q in range(P) if q != r]
+    rel = np.abs(ms[others] - gs[others]) / gs[others]
+    assert rel.max() < 0.01, rel
+    assert abs(ms.sum() - gs.sum()) / gs.sum() < 0.005
+    assert abs(m["H"].size - g["H"].size) / g["H"].size < 0.01
+    nl_g, nl_m = g["L_val"].size, m["L_val"].size
+    nr_g, nr_m = g["R_val"].size, m["R_val"].size
+    assert nl_g + nr_g == nl_m + nr_m                 # same own row lengths
+    assert abs(nr_m - nr_g) / nr_g < 0.01
+
+
+def test_plain_csr_baseline_is_the_left_to_right_loop():
+    """The CPU throughput baseline (plain CSR loop) computes each row as the
+    products added left to right with no compensation: bit for bit what the
+    same loop in Python floats gives, under both OpenMP schedules."""
+    import oracle
+    A = gen.power_law(3000, mean_len=12.0, seed=8)
+    x = gen.x_normal(A.n_cols, 9)
+    want = np.empty(A.n_rows)
+    for i in range(A.n_rows):
+        s = 0.0
+        for k in range(A.row_ptr[i], A.row_ptr[i + 1]):
+            s += float(A.val[k]) * float(x[A.col_idx[k]])
+        want[i] = s
+    for dyn in (False, True):
+        got = oracle.spmv_plain(A.row_ptr, A.col_idx, A.val, x, dyn)
+        assert np.array_equal(got.view(np.int64), want.view(np.int64))
