@@ -288,86 +288,92 @@ def cpu_plain(A, P, r, x, bytes_per_step: float, dynamic: bool, budget_s: float 
 
 def batched_section(sp, torch, gen, n_shares: int, reps: int) -> dict:
     """64 power-law rank shares (4M rows, 16 ranks, rank 5, one seed each) in
-    one batch: grouped persistent kernels inside one hipGraph, against the
-    same shares run one spmv_exec after another."""
-    plans, xs, ys = [], [], []
-    tune = {"kernel_local": 2, "kernel_remote": 2, "chunk_local": 8, "chunk_remote": 8, "width": 2,
-            "form": 1}
+    one batch: the shares' kernel variants searched on the batch's grouped
+    device phase over a sample of 8 shares, the batch options (copy streams,
+    pipeline chunks, grid, graph) searched over whole batches with the halo
+    staged, then the chosen batch timed against the same shares run one
+    spmv_exec after another."""
+    from paper_2203_02530_amd import tune as tuner
     t_gen = time.perf_counter()
+    shares, xs, ys = [], [], []
     for i in range(n_shares):
         d = gen.power_law_share(4_000_000, 16, 5, seed=4000 + i)
         x = gen.x_normal(d["n_global"], 4100 + i)
+        shares.append((d, x))
+    t_gen = time.perf_counter() - t_gen
+
+    def make_plan(i, tune):
+        d, x = shares[i]
         p = sp.spmv_plan_create_local(d["local"], d["n_global"], 16, 5, d["send_idx"],
                                       d["send_off"], tune=tune)
-        info = sp.spmv_plan_info(p)
         halo = sp.spmv_plan_get_i32(p, sp.SPMV_I32_HALO_COLS).astype(np.int64)
         sp.spmv_plan_inbox(p)[:] = x[halo]
-        lo, n = info["lo"], info["n_loc"]
-        plans.append(p)
+        return p
+    for d, x in shares:
+        lo, n = d["lo"], d["local"].n_rows
         xs.append(torch.from_numpy(np.ascontiguousarray(x[lo:lo + n])).cuda())
         ys.append(torch.empty(n, dtype=torch.float64, device="cuda"))
-    t_gen = time.perf_counter() - t_gen
     stream = torch.cuda.current_stream()
     out = {"workload": f"{n_shares} power-law rank shares: 4M rows, lognormal(16, 1.2) row "
                        f"lengths, 16 ranks, rank 5, seeds 4000..{4000 + n_shares - 1}"}
+    t0 = time.perf_counter()
+    kbest, kres = tuner.tune_batch_kernels(make_plan, min(8, n_shares), xs, ys, reps=3)
+    t_ktune = time.perf_counter() - t0
+    plans = []
     try:
-        full = sp.spmv_batch_create(plans, {"use_graph": 1})
-        full_st = sp.spmv_batch_create(plans, {"use_graph": 2})
-        by_cs = {k: sp.spmv_batch_create(plans, {"use_graph": 2, "copy_streams": k})
-                 for k in (2, 4)}
-        dev = sp.spmv_batch_create(plans, {"staging": 1})
-        try:
-            finfo = sp.spmv_batch_info(full)
+        plans = [make_plan(i, kbest) for i in range(n_shares)]
 
-            def timed(fn, k):
+        def timed(fn, k):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(k):
                 fn()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for _ in range(k):
-                    fn()
-                torch.cuda.synchronize()
-                return (time.perf_counter() - t0) / k
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / k
 
-            t_graph = timed(lambda: sp.spmv_batch_exec(full, xs, ys, stream), reps)
-            t_streams = timed(lambda: sp.spmv_batch_exec(full_st, xs, ys, stream), reps)
-            t_cs = {k: timed(lambda: sp.spmv_batch_exec(bk, xs, ys, stream), reps)
-                    for k, bk in by_cs.items()}
-            t_batch = min(t_graph, t_streams)
+        t0 = time.perf_counter()
+        tuned, tune_res = tuner.tune_batch(plans, xs, ys, reps=2)
+        t_btune = time.perf_counter() - t0
+        bt = sp.spmv_batch_create(plans, tuned)
+        dev = sp.spmv_batch_create(plans, {"staging": 1,
+                                           "persistent": tuned.get("persistent", 0),
+                                           "blocks_per_cu": tuned.get("blocks_per_cu", 0)})
+        try:
+            finfo = sp.spmv_batch_info(bt)
+            t_batch = timed(lambda: sp.spmv_batch_exec(bt, xs, ys, stream), reps)
             t_dev = timed(lambda: sp.spmv_batch_exec(dev, xs, ys, stream), reps * 4)
 
             def sequential():
                 for p, x_, y_ in zip(plans, xs, ys):
                     sp.spmv_exec(p, x_, y_, stream)
             t_seq = timed(sequential, max(1, reps // 2))
-            from paper_2203_02530_amd import tune as tuner
-            tuned, tune_res = tuner.tune_batch(plans, xs, ys, reps=2)
-            # the batch as the autotuner configures it, timed like the others
-            bt = sp.spmv_batch_create(plans, tuned)
-            try:
-                t_tuned = timed(lambda: sp.spmv_batch_exec(bt, xs, ys, stream), reps)
-            finally:
-                sp.spmv_batch_destroy(bt)
-            t_batch = min(t_batch, t_tuned)
         finally:
-            sp.spmv_batch_destroy(full)
-            sp.spmv_batch_destroy(full_st)
-            for bk in by_cs.values():
-                sp.spmv_batch_destroy(bk)
+            sp.spmv_batch_destroy(bt)
             sp.spmv_batch_destroy(dev)
+        infos = [sp.spmv_plan_info(p) for p in plans]
+        variants = {}
+        for inf in infos:
+            key = f"y_L {kernel_variant(inf, 'yL')}, y_R {kernel_variant(inf, 'yR')}"
+            variants[key] = variants.get(key, 0) + 1
         B = finfo["device_bytes"]
         out.update({
             "shares": n_shares, "work_items": finfo["n_items"], "grid": finfo["n_blocks"],
+            "chunks": finfo["n_chunks"], "persistent": finfo["persistent"],
             "ms_per_batch": round(t_batch * 1e3, 3),
-            "ms_per_batch_graph": round(t_graph * 1e3, 3),
-            "ms_per_batch_stream_launches": round(t_streams * 1e3, 3),
-            "ms_per_batch_by_copy_streams": {"1": round(t_streams * 1e3, 3),
-                                             **{str(k): round(v * 1e3, 3) for k, v in t_cs.items()}},
             "ms_per_batch_device_phase": round(t_dev * 1e3, 3),
             "ms_sequential_execs": round(t_seq * 1e3, 3),
             "speedup_vs_sequential": round(t_seq / t_batch, 3),
-            "autotuned": {"opts": tuned, "ms": round(t_tuned * 1e3, 3),
-                          "candidates": [{"opts": d["opts"], "ms": round(d["ms"], 3)}
-                                         for d in tune_res]},
+            "share_variants": variants,
+            "kernel_autotune": {"sample_shares": min(8, n_shares), "wall_s": round(t_ktune, 1),
+                                "best": kbest,
+                                "candidates": [{"tune": d["tune"],
+                                                "ms": None if d["ms"] is None else round(d["ms"], 3),
+                                                **({"forms": d["forms"]} if "forms" in d else {})}
+                                               for d in kres]},
+            "batch_autotune": {"opts": tuned, "wall_s": round(t_btune, 1),
+                               "candidates": [{"opts": d["opts"], "ms": round(d["ms"], 3)}
+                                              for d in tune_res]},
             "shares_per_s": round(n_shares / t_batch, 1),
             "device_bytes_per_batch": B,
             "device_phase_gbs": round(B / t_dev / 1e9, 1),
@@ -379,6 +385,52 @@ def batched_section(sp, torch, gen, n_shares: int, reps: int) -> dict:
         for p in plans:
             sp.spmv_plan_destroy(p)
     return out
+
+
+# the shares' kernel variant the batch autotuner picks on the power-law
+# shares (y_R in column slabs, windows of 1,024 entries, 2-wide loads)
+BATCH_TUNE = {"kernel_local": 2, "kernel_remote": 2, "chunk_local": 4, "chunk_remote": 4,
+              "width": 2, "form": 5}
+
+
+def batch_device_only(sp, torch, gen, n_shares: int, reps: int, opts: dict) -> dict:
+    """The device phase of the power-law batch alone (grouped kernels, no
+    staging), repeated: what a profiler run of the batch traces."""
+    plans, xs, ys = [], [], []
+    try:
+        for i in range(n_shares):
+            d = gen.power_law_share(4_000_000, 16, 5, seed=4000 + i)
+            x = gen.x_normal(d["n_global"], 4100 + i)
+            p = sp.spmv_plan_create_local(d["local"], d["n_global"], 16, 5, d["send_idx"],
+                                          d["send_off"], tune=BATCH_TUNE)
+            plans.append(p)
+            halo = sp.spmv_plan_get_i32(p, sp.SPMV_I32_HALO_COLS).astype(np.int64)
+            sp.spmv_plan_inbox(p)[:] = x[halo]
+            xs.append(torch.from_numpy(np.ascontiguousarray(x[d["lo"]:d["lo"] + d["local"].n_rows]))
+                      .cuda())
+            ys.append(torch.empty(d["local"].n_rows, dtype=torch.float64, device="cuda"))
+        progress("batch device phase")
+        b = sp.spmv_batch_create(plans, {**opts, "staging": 1})
+        try:
+            info = sp.spmv_batch_info(b)
+            stream = torch.cuda.current_stream()
+            sp.spmv_batch_exec(b, xs, ys, stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                sp.spmv_batch_exec(b, xs, ys, stream)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / reps * 1e3
+        finally:
+            sp.spmv_batch_destroy(b)
+    finally:
+        for p in plans:
+            sp.spmv_plan_destroy(p)
+    return {"batch_device_only": True, "shares": n_shares, "tune": BATCH_TUNE, "reps": reps,
+            "opts": opts, "ms": round(ms, 3), "chunks": info["n_chunks"],
+            "persistent": info["persistent"], "grid": info["n_blocks"],
+            "device_bytes": info["device_bytes"],
+            "gbs": round(info["device_bytes"] / (ms * 1e-3) / 1e9, 1)}
 
 
 def serving_section(sp, torch, gen, n_req: int, rate: float, n_mats: int) -> dict:
@@ -889,6 +941,11 @@ def main() -> int:
     ap.add_argument("--kernel-only", action="store_true",
                     help="only launch one op of the workload back-to-back and the copy probe "
                          "of known size (for hardware-counter runs), print their timings")
+    ap.add_argument("--batch-device-only", action="store_true",
+                    help="only run the device phase of the batch of --batch-shares power-law "
+                         "shares (no staging), --steps times (for profiler runs)")
+    ap.add_argument("--batch-opts", default="{}",
+                    help="batch options for --batch-device-only, as JSON")
     ap.add_argument("--op", default="", help="op for --kernel-only (pack, yL, unpack, yR; "
                                              "default: the one with the most bytes)")
     args = ap.parse_args()
@@ -909,6 +966,10 @@ def main() -> int:
     if args.kernel_only:
         out, _ = measure_share(sp, torch, gen, args.workload, args, sweep=False)
         print(json.dumps(out), flush=True)
+        return 0
+    if args.batch_device_only:
+        print(json.dumps(batch_device_only(sp, torch, gen, args.batch_shares, args.steps,
+                                           json.loads(args.batch_opts))), flush=True)
         return 0
 
     head, hctx = measure_share(sp, torch, gen, args.workload, args)

@@ -576,17 +576,19 @@ int spmv_mcts_run_seq(spmv_plan_t *const *plans, int32_t n_plans, const double *
 
 /*
  * A batch runs the SpMVs of many rank shares (plans, possibly of different
- * matrices and sizes) together: every GPU step of every share goes into one
- * of three grouped persistent kernels (Pack + y_L | Unpack | y_R), whose work
- * lists hold the stream-CSR tiles and gather ranges of all shares, balanced
- * over the blocks longest-first; the halo staging of all shares becomes
- * copies on one copy stream per direction (or copy nodes of a hipGraph).
- * The paper's host-blocking synchronisations (CER/CES before PostSend,
- * WaitRecv before y_R) become device-side dependencies: Pack+y_L -> send
- * copies; receive copies -> Unpack -> y_R; Pack+y_L -> y_R.  The whole batch
- * is three kernel launches and the copies (or one hipGraph launch), with
- * one host synchronisation at the end.  A share's y is bit-identical to
- * spmv_exec of its plan: the same tiles are summed by the same device code.
+ * matrices and sizes) together: every GPU step of every share goes into
+ * grouped persistent kernels whose work lists hold the stream-CSR tiles
+ * (column-slab tiles and slab sums included) and gather ranges of the
+ * shares, balanced over the blocks longest-first (a slab tile only on its
+ * slab's XCD, dealt in share order).  The shares are cut into chunks: per
+ * chunk one Pack and one y_L launch, then per chunk Unpack, y_R and the
+ * slab sums.  The halo staging becomes copies on the copy streams, chunk by
+ * chunk (or copy nodes of a hipGraph).  The paper's host-blocking
+ * synchronisations (CER/CES before PostSend, WaitRecv before y_R) become
+ * device-side dependencies: a chunk's Pack -> its send copies; a chunk's
+ * receive copies -> its Unpack -> its y_R; y_L -> y_R.  One host
+ * synchronisation at the end.  A share's y is bit-identical to spmv_exec
+ * of its plan: the same tiles are summed by the same device code.
  */
 typedef struct spmv_batch spmv_batch_t;   /* opaque */
 
@@ -597,8 +599,11 @@ typedef struct {
                                another and measured 1.3-1.5x slower; the
                                graph otherwise), 1 = hipGraph, 2 = stream
                                launches                                      */
-    int32_t xcd_affinity;   /* 0 = auto (on when >= 8 shares), 1 = on: the work
-                               of share s runs on XCD s mod 8, 2 = off        */
+    int32_t xcd_affinity;   /* 0 = auto (on when every chunk holds >= 8
+                               shares), 1 = on: the Pack, y_L, Unpack and
+                               packed y_R work of share s runs on XCD s mod 8
+                               (column-slab tiles always run on their slab's
+                               XCD), 2 = off                                 */
     int32_t staging;        /* 0 = halo staged through the plans' pinned
                                mailboxes (the program), 1 = device phase only
                                (no copies: for timing the grouped kernels;
@@ -610,17 +615,36 @@ typedef struct {
                                copies of one direction measured slower; the
                                graph chains each direction's copies too),
                                1..4                                           */
-    int32_t reserved[3];
+    int32_t chunks;         /* the shares cut into this many consecutive
+                               chunks (at most n): chunk c's send copies start
+                               once its Pack is done, its Unpack / y_R once
+                               its receive copies are in, so one chunk's
+                               device work runs under the copies of the
+                               others, and with XCD affinity a chunk of 8
+                               shares keeps one share's Pack and y_L per
+                               XCD; 0 = auto (n / 8 chunks, at least 1),
+                               1..256                                       */
+    int32_t persistent;     /* 0 = auto (2), 1 = persistent blocks: a fixed
+                               grid of 256 * blocks_per_cu blocks, each
+                               walking its own item list (assigned on the
+                               host longest-first, slab tiles dealt in share
+                               order), 2 = one block per work item, items
+                               that must run on XCD g placed at indices
+                               b with b % 8 == g (blocks_per_cu unused)      */
+    int32_t reserved[1];
 } spmv_batch_opts_t;
 
 typedef struct {
     int32_t n_shares;
-    int32_t n_blocks;        /* grid of each grouped kernel                 */
-    int64_t n_items[3];      /* work items: Pack+y_L, Unpack, y_R           */
+    int32_t n_blocks;        /* grid of each persistent grouped kernel      */
+    int64_t n_items[3];      /* work items: Pack+y_L, Unpack, y_R (column
+                                slab tiles and slab sums included)          */
     int64_t device_bytes;    /* algorithmic device bytes of one batch exec  */
     int64_t host_link_bytes; /* bytes staged over the host link, both ways  */
     int32_t chunk, width;    /* stream-CSR window and load width shared by all */
     int32_t use_graph, xcd_affinity, staging;
+    int32_t n_chunks;        /* pipeline chunks of shares                   */
+    int32_t persistent;      /* 1: persistent blocks; 0: one block per item  */
     int32_t reserved;
 } spmv_batch_info_t;
 
@@ -628,8 +652,9 @@ typedef struct {
  * Build a batch over `n` plans (borrowed: they must outlive the batch and are
  * not executed meanwhile).  Every plan must be a device plan whose y_L and
  * y_R use the stream-CSR kernel in packed tiles (y_L with 32- or 16-bit
- * columns, forms 1 and 4) with one common chunk and width (the lanes per
- * row may differ).  SPMV_EINVAL otherwise.
+ * columns, forms 1 and 4; y_R also in column slabs, form 5, with tiles of
+ * 256 / lanes rows) with one common chunk and width (the lanes per row may
+ * differ).  SPMV_EINVAL otherwise.
  */
 int spmv_batch_create(spmv_plan_t *const *plans, int32_t n, const spmv_batch_opts_t *opts,
                       spmv_batch_t **out);

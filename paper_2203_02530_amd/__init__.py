@@ -93,7 +93,8 @@ class spmv_tune_t(ctypes.Structure):
 class spmv_batch_opts_t(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("xcd_affinity", ctypes.c_int32), ("staging", ctypes.c_int32),
-                ("copy_streams", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("copy_streams", ctypes.c_int32), ("chunks", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class spmv_batch_info_t(ctypes.Structure):
@@ -102,6 +103,7 @@ class spmv_batch_info_t(ctypes.Structure):
                 ("host_link_bytes", ctypes.c_int64), ("chunk", ctypes.c_int32),
                 ("width", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("xcd_affinity", ctypes.c_int32), ("staging", ctypes.c_int32),
+                ("n_chunks", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
     def as_dict(self):

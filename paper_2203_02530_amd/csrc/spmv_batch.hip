@@ -1,15 +1,22 @@
-// Batches: the SpMVs of many rank shares in three grouped persistent
-// kernels inside one hipGraph.
+// Batches: the SpMVs of many rank shares in grouped persistent kernels,
+// with the halo staging pipelined per chunk of shares.
 //
-// Work items are the stream-CSR tiles of every share's y_L and y_R and the
-// gather ranges of every share's Pack and Unpack.  Each grouped kernel runs a
-// fixed grid (256 CUs x blocks_per_cu); every block walks its own list of
-// items, assigned on the host longest-first to the least-loaded block, and,
-// with XCD affinity, only to blocks of the XCD that owns the share (share s
-// -> XCD s mod 8) so the share's x stays in that XCD's L2.  The host-blocking
-// synchronisations of the single-share program become graph edges.
+// Work items are the stream-CSR tiles of every share's y_L and y_R (column
+// slabs included: a slab tile, then the sum of a row range's slab partial
+// sums) and the gather ranges of every share's Pack and Unpack.  Each
+// grouped kernel runs a fixed grid (256 CUs x blocks_per_cu); every block
+// walks its own list of items, assigned on the host longest-first to the
+// least-loaded block, and, with XCD affinity, only to blocks of the XCD that
+// owns the share (share s -> XCD s mod 8) so the share's x stays in that
+// XCD's L2; a slab tile always goes to its slab's XCD.  The shares are cut
+// into chunks: chunk c's Pack feeds chunk c's send copies while later chunks
+// pack, and chunk c's y_R runs as soon as chunk c's receive copies are in,
+// under the copies of the chunks after it.  The host-blocking
+// synchronisations of the single-share program become stream or graph
+// dependencies.
 #include <algorithm>
 #include <cstring>
+#include <deque>
 #include <functional>
 #include <numeric>
 #include <queue>
@@ -20,7 +27,12 @@
 namespace spmv {
 namespace {
 
-enum ItemKind : int32_t { kPack = 0, kLocal = 1, kUnpack = 2, kRemote = 3 };
+enum ItemKind : int32_t {
+    kPack = 0, kLocal = 1, kUnpack = 2, kRemote = 3,
+    kSlab = 4,      // tile a of column slab n of the share's y_R
+    kSlabSum = 5,   // y[rows[i]] += the 8 slab partial sums of row i, i in [a, a + n)
+    kNop = 6        // padding of the one-block-per-item form
+};
 
 // Device view of one share.
 struct ShareDev {
@@ -33,10 +45,16 @@ struct ShareDev {
     uint32_t L_nnz_alloc, R_nnz_alloc, n_loc, n_halo;
     int32_t L_lanes, R_lanes, fuse_unpack;
     int32_t L_col16;   // A_L columns as int16 offsets from each tile's first row
+    // y_R in column slabs: slab k's row pointer at R_rp + k * (n_rr + 1), its
+    // entries from slab_nnz[k], its tiles from slab_tile[k] of R_tile_row /
+    // R_tile_k; partial sums of slab k at slab_part + k * n_rr
+    double *slab_part;
+    int32_t n_rr;
+    int32_t slab_nnz[kSlabs + 1], slab_tile[kSlabs + 1];
 };
 
 struct Item {
-    int32_t kind, share, a, n;   // tile a, or gather range [a, a + n)
+    int32_t kind, share, a, n;   // tile a (of slab n), or a range [a, a + n)
 };
 
 template <int NPT, int VW, bool C16 = false>
@@ -52,6 +70,82 @@ __device__ __forceinline__ void tile_sl(int sl, const StreamArgs &A, int t, doub
     }
 }
 
+// One work item, by the whole block.  Contains barriers only in
+// block-uniform control flow.
+template <int NPT, int VW>
+__device__ __forceinline__ void run_item(const Item &it, const ShareDev *__restrict__ sh,
+                                         const double *const *__restrict__ xs,
+                                         double *const *__restrict__ ys, double *s_p,
+                                         int32_t *s_rp)
+{
+    const ShareDev &S = sh[it.share];
+    if (it.kind == kPack || it.kind == kUnpack) {
+        const double *src = it.kind == kPack ? xs[it.share] : S.recvbuf;
+        const int32_t *idx = it.kind == kPack ? S.send_idx : S.perm;
+        double *dst = it.kind == kPack ? S.sendbuf : S.xhalo;
+        for (int k = it.a + int(threadIdx.x); k < it.a + it.n; k += kBlock) dst[k] = src[idx[k]];
+    } else if (it.kind == kLocal) {
+        StreamArgs A;
+        A.tile_row = S.L_tile_row;
+        A.tile_k = S.L_tile_k;
+        A.rp = S.L_rp;
+        A.col = S.L_col;
+        A.rows = nullptr;
+        A.val = S.L_val;
+        A.x = xs[it.share];
+        A.out = ys[it.share];
+        A.acc = nullptr;
+        A.nnz_alloc = S.L_nnz_alloc;
+        A.n_x = S.n_loc;
+        if (S.L_col16)
+            tile_sl<NPT, VW, true>(S.L_lanes, A, it.a, s_p, s_rp);
+        else
+            tile_sl<NPT, VW, false>(S.L_lanes, A, it.a, s_p, s_rp);
+    } else if (it.kind == kRemote) {
+        StreamArgs A;
+        A.tile_row = S.R_tile_row;
+        A.tile_k = S.R_tile_k;
+        A.rp = S.R_rp;
+        A.col = S.R_col;
+        A.rows = S.R_rows;
+        A.val = S.R_val;
+        A.x = S.fuse_unpack ? S.recvbuf : S.xhalo;
+        A.out = nullptr;
+        A.acc = ys[it.share];
+        A.nnz_alloc = S.R_nnz_alloc;
+        A.n_x = S.n_halo;
+        tile_sl<NPT, VW>(S.R_lanes, A, it.a, s_p, s_rp);
+    } else if (it.kind == kSlab) {
+        // as k_csr_slabs: slab n's tile a, partial sums stored
+        const int k = it.n;
+        StreamArgs A;
+        A.tile_row = S.R_tile_row + S.slab_tile[k];
+        A.tile_k = S.R_tile_k + S.slab_tile[k];
+        A.rp = S.R_rp + int64_t(k) * (S.n_rr + 1);
+        A.col = S.R_col + S.slab_nnz[k];
+        A.rows = nullptr;
+        A.val = S.R_val + S.slab_nnz[k];
+        A.x = S.fuse_unpack ? S.recvbuf : S.xhalo;
+        A.out = S.slab_part + int64_t(k) * S.n_rr;
+        A.acc = nullptr;
+        A.nnz_alloc = S.R_nnz_alloc - uint32_t(S.slab_nnz[k]);
+        A.n_x = S.n_halo;
+        tile_sl<NPT, VW>(S.R_lanes, A, it.a, s_p, s_rp);
+    } else if (it.kind == kSlabSum) {
+        // as k_slab_sum adding into y: the partial sums in slab order
+        double *y = ys[it.share];
+        const int64_t n = S.n_rr;
+        for (int r = it.a + int(threadIdx.x); r < it.a + it.n; r += kBlock) {
+            double s = S.slab_part[r];
+#pragma unroll
+            for (int k = 1; k < kSlabs; ++k) s += S.slab_part[k * n + r];
+            y[S.R_rows[r]] += s;
+        }
+    }
+    // kNop: nothing
+}
+
+// Persistent form: block b walks its own item list.
 template <int NPT, int VW>
 __global__ __launch_bounds__(kBlock) void k_grouped(const ShareDev *__restrict__ sh,
                                                     const double *const *__restrict__ xs,
@@ -64,47 +158,25 @@ __global__ __launch_bounds__(kBlock) void k_grouped(const ShareDev *__restrict__
     const int b = int(blockIdx.x);
     const int i1 = blk_ptr[b + 1];
     for (int i = blk_ptr[b]; i < i1; ++i) {
-        const Item it = items[i];
-        const ShareDev &S = sh[it.share];
-        if (it.kind == kPack || it.kind == kUnpack) {
-            const double *src = it.kind == kPack ? xs[it.share] : S.recvbuf;
-            const int32_t *idx = it.kind == kPack ? S.send_idx : S.perm;
-            double *dst = it.kind == kPack ? S.sendbuf : S.xhalo;
-            for (int k = it.a + int(threadIdx.x); k < it.a + it.n; k += kBlock) dst[k] = src[idx[k]];
-        } else if (it.kind == kLocal) {
-            StreamArgs A;
-            A.tile_row = S.L_tile_row;
-            A.tile_k = S.L_tile_k;
-            A.rp = S.L_rp;
-            A.col = S.L_col;
-            A.rows = nullptr;
-            A.val = S.L_val;
-            A.x = xs[it.share];
-            A.out = ys[it.share];
-            A.acc = nullptr;
-            A.nnz_alloc = S.L_nnz_alloc;
-            A.n_x = S.n_loc;
-            if (S.L_col16)
-                tile_sl<NPT, VW, true>(S.L_lanes, A, it.a, s_p, s_rp);
-            else
-                tile_sl<NPT, VW, false>(S.L_lanes, A, it.a, s_p, s_rp);
-        } else {
-            StreamArgs A;
-            A.tile_row = S.R_tile_row;
-            A.tile_k = S.R_tile_k;
-            A.rp = S.R_rp;
-            A.col = S.R_col;
-            A.rows = S.R_rows;
-            A.val = S.R_val;
-            A.x = S.fuse_unpack ? S.recvbuf : S.xhalo;
-            A.out = nullptr;
-            A.acc = ys[it.share];
-            A.nnz_alloc = S.R_nnz_alloc;
-            A.n_x = S.n_halo;
-            tile_sl<NPT, VW>(S.R_lanes, A, it.a, s_p, s_rp);
-        }
+        run_item<NPT, VW>(items[i], sh, xs, ys, s_p, s_rp);
         __syncthreads();
     }
+}
+
+// One block per item: block b runs item b (blocks are dealt to the XCDs
+// round-robin, so the host places an item that must run on XCD g at an
+// index b with b % 8 == g, padding with kNop).  blk_ptr is not used.
+template <int NPT, int VW>
+__global__ __launch_bounds__(kBlock) void k_grouped_flat(const ShareDev *__restrict__ sh,
+                                                         const double *const *__restrict__ xs,
+                                                         double *const *__restrict__ ys,
+                                                         const Item *__restrict__ items,
+                                                         const int32_t *__restrict__ blk_ptr)
+{
+    (void)blk_ptr;
+    __shared__ double s_p[kBlock * NPT];
+    __shared__ int32_t s_rp[kBlock + 1];
+    run_item<NPT, VW>(items[blockIdx.x], sh, xs, ys, s_p, s_rp);
 }
 
 // Tile t of one request: y = A x over the request's matrix.
@@ -153,16 +225,16 @@ __global__ __launch_bounds__(kBlock) void k_serve(const ServeDev *__restrict__ d
 using GroupedFn = void (*)(const ShareDev *, const double *const *, double *const *, const Item *,
                            const int32_t *);
 
-GroupedFn grouped_fn(int npt, int vw)
+GroupedFn grouped_fn(int npt, int vw, bool flat)
 {
     if (vw == 2) {
-        if (npt == 4) return k_grouped<4, 2>;
-        if (npt == 8) return k_grouped<8, 2>;
-        if (npt == 16) return k_grouped<16, 2>;
+        if (npt == 4) return flat ? k_grouped_flat<4, 2> : k_grouped<4, 2>;
+        if (npt == 8) return flat ? k_grouped_flat<8, 2> : k_grouped<8, 2>;
+        if (npt == 16) return flat ? k_grouped_flat<16, 2> : k_grouped<16, 2>;
     } else if (vw == 4) {
-        if (npt == 4) return k_grouped<4, 4>;
-        if (npt == 8) return k_grouped<8, 4>;
-        if (npt == 16) return k_grouped<16, 4>;
+        if (npt == 4) return flat ? k_grouped_flat<4, 4> : k_grouped<4, 4>;
+        if (npt == 8) return flat ? k_grouped_flat<8, 4> : k_grouped<8, 4>;
+        if (npt == 16) return flat ? k_grouped_flat<16, 4> : k_grouped<16, 4>;
     }
     return nullptr;
 }
@@ -225,20 +297,36 @@ struct spmv_batch {
     int device = 0;
     GroupedFn fn = nullptr;
 
+    // Launch groups in issue order: per chunk c a Pack group; then y_L of
+    // every share; then per chunk Unpack, y_R (packed and slab tiles) and
+    // the slab sums.  Each group is one grouped launch over its items.
+    enum GroupKind : int32_t { gPack = 0, gLocal = 1, gUnpack = 2, gRemote = 3, gSlabSum = 4 };
+    struct Group {
+        int32_t kind, chunk;
+        int64_t n_items;      // entries of d_items (kNop padding included)
+        unsigned grid;        // blocks of its launch
+        Item *d_items;
+        int32_t *d_blk;
+    };
+    bool flat = false;        // one block per item instead of persistent blocks
+    std::vector<Group> groups;
+    int32_t n_chunks = 1;
+    std::vector<int32_t> chunk_lo;   // shares [chunk_lo[c], chunk_lo[c+1]) form chunk c
+
     void *arena = nullptr;
     size_t arena_bytes = 0;
     ShareDev *d_sh = nullptr;
     const double **d_x = nullptr;   // [n], then d_y right after (one table)
     double **d_y = nullptr;
-    Item *d_items[3] = {};
-    int32_t *d_blk[3] = {};
-    int64_t n_items[3] = {};
+    int64_t n_items[3] = {};        // totals: Pack + y_L, Unpack, y_R (incl. slab sums)
     void **h_xy = nullptr;          // pinned [2n]: x pointers then y pointers
 
     int32_t n_cs = 1;                                   // copy streams per direction
     hipStream_t cs_send_k[kCopyStreams] = {}, cs_recv_k[kCopyStreams] = {};
-    hipEvent_t ev_a = nullptr, ev_s = nullptr, ev_r = nullptr, ev_f = nullptr;
-    hipEvent_t ev_sk[kCopyStreams] = {}, ev_rk[kCopyStreams] = {};
+    hipEvent_t ev_f = nullptr;
+    std::vector<hipEvent_t> ev_pack;                    // [n_chunks]: chunk's Pack done
+    std::vector<hipEvent_t> ev_recv;                    // [n_chunks * n_cs]: chunk's copies in
+    hipEvent_t ev_sk[kCopyStreams] = {};                // each send stream drained
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int64_t dev_bytes = 0, link_bytes = 0;
@@ -252,41 +340,71 @@ void batch_release(spmv_batch *b)
     if (!b) return;
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    for (hipEvent_t e : {b->ev_a, b->ev_s, b->ev_r, b->ev_f})
+    if (b->ev_f) (void)hipEventDestroy(b->ev_f);
+    for (hipEvent_t e : b->ev_pack)
         if (e) (void)hipEventDestroy(e);
-    for (int k = 0; k < kCopyStreams; ++k) {
+    for (hipEvent_t e : b->ev_recv)
+        if (e) (void)hipEventDestroy(e);
+    for (int k = 0; k < kCopyStreams; ++k)
         if (b->ev_sk[k]) (void)hipEventDestroy(b->ev_sk[k]);
-        if (b->ev_rk[k]) (void)hipEventDestroy(b->ev_rk[k]);
-    }
     if (b->arena) (void)hipFree(b->arena);
     if (b->h_xy) (void)hipHostFree(b->h_xy);
     if (b->pool_held) pool_release(b->device);
     delete b;
 }
 
-// Longest-first assignment of items to blocks; with affinity, an item of
-// share s only goes to blocks b with b % 8 == s % 8.  Returns items grouped
-// by block and the per-block offsets.
-void assign(const std::vector<Item> &items, const std::vector<int64_t> &cost, int n_blocks,
-            bool aff, std::vector<Item> &out, std::vector<int32_t> &blk_ptr)
+// Assignment of items to blocks.  An item's XCD group g (0..7) restricts it
+// to blocks b with b % 8 == g (the XCD the hardware deals block b to); -1
+// lets it go to any block.  Items marked `ordered` are dealt round-robin in
+// their given order over their group's blocks, so every block walks them in
+// that order (column-slab tiles in share order: an XCD's blocks then work
+// on the slabs of one or two shares at a time, which fit its L2); the others
+// go longest-first to the least-loaded block.  Returns items grouped by
+// block and the per-block offsets.
+void assign(const std::vector<Item> &items, const std::vector<int64_t> &cost,
+            const std::vector<int8_t> &xcd, const std::vector<uint8_t> &ordered, int n_blocks,
+            std::vector<Item> &out, std::vector<int32_t> &blk_ptr)
 {
-    std::vector<size_t> order(items.size());
-    std::iota(order.begin(), order.end(), size_t(0));
+    std::vector<int64_t> load(size_t(n_blocks), 0);
+    std::vector<int32_t> owner(items.size(), -1);
+    std::vector<int64_t> cursor(size_t(kXcds) + 1, 0);
+    for (size_t i = 0; i < items.size(); ++i) {
+        if (!ordered[i]) continue;
+        const int g = xcd[i];
+        int32_t b;
+        if (g < 0) {
+            b = int32_t(cursor[size_t(kXcds)]++ % n_blocks);
+        } else {
+            const int64_t per = (n_blocks - g + kXcds - 1) / kXcds;   // blocks with b % 8 == g
+            b = int32_t(g + kXcds * (cursor[size_t(g)]++ % per));
+        }
+        owner[i] = b;
+        load[size_t(b)] += cost[i];
+    }
+    std::vector<size_t> order;
+    for (size_t i = 0; i < items.size(); ++i)
+        if (!ordered[i]) order.push_back(i);
     std::stable_sort(order.begin(), order.end(),
                      [&](size_t a, size_t b) { return cost[a] > cost[b]; });
     using Slot = std::pair<int64_t, int32_t>;   // (load, block)
-    const int groups = aff ? kXcds : 1;
-    std::vector<std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>>> heaps(
-        static_cast<size_t>(groups));
-    for (int32_t b = 0; b < n_blocks; ++b) heaps[size_t(aff ? b % kXcds : 0)].push({0, b});
-    std::vector<int32_t> owner(items.size());
+    using Heap = std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>>;
+    // one heap per XCD and one over every block; a block's entry is renewed
+    // in both whenever its load grows, and older entries (a smaller load
+    // than the block's current one: costs are positive) are dropped when met
+    std::vector<Heap> heaps(size_t(kXcds) + 1);
+    for (int32_t b = 0; b < n_blocks; ++b) {
+        heaps[size_t(b % kXcds)].push({load[size_t(b)], b});
+        heaps[size_t(kXcds)].push({load[size_t(b)], b});
+    }
     for (size_t i : order) {
-        auto &h = heaps[size_t(aff ? items[i].share % kXcds : 0)];
-        Slot s = h.top();
+        Heap &h = heaps[size_t(xcd[i] < 0 ? kXcds : xcd[i])];
+        while (h.top().first != load[size_t(h.top().second)]) h.pop();
+        const int32_t b = h.top().second;
         h.pop();
-        owner[i] = s.second;
-        s.first += cost[i];
-        h.push(s);
+        owner[i] = b;
+        load[size_t(b)] += cost[i];
+        heaps[size_t(b % kXcds)].push({load[size_t(b)], b});
+        heaps[size_t(kXcds)].push({load[size_t(b)], b});
     }
     blk_ptr.assign(size_t(n_blocks) + 1, 0);
     for (size_t i = 0; i < items.size(); ++i) ++blk_ptr[size_t(owner[i]) + 1];
@@ -296,112 +414,186 @@ void assign(const std::vector<Item> &items, const std::vector<int64_t> &cost, in
     for (size_t i = 0; i < items.size(); ++i) out[size_t(fill[size_t(owner[i])]++)] = items[i];
 }
 
+// One block per item: slot i of the list runs on XCD i % 8, so an item that
+// must run on XCD g takes the next free slot of that residue (in its given
+// order), items without a group fill the other slots, and slots left over
+// before the last item hold kNop.
+void interleave(const std::vector<Item> &items, const std::vector<int8_t> &xcd,
+                std::vector<Item> &out)
+{
+    std::deque<size_t> q[kXcds + 1];
+    for (size_t i = 0; i < items.size(); ++i) q[xcd[i] < 0 ? kXcds : xcd[i]].push_back(i);
+    out.clear();
+    size_t left = items.size();
+    for (size_t slot = 0; left > 0; ++slot) {
+        std::deque<size_t> &mine = q[slot % kXcds];
+        std::deque<size_t> &any = q[kXcds];
+        std::deque<size_t> *from = !mine.empty() ? &mine : !any.empty() ? &any : nullptr;
+        if (from) {
+            out.push_back(items[from->front()]);
+            from->pop_front();
+            --left;
+        } else {
+            out.push_back({kNop, 0, 0, 0});
+        }
+    }
+}
+
 int64_t tile_cost(const std::vector<int32_t> &tk, size_t t) { return int64_t(tk[t + 1] - tk[t]) + 64; }
 
-// One batch on stream s: the pointer table, the receive copies (forked
-// onto the copy streams right away: they need nothing from this batch),
-// Pack + y_L, the send copies behind it, Unpack once every receive copy is
-// in, y_R, and the join of the send copies (stream launches).
+hipError_t launch_group(const spmv_batch *b, const spmv_batch::Group &g, hipStream_t s)
+{
+    if (g.n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(b->fn, dim3(g.grid), dim3(kBlock), 0, s, b->d_sh, b->d_x, b->d_y,
+                       g.d_items, g.d_blk);
+    return hipGetLastError();
+}
+
+// One batch on stream s (stream launches): the pointer table; every
+// receive copy, chunk by chunk, on the copy streams (they need nothing from
+// this batch); per chunk its Pack, then its send copies behind it; y_L of
+// every share; per chunk, once its receive copies are in, its Unpack, y_R
+// and slab sums; then the join of the send copies.
 int issue(spmv_batch *b, hipStream_t s)
 {
-    auto launch = [&](int ph) -> hipError_t {
-        if (b->n_items[ph] == 0) return hipSuccess;
-        hipLaunchKernelGGL(b->fn, dim3(unsigned(b->n_blocks)), dim3(kBlock), 0, s, b->d_sh,
-                           b->d_x, b->d_y, b->d_items[ph], b->d_blk[ph]);
-        return hipGetLastError();
-    };
+    const int32_t K = b->n_cs, C = b->n_chunks;
     SPMV_HIP(hipMemcpyAsync(b->d_x, b->h_xy, size_t(2 * b->n) * sizeof(void *),
                             hipMemcpyHostToDevice, s));
     SPMV_HIP(hipEventRecord(b->ev_f, s));
-    for (int32_t k = 0; k < b->n_cs; ++k) SPMV_HIP(hipStreamWaitEvent(b->cs_recv_k[k], b->ev_f, 0));
-    // receive copies need nothing from this batch: issue them first, on
-    // n_cs streams, then Pack + y_L, then the send copies behind it
-    const int32_t K = b->n_cs;
-    if (b->staging) {
-        for (int32_t i = 0; i < b->n; ++i) {
-            const spmv_plan *p = b->plans[size_t(i)];
-            const size_t nh = p->share.halo.size() * 8;
-            if (nh)
-                SPMV_HIP(hipMemcpyAsync(p->d_recvbuf, p->h_inbox, nh, hipMemcpyHostToDevice,
-                                        b->cs_recv_k[i % K]));
-        }
+    for (int32_t k = 0; k < K; ++k) {
+        SPMV_HIP(hipStreamWaitEvent(b->cs_recv_k[k], b->ev_f, 0));
+        SPMV_HIP(hipStreamWaitEvent(b->cs_send_k[k], b->ev_f, 0));
     }
-    SPMV_HIP(launch(0));
-    SPMV_HIP(hipEventRecord(b->ev_a, s));
-    for (int32_t k = 0; k < K; ++k) SPMV_HIP(hipStreamWaitEvent(b->cs_send_k[k], b->ev_a, 0));
-    if (b->staging) {
-        for (int32_t i = 0; i < b->n; ++i) {
-            const spmv_plan *p = b->plans[size_t(i)];
-            const size_t ns = p->share.send_idx.size() * 8;
-            if (ns)
-                SPMV_HIP(hipMemcpyAsync(p->h_outbox, p->d_sendbuf, ns, hipMemcpyDeviceToHost,
-                                        b->cs_send_k[i % K]));
+    for (int32_t c = 0; c < C; ++c) {
+        if (b->staging)
+            for (int32_t i = b->chunk_lo[size_t(c)]; i < b->chunk_lo[size_t(c) + 1]; ++i) {
+                const spmv_plan *p = b->plans[size_t(i)];
+                const size_t nh = p->share.halo.size() * 8;
+                if (nh)
+                    SPMV_HIP(hipMemcpyAsync(p->d_recvbuf, p->h_inbox, nh, hipMemcpyHostToDevice,
+                                            b->cs_recv_k[i % K]));
+            }
+        for (int32_t k = 0; k < K; ++k)
+            SPMV_HIP(hipEventRecord(b->ev_recv[size_t(c * K + k)], b->cs_recv_k[k]));
+    }
+    for (const auto &g : b->groups) {
+        if (g.kind == spmv_batch::gLocal) SPMV_HIP(launch_group(b, g, s));
+        if (g.kind != spmv_batch::gPack) continue;
+        SPMV_HIP(launch_group(b, g, s));
+        SPMV_HIP(hipEventRecord(b->ev_pack[size_t(g.chunk)], s));
+        for (int32_t k = 0; k < K; ++k)
+            SPMV_HIP(hipStreamWaitEvent(b->cs_send_k[k], b->ev_pack[size_t(g.chunk)], 0));
+        if (b->staging)
+            for (int32_t i = b->chunk_lo[size_t(g.chunk)]; i < b->chunk_lo[size_t(g.chunk) + 1];
+                 ++i) {
+                const spmv_plan *p = b->plans[size_t(i)];
+                const size_t ns = p->share.send_idx.size() * 8;
+                if (ns)
+                    SPMV_HIP(hipMemcpyAsync(p->h_outbox, p->d_sendbuf, ns, hipMemcpyDeviceToHost,
+                                            b->cs_send_k[i % K]));
+            }
+    }
+    int32_t waited = -1;
+    for (const auto &g : b->groups) {
+        if (g.kind == spmv_batch::gPack || g.kind == spmv_batch::gLocal) continue;
+        if (g.chunk > waited) {
+            for (int32_t k = 0; k < K; ++k)
+                SPMV_HIP(hipStreamWaitEvent(s, b->ev_recv[size_t(g.chunk * K + k)], 0));
+            waited = g.chunk;
         }
+        SPMV_HIP(launch_group(b, g, s));
     }
     for (int32_t k = 0; k < K; ++k) {
         SPMV_HIP(hipEventRecord(b->ev_sk[k], b->cs_send_k[k]));
-        SPMV_HIP(hipEventRecord(b->ev_rk[k], b->cs_recv_k[k]));
-        SPMV_HIP(hipStreamWaitEvent(s, b->ev_rk[k], 0));
+        SPMV_HIP(hipStreamWaitEvent(s, b->ev_sk[k], 0));
     }
-    SPMV_HIP(launch(1));
-    SPMV_HIP(launch(2));
-    for (int32_t k = 0; k < K; ++k) SPMV_HIP(hipStreamWaitEvent(s, b->ev_sk[k], 0));
     return SPMV_OK;
 }
 
+// The same schedule as one graph: each direction's copies form one chain
+// (concurrent copies of one direction share the host link), the groups
+// follow stream order, and chunk c's first y_R-side group also waits for the
+// receive copy that closes chunk c.
 int build_graph(spmv_batch *b)
 {
     SPMV_HIP(hipGraphCreate(&b->graph, 0));
     hipGraphNode_t n_t;
     SPMV_HIP(hipGraphAddMemcpyNode1D(&n_t, b->graph, nullptr, 0, b->d_x, b->h_xy,
                                      size_t(2 * b->n) * sizeof(void *), hipMemcpyHostToDevice));
-    auto kernel_node = [&](int phase, const hipGraphNode_t *deps, size_t nd,
+    auto kernel_node = [&](const spmv_batch::Group &g, const std::vector<hipGraphNode_t> &deps,
                            hipGraphNode_t *node) -> int {
         hipKernelNodeParams kp{};
-        void *args[] = {&b->d_sh, &b->d_x, &b->d_y, &b->d_items[phase], &b->d_blk[phase]};
+        Item *items = g.d_items;
+        int32_t *blk = g.d_blk;
+        void *args[] = {&b->d_sh, &b->d_x, &b->d_y, &items, &blk};
         kp.func = reinterpret_cast<void *>(b->fn);
-        kp.gridDim = dim3(unsigned(b->n_blocks));
+        kp.gridDim = dim3(g.grid);
         kp.blockDim = dim3(kBlock);
         kp.sharedMemBytes = 0;
         kp.kernelParams = args;
         kp.extra = nullptr;
-        SPMV_HIP(hipGraphAddKernelNode(node, b->graph, deps, nd, &kp));
+        SPMV_HIP(hipGraphAddKernelNode(node, b->graph, deps.data(), deps.size(), &kp));
         return SPMV_OK;
     };
-    hipGraphNode_t n_a = nullptr, n_b = nullptr, n_c = nullptr;
-    if (int rc = kernel_node(0, &n_t, 1, &n_a)) return rc;
-    // the copies of each direction form one chain: concurrent copies of one
-    // direction share the host link and measured slower (64 power-law
-    // shares: 31.7 ms per batch with one copy stream per direction, 40.9
-    // with two, 49.4 with four)
-    std::vector<hipGraphNode_t> recv;
-    hipGraphNode_t prev_send = n_a, prev_recv = nullptr;
-    for (spmv_plan *p : b->staging ? b->plans : std::vector<spmv_plan *>{}) {
-        const size_t ns = p->share.send_idx.size() * 8, nh = p->share.halo.size() * 8;
-        if (ns) {
-            hipGraphNode_t n;
-            SPMV_HIP(hipGraphAddMemcpyNode1D(&n, b->graph, &prev_send, 1, p->h_outbox,
-                                             p->d_sendbuf, ns, hipMemcpyDeviceToHost));
-            prev_send = n;
+    // receive chain, the node closing each chunk
+    std::vector<hipGraphNode_t> recv_done(size_t(b->n_chunks), nullptr);
+    hipGraphNode_t prev_recv = n_t;
+    for (int32_t c = 0; c < b->n_chunks; ++c) {
+        if (b->staging)
+            for (int32_t i = b->chunk_lo[size_t(c)]; i < b->chunk_lo[size_t(c) + 1]; ++i) {
+                const spmv_plan *p = b->plans[size_t(i)];
+                const size_t nh = p->share.halo.size() * 8;
+                if (!nh) continue;
+                hipGraphNode_t nd;
+                SPMV_HIP(hipGraphAddMemcpyNode1D(&nd, b->graph, &prev_recv, 1, p->d_recvbuf,
+                                                 p->h_inbox, nh, hipMemcpyHostToDevice));
+                prev_recv = nd;
+            }
+        recv_done[size_t(c)] = prev_recv;
+    }
+    hipGraphNode_t prev_k = n_t, prev_send = n_t;
+    int32_t waited = -1;
+    for (const auto &g : b->groups) {
+        if (g.n_items == 0 && g.kind != spmv_batch::gPack) continue;
+        std::vector<hipGraphNode_t> deps{prev_k};
+        if (g.kind != spmv_batch::gPack && g.kind != spmv_batch::gLocal && g.chunk > waited) {
+            deps.push_back(recv_done[size_t(g.chunk)]);
+            waited = g.chunk;
         }
-        if (nh) {
-            hipGraphNode_t n;
-            SPMV_HIP(hipGraphAddMemcpyNode1D(&n, b->graph, prev_recv ? &prev_recv : nullptr,
-                                             prev_recv ? 1 : 0, p->d_recvbuf, p->h_inbox, nh,
-                                             hipMemcpyHostToDevice));
-            prev_recv = n;
+        hipGraphNode_t nd = nullptr;
+        if (g.n_items > 0) {
+            if (int rc = kernel_node(g, deps, &nd)) return rc;
+        } else {
+            SPMV_HIP(hipGraphAddEmptyNode(&nd, b->graph, deps.data(), deps.size()));
+        }
+        prev_k = nd;
+        if (g.kind == spmv_batch::gPack && b->staging) {
+            // the chunk's send copies after its Pack, chained behind earlier sends
+            for (int32_t i = b->chunk_lo[size_t(g.chunk)]; i < b->chunk_lo[size_t(g.chunk) + 1];
+                 ++i) {
+                const spmv_plan *p = b->plans[size_t(i)];
+                const size_t ns = p->share.send_idx.size() * 8;
+                if (!ns) continue;
+                hipGraphNode_t sd;
+                hipGraphNode_t sdeps[2] = {prev_send, nd};
+                SPMV_HIP(hipGraphAddMemcpyNode1D(&sd, b->graph, sdeps, 2, p->h_outbox,
+                                                 p->d_sendbuf, ns, hipMemcpyDeviceToHost));
+                prev_send = sd;
+            }
         }
     }
-    if (prev_recv) recv.push_back(prev_recv);
-    std::vector<hipGraphNode_t> deps_c{n_a};
-    if (b->n_items[1] > 0) {
-        if (int rc = kernel_node(1, recv.data(), recv.size(), &n_b)) return rc;
-        deps_c.push_back(n_b);
-    } else {
-        deps_c.insert(deps_c.end(), recv.begin(), recv.end());
+    if (waited < b->n_chunks - 1 && b->n_chunks > 0) {
+        // chunks without y_R work still join the receive chain
+        hipGraphNode_t nd;
+        hipGraphNode_t deps[2] = {prev_k, recv_done[size_t(b->n_chunks - 1)]};
+        SPMV_HIP(hipGraphAddEmptyNode(&nd, b->graph, deps, 2));
+        prev_k = nd;
     }
-    if (b->n_items[2] > 0)
-        if (int rc = kernel_node(2, deps_c.data(), deps_c.size(), &n_c)) return rc;
+    if (prev_send != n_t) {
+        hipGraphNode_t nd;
+        hipGraphNode_t deps[2] = {prev_k, prev_send};
+        SPMV_HIP(hipGraphAddEmptyNode(&nd, b->graph, deps, 2));
+    }
     SPMV_HIP(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
     return SPMV_OK;
 }
@@ -417,8 +609,9 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
     spmv_batch_opts_t o{};
     if (opts) o = *opts;
     if (o.blocks_per_cu < 0 || o.blocks_per_cu > 32 || o.use_graph < 0 || o.use_graph > 2 ||
+        o.persistent < 0 || o.persistent > 2 ||
         o.xcd_affinity < 0 || o.xcd_affinity > 2 || o.staging < 0 || o.staging > 1 ||
-        o.copy_streams < 0 || o.copy_streams > kCopyStreams)
+        o.copy_streams < 0 || o.copy_streams > kCopyStreams || o.chunks < 0 || o.chunks > 256)
         return set_error(SPMV_EINVAL, "batch option out of range");
     const int npt = plans[0] ? plans[0]->cfg[0].chunk : 0;
     const int vw = plans[0] ? plans[0]->cfg[0].width : 0;
@@ -428,13 +621,17 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
         if (p->host_only || p->device != plans[0]->device)
             return set_error(SPMV_EINVAL, "plan " + std::to_string(i) +
                                               " is host-only or on another device");
-        for (int side = 0; side < 2; ++side)
-            if (p->cfg[side].kernel != SPMV_KERNEL_STREAM || p->cfg[side].chunk != npt ||
-                p->cfg[side].width != vw ||
-                !(p->cfg[side].form == 1 || (side == 0 && p->cfg[side].form == 4)))
+        for (int side = 0; side < 2; ++side) {
+            const CsrCfg &c = p->cfg[side];
+            const bool form_ok = c.form == 1 || (side == 0 && c.form == 4) ||
+                                 (side == 1 && c.form == 5 && c.rows <= 1);
+            if (c.kernel != SPMV_KERNEL_STREAM || c.chunk != npt || c.width != vw || !form_ok)
                 return set_error(SPMV_EINVAL, "plan " + std::to_string(i) +
-                                                  ": batched shares need packed-tile stream-CSR "
-                                                  "products with one common chunk and width");
+                                                  ": batched shares need stream-CSR products "
+                                                  "in packed tiles (y_R also in column slabs "
+                                                  "of 256 / lanes rows per tile) with one "
+                                                  "common chunk and width");
+        }
     }
     const int dev = plans[0]->device;
     int cur_dev = 0;
@@ -447,25 +644,51 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
     b->npt = npt;
     b->vw = vw;
     b->device = dev;
-    b->fn = grouped_fn(npt, vw);
+    // automatic: one block per item (the persistent blocks pay a chain of
+    // dependent loads per item: item, share descriptor, tile bounds)
+    b->flat = o.persistent != 1;
+    b->fn = grouped_fn(npt, vw, b->flat);
     b->n_blocks = kCUs * (o.blocks_per_cu ? o.blocks_per_cu : 8);
     // automatic: stream launches when the halo is staged (the graph runs its
     // copy nodes one after another: 46 ms per batch of 64 power-law shares
     // against 31-37 ms with one copy stream per direction), the graph when
     // only the grouped kernels run
     b->use_graph = o.use_graph == 1 || (o.use_graph == 0 && o.staging == 1);
-    b->xcd_aff = o.xcd_affinity == 1 || (o.xcd_affinity == 0 && n >= kXcds);
     b->staging = o.staging == 0;
     b->n_cs = o.copy_streams ? o.copy_streams : 1;
+    // automatic chunks: one per 8 shares (y_R of a chunk overlaps the
+    // copies of later chunks, and with XCD affinity a chunk's Pack and y_L
+    // keep one share per XCD)
+    b->n_chunks = o.chunks ? std::min<int32_t>(o.chunks, n) : std::max<int32_t>(1, n / kXcds);
+    // automatic affinity: when every chunk holds at least one share per XCD
+    // (with fewer, the XCDs without a share would idle through that chunk's
+    // Pack and y_L)
+    b->xcd_aff = o.xcd_affinity == 1 || (o.xcd_affinity == 0 && n / b->n_chunks >= kXcds);
+    b->chunk_lo.resize(size_t(b->n_chunks) + 1);
+    for (int32_t c = 0; c <= b->n_chunks; ++c)
+        b->chunk_lo[size_t(c)] = int32_t(int64_t(c) * n / b->n_chunks);
 
     // descriptors and work items
     std::vector<ShareDev> sh(static_cast<size_t>(n));
-    std::vector<Item> items[3];
-    std::vector<int64_t> cost[3];
+    struct Work {
+        int32_t kind, chunk;
+        std::vector<Item> items;
+        std::vector<int64_t> cost;
+        std::vector<int8_t> xcd;
+        std::vector<uint8_t> ordered;
+    };
+    std::deque<Work> work;   // references stay valid while groups are added
+    auto add_group = [&](int32_t kind, int32_t chunk) -> Work & {
+        work.push_back({kind, chunk, {}, {}, {}, {}});
+        return work.back();
+    };
     const int gather_len = kBlock * npt;
+    const int C = b->n_chunks;
+    // per-share descriptors
     for (int32_t i = 0; i < n; ++i) {
         spmv_plan *p = plans[i];
         const Share &S = p->share;
+        const CsrCfg &cr = p->cfg[1];
         ShareDev &d = sh[size_t(i)];
         d.L_tile_row = p->d_tile_row[0];
         d.L_tile_k = p->d_tile_k[0];
@@ -474,7 +697,7 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
         d.L_val = p->dL_val;
         d.R_tile_row = p->d_tile_row[1];
         d.R_tile_k = p->d_tile_k[1];
-        d.R_rp = p->dR_ptr;
+        d.R_rp = cr.form == 5 ? p->d_sell_ptr[1] : p->dR_ptr;
         d.R_col = p->dR_col;
         d.R_rows = p->dR_rows;
         d.R_val = p->dR_val;
@@ -484,36 +707,21 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
         d.recvbuf = p->d_recvbuf;
         d.xhalo = p->d_xhalo;
         d.L_nnz_alloc = uint32_t(S.L_col.size() + kEntryPad);
-        d.R_nnz_alloc = uint32_t(S.R_col.size() + kEntryPad);
+        d.R_nnz_alloc = uint32_t((cr.form == 5 ? cr.slab_col.size() : S.R_col.size()) + kEntryPad);
         d.n_loc = uint32_t(S.n_loc);
         d.n_halo = uint32_t(S.halo.size());
         d.L_lanes = p->cfg[0].lanes;
-        d.R_lanes = p->cfg[1].lanes;
+        d.R_lanes = cr.lanes;
         d.fuse_unpack = p->fuse_unpack ? 1 : 0;
         d.L_col16 = p->cfg[0].form == 4 ? 1 : 0;
-        const int64_t n_send = int64_t(S.send_idx.size()), n_halo = int64_t(S.halo.size());
-        for (int64_t a = 0; a < n_send; a += gather_len) {
-            const int32_t len = int32_t(std::min<int64_t>(gather_len, n_send - a));
-            items[0].push_back({kPack, i, int32_t(a), len});
-            cost[0].push_back(len / 2 + 64);
-        }
-        const auto &tl = p->cfg[0].tile_k;
-        for (size_t t = 0; t + 1 < tl.size(); ++t) {
-            items[0].push_back({kLocal, i, int32_t(t), 0});
-            cost[0].push_back(tile_cost(tl, t));
-        }
-        if (!p->fuse_unpack)
-            for (int64_t a = 0; a < n_halo; a += gather_len) {
-                const int32_t len = int32_t(std::min<int64_t>(gather_len, n_halo - a));
-                items[1].push_back({kUnpack, i, int32_t(a), len});
-                cost[1].push_back(len / 2 + 64);
-            }
-        const auto &tr = p->cfg[1].tile_k;
-        for (size_t t = 0; t + 1 < tr.size(); ++t) {
-            items[2].push_back({kRemote, i, int32_t(t), 0});
-            cost[2].push_back(tile_cost(tr, t));
+        d.slab_part = p->d_slab_part;
+        d.n_rr = int32_t(S.R_rows.size());
+        for (int k = 0; k <= kSlabs; ++k) {
+            d.slab_nnz[k] = cr.form == 5 ? int32_t(cr.slab_nnz[k]) : 0;
+            d.slab_tile[k] = cr.form == 5 ? int32_t(cr.slab_tiles[k]) : 0;
         }
         // algorithmic bytes, as for one exec of the share
+        const int64_t n_send = int64_t(S.send_idx.size()), n_halo = int64_t(S.halo.size());
         const int64_t nl = int64_t(S.L_col.size()), nr = int64_t(S.R_col.size());
         const int64_t rr = int64_t(S.R_rows.size()), nloc = S.n_loc;
         b->dev_bytes += 20 * n_send + 12 * nl + 4 * (nloc + 1) + 16 * nloc +
@@ -521,11 +729,92 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
                         16 * rr;
         if (o.staging == 0) b->link_bytes += 8 * (n_send + n_halo);
     }
-    std::vector<Item> grouped[3];
-    std::vector<int32_t> blk[3];
-    for (int ph = 0; ph < 3; ++ph) {
-        assign(items[ph], cost[ph], b->n_blocks, b->xcd_aff, grouped[ph], blk[ph]);
-        b->n_items[ph] = int64_t(items[ph].size());
+    auto share_xcd = [&](int32_t i) -> int8_t { return b->xcd_aff ? int8_t(i % kXcds) : int8_t(-1); };
+    for (int32_t c = 0; c < C; ++c) {
+        Work &w = add_group(spmv_batch::gPack, c);
+        for (int32_t i = b->chunk_lo[size_t(c)]; i < b->chunk_lo[size_t(c) + 1]; ++i) {
+            const int64_t n_send = int64_t(plans[i]->share.send_idx.size());
+            for (int64_t a = 0; a < n_send; a += gather_len) {
+                const int32_t len = int32_t(std::min<int64_t>(gather_len, n_send - a));
+                w.items.push_back({kPack, i, int32_t(a), len});
+                w.cost.push_back(len / 2 + 64);
+                w.xcd.push_back(share_xcd(i));
+                w.ordered.push_back(0);
+            }
+        }
+        Work &wl = add_group(spmv_batch::gLocal, c);
+        for (int32_t i = b->chunk_lo[size_t(c)]; i < b->chunk_lo[size_t(c) + 1]; ++i) {
+            const auto &tl = plans[i]->cfg[0].tile_k;
+            for (size_t t = 0; t + 1 < tl.size(); ++t) {
+                wl.items.push_back({kLocal, i, int32_t(t), 0});
+                wl.cost.push_back(tile_cost(tl, t));
+                wl.xcd.push_back(share_xcd(i));
+                wl.ordered.push_back(0);
+            }
+        }
+    }
+    for (int32_t c = 0; c < C; ++c) {
+        Work &wu = add_group(spmv_batch::gUnpack, c);
+        for (int32_t i = b->chunk_lo[size_t(c)]; i < b->chunk_lo[size_t(c) + 1]; ++i) {
+            if (plans[i]->fuse_unpack) continue;
+            const int64_t n_halo = int64_t(plans[i]->share.halo.size());
+            for (int64_t a = 0; a < n_halo; a += gather_len) {
+                const int32_t len = int32_t(std::min<int64_t>(gather_len, n_halo - a));
+                wu.items.push_back({kUnpack, i, int32_t(a), len});
+                wu.cost.push_back(len / 2 + 64);
+                wu.xcd.push_back(share_xcd(i));
+                wu.ordered.push_back(0);
+            }
+        }
+        Work &wr = add_group(spmv_batch::gRemote, c);
+        for (int32_t i = b->chunk_lo[size_t(c)]; i < b->chunk_lo[size_t(c) + 1]; ++i) {
+            const CsrCfg &cr = plans[i]->cfg[1];
+            const auto &tr = cr.tile_k;
+            if (cr.form == 5) {
+                for (int k = 0; k < kSlabs; ++k)
+                    for (int64_t t = cr.slab_tiles[k]; t + 1 < cr.slab_tiles[k + 1]; ++t) {
+                        wr.items.push_back({kSlab, i, int32_t(t - cr.slab_tiles[k]), k});
+                        wr.cost.push_back(tile_cost(tr, size_t(t)));
+                        wr.xcd.push_back(int8_t(k));   // the slab's XCD
+                        wr.ordered.push_back(1);       // in share order
+                    }
+            } else {
+                for (size_t t = 0; t + 1 < tr.size(); ++t) {
+                    wr.items.push_back({kRemote, i, int32_t(t), 0});
+                    wr.cost.push_back(tile_cost(tr, t));
+                    wr.xcd.push_back(share_xcd(i));
+                    wr.ordered.push_back(0);
+                }
+            }
+        }
+        Work &ws = add_group(spmv_batch::gSlabSum, c);
+        for (int32_t i = b->chunk_lo[size_t(c)]; i < b->chunk_lo[size_t(c) + 1]; ++i) {
+            if (plans[i]->cfg[1].form != 5) continue;
+            const int64_t n_rr = int64_t(plans[i]->share.R_rows.size());
+            for (int64_t a = 0; a < n_rr; a += gather_len) {
+                const int32_t len = int32_t(std::min<int64_t>(gather_len, n_rr - a));
+                ws.items.push_back({kSlabSum, i, int32_t(a), len});
+                ws.cost.push_back(len + 64);
+                ws.xcd.push_back(share_xcd(i));
+                ws.ordered.push_back(0);
+            }
+        }
+    }
+    std::vector<std::vector<Item>> grouped(work.size());
+    std::vector<std::vector<int32_t>> blk(work.size());
+    for (size_t g = 0; g < work.size(); ++g) {
+        if (b->flat) {
+            interleave(work[g].items, work[g].xcd, grouped[g]);
+            blk[g].assign(1, 0);
+        } else {
+            assign(work[g].items, work[g].cost, work[g].xcd, work[g].ordered, b->n_blocks,
+                   grouped[g], blk[g]);
+        }
+        const int64_t ni = int64_t(work[g].items.size());
+        const int32_t kind = work[g].kind;
+        b->n_items[kind == spmv_batch::gPack || kind == spmv_batch::gLocal ? 0
+                   : kind == spmv_batch::gUnpack                          ? 1
+                                                                          : 2] += ni;
     }
 
     // one device arena: descriptors, pointer tables, items, block offsets
@@ -533,12 +822,12 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
     size_t off_sh = 0;
     size_t off_xy = off_sh + al(sh.size() * sizeof(ShareDev));
     size_t cur = off_xy + al(size_t(2 * n) * sizeof(void *));
-    size_t off_items[3], off_blk[3];
-    for (int ph = 0; ph < 3; ++ph) {
-        off_items[ph] = cur;
-        cur += al(std::max<size_t>(grouped[ph].size(), 1) * sizeof(Item));
-        off_blk[ph] = cur;
-        cur += al(blk[ph].size() * sizeof(int32_t));
+    std::vector<size_t> off_items(work.size()), off_blk(work.size());
+    for (size_t g = 0; g < work.size(); ++g) {
+        off_items[g] = cur;
+        cur += al(std::max<size_t>(grouped[g].size(), 1) * sizeof(Item));
+        off_blk[g] = cur;
+        cur += al(blk[g].size() * sizeof(int32_t));
     }
     int rc = SPMV_OK;
     auto fail = [&](int code) {
@@ -554,17 +843,24 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
     b->d_y = reinterpret_cast<double **>(base + off_xy + size_t(n) * sizeof(void *));
     e = hipMemcpy(b->d_sh, sh.data(), sh.size() * sizeof(ShareDev), hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(hip_error(e, "hipMemcpy(batch descriptors)"));
-    for (int ph = 0; ph < 3; ++ph) {
-        b->d_items[ph] = reinterpret_cast<Item *>(base + off_items[ph]);
-        b->d_blk[ph] = reinterpret_cast<int32_t *>(base + off_blk[ph]);
-        if (!grouped[ph].empty()) {
-            e = hipMemcpy(b->d_items[ph], grouped[ph].data(), grouped[ph].size() * sizeof(Item),
+    for (size_t g = 0; g < work.size(); ++g) {
+        spmv_batch::Group G;
+        G.kind = work[g].kind;
+        G.chunk = work[g].chunk;
+        G.n_items = int64_t(grouped[g].size());
+        G.grid = b->flat ? unsigned(std::max<size_t>(grouped[g].size(), 1))
+                         : unsigned(b->n_blocks);
+        G.d_items = reinterpret_cast<Item *>(base + off_items[g]);
+        G.d_blk = reinterpret_cast<int32_t *>(base + off_blk[g]);
+        if (!grouped[g].empty()) {
+            e = hipMemcpy(G.d_items, grouped[g].data(), grouped[g].size() * sizeof(Item),
                           hipMemcpyHostToDevice);
             if (e != hipSuccess) return fail(hip_error(e, "hipMemcpy(batch items)"));
         }
-        e = hipMemcpy(b->d_blk[ph], blk[ph].data(), blk[ph].size() * sizeof(int32_t),
+        e = hipMemcpy(G.d_blk, blk[g].data(), blk[g].size() * sizeof(int32_t),
                       hipMemcpyHostToDevice);
         if (e != hipSuccess) return fail(hip_error(e, "hipMemcpy(batch offsets)"));
+        b->groups.push_back(G);
     }
     e = hipHostMalloc((void **)&b->h_xy, size_t(2 * n) * sizeof(void *), hipHostMallocDefault);
     if (e != hipSuccess) return fail(hip_error(e, "hipHostMalloc(batch table)"));
@@ -577,15 +873,18 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
         b->cs_send_k[k] = send_k[k];
         b->cs_recv_k[k] = recv_k[k];
     }
-    for (hipEvent_t *ev : {&b->ev_a, &b->ev_s, &b->ev_r, &b->ev_f}) {
-        e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
-        if (e != hipSuccess) return fail(hip_error(e, "hipEventCreate(batch)"));
-    }
-    for (int k = 0; k < b->n_cs; ++k) {
-        for (hipEvent_t *ev : {&b->ev_sk[k], &b->ev_rk[k]}) {
-            e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+    e = hipEventCreateWithFlags(&b->ev_f, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(hip_error(e, "hipEventCreate(batch)"));
+    b->ev_pack.assign(size_t(C), nullptr);
+    b->ev_recv.assign(size_t(C) * size_t(b->n_cs), nullptr);
+    for (auto *v : {&b->ev_pack, &b->ev_recv})
+        for (hipEvent_t &ev : *v) {
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
             if (e != hipSuccess) return fail(hip_error(e, "hipEventCreate(batch)"));
         }
+    for (int k = 0; k < b->n_cs; ++k) {
+        e = hipEventCreateWithFlags(&b->ev_sk[k], hipEventDisableTiming);
+        if (e != hipSuccess) return fail(hip_error(e, "hipEventCreate(batch)"));
     }
     if (b->use_graph && (rc = build_graph(b))) return fail(rc);
     *out = b;
@@ -630,6 +929,8 @@ extern "C" int spmv_batch_info(const spmv_batch_t *b, spmv_batch_info_t *info)
     info->use_graph = b->use_graph ? 1 : 0;
     info->staging = b->staging ? 0 : 1;
     info->xcd_affinity = b->xcd_aff ? 1 : 0;
+    info->n_chunks = b->n_chunks;
+    info->persistent = b->flat ? 0 : 1;
     return SPMV_OK;
 }
 

@@ -13,9 +13,13 @@ Three searches, all timed on the device by the library itself:
   batch of loads; vector CSR: lanes per row, rows per lane group; for y_R
   also column slabs), timed with HIP events around back-to-back launches
   over cold replicas.
+* :func:`tune_batch_kernels` -- the kernel variants of a batch's shares
+  (window, load width, summing lanes of y_L and y_R, y_R in packed tiles or
+  column slabs), timed on the batch's grouped device phase over a sample
+  of its shares.
 * :func:`tune_batch` -- the options of a batch of shares (stream launches
-  or one graph, copy streams, persistent blocks per CU, XCD affinity),
-  timed over whole batches.
+  or one graph, copy streams, pipeline chunks, persistent blocks per CU,
+  XCD affinity), timed over whole batches.
 
 Results can be appended to a JSONL cache keyed by the matrix digest, so an
 interrupted sweep resumes where it stopped.
@@ -29,7 +33,7 @@ import os
 
 import numpy as np
 
-from . import (SPMV_OP_YL, SPMV_OP_YR, spmv_batch_create, spmv_batch_destroy, spmv_batch_exec,
+from . import (SPMV_OP_YL, SPMV_OP_YR, SpmvError, spmv_batch_create, spmv_batch_destroy, spmv_batch_exec,
                spmv_op_launch, spmv_plan_create, spmv_plan_destroy,
                spmv_plan_get_i32, spmv_plan_inbox, spmv_plan_info, spmv_plan_reorder,
                spmv_plan_space_count, spmv_plan_space_get, spmv_plan_time, SPMV_I32_HALO_COLS)
@@ -201,14 +205,29 @@ def tune_kernel(A, nranks: int, rank: int, x: np.ndarray, candidates=DEFAULT_CAN
 
 
 DEFAULT_BATCH_CANDIDATES = (
-    [{"use_graph": 2, "copy_streams": k, "blocks_per_cu": b} for k in (1, 2) for b in (4, 8, 16)] +
-    [{"use_graph": 1, "blocks_per_cu": b} for b in (8,)] +
-    [{"use_graph": 2, "copy_streams": 1, "blocks_per_cu": 8, "xcd_affinity": 2}])
+    [{"use_graph": 2, "copy_streams": 1, "chunks": c} for c in (1, 4, 8, 16)] +
+    [{"use_graph": 2, "copy_streams": 2, "chunks": c} for c in (1, 8)] +
+    [{"use_graph": 2, "copy_streams": 1, "chunks": 8, "persistent": 1, "blocks_per_cu": b}
+     for b in (4, 8)] +
+    [{"use_graph": 1, "chunks": c} for c in (1, 8)] +
+    [{"use_graph": 2, "copy_streams": 1, "chunks": 8, "xcd_affinity": 2}])
+
+# Kernel variants of a batch's shares: the window (entries per thread) and
+# load width every share of a batch has in common, the summing lanes of each
+# product, and y_R in packed tiles (form 4: y_L with 16-bit columns where
+# they fit) or in column slabs (form 5).
+DEFAULT_BATCH_KERNEL_CANDIDATES = (
+    [{"kernel_local": 2, "kernel_remote": 2, "chunk_local": c, "chunk_remote": c, "width": w,
+      "form": f} for c in (4, 8) for w in (2, 4) for f in (4, 5)] +
+    [{"kernel_local": 2, "kernel_remote": 2, "chunk_local": 8, "chunk_remote": 8, "width": 2,
+      "form": f, "lanes_local": ll, "lanes_remote": lr}
+     for f in (4, 5) for ll, lr in ((1, 1), (2, 2), (1, 4) if f == 4 else (1, 2))])
 
 
 def tune_batch(plans, xs, ys, candidates=DEFAULT_BATCH_CANDIDATES, reps: int = 3, log=None):
     """Search the batch options (stream launches or one graph, copy streams
-    per direction, persistent blocks per CU, XCD affinity) for a set of
+    per direction, pipeline chunks, persistent blocks or one block per item,
+    blocks per CU, XCD affinity) for a set of
     plans by timing whole batches (halo staging included).  Returns (best
     options, all results); every candidate computes the same bits."""
     import time
@@ -232,3 +251,49 @@ def tune_batch(plans, xs, ys, candidates=DEFAULT_BATCH_CANDIDATES, reps: int = 3
             log(json.dumps(results[-1]))
     best = min(results, key=lambda d: d["ms"])
     return best["opts"], results
+
+
+def tune_batch_kernels(make_plan, n_sample: int, xs, ys, candidates=DEFAULT_BATCH_KERNEL_CANDIDATES,
+                       reps: int = 3, log=None):
+    """Search the shares' kernel variants for a batch: for every candidate
+    tune, plans of the first n_sample shares (``make_plan(i, tune)``) are
+    built and their grouped device phase (the batch without staging) is
+    timed; candidates that cannot form a batch (a form the grouped kernels
+    do not run) are recorded as such.  Returns (best tune, all results)."""
+    import time
+    import torch
+    stream = torch.cuda.current_stream()
+    results = []
+    for tune in candidates:
+        plans = []
+        try:
+            plans = [make_plan(i, tune) for i in range(n_sample)]
+            b = spmv_batch_create(plans, {"staging": 1})
+        except SpmvError as e:
+            for p in plans:
+                spmv_plan_destroy(p)
+            results.append({"tune": dict(tune), "ms": None, "error": str(e)})
+            continue
+        try:
+            spmv_batch_exec(b, xs[:n_sample], ys[:n_sample], stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                spmv_batch_exec(b, xs[:n_sample], ys[:n_sample], stream)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / reps * 1e3
+            infos = [spmv_plan_info(p) for p in plans]
+        finally:
+            spmv_batch_destroy(b)
+            for p in plans:
+                spmv_plan_destroy(p)
+        results.append({"tune": dict(tune), "ms": ms,
+                        "forms": sorted({(i["form_local"], i["form_remote"]) for i in infos}),
+                        "lanes": sorted({(i["lanes_local"], i["lanes_remote"]) for i in infos})})
+        if log:
+            log(json.dumps(results[-1]))
+    ok = [d for d in results if d["ms"] is not None]
+    if not ok:
+        raise SpmvError(-1, "no candidate forms a batch")
+    best = min(ok, key=lambda d: d["ms"])
+    return best["tune"], results

@@ -1,7 +1,8 @@
-"""Batched execution: many rank shares in grouped persistent kernels inside
-one hipGraph.  Each share's y must be bit-identical to its own spmv_exec
-(same tiles, same device code), and within tolerance of the oracle; halo
-buffers bit-exact; every graph replay equal to the eager result."""
+"""Batched execution: many rank shares in grouped persistent kernels, as
+stream launches or one hipGraph, with the staging pipelined over chunks of
+shares.  Each share's y must be bit-identical to its own spmv_exec (same
+tiles, same device code), and within tolerance of the oracle; halo buffers
+bit-exact; every replay equal to the eager result."""
 import numpy as np
 import pytest
 
@@ -76,7 +77,15 @@ def _check(plans, ys, refs, solo):
                                   {"use_graph": 1, "xcd_affinity": 1, "blocks_per_cu": 2},
                                   {"use_graph": 2, "xcd_affinity": 2, "blocks_per_cu": 1},
                                   {"use_graph": 2, "copy_streams": 1},
-                                  {"use_graph": 2, "copy_streams": 3}])
+                                  {"use_graph": 2, "copy_streams": 3},
+                                  {"use_graph": 2, "chunks": 1},
+                                  {"use_graph": 2, "chunks": 3},
+                                  {"use_graph": 1, "chunks": 4},
+                                  {"use_graph": 2, "chunks": 9, "copy_streams": 2},
+                                  {"use_graph": 1, "chunks": 200},
+                                  {"use_graph": 2, "persistent": 1},
+                                  {"use_graph": 1, "persistent": 1, "chunks": 3},
+                                  {"use_graph": 2, "persistent": 2, "xcd_affinity": 1}])
 def test_batch_bit_identical_to_solo(opts):
     import torch
     log(f"batch opts {opts}")
@@ -87,6 +96,9 @@ def test_batch_bit_identical_to_solo(opts):
         try:
             info = sp.spmv_batch_info(b)
             assert info["n_shares"] == len(plans) and sum(info["n_items"]) > 0
+            want = min(opts.get("chunks", 0), len(plans)) or max(1, len(plans) // 8)
+            assert info["n_chunks"] == want, info
+            assert info["persistent"] == (1 if opts.get("persistent") == 1 else 0)
             for rep in range(3):
                 for y in ys:
                     if y is not None:
@@ -114,6 +126,48 @@ def test_batch_with_16bit_tiles(use_graph):
         b = sp.spmv_batch_create(plans, {"use_graph": use_graph})
         try:
             for rep in range(2):
+                for y in ys:
+                    if y is not None:
+                        y.fill_(float("nan"))
+                torch.cuda.synchronize()
+                sp.spmv_batch_exec(b, xs, ys, torch.cuda.current_stream())
+                _check(plans, ys, refs, solo)
+        finally:
+            sp.spmv_batch_destroy(b)
+    finally:
+        for p in plans:
+            sp.spmv_plan_destroy(p)
+
+
+@pytest.mark.parametrize("opts", [{"use_graph": 2}, {"use_graph": 1, "chunks": 3},
+                                  {"use_graph": 2, "chunks": 9, "xcd_affinity": 2},
+                                  {"use_graph": 2, "chunks": 2, "persistent": 1,
+                                   "blocks_per_cu": 1},
+                                  {"use_graph": 1, "persistent": 1, "xcd_affinity": 1}])
+def test_batch_with_column_slabs(opts):
+    """Shares whose y_R runs in column slabs (slab tiles on their slab's XCD,
+    then the slab sums) batched with shares in packed tiles: every share
+    bit-identical to its own exec, over repeated runs."""
+    import torch
+    log(f"batch with column slabs {opts}")
+    shares = _shares()
+    # form 5 leaves y_L automatic: the 7-point share would go sliced (not
+    # batchable), so it keeps packed tiles here
+    slab = {0, 2, 3, 7, 8}
+    plans, xs, ys, refs, solo = [], [], [], [], []
+    try:
+        for i, sh in enumerate(shares):
+            p_, x_, y_, r_, s_ = _setup([sh], tune={**TUNE, "form": 5} if i in slab else TUNE)
+            plans += p_
+            xs += x_
+            ys += y_
+            refs += r_
+            solo += s_
+        forms = [sp.spmv_plan_info(p)["form_remote"] for p in plans]
+        assert forms.count(5) >= 4 and 1 in forms, forms
+        b = sp.spmv_batch_create(plans, opts)
+        try:
+            for rep in range(3):
                 for y in ys:
                     if y is not None:
                         y.fill_(float("nan"))
@@ -184,26 +238,29 @@ def test_batch_rejects_mixed_configs():
             with pytest.raises(sp.SpmvError) as e:
                 sp.spmv_batch_create(bad)
             assert e.value.code == sp.SPMV_EINVAL
-        for opts in ({"copy_streams": 5}, {"copy_streams": -1}, {"use_graph": 3}):
+        for opts in ({"copy_streams": 5}, {"copy_streams": -1}, {"use_graph": 3},
+                     {"chunks": -1}, {"chunks": 257}, {"persistent": 3}):
             with pytest.raises(sp.SpmvError) as e:
                 sp.spmv_batch_create([p1], opts)
             assert e.value.code == sp.SPMV_EINVAL
     finally:
         for p in (p1, p2, p3, p4, p5, p6):
             sp.spmv_plan_destroy(p)
-    # y_R in column slabs cannot join a batch; the same share with y_R in
-    # packed tiles (and y_L in 16-bit tiles either way) can
+    # y_R in column slabs of 256 / lanes rows joins a batch, as does y_R in
+    # packed tiles (and y_L in 16-bit tiles either way); wide slab tiles
+    # (rows per thread > 1) do not
     B = gen.power_law(20000, seed=3)
     q4 = sp.spmv_plan_create(B, 4, 1, tune={**TUNE, "form": 4})
     q5 = sp.spmv_plan_create(B, 4, 1, tune={**TUNE, "form": 5})
+    qw = sp.spmv_plan_create(B, 4, 1, tune={**TUNE, "form": 5, "rows_remote": 4})
     try:
         i4, i5 = sp.spmv_plan_info(q4), sp.spmv_plan_info(q5)
         assert (i4["form_local"], i4["form_remote"]) == (4, 1)
         assert (i5["form_local"], i5["form_remote"]) == (4, 5)
-        sp.spmv_batch_destroy(sp.spmv_batch_create([q4]))
+        sp.spmv_batch_destroy(sp.spmv_batch_create([q4, q5]))
         with pytest.raises(sp.SpmvError) as e:
-            sp.spmv_batch_create([q5])
+            sp.spmv_batch_create([q4, qw])
         assert e.value.code == sp.SPMV_EINVAL
     finally:
-        sp.spmv_plan_destroy(q4)
-        sp.spmv_plan_destroy(q5)
+        for q in (q4, q5, qw):
+            sp.spmv_plan_destroy(q)
