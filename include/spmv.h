@@ -391,7 +391,8 @@ int spmv_plan_reorder(spmv_plan_t *plan, const int32_t *op_order, int32_t n_ops,
  * x[i % n_plans], y[i % n_plans], stream): with n_plans = 1 this is the
  * paper's protocol on one plan; with several replicas of one share (same
  * order and streams) the samples rotate over independent device copies,
- * which keeps the matrix out of the last-level cache between samples.
+ * which keeps the matrix out of the last-level cache between samples.  The
+ * call first waits for the whole device to go idle (hipDeviceSynchronize).
  */
 int spmv_plan_time(spmv_plan_t *const *plans, int32_t n_plans, const double *const *x,
                    double *const *y, void *stream, double t_measure, int32_t n_measure,

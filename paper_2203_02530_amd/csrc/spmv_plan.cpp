@@ -1014,6 +1014,14 @@ extern "C" int spmv_plan_time(spmv_plan_t *const *plans, int32_t n_plans, const 
     if (!plans || n_plans < 1 || !x || !y || !times || n_measure < 1 || !(t_measure > 0))
         return set_error(SPMV_EINVAL, "bad argument to spmv_plan_time");
     using clock = std::chrono::steady_clock;
+    for (int32_t j = 0; j < n_plans; ++j) {
+        if (!plans[j]) return set_error(SPMV_EINVAL, "plan is NULL");
+        if (plans[j]->host_only) return set_error(SPMV_ESTATE, "plan was created host-only");
+    }
+    // the measurements start from an idle device (this also ends a state in
+    // which the first send and receive copies of a process ran one after the
+    // other, until the first device-wide synchronisation after them)
+    SPMV_HIP(hipDeviceSynchronize());
     int64_t i = 0;
     for (int32_t m = 0; m < n_measure; ++m) {
         const auto t0 = clock::now();

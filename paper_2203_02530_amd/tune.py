@@ -95,7 +95,14 @@ def sweep_plans(A, nranks: int, rank: int, x: np.ndarray, n_streams: int = 2,
             ys.append(torch.empty(n, dtype=torch.float64, device="cuda"))
         stream = torch.cuda.current_stream()
         torch.cuda.synchronize()
-        spmv_plan_time(plans, xs, ys, stream, t_measure, 1)      # warm-up
+        # warm-up on both sides of a device-wide synchronisation: the first
+        # execs of a process ran their send and receive copies one after the
+        # other (the power-law share's step: 695 us instead of 441 us) until
+        # a device synchronisation followed them, and the first measurement
+        # after it is slow once more
+        spmv_plan_time(plans, xs, ys, stream, t_measure, 1)
+        torch.cuda.synchronize()
+        spmv_plan_time(plans, xs, ys, stream, t_measure, 2)
         fh = open(cache_path, "a") if cache_path else None
         try:
             for j, i in enumerate(idx):
