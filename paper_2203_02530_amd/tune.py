@@ -137,7 +137,9 @@ def sweep_summary(results) -> dict:
     t = np.array([d["t"] for d in results])
     i_best = int(np.argmin(t))
     i_worst = int(np.argmax(t))
+    pct = (0, 1, 5, 10, 25, 50, 75, 90, 95, 99, 100)
     return {"n_plans": int(t.size), "fastest_us": round(float(t[i_best]) * 1e6, 3),
+            "curve_us": {str(q): round(float(np.percentile(t, q)) * 1e6, 2) for q in pct},
             "slowest_us": round(float(t[i_worst]) * 1e6, 3),
             "median_us": round(float(np.median(t)) * 1e6, 3),
             "slowest_over_fastest": round(float(t[i_worst] / t[i_best]), 3),
