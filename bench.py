@@ -671,7 +671,8 @@ def stability_section(sp, A, P, r, x, replicas, ktune, first_res, repeats: int,
     return out
 
 
-def measure_share(sp, torch, gen, key: str, args, sweep: bool = True) -> tuple[dict, dict]:
+def measure_share(sp, torch, gen, key: str, args, sweep: bool = True,
+                  autotune: bool = False) -> tuple[dict, dict]:
     """One rank share: the plan (chosen by the cold sweep of every plan, or
     the default), timed steps, per-op event times and the host timeline of
     the chosen plan, each GPU op's duration over back-to-back launches, the
@@ -687,6 +688,19 @@ def measure_share(sp, torch, gen, key: str, args, sweep: bool = True) -> tuple[d
     ktune = {"lanes_local": args.lanes, "rows_local": args.rows, "kernel_local": args.kernel,
              "chunk_local": args.chunk, "form": args.form, "width": args.width}
     ctx = {"A": A, "P": P, "r": r, "x": x, "ktune": ktune, "res": None, "best": None}
+    tuned = None
+    if autotune:
+        # the y_L kernel variant chosen by the autotuner (stream forms, window,
+        # width, summing lanes, vector lanes and rows per group), timed over
+        # cold replicas; the sweep and every measurement below use it
+        progress(f"{key}: kernel autotuner")
+        t0 = time.perf_counter()
+        kbest, kres = tuner.tune_kernel(A, P, r, x, launches=200)
+        tuned = {"wall_s": round(time.perf_counter() - t0, 1), "best": kbest,
+                 "results": sorted(({"tune": d["tune"], "us": round(d["us"], 3)} for d in kres),
+                                   key=lambda d: d["us"])}
+        ktune = {**ktune, **kbest}
+        ctx["ktune"] = ktune
     ops = smap = None
     sweep_out = None
     if sweep and P > 1 and args.plan == "auto":
@@ -709,6 +723,8 @@ def measure_share(sp, torch, gen, key: str, args, sweep: bool = True) -> tuple[d
             "kernel_local": args.kernel, "chunk_local": args.chunk,
             "chunk_remote": args.chunk_remote, "xcd_remap": args.xcd_remap,
             "fuse_unpack": args.fuse_unpack, "form": args.form, "width": args.width}
+    if tuned:
+        tune.update(tuned["best"])
     ctx["ops"], ctx["smap"], ctx["tune"] = ops, smap, tune
 
     progress(f"{key}: timed steps")
@@ -844,6 +860,7 @@ def measure_share(sp, torch, gen, key: str, args, sweep: bool = True) -> tuple[d
         "host_timeline_us": [[name, round(float(t) / max(h_n, 1.0), 2)]
                              for name, t in zip(plan_order, h_us)],
         "plan_sweep": sweep_out, "plan_order": plan_order, "plan_streams": plan_streams,
+        "kernel_autotune": tuned,
     }
     ctx["info"] = info
     return out, ctx
@@ -880,7 +897,7 @@ def extra_summary(out: dict) -> dict:
             "value": out["value"], "device_phase": out["device_phase"],
             "hbm_probe": out["hbm_probe"],
             "kernel_us": out["kernel_us"], "plan_sweep": out["plan_sweep"],
-            "config": out["config"]}
+            "kernel_autotune": out["kernel_autotune"], "config": out["config"]}
 
 
 def paper_section(sp, torch, gen, tuner) -> dict:
@@ -1014,7 +1031,8 @@ def main() -> int:
     design = None
     if args.extras:
         for key in EXTRAS:
-            ex, ctx = measure_share(sp, torch, gen, key, args)
+            ex, ctx = measure_share(sp, torch, gen, key, args,
+                                    autotune=key == "stencil27_150_p8r3")
             extras[key] = extra_summary(ex)
             if key == "laplace3d_128_p4r1" and not args.no_rules and ctx["res"] is not None:
                 A, P, r, x = ctx["A"], ctx["P"], ctx["r"], ctx["x"]

@@ -693,14 +693,19 @@ def test_full_stencil27_150_p8_rank3():
     assert_share_parity(res, ref)
 
 
-def test_full_powerlaw_4m_p16_rank5_and_batch():
+@pytest.mark.parametrize("tune", [
+    {"kernel_local": 2, "kernel_remote": 2, "chunk_local": 8, "chunk_remote": 8, "width": 2,
+     "form": 1},
+    {"kernel_local": 2, "kernel_remote": 2, "chunk_local": 4, "chunk_remote": 4, "width": 2,
+     "form": 5}])
+def test_full_powerlaw_4m_p16_rank5_and_batch(tune):
     """The power-law 4M-row share (rank 5 of 16) at full size against the
     oracle's rank-local definition, every row checked, alone and in a batch
-    of two full shares in the batch launch configuration the benchmark
-    times (bit-identical to the solo execs)."""
+    of two full shares (bit-identical to the solo execs), with y_R in packed
+    tiles and in column slabs (the variant the batch autotuner picks for
+    the benchmark's 64-share batch), in the automatic batch options and in
+    persistent blocks."""
     import torch
-    tune = {"kernel_local": 2, "kernel_remote": 2, "chunk_local": 8, "chunk_remote": 8,
-            "width": 2, "form": 1}
     shares, plans, refs, xs, ys = [], [], [], [], []
     try:
         for seed in (4000, 4001):
@@ -714,19 +719,23 @@ def test_full_powerlaw_4m_p16_rank5_and_batch():
             plans.append(plan)
             res, _ = run_share(None, 16, 5, x, ref=ref, plan=plan)
             assert res["info"]["n_loc"] == 250_000
+            assert res["info"]["form_remote"] == tune["form"]
             assert_share_parity(res, ref)
             info = res["info"]
             lo, n = info["lo"], info["n_loc"]
             xs.append(torch.from_numpy(np.ascontiguousarray(x[lo:lo + n])).cuda())
             ys.append(torch.full((n,), float("nan"), dtype=torch.float64, device="cuda"))
             refs.append(res["y"])
-        b = sp.spmv_batch_create(plans)
-        try:
-            sp.spmv_batch_exec(b, xs, ys, torch.cuda.current_stream())
-            for y, solo in zip(ys, refs):
-                assert np.array_equal(bits(y.cpu().numpy()), bits(solo))
-        finally:
-            sp.spmv_batch_destroy(b)
+        for opts in ({}, {"persistent": 1}):
+            for y in ys:
+                y.fill_(float("nan"))
+            b = sp.spmv_batch_create(plans, opts)
+            try:
+                sp.spmv_batch_exec(b, xs, ys, torch.cuda.current_stream())
+                for y, solo in zip(ys, refs):
+                    assert np.array_equal(bits(y.cpu().numpy()), bits(solo)), opts
+            finally:
+                sp.spmv_batch_destroy(b)
     finally:
         for p in plans:
             sp.spmv_plan_destroy(p)
