@@ -221,6 +221,32 @@ def probe_ceiling(sp, torch, nbytes: int, launches: int = 200) -> dict:
             "read_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def gather_ceiling(sp, torch, n_gathers: int, window_doubles: int, launches: int = 200) -> dict:
+    """What the L2 and the MALL serve of random 8-byte gathers: the gather
+    probe making about n_gathers loads, each block inside its XCD's window
+    of window_doubles (the column-slab pattern; per_xcd) and over all 8
+    windows at once (a halo larger than the L2; whole)."""
+    per_block = sp.spmv_gathers_per_probe_block()
+    blocks = max(8, -(-n_gathers // per_block))
+    src = torch.ones(8 * window_doubles, dtype=torch.float64, device="cuda")
+    part = torch.empty(blocks, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.Stream()
+    out = {"gathers": blocks * per_block, "window_bytes": 8 * window_doubles}
+    for name, mode in (("per_xcd_us", 2), ("whole_us", 3)):
+        with torch.cuda.stream(stream):
+            for _ in range(20):
+                sp.spmv_hbm_probe(mode, src, part, src.numel() * 8, blocks, stream)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(launches):
+                sp.spmv_hbm_probe(mode, src, part, src.numel() * 8, blocks, stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        out[name] = round(e0.elapsed_time(e1) * 1e3 / launches, 3)
+    return out
+
+
 def host_cpu() -> dict:
     """The host's CPU model and logical core count."""
     model = "unknown"
@@ -805,6 +831,12 @@ def measure_share(sp, torch, gen, key: str, args, sweep: bool = True,
         tr = MEASURED_TRAFFIC.get((key, dom_variant))
         traffic, traffic_src = (tr if tr else (None, None))
         ceiling = probe_ceiling(sp, torch, traffic or LB[dom])
+        gathers = None
+        if dom == "yR" and info["form_remote"] == 5:
+            # y_R in column slabs: its x gathers against the gather probe
+            gathers = gather_ceiling(sp, torch, info["nnz_remote"],
+                                     -(-info["n_halo"] // 8))
+            gathers["kernel_over_per_xcd_gathers"] = round(kern_us[dom] / gathers["per_xcd_us"], 3)
         plan_order = [sp.spmv_op_name(int(t))
                       for t in sp.spmv_plan_get_i32(first, sp.SPMV_I32_OP_ORDER)]
         plan_streams = {sp.spmv_op_name(v): int(m) for v, m in enumerate(
@@ -839,6 +871,7 @@ def measure_share(sp, torch, gen, key: str, args, sweep: bool = True,
         "warm": {"kernel": dom, "avg_us": round(warm_us, 3),
                  "achieved": round(LB[dom] / (warm_us * 1e-6) / 1e9, 1),
                  "note": "one replica, launched back to back: its arrays stay in the MALL"},
+        "gather_probe": gathers,
         "hbm_probe": {**ceiling, "kernel_moved_over_probe": (
             round(traffic / (kern_us[dom] * 1e-6) / 1e9 / ceiling["read_gbs"], 3)
             if traffic else None)},
@@ -1079,6 +1112,7 @@ def main() -> int:
         "device_phase": head["device_phase"],
         "warm": head["warm"],
         "hbm_probe": head["hbm_probe"],
+        "gather_probe": head["gather_probe"],
         "gflops": head["gflops"],
         "kernel_us": head["kernel_us"],
         "kernel_bytes": head["kernel_bytes"],

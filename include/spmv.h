@@ -777,11 +777,20 @@ int64_t spmv_static_scratch_bytes(void);
  *   mode 0  read every byte of src once (16-byte loads) and write one partial
  *           sum per block to dst (device, >= `blocks` doubles)
  *   mode 1  copy `bytes` from src to dst (device, non-overlapping)
- * bytes: a multiple of 16; blocks: grid size, 0 = 2048.  Asynchronous on
- * `stream`; the caller times it (e.g. with events around repeated calls).
+ *   mode 2  gather: spmv_gathers_per_probe_block() random 8-byte loads per
+ *           block at hashed indices, block b inside window b mod 8 of src
+ *           (src cut into 8 equal windows of bytes / 64 doubles: the x
+ *           gathers of the column-slab remote product, each XCD's from its
+ *           own L2), one partial sum per block to dst
+ *   mode 3  the same gathers over all of src (a halo larger than the L2)
+ * bytes: a multiple of 16 (modes 2, 3: at most 2^32 - 1 doubles); blocks:
+ * grid size, 0 = 2048.  Asynchronous on `stream`; the caller times it (e.g.
+ * with events around repeated calls).
  */
 int spmv_hbm_probe(int32_t mode, const void *src, void *dst, int64_t bytes, int32_t blocks,
                    void *stream);
+/* Gathers one block of the gather probe (modes 2, 3) makes. */
+int64_t spmv_gathers_per_probe_block(void);
 
 /* ------------------------------------------------------------ misc */
 

@@ -207,6 +207,7 @@ _proto("spmv_fine_count", [_P, _I32, _P])
 _proto("spmv_plan_set_fine", [_P, _P, _P, _I32, _I32])
 _proto("spmv_fine_validate", [_P, _P, _P, _I32, _I32])
 _proto("spmv_hbm_probe", [_I32, _P, _P, _I64, _I32, _P])
+_proto("spmv_gathers_per_probe_block", [], _I64)
 _proto("spmv_batch_create", [_P, _I32, _P, _P])
 _proto("spmv_batch_exec", [_P, _P, _P, _P])
 _proto("spmv_batch_info", [_P, _P])
@@ -697,8 +698,20 @@ def spmv_op_name(op: int) -> str:
     return buf.value.decode()
 
 
+def spmv_gathers_per_probe_block() -> int:
+    return int(_lib.spmv_gathers_per_probe_block())
+
+
 def spmv_hbm_probe(mode: int, src, dst, nbytes: int, blocks: int = 0, stream=None) -> None:
-    """Launch the read (mode 0) or copy (mode 1) bandwidth probe."""
+    """Launch the read (mode 0), copy (mode 1) or gather (modes 2, 3) probe.
+    src and dst are contiguous CUDA tensors: src holds at least nbytes, dst
+    at least nbytes (copy) or one double per block (the others)."""
+    grid = blocks or 2048
+    for name, t, need in (("src", src, nbytes), ("dst", dst, nbytes if mode == 1 else 8 * grid)):
+        if not (hasattr(t, "is_cuda") and t.is_cuda and t.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous CUDA tensor")
+        if t.numel() * t.element_size() < need:
+            raise ValueError(f"{name} holds {t.numel() * t.element_size()} bytes, needs {need}")
     _check(_lib.spmv_hbm_probe(mode, _addr(src), _addr(dst), nbytes, blocks,
                                _stream_handle(stream)))
 
