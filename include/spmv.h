@@ -360,6 +360,27 @@ int spmv_plan_destroy(spmv_plan_t *plan);
 int spmv_exec(spmv_plan_t *plan, const double *x_local, double *y_local, void *stream);
 
 /*
+ * The share's device work alone, for a halo that is already in device
+ * memory (the receive buffer, spmv_plan_device_buffers: filled by an
+ * earlier spmv_exec, or written there by the caller, e.g. from a
+ * device-to-device exchange): Pack into the device send buffer, y_L,
+ * Unpack, y_R adding into y, launched in that order on `stream` and
+ * returning at once (asynchronous; no copies, no host waits, no other
+ * stream).  y has the bits spmv_exec gives for the same halo.  x_local,
+ * y_local as in spmv_exec.  The Sec. III-A product with its exchange taken
+ * out: what one rank's GPU computes once its halo has arrived.
+ */
+int spmv_exec_resident(spmv_plan_t *plan, const double *x_local, double *y_local, void *stream);
+
+/*
+ * Device addresses of the plan's send buffer (n_send doubles, written by
+ * Pack) and receive buffer (n_halo doubles, read by Unpack / y_R, in halo
+ * order), for callers that move the halo themselves.  Owned by the plan.
+ */
+int spmv_plan_device_buffers(const spmv_plan_t *plan, double **send_dev, int64_t *n_send,
+                             double **recv_dev, int64_t *n_halo);
+
+/*
  * Launch one GPU operation of the plan on `stream`, asynchronously: no
  * synchronisation token, no copy, no host wait.  For callers that compose
  * their own schedule (or capture one in a graph) and for kernel timing.

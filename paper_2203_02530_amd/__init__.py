@@ -180,6 +180,8 @@ _proto("spmv_plan_create_local", [_P, _I64, _I32, _I32, _P, _P, _P, _I32, _P, _I
 _proto("spmv_plan_destroy", [_P])
 _proto("spmv_exec", [_P, _P, _P, _P])
 _proto("spmv_exec_static", [_P, _P, _P, _P])
+_proto("spmv_exec_resident", [_P, _P, _P, _P])
+_proto("spmv_plan_device_buffers", [_P, _P, _P, _P, _P])
 _proto("spmv_static_scratch_bytes", [], _I64)
 _proto("spmv_plan_info", [_P, _P])
 _proto("spmv_op_launch", [_P, _I32, _P, _P, _P])
@@ -383,6 +385,23 @@ def spmv_exec_static(plan, x, y, stream=None) -> None:
     per-device scratch array (allocates nothing); same checks and results."""
     xa, ya = _plan_vecs(plan, x, y)
     _check(_lib.spmv_exec_static(plan, xa, ya, _stream_handle(stream)))
+
+
+def spmv_exec_resident(plan, x, y, stream=None) -> None:
+    """The share's device work (Pack, y_L, Unpack, y_R) on ``stream`` with
+    the halo already in the plan's device receive buffer; asynchronous."""
+    xa, ya = _plan_vecs(plan, x, y)
+    _check(_lib.spmv_exec_resident(plan, xa, ya, _stream_handle(stream)))
+
+
+def spmv_plan_device_buffers(plan) -> dict:
+    """Device addresses and lengths of the plan's send and receive buffers."""
+    sd, rd = ctypes.c_void_p(), ctypes.c_void_p()
+    ns, nh = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.spmv_plan_device_buffers(plan, ctypes.byref(sd), ctypes.byref(ns),
+                                         ctypes.byref(rd), ctypes.byref(nh)))
+    return {"send": sd.value or 0, "n_send": ns.value, "recv": rd.value or 0,
+            "n_halo": nh.value}
 
 
 def spmv_static_scratch_bytes() -> int:

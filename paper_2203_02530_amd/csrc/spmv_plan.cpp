@@ -917,6 +917,43 @@ extern "C" int spmv_exec(spmv_plan_t *p, const double *x, double *y, void *strea
     return SPMV_OK;
 }
 
+extern "C" int spmv_exec_resident(spmv_plan_t *p, const double *x, double *y, void *stream_v)
+{
+    if (!p) return set_error(SPMV_EINVAL, "plan is NULL");
+    if (p->host_only) return set_error(SPMV_ESTATE, "plan was created host-only");
+    const Share &S = p->share;
+    if (S.n_loc > 0 && (!x || !y)) return set_error(SPMV_EINVAL, "x or y is NULL");
+    if (x && y && x == y) return set_error(SPMV_EINVAL, "x and y alias");
+    hipStream_t s = static_cast<hipStream_t>(stream_v);
+    int dev = 0;
+    SPMV_HIP(hipGetDevice(&dev));
+    if (dev != p->device) SPMV_HIP(hipSetDevice(p->device));
+    // Pack, y_L, Unpack, y_R in the order of the DAG's GPU vertices, on one
+    // stream: y_R adds into what y_L stored, so y = fl(s_L + s_R) as in
+    // every plan of spmv_exec
+    SPMV_HIP(launch_pack(x, p->d_send_idx, p->d_sendbuf, int64_t(S.send_idx.size()), s));
+    SPMV_HIP(launch_product(p, 0, x, y, nullptr, s));
+    if (!p->fuse_unpack)
+        SPMV_HIP(launch_unpack(p->d_recvbuf, p->d_perm, p->d_xhalo, int64_t(S.halo.size()), s));
+    if (!S.R_rows.empty()) {
+        const double *xh = p->fuse_unpack ? p->d_recvbuf : p->d_xhalo;
+        SPMV_HIP(launch_product(p, 1, xh, nullptr, y, s));
+    }
+    return SPMV_OK;
+}
+
+extern "C" int spmv_plan_device_buffers(const spmv_plan_t *p, double **send_dev, int64_t *n_send,
+                                        double **recv_dev, int64_t *n_halo)
+{
+    if (!p) return set_error(SPMV_EINVAL, "plan is NULL");
+    if (p->host_only) return set_error(SPMV_ESTATE, "plan was created host-only");
+    if (send_dev) *send_dev = p->d_sendbuf;
+    if (n_send) *n_send = int64_t(p->share.send_idx.size());
+    if (recv_dev) *recv_dev = p->d_recvbuf;
+    if (n_halo) *n_halo = int64_t(p->share.halo.size());
+    return SPMV_OK;
+}
+
 extern "C" int spmv_op_launch(spmv_plan_t *p, int32_t op, const double *x, double *y,
                               void *stream_v)
 {

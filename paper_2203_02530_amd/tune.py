@@ -169,18 +169,21 @@ DEFAULT_REMOTE_CANDIDATES = (
 
 
 def tune_kernel(A, nranks: int, rank: int, x: np.ndarray, candidates=DEFAULT_CANDIDATES,
-                launches: int = 100, log=None, op: int = SPMV_OP_YL):
+                launches: int = 100, log=None, op: int = SPMV_OP_YL, margin: float = 0.02):
     """Search kernel variants for one product (y_L by default: both CSR
     kernels, stream chunk / width / summing lanes, vector lanes / rows; with
     op = SPMV_OP_YR and DEFAULT_REMOTE_CANDIDATES the forms of y_R) by timing
-    back-to-back launches of that op over cold replicas.  Returns (best tune
-    dict, all results)."""
+    back-to-back launches of that op over cold replicas.  The automatic
+    choice (an empty tune) is timed too and kept unless a candidate beats it
+    by more than ``margin``: rankings inside the timing noise would
+    otherwise trade it for a variant no faster.  Returns (best tune dict,
+    all results; the automatic choice as {})."""
     import torch
     if op not in (SPMV_OP_YL, SPMV_OP_YR):
         raise ValueError("tune_kernel times y_L or y_R")
     results = []
     stream = torch.cuda.Stream()
-    for tune in candidates:
+    for tune in [{}] + list(candidates):
         p0 = spmv_plan_create(A, nranks, rank, None, None, 2, tune)
         info = spmv_plan_info(p0)
         n = info["n_loc"]
@@ -210,6 +213,8 @@ def tune_kernel(A, nranks: int, rank: int, x: np.ndarray, candidates=DEFAULT_CAN
         if log:
             log(json.dumps(results[-1]))
     best = min(results, key=lambda d: d["us"])
+    if best["us"] > results[0]["us"] * (1.0 - margin):
+        best = results[0]
     return best["tune"], results
 
 

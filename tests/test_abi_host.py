@@ -257,6 +257,17 @@ def test_malformed_csr_rejected():
     assert e.value.code == sp.SPMV_EINVAL
 
 
+def test_host_only_plan_refuses_device_calls():
+    A = gen.laplacian_3d7(8)
+    p = sp.spmv_plan_create(A, 2, 1, tune=HOST_ONLY)
+    try:
+        for fn in (lambda: sp._lib.spmv_exec_resident(p, None, None, None),
+                   lambda: sp._lib.spmv_plan_device_buffers(p, None, None, None, None)):
+            assert fn() == sp.SPMV_ESTATE
+    finally:
+        sp.spmv_plan_destroy(p)
+
+
 def test_host_only_plan_refuses_exec():
     A = gen.laplacian_2d5(4)
     p = sp.spmv_plan_create(A, 1, 0, tune=HOST_ONLY)

@@ -542,9 +542,21 @@ def test_empty_share_and_empty_rows():
     assert res["info"]["form_remote"] == 5
 
 
+def check_tuner_choice(best, res, cands, margin=0.02):
+    assert [d["tune"] for d in res] == [{}] + list(cands)
+    assert all(d["us"] > 0 for d in res)
+    fastest = min(res, key=lambda d: d["us"])
+    if fastest["us"] <= res[0]["us"] * (1 - margin):
+        assert best == fastest["tune"]
+    else:
+        assert best == {}
+
+
 def test_kernel_autotuner():
-    """The kernel autotuner times every candidate and returns the fastest;
-    the tune it returns computes y within tolerance."""
+    """The kernel autotuner times the automatic choice and every candidate
+    and returns the fastest, keeping the automatic choice unless a
+    candidate beats it by more than the margin; the tune it returns
+    computes y within tolerance."""
     from paper_2203_02530_amd import tune as tuner
     A = gen.laplacian_3d7(48)
     P, r = 4, 1
@@ -555,9 +567,7 @@ def test_kernel_autotuner():
              {"kernel_local": 2, "form": 1, "chunk_local": 4, "width": 2},
              {"kernel_local": 1, "lanes_local": 8, "rows_local": 4}]
     best, res = tuner.tune_kernel(A, P, r, x, candidates=cands, launches=20)
-    assert [d["tune"] for d in res] == cands
-    assert all(d["us"] > 0 for d in res)
-    assert best == min(res, key=lambda d: d["us"])["tune"]
+    check_tuner_choice(best, res, cands)
     out, ref = run_share(A, P, r, x, tune=best)
     assert_share_parity(out, ref)
 
@@ -573,10 +583,8 @@ def test_remote_autotuner():
     x = gen.x_normal(A.n_cols, 82)
     cands = list(tuner.DEFAULT_REMOTE_CANDIDATES)
     best, res = tuner.tune_kernel(A, P, r, x, candidates=cands, launches=20, op=sp.SPMV_OP_YR)
-    assert [d["tune"] for d in res] == cands
-    assert all(d["us"] > 0 for d in res)
-    assert best == min(res, key=lambda d: d["us"])["tune"]
-    log("remote autotuner: " + ", ".join(f'{d["tune"]["form"]}/{d["tune"].get("lanes_remote", 0)}'
+    check_tuner_choice(best, res, cands)
+    log("remote autotuner: " + ", ".join(f'{d["tune"].get("form", "auto")}/{d["tune"].get("lanes_remote", 0)}'
                                           f' {d["us"]:.1f} us' for d in res))
     out, ref = run_share(A, P, r, x, tune=best)
     assert_share_parity(out, ref)
@@ -810,3 +818,38 @@ def test_full_paper_banded_150k_p4_rank1_sampled_plans():
             assert np.array_equal(bits(got["outbox"]), bits(ref["sendbuf"])), i
     finally:
         sp.spmv_plan_destroy(plan)
+
+
+def test_exec_resident_matches_exec():
+    """The device work alone (halo already in the receive buffer): the bits
+    of spmv_exec for the same halo, the send buffer exact, and no copy from
+    the inbox (a changed inbox does not reach y until the next spmv_exec)."""
+    import torch
+    cases = [(gen.power_law(30000, seed=17), 4, 2, 18, {}),
+             (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5}),
+             (gen.power_law(30000, seed=17), 4, 2, 18, {"fuse_unpack": 2}),
+             (gen.laplacian_3d7(24), 4, 1, 20, {}),
+             (gen.laplacian_2d5(40), 1, 0, 21, {})]
+    for A, P, r, seed, tune in cases:
+        log(f"exec_resident n={A.n_rows} P={P} r={r} {tune}")
+        x = gen.x_normal(A.n_cols, seed)
+        ref = oracle.share_reference(A, P, r, x)
+        res, _ = run_share(A, P, r, x, tune=tune, ref=ref, keep_plan=True)
+        plan = res.pop("plan")
+        try:
+            info = res["info"]
+            lo, n = info["lo"], info["n_loc"]
+            bufs = sp.spmv_plan_device_buffers(plan)
+            assert bufs["n_send"] == info["n_send"] and bufs["n_halo"] == info["n_halo"]
+            assert bufs["recv"] != 0 or info["n_halo"] == 0
+            xd = torch.from_numpy(np.ascontiguousarray(x[lo:lo + n])).cuda()
+            for rep in range(2):
+                yd = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+                sp.spmv_exec_resident(plan, xd, yd, torch.cuda.current_stream())
+                torch.cuda.synchronize()
+                assert np.array_equal(bits(yd.cpu().numpy()), bits(res["y"]))
+                assert np.array_equal(bits(sp.spmv_plan_get_f64(plan, sp.SPMV_F64_SENDBUF)),
+                                      bits(ref["sendbuf"]))
+                sp.spmv_plan_inbox(plan)[:] = 0.0     # not copied by the resident exec
+        finally:
+            sp.spmv_plan_destroy(plan)
