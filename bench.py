@@ -3,8 +3,9 @@
 
 One step = the whole device work of a rank share with every input (A, x and
 the halo the other ranks sent) resident in HBM: Pack, local product y_L,
-Unpack and remote product y_R accumulated into y (``spmv_exec_resident``),
-rotating over cold replicas.  The full program with the exchange emulated
+Unpack and remote product y_R accumulated into y (``spmv_exec_resident``;
+where y_R is in column slabs, Pack, y_L and the slab tiles as one grouped
+launch, then the slab sums), rotating over cold replicas.  The full program with the exchange emulated
 through pinned host memory (``spmv_exec``: the plan's order and streams,
 PostSend/PostRecv/Wait*, host-synchronous) is timed beside it and reported
 as the PCIe-inclusive rate; it is not the headline value.
@@ -23,8 +24,9 @@ rotate over the copies, so each step streams A from HBM.
 
 Printed: one JSON line with the metric ``rank-share SpMV GB/s`` (algorithmic
 device bytes of a step / wall time per step), the roofline of the headline
-share's dominant kernel (y_R, timed with HIP events on the stream it is
-launched on), the staged program's rate, the CPU oracle's rate on a bounded
+share's dominant kernel (the step's grouped launch, or its largest op;
+timed with HIP events on the stream it is launched on) and of its largest
+op alone (``op_roofline``: y_R), the staged program's rate, the CPU oracle's rate on a bounded
 sample, the 64-share batch and the serving trace.
 """
 from __future__ import annotations
@@ -54,6 +56,8 @@ EXTRAS = ("laplace3d_128_p4r1", "stencil27_150_p8r3")
 MEASURED_TRAFFIC = {
     ("powerlaw_4m_p16r5", "k_csr_slabs<4,2,1>+k_slab_sum"):
         (111_144_633, "profiles/yr_slabs_powerlaw_4m_p16r5.md"),
+    ("powerlaw_4m_p16r5", "k_resident<4,2>"):
+        (146_514_903, "profiles/resident_grouped_powerlaw_4m_p16r5.md"),
     ("laplace3d_128_p4r1", "k_sell16<1>"):
         (47_997_896, "profiles/sliced16_laplace3d_128_p4r1.md"),
     ("stencil27_150_p8r3", "k_csr_stream<4,2,2,true>"):
@@ -93,13 +97,20 @@ def step_bytes(info: dict) -> dict:
 
 def launch_bytes(info: dict) -> dict:
     """Algorithmic bytes of one spmv_op_launch of each GPU op (y_R launched
-    alone adds into y: its row ids, y read and written)."""
+    alone adds into y: its row ids, y read and written).  Where the resident
+    step is grouped, also its two launches: Pack, y_L and y_R's slab tiles
+    (entries, row pointers, halo), then the slab sums (row ids, y read and
+    written); together the bytes of Pack, y_L and y_R."""
     n, nl, nr = info["n_loc"], info["nnz_local"], info["nnz_remote"]
     h, s, rr = info["n_halo"], info["n_send"], info["n_remote_rows"]
-    return {"pack": 20 * s,
-            "yL": 12 * nl + 4 * (n + 1) + 16 * n,
-            "unpack": 0 if info["fuse_unpack"] else 20 * h,
-            "yR": 12 * nr + 4 * (rr + 1) + 4 * rr + 8 * h + 16 * rr if rr else 0}
+    b = {"pack": 20 * s,
+         "yL": 12 * nl + 4 * (n + 1) + 16 * n,
+         "unpack": 0 if info["fuse_unpack"] else 20 * h,
+         "yR": 12 * nr + 4 * (rr + 1) + 4 * rr + 8 * h + 16 * rr if rr else 0}
+    if info.get("resident_grouped"):
+        b["grouped"] = b["pack"] + b["yL"] + 12 * nr + 4 * (rr + 1) + 8 * h
+        b["slab_sums"] = 4 * rr + 16 * rr
+    return b
 
 
 def replicas_for(A, P, r, tune, sp) -> int:
@@ -137,6 +148,28 @@ def kernel_variant(info: dict, side: str = "yL") -> str:
     if kern == 2:
         return _stream_variant(form, chunk, info["width"], lanes)
     return "k_csr_vector_buf<%d,%d>" % (lanes, rows)
+
+
+def time_part(sp, torch, plans, part, xs, ys, launches: int) -> float:
+    """Average duration (us) of one of the grouped resident launches, timed
+    as time_op times an op."""
+    stream = torch.cuda.Stream()
+    R = len(plans)
+    with torch.cuda.stream(stream):
+        for i in range(2 * R):
+            sp.spmv_exec_resident_part(plans[i % R], part, xs[i % R], ys[i % R], stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(launches):
+            sp.spmv_exec_resident_part(plans[i % R], part, xs[i % R], ys[i % R], stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / launches
+
+
+def grouped_variant(info: dict) -> str:
+    return "k_resident<%d,%d>" % (info["chunk_local"], info["width"])
 
 
 def time_op(sp, torch, plans, op, xs, ys, launches: int) -> float:
@@ -824,21 +857,37 @@ def measure_share(sp, torch, gen, key: str, args, sweep: bool = True,
                           if LB[name] > 0 else 0.0) for name in OPS}
         # the same launches of the dominant op on one replica: its arrays
         # stay in the 256 MB MALL (warm)
-        dom0 = max(("yL", "yR", "pack"), key=lambda k: LB[k])
-        warm_us = time_op(sp, torch, plans[:1], op_code(sp, dom0), xs[:1], ys[:1], launches)
-        dev_bytes = sum(LB.values())     # one resident step
-        dom = max(("yL", "yR", "pack"), key=lambda k: LB[k])
-        dom_variant = kernel_variant(info, dom) if dom in ("yL", "yR") else "k_gather"
+        op_dom = max(("yL", "yR", "pack"), key=lambda k: LB[k])
+        dev_bytes = sum(LB[k] for k in OPS)     # one resident step
+        grouped = bool(info["resident_grouped"])
+        if grouped:
+            # the step's dominant kernel is its first grouped launch (Pack,
+            # y_L and y_R's slab tiles as the items of one kernel)
+            kern_us["grouped"] = time_part(sp, torch, plans, 0, xs, ys, launches)
+            kern_us["slab_sums"] = time_part(sp, torch, plans, 1, xs, ys, launches)
+            dom, dom_variant = "grouped", grouped_variant(info)
+            warm_us = time_part(sp, torch, plans[:1], 0, xs[:1], ys[:1], launches)
+        else:
+            dom = op_dom
+            dom_variant = kernel_variant(info, dom) if dom in ("yL", "yR") else "k_gather"
+            warm_us = time_op(sp, torch, plans[:1], op_code(sp, dom), xs[:1], ys[:1], launches)
         achieved = LB[dom] / (kern_us[dom] * 1e-6) / 1e9
         tr = MEASURED_TRAFFIC.get((key, dom_variant))
         traffic, traffic_src = (tr if tr else (None, None))
         ceiling = probe_ceiling(sp, torch, traffic or LB[dom])
+        op_variant = kernel_variant(info, op_dom) if op_dom in ("yL", "yR") else "k_gather"
+        tr = MEASURED_TRAFFIC.get((key, op_variant))
+        op_roof = {"op": op_dom, "kernel": op_variant, "bytes_per_launch": LB[op_dom],
+                   "avg_us": round(kern_us[op_dom], 3),
+                   "achieved": round(LB[op_dom] / (kern_us[op_dom] * 1e-6) / 1e9, 2),
+                   "frac": round(LB[op_dom] / (kern_us[op_dom] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                   "traffic": tr[0] if tr else None, "traffic_source": tr[1] if tr else None}
         gathers = None
-        if dom == "yR" and info["form_remote"] == 5:
+        if op_dom == "yR" and info["form_remote"] == 5:
             # y_R in column slabs: its x gathers against the gather probe
             gathers = gather_ceiling(sp, torch, info["nnz_remote"],
                                      -(-info["n_halo"] // 8))
-            gathers["kernel_over_per_xcd_gathers"] = round(kern_us[dom] / gathers["per_xcd_us"], 3)
+            gathers["yR_over_per_xcd_gathers"] = round(kern_us["yR"] / gathers["per_xcd_us"], 3)
         plan_order = [sp.spmv_op_name(int(t))
                       for t in sp.spmv_plan_get_i32(first, sp.SPMV_I32_OP_ORDER)]
         plan_streams = {sp.spmv_op_name(v): int(m) for v, m in enumerate(
@@ -867,8 +916,12 @@ def measure_share(sp, torch, gen, key: str, args, sweep: bool = True,
                    "n_tiles_local": info["n_tiles_local"], "n_tiles_remote": info["n_tiles_remote"],
                    "xcd_remap": info["xcd_remap"], "fuse_unpack": info["fuse_unpack"],
                    "fused_combine": info["fused_combine"], "replicas": R,
-                   "step": "Pack, y_L, Unpack, y_R of the share on one stream, halo resident "
-                           "in HBM (spmv_exec_resident)",
+                   "step": ("Pack, y_L and y_R's column-slab tiles as one grouped launch, then "
+                            "the slab sums into y, halo resident in HBM (spmv_exec_resident)"
+                            if grouped else
+                            "Pack, y_L, Unpack, y_R of the share on one stream, halo resident "
+                            "in HBM (spmv_exec_resident)"),
+                   "resident_grouped": int(grouped),
                    "step_device_bytes": dev_bytes, "exec_device_bytes": B["total"],
                    "exec_host_link_bytes": B["host_link"]},
         "roofline": {"bound": "hbm", "kernel": f"{dom} {dom_variant}",
@@ -879,7 +932,9 @@ def measure_share(sp, torch, gen, key: str, args, sweep: bool = True,
                      "traffic_gbs": (round(traffic / (kern_us[dom] * 1e-6) / 1e9, 1)
                                      if traffic else None),
                      "bytes_per_launch": LB[dom], "avg_us": round(kern_us[dom], 3),
-                     "launches": launches},
+                     "launches": launches,
+                     **({"items": "Pack, y_L and y_R's column-slab tiles"} if grouped else {})},
+        "op_roofline": op_roof,
         "warm": {"kernel": dom, "avg_us": round(warm_us, 3),
                  "achieved": round(LB[dom] / (warm_us * 1e-6) / 1e9, 1),
                  "note": "one replica, launched back to back: its arrays stay in the MALL"},
@@ -913,9 +968,16 @@ def kernel_only(sp, torch, key, info, plans, xs, ys, stream, args) -> dict:
     then a plain copy of known size whose FETCH_SIZE / WRITE_SIZE readings
     calibrate the counters."""
     LB = launch_bytes(info)
-    name = args.op or max(("yL", "yR", "pack"), key=lambda k: LB[k])
+    name = args.op or ("grouped" if info["resident_grouped"]
+                       else max(("yL", "yR", "pack"), key=lambda k: LB[k]))
     launches = max(10 * len(plans), 200)
-    us = time_op(sp, torch, plans, op_code(sp, name), xs, ys, launches)
+    if name in ("grouped", "slab_sums"):
+        # a resident step's halo: one full exec per replica first
+        for i in range(len(plans)):
+            sp.spmv_exec(plans[i], xs[i], ys[i], stream)
+        us = time_part(sp, torch, plans, 0 if name == "grouped" else 1, xs, ys, launches)
+    else:
+        us = time_op(sp, torch, plans, op_code(sp, name), xs, ys, launches)
     nbytes = 64 << 20
     src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").normal_()
     dst = torch.empty_like(src)
@@ -924,7 +986,8 @@ def kernel_only(sp, torch, key, info, plans, xs, ys, stream, args) -> dict:
         sp.spmv_hbm_probe(1, src, dst, nbytes, 0, stream)
     torch.cuda.synchronize()
     return {"kernel_only": True, "workload": key, "op": name,
-            "variant": kernel_variant(info, name) if name in ("yL", "yR") else "k_gather",
+            "variant": (kernel_variant(info, name) if name in ("yL", "yR") else
+                        grouped_variant(info) if name in ("grouped", "slab_sums") else "k_gather"),
             "avg_us": round(us, 3), "launches": launches + 2 * len(plans),
             "bytes_per_launch": LB[name], "copy_bytes_each_way": nbytes, "copy_launches": 10}
 
@@ -1013,8 +1076,10 @@ def main() -> int:
                          "shares (no staging), --steps times (for profiler runs)")
     ap.add_argument("--batch-opts", default="{}",
                     help="batch options for --batch-device-only, as JSON")
-    ap.add_argument("--op", default="", help="op for --kernel-only (pack, yL, unpack, yR; "
-                                             "default: the one with the most bytes)")
+    ap.add_argument("--op", default="", help="op for --kernel-only (pack, yL, unpack, yR, "
+                                             "grouped, slab_sums; default: the grouped "
+                                             "launch where the resident step is grouped, "
+                                             "else the op with the most bytes)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -1117,6 +1182,7 @@ def main() -> int:
         "data": "synthetic",
         "config": head["config"],
         "roofline": head["roofline"],
+        "op_roofline": head["op_roofline"],
         "cpu_baseline": cpu,
         "cpu_plain": plain,
         "frac_of_peak": head["frac_of_peak"],

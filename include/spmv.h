@@ -194,6 +194,9 @@ typedef struct {
 #define SPMV_F_NO_BUFFER  4  /* CSR kernels address memory with 64-bit
                                 pointers instead of buffer resources (the
                                 latter is used when every array < 4 GiB)     */
+#define SPMV_F_RESIDENT_SEQUENTIAL 8  /* spmv_exec_resident launches the ops
+                                one after another even where the two grouped
+                                launches apply (same bits)                   */
 
 typedef struct spmv_plan  spmv_plan_t;   /* opaque */
 
@@ -227,6 +230,8 @@ typedef struct {
     int32_t n_slices_local, n_slices_remote;  /* sliced-ELL slices (0: none) */
     int32_t fine;          /* 1 while a fine-grained order is in force       */
     int32_t device;        /* HIP device of the plan's memory (-1 host-only) */
+    int32_t resident_grouped; /* 1: spmv_exec_resident runs the two grouped
+                              launches (see there); 0: the ops one by one   */
 } spmv_info_t;
 
 /* Integer metadata selectors for spmv_plan_get_i32. */
@@ -364,13 +369,31 @@ int spmv_exec(spmv_plan_t *plan, const double *x_local, double *y_local, void *s
  * memory (the receive buffer, spmv_plan_device_buffers: filled by an
  * earlier spmv_exec, or written there by the caller, e.g. from a
  * device-to-device exchange): Pack into the device send buffer, y_L,
- * Unpack, y_R adding into y, launched in that order on `stream` and
- * returning at once (asynchronous; no copies, no host waits, no other
- * stream).  y has the bits spmv_exec gives for the same halo.  x_local,
- * y_local as in spmv_exec.  The Sec. III-A product with its exchange taken
- * out: what one rank's GPU computes once its halo has arrived.
+ * Unpack, y_R adding into y, launched on `stream` and returning at once
+ * (asynchronous; no copies, no host waits, no other stream).  Where y_R is
+ * in column slabs, y_L in packed tiles of the same window and width, and
+ * the Unpack is fused (spmv_info_t.resident_grouped), in two grouped
+ * launches: Pack, y_L and the slab tiles, which read nothing the others
+ * write, as the work items of one launch, then the slab sums adding into
+ * y; otherwise one launch per op in the DAG's order (always with
+ * SPMV_F_RESIDENT_SEQUENTIAL).  y has the bits spmv_exec gives for the
+ * same halo either way.  x_local, y_local as in spmv_exec.  The Sec. III-A
+ * product with its exchange taken out: what one rank's GPU computes once
+ * its halo has arrived.
  */
 int spmv_exec_resident(spmv_plan_t *plan, const double *x_local, double *y_local, void *stream);
+
+/*
+ * One of the two grouped launches of spmv_exec_resident, for timing them
+ * apart: part 0 = Pack, y_L and the column-slab tiles (y_L stores its row
+ * sums into y, the slab tiles their partial sums into the plan's device
+ * buffer), part 1 = the slab sums adding into y (after part 0 of the same
+ * plan).  Asynchronous on `stream`.  SPMV_ESTATE when the plan's resident
+ * step is not grouped (spmv_info_t.resident_grouped = 0), SPMV_EINVAL for
+ * another part or NULL / aliasing vectors.
+ */
+int spmv_exec_resident_part(spmv_plan_t *plan, int32_t part, const double *x_local,
+                            double *y_local, void *stream);
 
 /*
  * Device addresses of the plan's send buffer (n_send doubles, written by

@@ -64,6 +64,7 @@ def SPMV_PEER(op, q): return op | ((q + 1) << 8)
 
 
 SPMV_F_HOST_ONLY, SPMV_F_PROFILE, SPMV_F_NO_BUFFER = 1, 2, 4
+SPMV_F_RESIDENT_SEQUENTIAL = 8
 SPMV_KERNEL_VECTOR, SPMV_KERNEL_STREAM = 1, 2
 
 (SPMV_I32_HALO_COLS, SPMV_I32_RECV_OFF, SPMV_I32_SEND_IDX, SPMV_I32_SEND_OFF,
@@ -157,7 +158,7 @@ class spmv_info_t(ctypes.Structure):
             "lanes_local", "lanes_remote", "rows_local", "rows_remote", "chunk_local",
             "chunk_remote", "width", "xcd_remap", "fuse_unpack", "fused_combine",
             "n_tiles_local", "n_tiles_remote", "form_local", "form_remote",
-            "n_slices_local", "n_slices_remote", "fine", "device")]
+            "n_slices_local", "n_slices_remote", "fine", "device", "resident_grouped")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -181,6 +182,7 @@ _proto("spmv_plan_destroy", [_P])
 _proto("spmv_exec", [_P, _P, _P, _P])
 _proto("spmv_exec_static", [_P, _P, _P, _P])
 _proto("spmv_exec_resident", [_P, _P, _P, _P])
+_proto("spmv_exec_resident_part", [_P, _I32, _P, _P, _P])
 _proto("spmv_plan_device_buffers", [_P, _P, _P, _P, _P])
 _proto("spmv_static_scratch_bytes", [], _I64)
 _proto("spmv_plan_info", [_P, _P])
@@ -392,6 +394,13 @@ def spmv_exec_resident(plan, x, y, stream=None) -> None:
     the halo already in the plan's device receive buffer; asynchronous."""
     xa, ya = _plan_vecs(plan, x, y)
     _check(_lib.spmv_exec_resident(plan, xa, ya, _stream_handle(stream)))
+
+
+def spmv_exec_resident_part(plan, part: int, x, y, stream=None) -> None:
+    """One of the two grouped launches of the resident step (0: Pack, y_L
+    and the column-slab tiles; 1: the slab sums into y); asynchronous."""
+    xa, ya = _plan_vecs(plan, x, y)
+    _check(_lib.spmv_exec_resident_part(plan, int(part), xa, ya, _stream_handle(stream)))
 
 
 def spmv_plan_device_buffers(plan) -> dict:

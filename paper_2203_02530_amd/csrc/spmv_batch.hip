@@ -70,17 +70,15 @@ __device__ __forceinline__ void tile_sl(int sl, const StreamArgs &A, int t, doub
     }
 }
 
-// One work item, by the whole block.  Contains barriers only in
-// block-uniform control flow.
+// One work item of a share whose x and y are `x`, `y`, by the whole block.
+// Contains barriers only in block-uniform control flow.
 template <int NPT, int VW>
-__device__ __forceinline__ void run_item(const Item &it, const ShareDev *__restrict__ sh,
-                                         const double *const *__restrict__ xs,
-                                         double *const *__restrict__ ys, double *s_p,
-                                         int32_t *s_rp)
+__device__ __forceinline__ void run_item(const Item &it, const ShareDev &S,
+                                         const double *__restrict__ x, double *__restrict__ y,
+                                         double *s_p, int32_t *s_rp)
 {
-    const ShareDev &S = sh[it.share];
     if (it.kind == kPack || it.kind == kUnpack) {
-        const double *src = it.kind == kPack ? xs[it.share] : S.recvbuf;
+        const double *src = it.kind == kPack ? x : S.recvbuf;
         const int32_t *idx = it.kind == kPack ? S.send_idx : S.perm;
         double *dst = it.kind == kPack ? S.sendbuf : S.xhalo;
         for (int k = it.a + int(threadIdx.x); k < it.a + it.n; k += kBlock) dst[k] = src[idx[k]];
@@ -92,8 +90,8 @@ __device__ __forceinline__ void run_item(const Item &it, const ShareDev *__restr
         A.col = S.L_col;
         A.rows = nullptr;
         A.val = S.L_val;
-        A.x = xs[it.share];
-        A.out = ys[it.share];
+        A.x = x;
+        A.out = y;
         A.acc = nullptr;
         A.nnz_alloc = S.L_nnz_alloc;
         A.n_x = S.n_loc;
@@ -111,7 +109,7 @@ __device__ __forceinline__ void run_item(const Item &it, const ShareDev *__restr
         A.val = S.R_val;
         A.x = S.fuse_unpack ? S.recvbuf : S.xhalo;
         A.out = nullptr;
-        A.acc = ys[it.share];
+        A.acc = y;
         A.nnz_alloc = S.R_nnz_alloc;
         A.n_x = S.n_halo;
         tile_sl<NPT, VW>(S.R_lanes, A, it.a, s_p, s_rp);
@@ -133,7 +131,6 @@ __device__ __forceinline__ void run_item(const Item &it, const ShareDev *__restr
         tile_sl<NPT, VW>(S.R_lanes, A, it.a, s_p, s_rp);
     } else if (it.kind == kSlabSum) {
         // as k_slab_sum adding into y: the partial sums in slab order
-        double *y = ys[it.share];
         const int64_t n = S.n_rr;
         for (int r = it.a + int(threadIdx.x); r < it.a + it.n; r += kBlock) {
             double s = S.slab_part[r];
@@ -158,7 +155,8 @@ __global__ __launch_bounds__(kBlock) void k_grouped(const ShareDev *__restrict__
     const int b = int(blockIdx.x);
     const int i1 = blk_ptr[b + 1];
     for (int i = blk_ptr[b]; i < i1; ++i) {
-        run_item<NPT, VW>(items[i], sh, xs, ys, s_p, s_rp);
+        const Item it = items[i];
+        run_item<NPT, VW>(it, sh[it.share], xs[it.share], ys[it.share], s_p, s_rp);
         __syncthreads();
     }
 }
@@ -176,7 +174,8 @@ __global__ __launch_bounds__(kBlock) void k_grouped_flat(const ShareDev *__restr
     (void)blk_ptr;
     __shared__ double s_p[kBlock * NPT];
     __shared__ int32_t s_rp[kBlock + 1];
-    run_item<NPT, VW>(items[blockIdx.x], sh, xs, ys, s_p, s_rp);
+    const Item it = items[blockIdx.x];
+    run_item<NPT, VW>(it, sh[it.share], xs[it.share], ys[it.share], s_p, s_rp);
 }
 
 // Tile t of one request: y = A x over the request's matrix.
@@ -441,6 +440,45 @@ void interleave(const std::vector<Item> &items, const std::vector<int8_t> &xcd,
 
 int64_t tile_cost(const std::vector<int32_t> &tk, size_t t) { return int64_t(tk[t + 1] - tk[t]) + 64; }
 
+// Device view of one plan's share.
+ShareDev share_dev(const spmv_plan *p)
+{
+    const Share &S = p->share;
+    const CsrCfg &cr = p->cfg[1];
+    ShareDev d;
+    d.L_tile_row = p->d_tile_row[0];
+    d.L_tile_k = p->d_tile_k[0];
+    d.L_rp = p->dL_ptr;
+    d.L_col = p->dL_col;
+    d.L_val = p->dL_val;
+    d.R_tile_row = p->d_tile_row[1];
+    d.R_tile_k = p->d_tile_k[1];
+    d.R_rp = cr.form == 5 ? p->d_sell_ptr[1] : p->dR_ptr;
+    d.R_col = p->dR_col;
+    d.R_rows = p->dR_rows;
+    d.R_val = p->dR_val;
+    d.send_idx = p->d_send_idx;
+    d.perm = p->d_perm;
+    d.sendbuf = p->d_sendbuf;
+    d.recvbuf = p->d_recvbuf;
+    d.xhalo = p->d_xhalo;
+    d.L_nnz_alloc = uint32_t(S.L_col.size() + kEntryPad);
+    d.R_nnz_alloc = uint32_t((cr.form == 5 ? cr.slab_col.size() : S.R_col.size()) + kEntryPad);
+    d.n_loc = uint32_t(S.n_loc);
+    d.n_halo = uint32_t(S.halo.size());
+    d.L_lanes = p->cfg[0].lanes;
+    d.R_lanes = cr.lanes;
+    d.fuse_unpack = p->fuse_unpack ? 1 : 0;
+    d.L_col16 = p->cfg[0].form == 4 ? 1 : 0;
+    d.slab_part = p->d_slab_part;
+    d.n_rr = int32_t(S.R_rows.size());
+    for (int k = 0; k <= kSlabs; ++k) {
+        d.slab_nnz[k] = cr.form == 5 ? int32_t(cr.slab_nnz[k]) : 0;
+        d.slab_tile[k] = cr.form == 5 ? int32_t(cr.slab_tiles[k]) : 0;
+    }
+    return d;
+}
+
 hipError_t launch_group(const spmv_batch *b, const spmv_batch::Group &g, hipStream_t s)
 {
     if (g.n_items == 0) return hipSuccess;
@@ -689,37 +727,7 @@ extern "C" int spmv_batch_create(spmv_plan_t *const *plans, int32_t n,
         spmv_plan *p = plans[i];
         const Share &S = p->share;
         const CsrCfg &cr = p->cfg[1];
-        ShareDev &d = sh[size_t(i)];
-        d.L_tile_row = p->d_tile_row[0];
-        d.L_tile_k = p->d_tile_k[0];
-        d.L_rp = p->dL_ptr;
-        d.L_col = p->dL_col;
-        d.L_val = p->dL_val;
-        d.R_tile_row = p->d_tile_row[1];
-        d.R_tile_k = p->d_tile_k[1];
-        d.R_rp = cr.form == 5 ? p->d_sell_ptr[1] : p->dR_ptr;
-        d.R_col = p->dR_col;
-        d.R_rows = p->dR_rows;
-        d.R_val = p->dR_val;
-        d.send_idx = p->d_send_idx;
-        d.perm = p->d_perm;
-        d.sendbuf = p->d_sendbuf;
-        d.recvbuf = p->d_recvbuf;
-        d.xhalo = p->d_xhalo;
-        d.L_nnz_alloc = uint32_t(S.L_col.size() + kEntryPad);
-        d.R_nnz_alloc = uint32_t((cr.form == 5 ? cr.slab_col.size() : S.R_col.size()) + kEntryPad);
-        d.n_loc = uint32_t(S.n_loc);
-        d.n_halo = uint32_t(S.halo.size());
-        d.L_lanes = p->cfg[0].lanes;
-        d.R_lanes = cr.lanes;
-        d.fuse_unpack = p->fuse_unpack ? 1 : 0;
-        d.L_col16 = p->cfg[0].form == 4 ? 1 : 0;
-        d.slab_part = p->d_slab_part;
-        d.n_rr = int32_t(S.R_rows.size());
-        for (int k = 0; k <= kSlabs; ++k) {
-            d.slab_nnz[k] = cr.form == 5 ? int32_t(cr.slab_nnz[k]) : 0;
-            d.slab_tile[k] = cr.form == 5 ? int32_t(cr.slab_tiles[k]) : 0;
-        }
+        sh[size_t(i)] = share_dev(p);
         // algorithmic bytes, as for one exec of the share
         const int64_t n_send = int64_t(S.send_idx.size()), n_halo = int64_t(S.halo.size());
         const int64_t nl = int64_t(S.L_col.size()), nr = int64_t(S.R_col.size());
@@ -941,3 +949,167 @@ extern "C" int spmv_batch_destroy(spmv_batch_t *b)
     batch_release(b);
     return SPMV_OK;
 }
+
+// ------------------------------------------------------------------------
+// The resident step of one plan in two grouped launches, for a share whose
+// y_R is in column slabs.  With the halo already in the receive buffer (read
+// in place: fused Unpack), Pack, y_L and the slab tiles read nothing another
+// of them writes, so they run as the work items of one launch, one block
+// per item, each slab tile on its slab's XCD: Pack's streaming and y_L run
+// beside the slabs' L2-bound gathers instead of before them.  The second
+// launch adds the slab sums into y, which needs y_L's result there.  Each
+// item runs the device code of the single-share kernels, so y has the bits
+// of spmv_exec.  On the power-law 4M share (P = 16, rank 5) the step took
+// 49.7 us against 57.0 op by op; with Pack and y_L mixed among the slab
+// tiles instead of before them 53.4 us (y_L's x then shares each XCD's L2
+// with the slab's x).  Where y_R is in packed tiles there is no such
+// overlap to win and the generic item (its table entry, the share
+// descriptor, then the tile) cost more than the launches it saves: 30.6-
+// 31.8 us against 28.7-29.3 on the 27-point share, so those shares stay
+// op by op.
+
+namespace spmv {
+
+struct ResidentProg {
+    void *arena = nullptr;
+    ShareDev *d_sh = nullptr;
+    Item *d_a = nullptr, *d_b = nullptr;
+    unsigned grid_a = 0, grid_b = 0;
+    void (*fn)(const ShareDev *, const double *, double *, const Item *) = nullptr;
+};
+
+namespace {
+
+template <int NPT, int VW>
+__global__ __launch_bounds__(kBlock) void k_resident(const ShareDev *__restrict__ sh,
+                                                     const double *__restrict__ x,
+                                                     double *__restrict__ y,
+                                                     const Item *__restrict__ items)
+{
+    __shared__ double s_p[kBlock * NPT];
+    __shared__ int32_t s_rp[kBlock + 1];
+    run_item<NPT, VW>(items[blockIdx.x], *sh, x, y, s_p, s_rp);
+}
+
+using ResidentFn = void (*)(const ShareDev *, const double *, double *, const Item *);
+
+ResidentFn resident_fn(int npt, int vw)
+{
+    if (vw == 2) return npt == 4 ? k_resident<4, 2> : npt == 8 ? k_resident<8, 2> : npt == 16 ? k_resident<16, 2> : nullptr;
+    if (vw == 4) return npt == 4 ? k_resident<4, 4> : npt == 8 ? k_resident<8, 4> : npt == 16 ? k_resident<16, 4> : nullptr;
+    return nullptr;
+}
+
+// A launch's list, one block per item: block b runs on XCD b % 8, so the
+// list is built in rounds of 8 slots, slot g of each round taking the next
+// item of XCD g's queue (kNop once that queue is empty); XCD g's queue
+// holds its `first` items, then its `second` items.
+std::vector<Item> place_items(const std::vector<Item> (&first)[kXcds],
+                              const std::vector<Item> (&second)[kXcds])
+{
+    std::vector<Item> q[kXcds];
+    size_t rounds = 0;
+    for (int g = 0; g < kXcds; ++g) {
+        q[g] = first[g];
+        q[g].insert(q[g].end(), second[g].begin(), second[g].end());
+        rounds = std::max(rounds, q[g].size());
+    }
+    const Item nop{kNop, 0, 0, 0};
+    std::vector<Item> out;
+    out.reserve(rounds * kXcds);
+    for (size_t r = 0; r < rounds; ++r)
+        for (int g = 0; g < kXcds; ++g) out.push_back(r < q[g].size() ? q[g][r] : nop);
+    while (!out.empty() && out.back().kind == kNop) out.pop_back();
+    return out;
+}
+
+}  // namespace
+
+int resident_build(spmv_plan *p)
+{
+    p->res = nullptr;
+    const Share &S = p->share;
+    const CsrCfg &cl = p->cfg[0], &cr = p->cfg[1];
+    if (p->host_only || !p->fuse_unpack || S.n_loc <= 0 || S.R_rows.empty()) return SPMV_OK;
+    if (cl.kernel != SPMV_KERNEL_STREAM || (cl.form != 1 && cl.form != 4)) return SPMV_OK;
+    if (cr.kernel != SPMV_KERNEL_STREAM || cr.form != 5 || cr.rows > 1 || cr.chunk != cl.chunk ||
+        cr.width != cl.width)
+        return SPMV_OK;
+    const ResidentFn fn = resident_fn(cl.chunk, cl.width);
+    if (!fn) return SPMV_OK;
+    const int gather_len = kBlock * cl.chunk;
+    // Pack and y_L items go to the XCDs by contiguous ranges (item i of n on
+    // XCD 8 i / n), as the single-share kernels order their blocks, and run
+    // before the XCD's slab tiles; the slab sums likewise
+    auto xcd_of = [](int64_t i, int64_t n) { return int(i * kXcds / std::max<int64_t>(n, 1)); };
+    std::vector<Item> a1[kXcds], a2[kXcds], b1[kXcds], none[kXcds];
+    const int64_t n_lt = int64_t(cl.tile_k.size()) - 1;
+    for (int64_t t = 0; t < n_lt; ++t) a1[xcd_of(t, n_lt)].push_back({kLocal, 0, int32_t(t), 0});
+    const int64_t n_send = int64_t(S.send_idx.size());
+    const int64_t n_pk = (n_send + gather_len - 1) / gather_len;
+    for (int64_t j = 0; j < n_pk; ++j) {
+        const int64_t a = j * gather_len;
+        a1[xcd_of(j, n_pk)].push_back({kPack, 0, int32_t(a), int32_t(std::min<int64_t>(gather_len, n_send - a))});
+    }
+    for (int k = 0; k < kSlabs; ++k)
+        for (int64_t t = cr.slab_tiles[k]; t + 1 < cr.slab_tiles[k + 1]; ++t)
+            a2[k].push_back({kSlab, 0, int32_t(t - cr.slab_tiles[k]), k});
+    const int64_t n_rr = int64_t(S.R_rows.size());
+    const int64_t n_sum = (n_rr + gather_len - 1) / gather_len;
+    for (int64_t j = 0; j < n_sum; ++j) {
+        const int64_t a = j * gather_len;
+        b1[xcd_of(j, n_sum)].push_back({kSlabSum, 0, int32_t(a), int32_t(std::min<int64_t>(gather_len, n_rr - a))});
+    }
+    const std::vector<Item> a_items = place_items(a1, a2);
+    const std::vector<Item> b_items = place_items(b1, none);
+    auto *r = new (std::nothrow) ResidentProg();
+    if (!r) return set_error(SPMV_ENOMEM, "resident program");
+    const size_t sh_bytes = (sizeof(ShareDev) + 255) & ~size_t(255);
+    const size_t a_bytes = ((a_items.size() * sizeof(Item)) + 255) & ~size_t(255);
+    const size_t b_bytes = std::max<size_t>(b_items.size() * sizeof(Item), 1);
+    if (hipMalloc(&r->arena, sh_bytes + a_bytes + b_bytes) != hipSuccess) {
+        delete r;
+        return set_error(SPMV_EHIP, "resident program: hipMalloc failed");
+    }
+    char *base = static_cast<char *>(r->arena);
+    r->d_sh = reinterpret_cast<ShareDev *>(base);
+    r->d_a = reinterpret_cast<Item *>(base + sh_bytes);
+    r->d_b = reinterpret_cast<Item *>(base + sh_bytes + a_bytes);
+    const ShareDev d = share_dev(p);
+    hipError_t e = hipMemcpy(r->d_sh, &d, sizeof(d), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !a_items.empty())
+        e = hipMemcpy(r->d_a, a_items.data(), a_items.size() * sizeof(Item), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !b_items.empty())
+        e = hipMemcpy(r->d_b, b_items.data(), b_items.size() * sizeof(Item), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(r->arena);
+        delete r;
+        return set_error(SPMV_EHIP, std::string("resident program: ") + hipGetErrorString(e));
+    }
+    r->grid_a = unsigned(a_items.size());
+    r->grid_b = unsigned(b_items.size());
+    r->fn = fn;
+    p->res = r;
+    return SPMV_OK;
+}
+
+void resident_free(spmv_plan *p)
+{
+    if (!p || !p->res) return;
+    if (p->res->arena) (void)hipFree(p->res->arena);
+    delete p->res;
+    p->res = nullptr;
+}
+
+hipError_t resident_launch(const spmv_plan *p, int part, const double *x, double *y,
+                           hipStream_t s)
+{
+    const ResidentProg *r = p->res;
+    if (part != 1 && r->grid_a)
+        hipLaunchKernelGGL(r->fn, dim3(r->grid_a), dim3(kBlock), 0, s, r->d_sh, x, y, r->d_a);
+    if (part != 0 && r->grid_b)
+        hipLaunchKernelGGL(r->fn, dim3(r->grid_b), dim3(kBlock), 0, s, r->d_sh, x, y, r->d_b);
+    return hipGetLastError();
+}
+
+}  // namespace spmv

@@ -323,6 +323,17 @@ void pool_release(int device);
 // (spmv_batch.hip) read its device arrays and tiles.
 namespace spmv {
 // Kernel configuration of one product (y_L or y_R).
+// The resident step of one plan in two grouped launches (defined with the
+// batch kernels): built at plan creation for a share whose y_R is in column
+// slabs and whose y_L is in packed tiles of the same window and width.
+struct ResidentProg;
+int resident_build(spmv_plan *p);
+void resident_free(spmv_plan *p);
+// part 0: the launch of Pack, y_L and the slab tiles; 1: the slab sums;
+// -1: both in that order.
+hipError_t resident_launch(const spmv_plan *p, int part, const double *x, double *y,
+                           hipStream_t s);
+
 struct CsrCfg {
     int32_t kernel = SPMV_KERNEL_VECTOR;
     int32_t lanes = 1, rows = 1;   // vector CSR
@@ -366,6 +377,8 @@ struct spmv_plan {
     int32_t *d_send_idx = nullptr, *d_perm = nullptr;
     double *d_sendbuf = nullptr, *d_recvbuf = nullptr, *d_xhalo = nullptr, *d_part = nullptr;
     double *d_slab_part = nullptr;   // form 5: [kSlabs * n_remote_rows]
+    spmv::ResidentProg *res = nullptr;   // grouped resident step, or null
+    bool resident_seq = false;       // resident step op by op even with res
     int32_t *d_tile_row[2] = {}, *d_tile_k[2] = {};
     int32_t *d_sell_ptr[2] = {};
 

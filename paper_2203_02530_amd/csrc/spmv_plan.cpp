@@ -95,6 +95,7 @@ void release(spmv_plan *p)
         if (p->ev_b[i]) (void)hipEventDestroy(p->ev_b[i]);
         if (p->ev_e[i]) (void)hipEventDestroy(p->ev_e[i]);
     }
+    resident_free(p);
     if (p->arena) (void)hipFree(p->arena);
     if (p->h_inbox) (void)hipHostFree(p->h_inbox);
     if (p->h_outbox) (void)hipHostFree(p->h_outbox);
@@ -197,6 +198,7 @@ int allocate_and_upload(spmv_plan *p)
             SPMV_HIP(hipEventCreate(&p->ev_b[i]));
             SPMV_HIP(hipEventCreate(&p->ev_e[i]));
         }
+    if (int rc = resident_build(p)) return rc;
     SPMV_HIP(hipDeviceSynchronize());
     return SPMV_OK;
 }
@@ -560,6 +562,7 @@ int create_plan(Build build_share_fn, int32_t nranks, const int32_t *op_order, i
     p->host_only = (t.flags & SPMV_F_HOST_ONLY) != 0;
     p->profile = (t.flags & SPMV_F_PROFILE) != 0;
     p->use_buffer = (t.flags & SPMV_F_NO_BUFFER) == 0;
+    p->resident_seq = (t.flags & SPMV_F_RESIDENT_SEQUENTIAL) != 0;
     p->fused_combine = fuses_combine(p->sch);
     p->n_streams_max = n_streams;
     if (nranks > 1) p->fdag.build(p->share);
@@ -928,6 +931,10 @@ extern "C" int spmv_exec_resident(spmv_plan_t *p, const double *x, double *y, vo
     int dev = 0;
     SPMV_HIP(hipGetDevice(&dev));
     if (dev != p->device) SPMV_HIP(hipSetDevice(p->device));
+    if (p->res && !p->resident_seq) {
+        SPMV_HIP(resident_launch(p, -1, x, y, s));
+        return SPMV_OK;
+    }
     // Pack, y_L, Unpack, y_R in the order of the DAG's GPU vertices, on one
     // stream: y_R adds into what y_L stored, so y = fl(s_L + s_R) as in
     // every plan of spmv_exec
@@ -939,6 +946,23 @@ extern "C" int spmv_exec_resident(spmv_plan_t *p, const double *x, double *y, vo
         const double *xh = p->fuse_unpack ? p->d_recvbuf : p->d_xhalo;
         SPMV_HIP(launch_product(p, 1, xh, nullptr, y, s));
     }
+    return SPMV_OK;
+}
+
+extern "C" int spmv_exec_resident_part(spmv_plan_t *p, int32_t part, const double *x, double *y,
+                                       void *stream_v)
+{
+    if (!p) return set_error(SPMV_EINVAL, "plan is NULL");
+    if (p->host_only) return set_error(SPMV_ESTATE, "plan was created host-only");
+    if (!p->res || p->resident_seq)
+        return set_error(SPMV_ESTATE, "the plan's resident step is not grouped");
+    if (part != 0 && part != 1) return set_error(SPMV_EINVAL, "part must be 0 or 1");
+    if (!x || !y) return set_error(SPMV_EINVAL, "x or y is NULL");
+    if (x == y) return set_error(SPMV_EINVAL, "x and y alias");
+    int dev = 0;
+    SPMV_HIP(hipGetDevice(&dev));
+    if (dev != p->device) SPMV_HIP(hipSetDevice(p->device));
+    SPMV_HIP(resident_launch(p, part, x, y, static_cast<hipStream_t>(stream_v)));
     return SPMV_OK;
 }
 
@@ -1125,6 +1149,7 @@ extern "C" int spmv_plan_info(const spmv_plan_t *p, spmv_info_t *info)
     info->fuse_unpack = p->fuse_unpack;
     info->fused_combine = p->fused_combine;
     info->device = p->host_only ? -1 : p->device;
+    info->resident_grouped = p->res && !p->resident_seq ? 1 : 0;
     return SPMV_OK;
 }
 

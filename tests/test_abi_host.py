@@ -262,10 +262,15 @@ def test_host_only_plan_refuses_device_calls():
     p = sp.spmv_plan_create(A, 2, 1, tune=HOST_ONLY)
     try:
         for fn in (lambda: sp._lib.spmv_exec_resident(p, None, None, None),
+                   lambda: sp._lib.spmv_exec_resident_part(p, 0, None, None, None),
                    lambda: sp._lib.spmv_plan_device_buffers(p, None, None, None, None)):
             assert fn() == sp.SPMV_ESTATE
     finally:
         sp.spmv_plan_destroy(p)
+
+
+def test_resident_part_rejects_null_plan():
+    assert sp._lib.spmv_exec_resident_part(None, 0, None, None, None) == sp.SPMV_EINVAL
 
 
 def test_host_only_plan_refuses_exec():

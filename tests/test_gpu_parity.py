@@ -820,24 +820,43 @@ def test_full_paper_banded_150k_p4_rank1_sampled_plans():
         sp.spmv_plan_destroy(plan)
 
 
-def test_exec_resident_matches_exec():
+@pytest.mark.parametrize("mode", ["grouped", "sequential"])
+def test_exec_resident_matches_exec(mode):
     """The device work alone (halo already in the receive buffer): the bits
     of spmv_exec for the same halo, the send buffer exact, and no copy from
-    the inbox (a changed inbox does not reach y until the next spmv_exec)."""
+    the inbox (a changed inbox does not reach y until the next spmv_exec).
+    Two grouped launches (Pack, y_L and the column-slab tiles as the items
+    of one, the slab sums of the other) where y_R is in column slabs and
+    y_L in packed tiles (32- or 16-bit columns) of one window and width,
+    with one or two summing lanes and rows longer than a window; otherwise,
+    or with the flag, the ops one by one."""
     import torch
-    cases = [(gen.power_law(30000, seed=17), 4, 2, 18, {}),
-             (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5}),
-             (gen.power_law(30000, seed=17), 4, 2, 18, {"fuse_unpack": 2}),
-             (gen.laplacian_3d7(24), 4, 1, 20, {}),
-             (gen.laplacian_2d5(40), 1, 0, 21, {})]
-    for A, P, r, seed, tune in cases:
-        log(f"exec_resident n={A.n_rows} P={P} r={r} {tune}")
+    flags = {"grouped": 0, "sequential": sp.SPMV_F_RESIDENT_SEQUENTIAL}[mode]
+    cases = [(gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5}, 1),
+             (gen.power_law(60000, seed=21), 8, 3, 22, {"form": 5, "lanes_remote": 2}, 1),
+             (gen.power_law(20000, mean_len=100.0, sigma=1.5, max_len=30000, seed=45), 4, 1,
+              23, {"form": 5}, 1),                                          # long rows
+             (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5, "width": 4, "chunk_local": 8,
+                                                         "chunk_remote": 8}, 1),
+             (gen.power_law(30000, seed=17), 4, 2, 18, {}, 0),           # y_R in packed tiles
+             (_dense_remote_rows(), 2, 1, 23, {"form": 5}, 0),            # sliced y_L
+             (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5, "fuse_unpack": 2}, 0),
+             (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5, "rows_remote": 2}, 0),
+             (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5, "kernel_local": 1}, 0),
+             (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5, "chunk_local": 8,
+                                                         "chunk_remote": 4}, 0),
+             (gen.laplacian_3d7(24), 4, 1, 20, {}, 0),                   # sliced y_L
+             (gen.laplacian_2d5(40), 1, 0, 21, {"form": 1}, 0)]          # no remote rows
+    for A, P, r, seed, tune, grouped in cases:
+        tune = {**tune, "flags": flags}
+        log(f"exec_resident {mode} n={A.n_rows} P={P} r={r} {tune}")
         x = gen.x_normal(A.n_cols, seed)
         ref = oracle.share_reference(A, P, r, x)
         res, _ = run_share(A, P, r, x, tune=tune, ref=ref, keep_plan=True)
         plan = res.pop("plan")
         try:
             info = res["info"]
+            assert info["resident_grouped"] == (grouped if mode != "sequential" else 0), tune
             lo, n = info["lo"], info["n_loc"]
             bufs = sp.spmv_plan_device_buffers(plan)
             assert bufs["n_send"] == info["n_send"] and bufs["n_halo"] == info["n_halo"]
@@ -848,6 +867,17 @@ def test_exec_resident_matches_exec():
                 sp.spmv_exec_resident(plan, xd, yd, torch.cuda.current_stream())
                 torch.cuda.synchronize()
                 assert np.array_equal(bits(yd.cpu().numpy()), bits(res["y"]))
+                if info["resident_grouped"]:   # its two launches one at a time
+                    yd.fill_(float("nan"))
+                    for part in (0, 1):
+                        sp.spmv_exec_resident_part(plan, part, xd, yd,
+                                                   torch.cuda.current_stream())
+                    torch.cuda.synchronize()
+                    assert np.array_equal(bits(yd.cpu().numpy()), bits(res["y"]))
+                else:
+                    with pytest.raises(sp.SpmvError) as e:
+                        sp.spmv_exec_resident_part(plan, 0, xd, yd, torch.cuda.current_stream())
+                    assert e.value.code == sp.SPMV_ESTATE
                 assert np.array_equal(bits(sp.spmv_plan_get_f64(plan, sp.SPMV_F64_SENDBUF)),
                                       bits(ref["sendbuf"]))
                 sp.spmv_plan_inbox(plan)[:] = 0.0     # not copied by the resident exec
