@@ -978,6 +978,12 @@ def kernel_only(sp, torch, key, info, plans, xs, ys, stream, args) -> dict:
         us = time_part(sp, torch, plans, 0 if name == "grouped" else 1, xs, ys, launches)
     else:
         us = time_op(sp, torch, plans, op_code(sp, name), xs, ys, launches)
+    gathers = None
+    if name == "yR" and info["form_remote"] == 5:
+        # the gather probe beside y_R in column slabs (per XCD, then over
+        # the whole halo), for counters of the same gathers without rows
+        gathers = gather_ceiling(sp, torch, info["nnz_remote"], -(-info["n_halo"] // 8),
+                                 launches=20)
     nbytes = 64 << 20
     src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").normal_()
     dst = torch.empty_like(src)
@@ -989,7 +995,8 @@ def kernel_only(sp, torch, key, info, plans, xs, ys, stream, args) -> dict:
             "variant": (kernel_variant(info, name) if name in ("yL", "yR") else
                         grouped_variant(info) if name in ("grouped", "slab_sums") else "k_gather"),
             "avg_us": round(us, 3), "launches": launches + 2 * len(plans),
-            "bytes_per_launch": LB[name], "copy_bytes_each_way": nbytes, "copy_launches": 10}
+            "bytes_per_launch": LB[name], "copy_bytes_each_way": nbytes, "copy_launches": 10,
+            "gather_probe": gathers}
 
 
 def extra_summary(out: dict) -> dict:
