@@ -756,8 +756,11 @@ def test_full_powerlaw_4m_global_p16_rank5_column_slabs():
     automatic form puts y_R in column slabs (its 19 MB halo exceeds one
     XCD's L2).  Every row against the oracle, the outbox and
     receive buffer bit-exact, then 8 plans spread over the space on the same
-    uploaded share, each bit-identical to the first; wide slab tiles
-    (rows_remote = 4) agree with the oracle too."""
+    uploaded share, each bit-identical to the first; the resident step the
+    benchmark times (two grouped launches, and each launch alone) gives the
+    same bits on the halo that exec left in the receive buffer; wide slab
+    tiles (rows_remote = 4) agree with the oracle too."""
+    import torch
     w = gen.WORKLOADS["powerlaw_4m_p16r5"]
     A = w["build"]()
     x = w["x"](A.n_cols)
@@ -779,6 +782,22 @@ def test_full_powerlaw_4m_global_p16_rank5_column_slabs():
             sp.spmv_plan_reorder(plan, ops, smap, 2)
             got, _ = run_share(A, P, r, x, ref=ref, plan=plan)
             assert np.array_equal(bits(got["y"]), first), i
+        assert info["resident_grouped"] == 1
+        lo, n_loc = info["lo"], info["n_loc"]
+        xd = torch.from_numpy(np.ascontiguousarray(x[lo:lo + n_loc])).cuda()
+        yd = torch.full((n_loc,), float("nan"), dtype=torch.float64, device="cuda")
+        s = torch.cuda.current_stream()
+        for _ in range(3):
+            sp.spmv_exec_resident(plan, xd, yd, s)
+        torch.cuda.synchronize()
+        assert np.array_equal(bits(yd.cpu().numpy()), first)
+        assert np.array_equal(bits(sp.spmv_plan_get_f64(plan, sp.SPMV_F64_SENDBUF)),
+                              bits(ref["sendbuf"]))
+        yd.fill_(float("nan"))
+        sp.spmv_exec_resident_part(plan, 0, xd, yd, s)
+        sp.spmv_exec_resident_part(plan, 1, xd, yd, s)
+        torch.cuda.synchronize()
+        assert np.array_equal(bits(yd.cpu().numpy()), first)
     finally:
         sp.spmv_plan_destroy(plan)
     log("full global power-law 4M P=16 r=5, wide slab tiles")
