@@ -82,17 +82,23 @@ __device__ __forceinline__ void run_item(const Item &it, const ShareDev &S,
         const int32_t *idx = it.kind == kPack ? S.send_idx : S.perm;
         double *dst = it.kind == kPack ? S.sendbuf : S.xhalo;
         // a range holds at most NPT * kBlock entries: each thread loads all
-        // its indices, then gathers all its values, then stores them
+        // its indices, then gathers all its values, then stores them.  The
+        // indices and the stores stream past the L2 (non-temporal): in the
+        // resident step they would otherwise evict the x lines of the slab
+        // tiles beside them (43.9 against 47.1 us per step of the power-law
+        // 4M share); x itself keeps the default policy, its lines are
+        // reused by every destination's list
         const int end = it.a + it.n, t0 = it.a + int(threadIdx.x);
         int32_t id[NPT];
         double v[NPT];
 #pragma unroll
-        for (int j = 0; j < NPT; ++j) id[j] = t0 + j * kBlock < end ? idx[t0 + j * kBlock] : -1;
+        for (int j = 0; j < NPT; ++j)
+            id[j] = t0 + j * kBlock < end ? __builtin_nontemporal_load(idx + t0 + j * kBlock) : -1;
 #pragma unroll
         for (int j = 0; j < NPT; ++j) v[j] = id[j] >= 0 ? src[id[j]] : 0.0;
 #pragma unroll
         for (int j = 0; j < NPT; ++j)
-            if (t0 + j * kBlock < end) dst[t0 + j * kBlock] = v[j];
+            if (t0 + j * kBlock < end) __builtin_nontemporal_store(v[j], dst + t0 + j * kBlock);
         for (int k = t0 + NPT * kBlock; k < end; k += kBlock) dst[k] = src[idx[k]];
     } else if (it.kind == kLocal) {
         StreamArgs A;
@@ -1053,7 +1059,8 @@ int resident_build(spmv_plan *p)
     // y_L tiles, then Pack ranges, go to the XCDs by contiguous ranges (item
     // i of n on XCD 8 i / n), as the single-share kernels order their
     // blocks, and run before the XCD's slab tiles (the other order of y_L
-    // and Pack measured 0.6 us slower per step); the slab sums likewise
+    // and Pack measured 0.6 us slower per step, Pack spread evenly among
+    // the slab tiles 2.7 us slower); the slab sums likewise
     auto xcd_of = [](int64_t i, int64_t n) { return int(i * kXcds / std::max<int64_t>(n, 1)); };
     std::vector<Item> a1[kXcds], a2[kXcds], b1[kXcds], none[kXcds];
     const int64_t n_lt = int64_t(cl.tile_k.size()) - 1;
