@@ -194,9 +194,9 @@ typedef struct {
 #define SPMV_F_NO_BUFFER  4  /* CSR kernels address memory with 64-bit
                                 pointers instead of buffer resources (the
                                 latter is used when every array < 4 GiB)     */
-#define SPMV_F_RESIDENT_SEQUENTIAL 8  /* spmv_exec_resident launches the ops
-                                one after another even where the two grouped
-                                launches apply (same bits)                   */
+#define SPMV_F_RESIDENT_SEQUENTIAL 8  /* spmv_exec_resident launches each op
+                                on its own even where it could group them
+                                (same bits)                                  */
 
 typedef struct spmv_plan  spmv_plan_t;   /* opaque */
 
@@ -230,8 +230,10 @@ typedef struct {
     int32_t n_slices_local, n_slices_remote;  /* sliced-ELL slices (0: none) */
     int32_t fine;          /* 1 while a fine-grained order is in force       */
     int32_t device;        /* HIP device of the plan's memory (-1 host-only) */
-    int32_t resident_grouped; /* 1: spmv_exec_resident runs the two grouped
-                              launches (see there); 0: the ops one by one   */
+    int32_t resident_grouped; /* launches of spmv_exec_resident: 1 = the two
+                              grouped launches, 2 = Pack as extra blocks of
+                              y_L's launch, then y_R, 0 = one per op (see
+                              spmv_exec_resident)                           */
 } spmv_info_t;
 
 /* Integer metadata selectors for spmv_plan_get_i32. */
@@ -370,14 +372,17 @@ int spmv_exec(spmv_plan_t *plan, const double *x_local, double *y_local, void *s
  * earlier spmv_exec, or written there by the caller, e.g. from a
  * device-to-device exchange): Pack into the device send buffer, y_L,
  * Unpack, y_R adding into y, launched on `stream` and returning at once
- * (asynchronous; no copies, no host waits, no other stream).  Where y_R is
- * in column slabs, y_L in packed tiles of the same window and width, and
- * the Unpack is fused (spmv_info_t.resident_grouped), in two grouped
- * launches: Pack, y_L and the slab tiles, which read nothing the others
- * write, as the work items of one launch, then the slab sums adding into
- * y; otherwise one launch per op in the DAG's order (always with
- * SPMV_F_RESIDENT_SEQUENTIAL).  y has the bits spmv_exec gives for the
- * same halo either way.  x_local, y_local as in spmv_exec.  The Sec. III-A
+ * (asynchronous; no copies, no host waits, no other stream).  The launches
+ * (spmv_info_t.resident_grouped):
+ *   1  y_R in column slabs, y_L in packed tiles of the same window and
+ *      width, Unpack fused: two grouped launches, Pack, y_L and the slab
+ *      tiles (none reads what another writes) as the work items of one,
+ *      then the slab sums adding into y;
+ *   2  y_L in packed tiles or the 16-bit sliced form: Pack as extra blocks
+ *      of y_L's launch, then Unpack (unless fused) and y_R;
+ *   0  otherwise, and always with SPMV_F_RESIDENT_SEQUENTIAL: one launch
+ *      per op in the DAG's order.
+ * y has the bits spmv_exec gives for the same halo in every case.  x_local, y_local as in spmv_exec.  The Sec. III-A
  * product with its exchange taken out: what one rank's GPU computes once
  * its halo has arrived.
  */

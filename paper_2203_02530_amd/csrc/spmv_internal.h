@@ -199,8 +199,19 @@ hipError_t launch_csr(const CsrDev &A, const double *x, double *out, double *acc
                       int lanes, int rows, int xcd_remap, bool allow_buffer, hipStream_t s);
 hipError_t launch_combine(const int32_t *rows, const double *part, double *y, int64_t n,
                           hipStream_t s);
+// Pack run by extra blocks of a product's launch (the resident step): the
+// blocks after the product's own each gather kPackPerThread entries per
+// thread of dst[k] = x[idx[k]], k < n.  A default PackTail adds nothing.
+struct PackTail {
+    const double *x = nullptr;
+    const int32_t *idx = nullptr;
+    double *dst = nullptr;
+    int32_t n = 0;
+};
+constexpr int kPackPerThread = 4;
 hipError_t launch_csr_stream(const CsrDev &A, const double *x, double *out, double *acc,
-                             int npt, int vw, int sum_lanes, int xcd_remap, hipStream_t s);
+                             int npt, int vw, int sum_lanes, int xcd_remap, hipStream_t s,
+                             const PackTail &tail = PackTail());
 // Sliced-ELL product (CsrDev.sell_ptr set): one wave per slice of 64 rows.
 hipError_t launch_sell(const CsrDev &A, const double *x, double *out, double *acc,
                        int xcd_remap, hipStream_t s);
@@ -252,7 +263,7 @@ bool build_sell(const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
 // for every slice, values in pairs: see pair_values): entries in groups of
 // 8 per lane, 8 * `sell_u` entries per batch of loads.
 hipError_t launch_sell16(const CsrDev &A, const double *x, double *out, int xcd_remap,
-                         hipStream_t s);
+                         hipStream_t s, const PackTail &tail = PackTail());
 // Padding marker of the 16-bit column offsets (never a valid offset).
 constexpr int16_t kPad16 = -32768;
 // The columns of a uniform-width sliced layout as offsets from the row:

@@ -176,14 +176,45 @@ __global__ __launch_bounds__(kBlock) void k_csr_vector_buf(
     }
 }
 
-// Single-share stream-CSR product: one block per tile (see spmv_stream.h).
+// Block j of a PackTail: entries [j * NT * K, (j + 1) * NT * K), each
+// thread's indices first, then its gathers, then its stores; indices and
+// stores stream past the L2 (non-temporal), x keeps the default policy.
+template <int NT>
+__device__ __forceinline__ void pack_block(const PackTail &P, int j)
+{
+    constexpr int K = kPackPerThread;
+    const int t0 = j * NT * K + int(threadIdx.x);
+    int32_t id[K];
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        id[k] = t0 + k * NT < P.n ? __builtin_nontemporal_load(P.idx + t0 + k * NT) : -1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = id[k] >= 0 ? P.x[id[k]] : 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (t0 + k * NT < P.n) __builtin_nontemporal_store(v[k], P.dst + t0 + k * NT);
+}
+
+template <int NT>
+int pack_blocks(const PackTail &P)
+{
+    return P.n > 0 ? (P.n + NT * kPackPerThread - 1) / (NT * kPackPerThread) : 0;
+}
+
+// Single-share stream-CSR product: one block per tile (see spmv_stream.h);
+// the n_tiles blocks are followed by the PackTail's blocks.
 template <int NPT, int VW, int SL, bool C16>
-__global__ __launch_bounds__(kBlock) void k_csr_stream(StreamArgs A, int remap)
+__global__ __launch_bounds__(kBlock) void k_csr_stream(StreamArgs A, int remap, int n_tiles,
+                                                       PackTail P)
 {
     __shared__ double s_p[kBlock * NPT];
     __shared__ int32_t s_rp[kBlock / SL + 1];
-    stream_tile<NPT, VW, SL, C16>(A, tile_of_block(int(blockIdx.x), int(gridDim.x), remap), s_p,
-                                  s_rp);
+    if (int(blockIdx.x) >= n_tiles) {   // whole block, before any barrier
+        pack_block<kBlock>(P, int(blockIdx.x) - n_tiles);
+        return;
+    }
+    stream_tile<NPT, VW, SL, C16>(A, tile_of_block(int(blockIdx.x), n_tiles, remap), s_p, s_rp);
 }
 
 // Sliced-ELL product: one wave per slice of 64 rows; lane l owns row
@@ -277,11 +308,14 @@ __device__ __forceinline__ void unpack16(const uint32_t w, int32_t &lo, int32_t 
 }
 
 template <int NG>
-__global__ __launch_bounds__(64) void k_sell16(Sell16Args A, int remap)
+__global__ __launch_bounds__(64) void k_sell16(Sell16Args A, int remap, PackTail P)
 {
     constexpr int U = 8 * NG;
-    const int slice = tile_of_block(int(blockIdx.x), int(gridDim.x), remap);
-    if (slice >= A.n_slices) return;
+    if (int(blockIdx.x) >= A.n_slices) {   // the PackTail's blocks follow the slices
+        pack_block<64>(P, int(blockIdx.x) - A.n_slices);
+        return;
+    }
+    const int slice = tile_of_block(int(blockIdx.x), A.n_slices, remap);
     const int lane = int(threadIdx.x);
     const int r = slice * 64 + lane;
     const auto r_off = rsrc(A.off, A.off_bytes);
@@ -391,7 +425,7 @@ hipError_t launch_csr_l(const CsrDev &A, const double *x, double *out, double *a
 
 template <int NPT, int VW, int SL>
 hipError_t launch_stream_t(const CsrDev &A, const double *x, double *out, double *acc, int remap,
-                           hipStream_t s)
+                           hipStream_t s, const PackTail &tail)
 {
     StreamArgs a;
     a.tile_row = A.tile_row;
@@ -405,25 +439,27 @@ hipError_t launch_stream_t(const CsrDev &A, const double *x, double *out, double
     a.acc = acc;
     a.nnz_alloc = uint32_t(A.nnz_alloc);
     a.n_x = uint32_t(A.n_x);
+    const unsigned grid = unsigned(std::max(A.n_tiles, 0) + pack_blocks<kBlock>(tail));
+    if (grid == 0) return hipSuccess;
     if (A.col16)
-        hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, true>), dim3(unsigned(A.n_tiles)),
-                           dim3(kBlock), 0, s, a, remap);
+        hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, true>), dim3(grid), dim3(kBlock), 0, s, a,
+                           remap, std::max(A.n_tiles, 0), tail);
     else
-        hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, false>), dim3(unsigned(A.n_tiles)),
-                           dim3(kBlock), 0, s, a, remap);
+        hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, false>), dim3(grid), dim3(kBlock), 0, s,
+                           a, remap, std::max(A.n_tiles, 0), tail);
     return hipGetLastError();
 }
 
 template <int NPT, int VW>
 hipError_t launch_stream_v(const CsrDev &A, const double *x, double *out, double *acc, int sl,
-                           int remap, hipStream_t s)
+                           int remap, hipStream_t s, const PackTail &tail)
 {
     switch (sl) {
-        case 1: return launch_stream_t<NPT, VW, 1>(A, x, out, acc, remap, s);
-        case 2: return launch_stream_t<NPT, VW, 2>(A, x, out, acc, remap, s);
-        case 4: return launch_stream_t<NPT, VW, 4>(A, x, out, acc, remap, s);
-        case 8: return launch_stream_t<NPT, VW, 8>(A, x, out, acc, remap, s);
-        case 16: return launch_stream_t<NPT, VW, 16>(A, x, out, acc, remap, s);
+        case 1: return launch_stream_t<NPT, VW, 1>(A, x, out, acc, remap, s, tail);
+        case 2: return launch_stream_t<NPT, VW, 2>(A, x, out, acc, remap, s, tail);
+        case 4: return launch_stream_t<NPT, VW, 4>(A, x, out, acc, remap, s, tail);
+        case 8: return launch_stream_t<NPT, VW, 8>(A, x, out, acc, remap, s, tail);
+        case 16: return launch_stream_t<NPT, VW, 16>(A, x, out, acc, remap, s, tail);
         default: return hipErrorInvalidValue;
     }
 }
@@ -502,10 +538,10 @@ hipError_t launch_sell(const CsrDev &A, const double *x, double *out, double *ac
 }
 
 hipError_t launch_sell16(const CsrDev &A, const double *x, double *out, int xcd_remap,
-                         hipStream_t s)
+                         hipStream_t s, const PackTail &tail)
 {
-    if (A.n_slices <= 0) return hipSuccess;
-    if (A.sell_width <= 0 || A.rows) return hipErrorInvalidValue;
+    if (A.n_slices < 0 || (A.n_slices == 0 && tail.n <= 0)) return hipSuccess;
+    if (A.n_slices > 0 && (A.sell_width <= 0 || A.rows)) return hipErrorInvalidValue;
     Sell16Args a;
     a.off = A.col;
     a.val = A.val;
@@ -518,11 +554,11 @@ hipError_t launch_sell16(const CsrDev &A, const double *x, double *out, int xcd_
     a.off_bytes = A.off_bytes;
     a.n_alloc = uint32_t(A.nnz_alloc);
     a.n_x = uint32_t(A.n_x);
-    const unsigned grid = unsigned(A.n_slices);
+    const unsigned grid = unsigned(A.n_slices + pack_blocks<64>(tail));
     const int remap = xcd_remap == 2 ? 0 : 1;
     switch (A.sell_u) {
-        case 8: hipLaunchKernelGGL(k_sell16<1>, dim3(grid), dim3(64), 0, s, a, remap); break;
-        case 16: hipLaunchKernelGGL(k_sell16<2>, dim3(grid), dim3(64), 0, s, a, remap); break;
+        case 8: hipLaunchKernelGGL(k_sell16<1>, dim3(grid), dim3(64), 0, s, a, remap, tail); break;
+        case 16: hipLaunchKernelGGL(k_sell16<2>, dim3(grid), dim3(64), 0, s, a, remap, tail); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -532,23 +568,24 @@ int stream_cap(int npt) { return kBlock * npt; }
 int stream_maxr(int sum_lanes) { return kBlock / sum_lanes; }
 
 hipError_t launch_csr_stream(const CsrDev &A, const double *x, double *out, double *acc, int npt,
-                             int vw, int sum_lanes, int xcd_remap, hipStream_t s)
+                             int vw, int sum_lanes, int xcd_remap, hipStream_t s,
+                             const PackTail &tail)
 {
-    if (A.n_tiles <= 0) return hipSuccess;
+    if (A.n_tiles <= 0 && tail.n <= 0) return hipSuccess;
     const int remap = xcd_remap == 2 ? 0 : 1;
     if (vw == 2) {
         switch (npt) {
-            case 4: return launch_stream_v<4, 2>(A, x, out, acc, sum_lanes, remap, s);
-            case 8: return launch_stream_v<8, 2>(A, x, out, acc, sum_lanes, remap, s);
-            case 16: return launch_stream_v<16, 2>(A, x, out, acc, sum_lanes, remap, s);
+            case 4: return launch_stream_v<4, 2>(A, x, out, acc, sum_lanes, remap, s, tail);
+            case 8: return launch_stream_v<8, 2>(A, x, out, acc, sum_lanes, remap, s, tail);
+            case 16: return launch_stream_v<16, 2>(A, x, out, acc, sum_lanes, remap, s, tail);
             default: return hipErrorInvalidValue;
         }
     }
     if (vw == 4) {
         switch (npt) {
-            case 4: return launch_stream_v<4, 4>(A, x, out, acc, sum_lanes, remap, s);
-            case 8: return launch_stream_v<8, 4>(A, x, out, acc, sum_lanes, remap, s);
-            case 16: return launch_stream_v<16, 4>(A, x, out, acc, sum_lanes, remap, s);
+            case 4: return launch_stream_v<4, 4>(A, x, out, acc, sum_lanes, remap, s, tail);
+            case 8: return launch_stream_v<8, 4>(A, x, out, acc, sum_lanes, remap, s, tail);
+            case 16: return launch_stream_v<16, 4>(A, x, out, acc, sum_lanes, remap, s, tail);
             default: return hipErrorInvalidValue;
         }
     }

@@ -412,8 +412,18 @@ bool select_slabs(CsrCfg &c, const std::vector<int32_t> &rp, const std::vector<i
     return true;
 }
 
+// y_L's kernel can run Pack as extra blocks of its launch: the stream-CSR
+// packed tiles (forms 1, 4) and the 16-bit sliced form (3).
+bool packs_with_yl(const spmv_plan *p)
+{
+    const CsrCfg &c = p->cfg[0];
+    return c.kernel == SPMV_KERNEL_STREAM && (c.form == 1 || c.form == 3 || c.form == 4);
+}
+
+// `tail`: Pack blocks appended to the launch (y_L in a stream-CSR packed or
+// 16-bit sliced form only, see packs_with_yl).
 hipError_t launch_product(const spmv_plan *p, int side, const double *x, double *out,
-                          double *acc, hipStream_t s)
+                          double *acc, hipStream_t s, const PackTail &tail = PackTail())
 {
     CsrDev A = side == 0 ? local_csr(p) : remote_csr(p);
     const CsrCfg &c = p->cfg[side];
@@ -450,7 +460,7 @@ hipError_t launch_product(const spmv_plan *p, int side, const double *x, double 
         A.nnz_alloc = int64_t(c.sell_val.size()) + kEntryPad;
         if (c.form == 3) {
             A.off_bytes = uint32_t((c.sell_off.size() + 2 * kEntryPad) * 2);
-            return launch_sell16(A, x, out, p->xcd_remap, s);
+            return launch_sell16(A, x, out, p->xcd_remap, s, tail);
         }
         return launch_sell(A, x, out, acc, p->xcd_remap, s);
     }
@@ -459,7 +469,8 @@ hipError_t launch_product(const spmv_plan *p, int side, const double *x, double 
         A.tile_k = p->d_tile_k[side];
         A.n_tiles = int32_t(c.tile_row.size()) - 1;
         A.col16 = c.form == 4;
-        return launch_csr_stream(A, x, out, acc, c.chunk, c.width, c.lanes, p->xcd_remap, s);
+        return launch_csr_stream(A, x, out, acc, c.chunk, c.width, c.lanes, p->xcd_remap, s,
+                                 tail);
     }
     return launch_csr(A, x, out, acc, c.lanes, c.rows, p->xcd_remap, p->use_buffer, s);
 }
@@ -937,9 +948,20 @@ extern "C" int spmv_exec_resident(spmv_plan_t *p, const double *x, double *y, vo
     }
     // Pack, y_L, Unpack, y_R in the order of the DAG's GPU vertices, on one
     // stream: y_R adds into what y_L stored, so y = fl(s_L + s_R) as in
-    // every plan of spmv_exec
-    SPMV_HIP(launch_pack(x, p->d_send_idx, p->d_sendbuf, int64_t(S.send_idx.size()), s));
-    SPMV_HIP(launch_product(p, 0, x, y, nullptr, s));
+    // every plan of spmv_exec.  Pack (it reads only x) runs as extra blocks
+    // of y_L's launch where y_L's kernel takes them.
+    const int64_t n_send = int64_t(S.send_idx.size());
+    if (!p->resident_seq && n_send > 0 && packs_with_yl(p)) {
+        PackTail t;
+        t.x = x;
+        t.idx = p->d_send_idx;
+        t.dst = p->d_sendbuf;
+        t.n = int32_t(n_send);
+        SPMV_HIP(launch_product(p, 0, x, y, nullptr, s, t));
+    } else {
+        SPMV_HIP(launch_pack(x, p->d_send_idx, p->d_sendbuf, n_send, s));
+        SPMV_HIP(launch_product(p, 0, x, y, nullptr, s));
+    }
     if (!p->fuse_unpack)
         SPMV_HIP(launch_unpack(p->d_recvbuf, p->d_perm, p->d_xhalo, int64_t(S.halo.size()), s));
     if (!S.R_rows.empty()) {
@@ -1149,7 +1171,10 @@ extern "C" int spmv_plan_info(const spmv_plan_t *p, spmv_info_t *info)
     info->fuse_unpack = p->fuse_unpack;
     info->fused_combine = p->fused_combine;
     info->device = p->host_only ? -1 : p->device;
-    info->resident_grouped = p->res && !p->resident_seq ? 1 : 0;
+    info->resident_grouped = p->resident_seq ? 0
+                             : p->res        ? 1
+                             : (!p->host_only && !p->share.send_idx.empty() && packs_with_yl(p)) ? 2
+                                             : 0;
     return SPMV_OK;
 }
 

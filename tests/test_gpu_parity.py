@@ -847,8 +847,9 @@ def test_exec_resident_matches_exec(mode):
     Two grouped launches (Pack, y_L and the column-slab tiles as the items
     of one, the slab sums of the other) where y_R is in column slabs and
     y_L in packed tiles (32- or 16-bit columns) of one window and width,
-    with one or two summing lanes and rows longer than a window; otherwise,
-    or with the flag, the ops one by one."""
+    with one or two summing lanes and rows longer than a window; else Pack
+    as extra blocks of y_L's launch where y_L is in packed tiles or the
+    16-bit sliced form; otherwise, or with the flag, the ops one by one."""
     import torch
     flags = {"grouped": 0, "sequential": sp.SPMV_F_RESIDENT_SEQUENTIAL}[mode]
     cases = [(gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5}, 1),
@@ -857,15 +858,17 @@ def test_exec_resident_matches_exec(mode):
               23, {"form": 5}, 1),                                          # long rows
              (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5, "width": 4, "chunk_local": 8,
                                                          "chunk_remote": 8}, 1),
-             (gen.power_law(30000, seed=17), 4, 2, 18, {}, 0),           # y_R in packed tiles
-             (_dense_remote_rows(), 2, 1, 23, {"form": 5}, 0),            # sliced y_L
-             (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5, "fuse_unpack": 2}, 0),
-             (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5, "rows_remote": 2}, 0),
+             (gen.power_law(30000, seed=17), 4, 2, 18, {}, 2),           # y_R in packed tiles
+             (gen.power_law(30000, seed=17), 4, 2, 18, {"form": 1}, 2),  # 32-bit y_L columns
+             (_dense_remote_rows(), 2, 1, 23, {"form": 5}, 0),            # nothing to send
+             (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5, "fuse_unpack": 2}, 2),
+             (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5, "rows_remote": 2}, 2),
              (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5, "kernel_local": 1}, 0),
              (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5, "chunk_local": 8,
-                                                         "chunk_remote": 4}, 0),
-             (gen.laplacian_3d7(24), 4, 1, 20, {}, 0),                   # sliced y_L
-             (gen.laplacian_2d5(40), 1, 0, 21, {"form": 1}, 0)]          # no remote rows
+                                                         "chunk_remote": 4}, 2),
+             (gen.laplacian_3d7(24), 4, 1, 20, {}, 2),                   # 16-bit sliced y_L
+             (gen.stencil_3d27(20, seed=3), 4, 1, 25, {"form": 2}, 0),   # 32-bit sliced y_L
+             (gen.laplacian_2d5(40), 1, 0, 21, {"form": 1}, 0)]          # no send list
     for A, P, r, seed, tune, grouped in cases:
         tune = {**tune, "flags": flags}
         log(f"exec_resident {mode} n={A.n_rows} P={P} r={r} {tune}")
@@ -886,7 +889,7 @@ def test_exec_resident_matches_exec(mode):
                 sp.spmv_exec_resident(plan, xd, yd, torch.cuda.current_stream())
                 torch.cuda.synchronize()
                 assert np.array_equal(bits(yd.cpu().numpy()), bits(res["y"]))
-                if info["resident_grouped"]:   # its two launches one at a time
+                if info["resident_grouped"] == 1:   # its two launches one at a time
                     yd.fill_(float("nan"))
                     for part in (0, 1):
                         sp.spmv_exec_resident_part(plan, part, xd, yd,
