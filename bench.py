@@ -107,7 +107,7 @@ def launch_bytes(info: dict) -> dict:
          "yL": 12 * nl + 4 * (n + 1) + 16 * n,
          "unpack": 0 if info["fuse_unpack"] else 20 * h,
          "yR": 12 * nr + 4 * (rr + 1) + 4 * rr + 8 * h + 16 * rr if rr else 0}
-    if info.get("resident_grouped"):
+    if info.get("resident_grouped") == 1:
         b["grouped"] = b["pack"] + b["yL"] + 12 * nr + 4 * (rr + 1) + 8 * h
         b["slab_sums"] = 4 * rr + 16 * rr
     return b
@@ -859,7 +859,7 @@ def measure_share(sp, torch, gen, key: str, args, sweep: bool = True,
         # stay in the 256 MB MALL (warm)
         op_dom = max(("yL", "yR", "pack"), key=lambda k: LB[k])
         dev_bytes = sum(LB[k] for k in OPS)     # one resident step
-        grouped = bool(info["resident_grouped"])
+        grouped = info["resident_grouped"] == 1
         if grouped:
             # the step's dominant kernel is its first grouped launch (Pack,
             # y_L and y_R's slab tiles as the items of one kernel)
@@ -916,12 +916,13 @@ def measure_share(sp, torch, gen, key: str, args, sweep: bool = True,
                    "n_tiles_local": info["n_tiles_local"], "n_tiles_remote": info["n_tiles_remote"],
                    "xcd_remap": info["xcd_remap"], "fuse_unpack": info["fuse_unpack"],
                    "fused_combine": info["fused_combine"], "replicas": R,
-                   "step": ("Pack, y_L and y_R's column-slab tiles as one grouped launch, then "
-                            "the slab sums into y, halo resident in HBM (spmv_exec_resident)"
-                            if grouped else
-                            "Pack, y_L, Unpack, y_R of the share on one stream, halo resident "
-                            "in HBM (spmv_exec_resident)"),
-                   "resident_grouped": int(grouped),
+                   "step": {1: "Pack, y_L and y_R's column-slab tiles as one grouped launch, "
+                                   "then the slab sums into y",
+                            2: "y_L with Pack as extra blocks of its launch, then y_R into y",
+                            0: "Pack, y_L, Unpack, y_R, one launch each"}[
+                                info["resident_grouped"]] +
+                           ", on one stream, halo resident in HBM (spmv_exec_resident)",
+                   "resident_grouped": info["resident_grouped"],
                    "step_device_bytes": dev_bytes, "exec_device_bytes": B["total"],
                    "exec_host_link_bytes": B["host_link"]},
         "roofline": {"bound": "hbm", "kernel": f"{dom} {dom_variant}",
@@ -968,7 +969,7 @@ def kernel_only(sp, torch, key, info, plans, xs, ys, stream, args) -> dict:
     then a plain copy of known size whose FETCH_SIZE / WRITE_SIZE readings
     calibrate the counters."""
     LB = launch_bytes(info)
-    name = args.op or ("grouped" if info["resident_grouped"]
+    name = args.op or ("grouped" if info["resident_grouped"] == 1
                        else max(("yL", "yR", "pack"), key=lambda k: LB[k]))
     launches = max(10 * len(plans), 200)
     if name in ("grouped", "slab_sums"):
