@@ -203,18 +203,22 @@ int pack_blocks(const PackTail &P)
 }
 
 // Single-share stream-CSR product: one block per tile (see spmv_stream.h);
-// the n_tiles blocks are followed by the PackTail's blocks.
-template <int NPT, int VW, int SL, bool C16>
+// with TAIL the n_tiles blocks are followed by the PackTail's blocks (the
+// instances without it are the plain product).
+template <int NPT, int VW, int SL, bool C16, bool TAIL>
 __global__ __launch_bounds__(kBlock) void k_csr_stream(StreamArgs A, int remap, int n_tiles,
                                                        PackTail P)
 {
     __shared__ double s_p[kBlock * NPT];
     __shared__ int32_t s_rp[kBlock / SL + 1];
-    if (int(blockIdx.x) >= n_tiles) {   // whole block, before any barrier
-        pack_block<kBlock>(P, int(blockIdx.x) - n_tiles);
-        return;
+    if constexpr (TAIL) {
+        if (int(blockIdx.x) >= n_tiles) {   // whole block, before any barrier
+            pack_block<kBlock>(P, int(blockIdx.x) - n_tiles);
+            return;
+        }
     }
-    stream_tile<NPT, VW, SL, C16>(A, tile_of_block(int(blockIdx.x), n_tiles, remap), s_p, s_rp);
+    stream_tile<NPT, VW, SL, C16>(A, tile_of_block(int(blockIdx.x), TAIL ? n_tiles : int(gridDim.x), remap),
+                                  s_p, s_rp);
 }
 
 // Sliced-ELL product: one wave per slice of 64 rows; lane l owns row
@@ -307,15 +311,18 @@ __device__ __forceinline__ void unpack16(const uint32_t w, int32_t &lo, int32_t 
     hi = int32_t(w) >> 16;
 }
 
-template <int NG>
+template <int NG, bool TAIL>
 __global__ __launch_bounds__(64) void k_sell16(Sell16Args A, int remap, PackTail P)
 {
     constexpr int U = 8 * NG;
-    if (int(blockIdx.x) >= A.n_slices) {   // the PackTail's blocks follow the slices
-        pack_block<64>(P, int(blockIdx.x) - A.n_slices);
-        return;
+    if constexpr (TAIL) {
+        if (int(blockIdx.x) >= A.n_slices) {   // the PackTail's blocks follow the slices
+            pack_block<64>(P, int(blockIdx.x) - A.n_slices);
+            return;
+        }
     }
-    const int slice = tile_of_block(int(blockIdx.x), A.n_slices, remap);
+    const int slice = tile_of_block(int(blockIdx.x), TAIL ? A.n_slices : int(gridDim.x), remap);
+    if (slice >= A.n_slices) return;
     const int lane = int(threadIdx.x);
     const int r = slice * 64 + lane;
     const auto r_off = rsrc(A.off, A.off_bytes);
@@ -439,14 +446,21 @@ hipError_t launch_stream_t(const CsrDev &A, const double *x, double *out, double
     a.acc = acc;
     a.nnz_alloc = uint32_t(A.nnz_alloc);
     a.n_x = uint32_t(A.n_x);
-    const unsigned grid = unsigned(std::max(A.n_tiles, 0) + pack_blocks<kBlock>(tail));
+    const int nt = std::max(A.n_tiles, 0), nb = pack_blocks<kBlock>(tail);
+    const unsigned grid = unsigned(nt + nb);
     if (grid == 0) return hipSuccess;
-    if (A.col16)
-        hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, true>), dim3(grid), dim3(kBlock), 0, s, a,
-                           remap, std::max(A.n_tiles, 0), tail);
+    if (A.col16 && nb)
+        hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, true, true>), dim3(grid), dim3(kBlock), 0, s,
+                           a, remap, nt, tail);
+    else if (A.col16)
+        hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, true, false>), dim3(grid), dim3(kBlock), 0,
+                           s, a, remap, nt, tail);
+    else if (nb)
+        hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, false, true>), dim3(grid), dim3(kBlock), 0,
+                           s, a, remap, nt, tail);
     else
-        hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, false>), dim3(grid), dim3(kBlock), 0, s,
-                           a, remap, std::max(A.n_tiles, 0), tail);
+        hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, false, false>), dim3(grid), dim3(kBlock), 0,
+                           s, a, remap, nt, tail);
     return hipGetLastError();
 }
 
@@ -554,11 +568,14 @@ hipError_t launch_sell16(const CsrDev &A, const double *x, double *out, int xcd_
     a.off_bytes = A.off_bytes;
     a.n_alloc = uint32_t(A.nnz_alloc);
     a.n_x = uint32_t(A.n_x);
-    const unsigned grid = unsigned(A.n_slices + pack_blocks<64>(tail));
+    const int nb = pack_blocks<64>(tail);
+    const unsigned grid = unsigned(A.n_slices + nb);
     const int remap = xcd_remap == 2 ? 0 : 1;
-    switch (A.sell_u) {
-        case 8: hipLaunchKernelGGL(k_sell16<1>, dim3(grid), dim3(64), 0, s, a, remap, tail); break;
-        case 16: hipLaunchKernelGGL(k_sell16<2>, dim3(grid), dim3(64), 0, s, a, remap, tail); break;
+    switch (A.sell_u * 2 + (nb ? 1 : 0)) {
+        case 16: hipLaunchKernelGGL((k_sell16<1, false>), dim3(grid), dim3(64), 0, s, a, remap, tail); break;
+        case 17: hipLaunchKernelGGL((k_sell16<1, true>), dim3(grid), dim3(64), 0, s, a, remap, tail); break;
+        case 32: hipLaunchKernelGGL((k_sell16<2, false>), dim3(grid), dim3(64), 0, s, a, remap, tail); break;
+        case 33: hipLaunchKernelGGL((k_sell16<2, true>), dim3(grid), dim3(64), 0, s, a, remap, tail); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
