@@ -209,6 +209,9 @@ struct PackTail {
     int32_t n = 0;
 };
 constexpr int kPackPerThread = 4;
+// Longest send list a PackTail takes (its block and entry indices are int;
+// a longer one runs Pack as a kernel of its own).
+constexpr int64_t kPackTailMax = int64_t(1) << 30;
 hipError_t launch_csr_stream(const CsrDev &A, const double *x, double *out, double *acc,
                              int npt, int vw, int sum_lanes, int xcd_remap, hipStream_t s,
                              const PackTail &tail = PackTail());

@@ -951,7 +951,7 @@ extern "C" int spmv_exec_resident(spmv_plan_t *p, const double *x, double *y, vo
     // every plan of spmv_exec.  Pack (it reads only x) runs as extra blocks
     // of y_L's launch where y_L's kernel takes them.
     const int64_t n_send = int64_t(S.send_idx.size());
-    if (!p->resident_seq && n_send > 0 && packs_with_yl(p)) {
+    if (!p->resident_seq && n_send > 0 && n_send <= kPackTailMax && packs_with_yl(p)) {
         PackTail t;
         t.x = x;
         t.idx = p->d_send_idx;
@@ -1173,7 +1173,8 @@ extern "C" int spmv_plan_info(const spmv_plan_t *p, spmv_info_t *info)
     info->device = p->host_only ? -1 : p->device;
     info->resident_grouped = p->resident_seq ? 0
                              : p->res        ? 1
-                             : (!p->host_only && !p->share.send_idx.empty() && packs_with_yl(p)) ? 2
+                             : (!p->host_only && !p->share.send_idx.empty() &&
+                                int64_t(p->share.send_idx.size()) <= kPackTailMax && packs_with_yl(p)) ? 2
                                              : 0;
     return SPMV_OK;
 }
