@@ -208,13 +208,30 @@ struct PackTail {
     double *dst = nullptr;
     int32_t n = 0;
 };
+// The remote part of a row added where the row's local sum is stored (the
+// resident step with y_R in y_L's launch).  Local rows come in groups of
+// 64: mask[g] marks the rows of group g that have remote entries, j0[g] is
+// the compressed index of the first of them; A_R is a CSR over the
+// compressed rows (rp, col into xh = x_halo, val).  The remote sum repeats
+// the arithmetic of the plan's y_R kernel: an fma chain over the row's
+// entries in order (sliced form, fma_chain = 1), or each product rounded
+// and the products added left to right from zero (packed tiles with one
+// summing lane), so that local + remote has the bits of spmv_exec.
+// mask == nullptr: no remote part.
+struct RemoteFuse {
+    const uint64_t *mask = nullptr;
+    const int32_t *j0 = nullptr, *rp = nullptr, *col = nullptr;
+    const double *val = nullptr, *xh = nullptr;
+    int32_t fma_chain = 0;
+};
 constexpr int kPackPerThread = 4;
 // Longest send list a PackTail takes (its block and entry indices are int;
 // a longer one runs Pack as a kernel of its own).
 constexpr int64_t kPackTailMax = int64_t(1) << 30;
 hipError_t launch_csr_stream(const CsrDev &A, const double *x, double *out, double *acc,
                              int npt, int vw, int sum_lanes, int xcd_remap, hipStream_t s,
-                             const PackTail &tail = PackTail());
+                             const PackTail &tail = PackTail(),
+                             const RemoteFuse &rem = RemoteFuse());
 // Sliced-ELL product (CsrDev.sell_ptr set): one wave per slice of 64 rows.
 hipError_t launch_sell(const CsrDev &A, const double *x, double *out, double *acc,
                        int xcd_remap, hipStream_t s);
@@ -266,7 +283,8 @@ bool build_sell(const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
 // for every slice, values in pairs: see pair_values): entries in groups of
 // 8 per lane, 8 * `sell_u` entries per batch of loads.
 hipError_t launch_sell16(const CsrDev &A, const double *x, double *out, int xcd_remap,
-                         hipStream_t s, const PackTail &tail = PackTail());
+                         hipStream_t s, const PackTail &tail = PackTail(),
+                         const RemoteFuse &rem = RemoteFuse());
 // Padding marker of the 16-bit column offsets (never a valid offset).
 constexpr int16_t kPad16 = -32768;
 // The columns of a uniform-width sliced layout as offsets from the row:
@@ -393,6 +411,13 @@ struct spmv_plan {
     double *d_slab_part = nullptr;   // form 5: [kSlabs * n_remote_rows]
     spmv::ResidentProg *res = nullptr;   // grouped resident step, or null
     bool resident_seq = false;       // resident step op by op even with res
+    // resident step in y_L's launch (rf.mask set): per 64 local rows the
+    // mask of remote rows and the first one's compressed index, and A_R's
+    // CSR (y_R's own arrays in packed tiles, a copy beside the sliced form)
+    spmv::RemoteFuse rf;
+    uint64_t *d_rf_mask = nullptr;
+    int32_t *d_rf_j0 = nullptr, *d_rf_rp = nullptr, *d_rf_col = nullptr;
+    double *d_rf_val = nullptr;
     int32_t *d_tile_row[2] = {}, *d_tile_k[2] = {};
     int32_t *d_sell_ptr[2] = {};
 

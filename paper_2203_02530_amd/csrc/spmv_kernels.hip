@@ -207,7 +207,7 @@ int pack_blocks(const PackTail &P)
 // instances without it are the plain product).
 template <int NPT, int VW, int SL, bool C16, bool TAIL>
 __global__ __launch_bounds__(kBlock) void k_csr_stream(StreamArgs A, int remap, int n_tiles,
-                                                       PackTail P)
+                                                       PackTail P, RemoteFuse F)
 {
     __shared__ double s_p[kBlock * NPT];
     __shared__ int32_t s_rp[kBlock / SL + 1];
@@ -216,9 +216,12 @@ __global__ __launch_bounds__(kBlock) void k_csr_stream(StreamArgs A, int remap, 
             pack_block<kBlock>(P, int(blockIdx.x) - n_tiles);
             return;
         }
+        stream_tile<NPT, VW, SL, C16>(A, tile_of_block(int(blockIdx.x), n_tiles, remap), s_p,
+                                      s_rp, &F);
+    } else {
+        stream_tile<NPT, VW, SL, C16>(A, tile_of_block(int(blockIdx.x), int(gridDim.x), remap),
+                                      s_p, s_rp);
     }
-    stream_tile<NPT, VW, SL, C16>(A, tile_of_block(int(blockIdx.x), TAIL ? n_tiles : int(gridDim.x), remap),
-                                  s_p, s_rp);
 }
 
 // Sliced-ELL product: one wave per slice of 64 rows; lane l owns row
@@ -312,7 +315,7 @@ __device__ __forceinline__ void unpack16(const uint32_t w, int32_t &lo, int32_t 
 }
 
 template <int NG, bool TAIL>
-__global__ __launch_bounds__(64) void k_sell16(Sell16Args A, int remap, PackTail P)
+__global__ __launch_bounds__(64) void k_sell16(Sell16Args A, int remap, PackTail P, RemoteFuse F)
 {
     constexpr int U = 8 * NG;
     if constexpr (TAIL) {
@@ -373,7 +376,11 @@ __global__ __launch_bounds__(64) void k_sell16(Sell16Args A, int remap, PackTail
             if (d[u] != kPad16) s = fma(av, xv[u], s);
         }
     }
-    if (r < A.n_rows) A.out[r] = s;
+    if (r < A.n_rows) {
+        if constexpr (TAIL)
+            if (F.mask) s = remote_add(F, r, s);
+        A.out[r] = s;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_gather(const double *__restrict__ src,
@@ -432,7 +439,7 @@ hipError_t launch_csr_l(const CsrDev &A, const double *x, double *out, double *a
 
 template <int NPT, int VW, int SL>
 hipError_t launch_stream_t(const CsrDev &A, const double *x, double *out, double *acc, int remap,
-                           hipStream_t s, const PackTail &tail)
+                           hipStream_t s, const PackTail &tail, const RemoteFuse &rem)
 {
     StreamArgs a;
     a.tile_row = A.tile_row;
@@ -449,31 +456,32 @@ hipError_t launch_stream_t(const CsrDev &A, const double *x, double *out, double
     const int nt = std::max(A.n_tiles, 0), nb = pack_blocks<kBlock>(tail);
     const unsigned grid = unsigned(nt + nb);
     if (grid == 0) return hipSuccess;
-    if (A.col16 && nb)
+    const bool tl = nb > 0 || rem.mask;   // the resident step's instance
+    if (A.col16 && tl)
         hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, true, true>), dim3(grid), dim3(kBlock), 0, s,
-                           a, remap, nt, tail);
+                           a, remap, nt, tail, rem);
     else if (A.col16)
         hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, true, false>), dim3(grid), dim3(kBlock), 0,
-                           s, a, remap, nt, tail);
-    else if (nb)
+                           s, a, remap, nt, tail, rem);
+    else if (tl)
         hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, false, true>), dim3(grid), dim3(kBlock), 0,
-                           s, a, remap, nt, tail);
+                           s, a, remap, nt, tail, rem);
     else
         hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, false, false>), dim3(grid), dim3(kBlock), 0,
-                           s, a, remap, nt, tail);
+                           s, a, remap, nt, tail, rem);
     return hipGetLastError();
 }
 
 template <int NPT, int VW>
 hipError_t launch_stream_v(const CsrDev &A, const double *x, double *out, double *acc, int sl,
-                           int remap, hipStream_t s, const PackTail &tail)
+                           int remap, hipStream_t s, const PackTail &tail, const RemoteFuse &rem)
 {
     switch (sl) {
-        case 1: return launch_stream_t<NPT, VW, 1>(A, x, out, acc, remap, s, tail);
-        case 2: return launch_stream_t<NPT, VW, 2>(A, x, out, acc, remap, s, tail);
-        case 4: return launch_stream_t<NPT, VW, 4>(A, x, out, acc, remap, s, tail);
-        case 8: return launch_stream_t<NPT, VW, 8>(A, x, out, acc, remap, s, tail);
-        case 16: return launch_stream_t<NPT, VW, 16>(A, x, out, acc, remap, s, tail);
+        case 1: return launch_stream_t<NPT, VW, 1>(A, x, out, acc, remap, s, tail, rem);
+        case 2: return launch_stream_t<NPT, VW, 2>(A, x, out, acc, remap, s, tail, rem);
+        case 4: return launch_stream_t<NPT, VW, 4>(A, x, out, acc, remap, s, tail, rem);
+        case 8: return launch_stream_t<NPT, VW, 8>(A, x, out, acc, remap, s, tail, rem);
+        case 16: return launch_stream_t<NPT, VW, 16>(A, x, out, acc, remap, s, tail, rem);
         default: return hipErrorInvalidValue;
     }
 }
@@ -552,7 +560,7 @@ hipError_t launch_sell(const CsrDev &A, const double *x, double *out, double *ac
 }
 
 hipError_t launch_sell16(const CsrDev &A, const double *x, double *out, int xcd_remap,
-                         hipStream_t s, const PackTail &tail)
+                         hipStream_t s, const PackTail &tail, const RemoteFuse &rem)
 {
     if (A.n_slices < 0 || (A.n_slices == 0 && tail.n <= 0)) return hipSuccess;
     if (A.n_slices > 0 && (A.sell_width <= 0 || A.rows)) return hipErrorInvalidValue;
@@ -571,11 +579,11 @@ hipError_t launch_sell16(const CsrDev &A, const double *x, double *out, int xcd_
     const int nb = pack_blocks<64>(tail);
     const unsigned grid = unsigned(A.n_slices + nb);
     const int remap = xcd_remap == 2 ? 0 : 1;
-    switch (A.sell_u * 2 + (nb ? 1 : 0)) {
-        case 16: hipLaunchKernelGGL((k_sell16<1, false>), dim3(grid), dim3(64), 0, s, a, remap, tail); break;
-        case 17: hipLaunchKernelGGL((k_sell16<1, true>), dim3(grid), dim3(64), 0, s, a, remap, tail); break;
-        case 32: hipLaunchKernelGGL((k_sell16<2, false>), dim3(grid), dim3(64), 0, s, a, remap, tail); break;
-        case 33: hipLaunchKernelGGL((k_sell16<2, true>), dim3(grid), dim3(64), 0, s, a, remap, tail); break;
+    switch (A.sell_u * 2 + (nb > 0 || rem.mask ? 1 : 0)) {
+        case 16: hipLaunchKernelGGL((k_sell16<1, false>), dim3(grid), dim3(64), 0, s, a, remap, tail, rem); break;
+        case 17: hipLaunchKernelGGL((k_sell16<1, true>), dim3(grid), dim3(64), 0, s, a, remap, tail, rem); break;
+        case 32: hipLaunchKernelGGL((k_sell16<2, false>), dim3(grid), dim3(64), 0, s, a, remap, tail, rem); break;
+        case 33: hipLaunchKernelGGL((k_sell16<2, true>), dim3(grid), dim3(64), 0, s, a, remap, tail, rem); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -586,23 +594,23 @@ int stream_maxr(int sum_lanes) { return kBlock / sum_lanes; }
 
 hipError_t launch_csr_stream(const CsrDev &A, const double *x, double *out, double *acc, int npt,
                              int vw, int sum_lanes, int xcd_remap, hipStream_t s,
-                             const PackTail &tail)
+                             const PackTail &tail, const RemoteFuse &rem)
 {
     if (A.n_tiles <= 0 && tail.n <= 0) return hipSuccess;
     const int remap = xcd_remap == 2 ? 0 : 1;
     if (vw == 2) {
         switch (npt) {
-            case 4: return launch_stream_v<4, 2>(A, x, out, acc, sum_lanes, remap, s, tail);
-            case 8: return launch_stream_v<8, 2>(A, x, out, acc, sum_lanes, remap, s, tail);
-            case 16: return launch_stream_v<16, 2>(A, x, out, acc, sum_lanes, remap, s, tail);
+            case 4: return launch_stream_v<4, 2>(A, x, out, acc, sum_lanes, remap, s, tail, rem);
+            case 8: return launch_stream_v<8, 2>(A, x, out, acc, sum_lanes, remap, s, tail, rem);
+            case 16: return launch_stream_v<16, 2>(A, x, out, acc, sum_lanes, remap, s, tail, rem);
             default: return hipErrorInvalidValue;
         }
     }
     if (vw == 4) {
         switch (npt) {
-            case 4: return launch_stream_v<4, 4>(A, x, out, acc, sum_lanes, remap, s, tail);
-            case 8: return launch_stream_v<8, 4>(A, x, out, acc, sum_lanes, remap, s, tail);
-            case 16: return launch_stream_v<16, 4>(A, x, out, acc, sum_lanes, remap, s, tail);
+            case 4: return launch_stream_v<4, 4>(A, x, out, acc, sum_lanes, remap, s, tail, rem);
+            case 8: return launch_stream_v<8, 4>(A, x, out, acc, sum_lanes, remap, s, tail, rem);
+            case 16: return launch_stream_v<16, 4>(A, x, out, acc, sum_lanes, remap, s, tail, rem);
             default: return hipErrorInvalidValue;
         }
     }

@@ -80,6 +80,45 @@ namespace {
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
+// y_L's kernel can run Pack as extra blocks of its launch: the stream-CSR
+// packed tiles (forms 1, 4) and the 16-bit sliced form (3).
+bool packs_with_yl(const spmv_plan *p)
+{
+    const CsrCfg &c = p->cfg[0];
+    return c.kernel == SPMV_KERNEL_STREAM && (c.form == 1 || c.form == 3 || c.form == 4);
+}
+
+// y_R can be added where y_L stores its rows (the resident step in one
+// launch): y_L's kernel takes the extra work, the Unpack is fused, every
+// remote row is short, and y_R's kernel sums a row the way remote_add
+// does: the sliced form (an fma chain), or packed tiles with one summing
+// lane and no row longer than a window (those a block sums with fma
+// chains and a tree).  Short: the remote rows of a contiguous row block
+// sit in its first and last tiles, which the XCD-contiguous tile order
+// puts on two XCDs, and one lane of each row walks its remote entries;
+// with one entry per remote row (7-point share) the step took 10.6 us
+// against 12.9 with y_R in a launch of its own, with nine (27-point) 30.2
+// against 26.8.
+constexpr int kFuseMaxRemote = 4;
+
+bool fuses_remote(const spmv_plan *p)
+{
+    const Share &S = p->share;
+    const CsrCfg &c = p->cfg[1];
+    if (!packs_with_yl(p) || !p->fuse_unpack || S.R_rows.empty()) return false;
+    if (int64_t(S.send_idx.size()) > kPackTailMax || c.kernel != SPMV_KERNEL_STREAM) return false;
+    for (size_t j = 0; j + 1 < S.R_ptr.size(); ++j)
+        if (S.R_ptr[j + 1] - S.R_ptr[j] > kFuseMaxRemote) return false;
+    if (c.form == 2) return true;
+    if (c.form != 1 || c.lanes != 1) return false;
+    const int cap = stream_cap(c.chunk);
+    for (size_t t = 0; t + 1 < c.tile_row.size(); ++t)
+        if (c.tile_row[t + 1] - c.tile_row[t] == 1 &&
+            c.tile_k[t + 1] - (c.tile_k[t] & ~(c.width - 1)) > cap)
+            return false;
+    return true;
+}
+
 void release(spmv_plan *p)
 {
     if (!p) return;
@@ -116,6 +155,23 @@ int allocate_and_upload(spmv_plan *p)
     };
     const size_t n_halo = S.halo.size(), n_send = S.send_idx.size(), n_rr = S.R_rows.size();
     const size_t pad = kEntryPad;
+    // the resident step in y_L's launch: masks of remote rows per 64 local
+    // rows, and A_R's CSR where y_R's arrays hold the sliced layout
+    const bool rf = fuses_remote(p);
+    const bool rf_copy = rf && p->cfg[1].form != 1;
+    std::vector<uint64_t> rf_mask;
+    std::vector<int32_t> rf_j0;
+    if (rf) {
+        const int64_t ng = (S.n_loc + 63) / 64;
+        rf_mask.assign(size_t(ng), 0);
+        rf_j0.assign(size_t(ng), 0);
+        size_t j = 0;
+        for (int64_t g = 0; g < ng; ++g) {
+            rf_j0[size_t(g)] = int32_t(j);
+            for (; j < n_rr && S.R_rows[j] < (g + 1) * 64; ++j)
+                rf_mask[size_t(g)] |= uint64_t(1) << (S.R_rows[j] - g * 64);
+        }
+    }
     // col/val of each product: the CSR arrays, or the sliced layout (form
     // 2), whose columns form 3 replaces by 16-bit offsets
     auto sliced = [&](int side) { return p->cfg[side].form == 2 || p->cfg[side].form == 3; };
@@ -164,6 +220,11 @@ int allocate_and_upload(spmv_plan *p)
         {(void **)&p->d_xhalo, p->fuse_unpack ? 0 : n_halo * 8, nullptr, 0},
         {(void **)&p->d_part, n_rr * 8, nullptr, 0},
         {(void **)&p->d_slab_part, p->cfg[1].form == 5 ? kSlabs * n_rr * 8 : 0, nullptr, 0},
+        {(void **)&p->d_rf_mask, rf_mask.size() * 8, rf_mask.data(), 0},
+        {(void **)&p->d_rf_j0, rf_j0.size() * 4, rf_j0.data(), 0},
+        {(void **)&p->d_rf_rp, rf_copy ? S.R_ptr.size() * 4 : 0, S.R_ptr.data(), 0},
+        {(void **)&p->d_rf_col, rf_copy ? S.R_col.size() * 4 : 0, S.R_col.data(), 0},
+        {(void **)&p->d_rf_val, rf_copy ? S.R_val.size() * 8 : 0, S.R_val.data(), 0},
     };
     size_t total = 0;
     for (const Item &it : items) total += align_up(std::max<size_t>(it.bytes + it.pad, 1));
@@ -198,6 +259,15 @@ int allocate_and_upload(spmv_plan *p)
             SPMV_HIP(hipEventCreate(&p->ev_b[i]));
             SPMV_HIP(hipEventCreate(&p->ev_e[i]));
         }
+    if (rf) {
+        p->rf.mask = p->d_rf_mask;
+        p->rf.j0 = p->d_rf_j0;
+        p->rf.rp = rf_copy ? p->d_rf_rp : p->dR_ptr;
+        p->rf.col = rf_copy ? p->d_rf_col : p->dR_col;
+        p->rf.val = rf_copy ? p->d_rf_val : p->dR_val;
+        p->rf.xh = p->d_recvbuf;
+        p->rf.fma_chain = p->cfg[1].form == 2 ? 1 : 0;
+    }
     if (int rc = resident_build(p)) return rc;
     SPMV_HIP(hipDeviceSynchronize());
     return SPMV_OK;
@@ -412,18 +482,11 @@ bool select_slabs(CsrCfg &c, const std::vector<int32_t> &rp, const std::vector<i
     return true;
 }
 
-// y_L's kernel can run Pack as extra blocks of its launch: the stream-CSR
-// packed tiles (forms 1, 4) and the 16-bit sliced form (3).
-bool packs_with_yl(const spmv_plan *p)
-{
-    const CsrCfg &c = p->cfg[0];
-    return c.kernel == SPMV_KERNEL_STREAM && (c.form == 1 || c.form == 3 || c.form == 4);
-}
-
 // `tail`: Pack blocks appended to the launch (y_L in a stream-CSR packed or
 // 16-bit sliced form only, see packs_with_yl).
 hipError_t launch_product(const spmv_plan *p, int side, const double *x, double *out,
-                          double *acc, hipStream_t s, const PackTail &tail = PackTail())
+                          double *acc, hipStream_t s, const PackTail &tail = PackTail(),
+                          const RemoteFuse &rem = RemoteFuse())
 {
     CsrDev A = side == 0 ? local_csr(p) : remote_csr(p);
     const CsrCfg &c = p->cfg[side];
@@ -460,7 +523,7 @@ hipError_t launch_product(const spmv_plan *p, int side, const double *x, double 
         A.nnz_alloc = int64_t(c.sell_val.size()) + kEntryPad;
         if (c.form == 3) {
             A.off_bytes = uint32_t((c.sell_off.size() + 2 * kEntryPad) * 2);
-            return launch_sell16(A, x, out, p->xcd_remap, s, tail);
+            return launch_sell16(A, x, out, p->xcd_remap, s, tail, rem);
         }
         return launch_sell(A, x, out, acc, p->xcd_remap, s);
     }
@@ -470,7 +533,7 @@ hipError_t launch_product(const spmv_plan *p, int side, const double *x, double 
         A.n_tiles = int32_t(c.tile_row.size()) - 1;
         A.col16 = c.form == 4;
         return launch_csr_stream(A, x, out, acc, c.chunk, c.width, c.lanes, p->xcd_remap, s,
-                                 tail);
+                                 tail, rem);
     }
     return launch_csr(A, x, out, acc, c.lanes, c.rows, p->xcd_remap, p->use_buffer, s);
 }
@@ -951,12 +1014,18 @@ extern "C" int spmv_exec_resident(spmv_plan_t *p, const double *x, double *y, vo
     // every plan of spmv_exec.  Pack (it reads only x) runs as extra blocks
     // of y_L's launch where y_L's kernel takes them.
     const int64_t n_send = int64_t(S.send_idx.size());
+    PackTail t;
+    t.x = x;
+    t.idx = p->d_send_idx;
+    t.dst = p->d_sendbuf;
+    t.n = int32_t(std::min<int64_t>(n_send, kPackTailMax));
+    if (!p->resident_seq && p->rf.mask) {
+        // the whole step in y_L's launch: Pack as extra blocks, each row's
+        // remote sum added where its local sum is stored
+        SPMV_HIP(launch_product(p, 0, x, y, nullptr, s, t, p->rf));
+        return SPMV_OK;
+    }
     if (!p->resident_seq && n_send > 0 && n_send <= kPackTailMax && packs_with_yl(p)) {
-        PackTail t;
-        t.x = x;
-        t.idx = p->d_send_idx;
-        t.dst = p->d_sendbuf;
-        t.n = int32_t(n_send);
         SPMV_HIP(launch_product(p, 0, x, y, nullptr, s, t));
     } else {
         SPMV_HIP(launch_pack(x, p->d_send_idx, p->d_sendbuf, n_send, s));
@@ -1173,6 +1242,7 @@ extern "C" int spmv_plan_info(const spmv_plan_t *p, spmv_info_t *info)
     info->device = p->host_only ? -1 : p->device;
     info->resident_grouped = p->resident_seq ? 0
                              : p->res        ? 1
+                             : p->rf.mask    ? 3
                              : (!p->host_only && !p->share.send_idx.empty() &&
                                 int64_t(p->share.send_idx.size()) <= kPackTailMax && packs_with_yl(p)) ? 2
                                              : 0;

@@ -14,6 +14,7 @@
 #pragma once
 
 #include "spmv_device.h"
+#include "spmv_internal.h"
 
 namespace spmv {
 
@@ -124,6 +125,51 @@ __device__ __forceinline__ double load_x(__amdgpu_buffer_rsrc_t rx, uint32_t off
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rx, off, 0, 0));
 }
 
+// The remote sum of entries [e0, e1), 8 at a time: columns and values of
+// the 8 first, then their x values, then the 8 terms in order (FMA: an fma
+// chain; else each product rounded, then added).
+template <bool FMA>
+__device__ __forceinline__ double remote_sum(const RemoteFuse &F, int e0, int e1)
+{
+#pragma clang fp contract(off)
+    double t = 0.0;
+    for (int e = e0; e < e1; e += 8) {
+        int32_t c[8];
+        double a[8], xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const bool in = e + u < e1;
+            c[u] = in ? F.col[e + u] : 0;
+            a[u] = in ? F.val[e + u] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xv[u] = e + u < e1 ? F.xh[c[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (e + u >= e1) break;
+            if constexpr (FMA) {
+                t = fma(a[u], xv[u], t);
+            } else {
+                const double p = a[u] * xv[u];
+                t += p;
+            }
+        }
+    }
+    return t;
+}
+
+// fl(s + s_R(r)) for a local row r with remote entries, else s.
+__device__ __forceinline__ double remote_add(const RemoteFuse &F, int r, double s)
+{
+    const uint64_t m = F.mask[r >> 6];
+    const int l = r & 63;
+    if (!((m >> l) & 1ull)) return s;
+    const int j = F.j0[r >> 6] + __popcll(m & ((1ull << l) - 1ull));
+    const int e0 = F.rp[j], e1 = F.rp[j + 1];
+    const double t = F.fma_chain ? remote_sum<true>(F, e0, e1) : remote_sum<false>(F, e0, e1);
+    return s + t;
+}
+
 // Operands of one stream-CSR product.  out[r] = row sum (acc == nullptr) or
 // acc[rows[r]] += row sum.  nnz_alloc = entries incl. padding, n_x = |x|.
 // With 16-bit columns (C16), col holds int16 offsets of each entry's column
@@ -204,7 +250,8 @@ __device__ __forceinline__ void tile_gather(__amdgpu_buffer_rsrc_t r_x, TileRegs
 // consecutive tiles with another (LDS is reused).
 template <int NPT, int VW, int SL>
 __device__ __forceinline__ void tile_reduce(const StreamArgs &A, const TileRegs<NPT, VW> &T,
-                                            double *s_p, int32_t *s_rp)
+                                            double *s_p, int32_t *s_rp,
+                                            const RemoteFuse *F = nullptr)
 {
     const int tid = int(threadIdx.x);
 #pragma unroll
@@ -233,6 +280,7 @@ __device__ __forceinline__ void tile_reduce(const StreamArgs &A, const TileRegs<
     }
     s = group_sum<SL>(s);
     if (lane == SL - 1 && g < T.nr) {
+        if (F && F->mask) s = remote_add(*F, T.r0 + g, s);
         if (A.acc)
             A.acc[A.rows[T.r0 + g]] += s;
         else
@@ -247,7 +295,7 @@ template <int NPT, int VW, bool C16 = false>
 __device__ __forceinline__ void long_row_tile(const StreamArgs &A, __amdgpu_buffer_rsrc_t r_col,
                                               __amdgpu_buffer_rsrc_t r_val,
                                               __amdgpu_buffer_rsrc_t r_x, int r0, int k0, int k1,
-                                              double *s_p)
+                                              double *s_p, const RemoteFuse *F = nullptr)
 {
     constexpr int CAP = kBlock * NPT;
     constexpr int NV = NPT / VW;
@@ -279,7 +327,8 @@ __device__ __forceinline__ void long_row_tile(const StreamArgs &A, __amdgpu_buff
     if ((tid & 63) == 63) s_p[tid >> 6] = s;
     __syncthreads();
     if (tid == 0) {
-        const double tot = (s_p[0] + s_p[1]) + (s_p[2] + s_p[3]);
+        double tot = (s_p[0] + s_p[1]) + (s_p[2] + s_p[3]);
+        if (F && F->mask) tot = remote_add(*F, r0, tot);
         if (A.acc)
             A.acc[A.rows[r0]] += tot;
         else
@@ -291,7 +340,8 @@ __device__ __forceinline__ void long_row_tile(const StreamArgs &A, __amdgpu_buff
 // Block-uniform control flow; the caller separates consecutive tiles with a
 // barrier (LDS is reused).
 template <int NPT, int VW, int SL, bool C16 = false>
-__device__ __forceinline__ void stream_tile(const StreamArgs &A, int t, double *s_p, int32_t *s_rp)
+__device__ __forceinline__ void stream_tile(const StreamArgs &A, int t, double *s_p, int32_t *s_rp,
+                                            const RemoteFuse *F = nullptr)
 {
     constexpr int CAP = kBlock * NPT;
     static_assert(NPT % VW == 0, "NPT must be a multiple of VW");
@@ -303,14 +353,14 @@ __device__ __forceinline__ void stream_tile(const StreamArgs &A, int t, double *
     const int base = k0 & ~(VW - 1);
 
     if (r1 - r0 == 1 && k1 - base > CAP) {
-        long_row_tile<NPT, VW, C16>(A, r_col, r_val, r_x, r0, k0, k1, s_p);
+        long_row_tile<NPT, VW, C16>(A, r_col, r_val, r_x, r0, k0, k1, s_p, F);
         return;
     }
 
     TileRegs<NPT, VW> T;
     tile_load<NPT, VW, C16>(A, r_col, r_val, t, T);
     tile_gather<NPT, VW>(r_x, T);
-    tile_reduce<NPT, VW, SL>(A, T, s_p, s_rp);
+    tile_reduce<NPT, VW, SL>(A, T, s_p, s_rp, F);
 }
 
 // Wide tile: up to RPT * kBlock short rows whose entries fit one window of

@@ -678,27 +678,54 @@ def _sampled(res, ref, rows):
     assert ok.all()
 
 
+def _resident_bits(res, x, mode):
+    """The resident step of the plan in `res` (its receive buffer holds the
+    halo of the exec that made `res`): its launch mode, and y's bits equal
+    to that exec's, twice in a row."""
+    import torch
+    plan, info = res["plan"], res["info"]
+    assert info["resident_grouped"] == mode
+    lo, n = info["lo"], info["n_loc"]
+    xd = torch.from_numpy(np.ascontiguousarray(x[lo:lo + n])).cuda()
+    for _ in range(2):
+        yd = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+        sp.spmv_exec_resident(plan, xd, yd, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        assert np.array_equal(bits(yd.cpu().numpy()), bits(res["y"]))
+
+
 def test_full_laplace3d_128_p4_rank1():
     """The measured workload at full size, in the launch configuration the
-    benchmark times, every row checked."""
+    benchmark times, every row checked; its resident step (the whole step
+    in y_L's launch) gives the exec's bits."""
     A = gen.laplacian_3d7(128)
     x = gen.x_uniform(A.n_cols, 2)
     log("full 3D 7-point 128^3 P=4 r=1")
-    res, ref = run_share(A, 4, 1, x)
-    info = res["info"]
-    assert info["n_loc"] == 524288 and info["nnz_local"] == 3620864
-    assert info["n_halo"] == 32768 and info["n_send"] == 32768
-    assert_share_parity(res, ref)
+    res, ref = run_share(A, 4, 1, x, keep_plan=True)
+    try:
+        info = res["info"]
+        assert info["n_loc"] == 524288 and info["nnz_local"] == 3620864
+        assert info["n_halo"] == 32768 and info["n_send"] == 32768
+        assert_share_parity(res, ref)
+        _resident_bits(res, x, 3)
+    finally:
+        sp.spmv_plan_destroy(res["plan"])
 
 
 def test_full_stencil27_150_p8_rank3():
+    """As above for the 27-point share (its resident step: Pack in y_L's
+    launch, then y_R)."""
     A = gen.stencil_3d27(150, seed=3)
     x = gen.x_normal(A.n_cols, 30)
     log("full 3D 27-point 150^3 P=8 r=3")
-    res, ref = run_share(A, 8, 3, x)
-    info = res["info"]
-    assert info["n_loc"] == 421875 and info["n_halo"] == 45151
-    assert_share_parity(res, ref)
+    res, ref = run_share(A, 8, 3, x, keep_plan=True)
+    try:
+        info = res["info"]
+        assert info["n_loc"] == 421875 and info["n_halo"] == 45151
+        assert_share_parity(res, ref)
+        _resident_bits(res, x, 2)
+    finally:
+        sp.spmv_plan_destroy(res["plan"])
 
 
 @pytest.mark.parametrize("tune", [
@@ -839,6 +866,27 @@ def test_full_paper_banded_150k_p4_rank1_sampled_plans():
         sp.spmv_plan_destroy(plan)
 
 
+def _two_remote_per_row(n_half=4096, seed=0, uneven_local=False):
+    """Two ranks; rank 0's rows hold their diagonal (and with uneven_local
+    0-2 more local entries, so that y_L's slices differ in width) and
+    exactly two entries in rank 1's block (so its remote rows are one
+    uniform sliced width of 2), rank 1's rows their diagonal only."""
+    rng = np.random.default_rng(seed)
+    ptr, cols = [0], []
+    for i in range(2 * n_half):
+        c = [i]
+        if i < n_half:
+            c += [n_half + (7 * i) % n_half, n_half + (7 * i + 13) % n_half]
+            if uneven_local:
+                c += [(i + 1 + k * 97) % n_half for k in range(i % 3)]
+        c = sorted(set(c))
+        cols.append(np.asarray(c, np.int32))
+        ptr.append(ptr[-1] + len(c))
+    col = np.concatenate(cols)
+    return gen.CSR(2 * n_half, 2 * n_half, np.asarray(ptr, np.int32), col,
+                   rng.standard_normal(col.size))
+
+
 @pytest.mark.parametrize("mode", ["grouped", "sequential"])
 def test_exec_resident_matches_exec(mode):
     """The device work alone (halo already in the receive buffer): the bits
@@ -847,28 +895,45 @@ def test_exec_resident_matches_exec(mode):
     Two grouped launches (Pack, y_L and the column-slab tiles as the items
     of one, the slab sums of the other) where y_R is in column slabs and
     y_L in packed tiles (32- or 16-bit columns) of one window and width,
-    with one or two summing lanes and rows longer than a window; else Pack
-    as extra blocks of y_L's launch where y_L is in packed tiles or the
-    16-bit sliced form; otherwise, or with the flag, the ops one by one."""
+    with one or two summing lanes and rows longer than a window (mode 1);
+    else, where y_L is in packed tiles or the 16-bit sliced form, the whole
+    step in y_L's launch, Pack as extra blocks and each row's remote sum
+    added where its local sum is stored, when y_R is sliced (an fma chain,
+    one or two entries per row) or packed with one summing lane and no row
+    longer than a window (mode 3), or Pack alone in y_L's launch and y_R
+    after it (mode 2); otherwise, or with the flag, the ops one by one."""
     import torch
     flags = {"grouped": 0, "sequential": sp.SPMV_F_RESIDENT_SEQUENTIAL}[mode]
+    long_pl = gen.power_law(40000, mean_len=200.0, sigma=1.2, max_len=10000, seed=44)
     cases = [(gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5}, 1),
              (gen.power_law(60000, seed=21), 8, 3, 22, {"form": 5, "lanes_remote": 2}, 1),
              (gen.power_law(20000, mean_len=100.0, sigma=1.5, max_len=30000, seed=45), 4, 1,
               23, {"form": 5}, 1),                                          # long rows
              (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5, "width": 4, "chunk_local": 8,
                                                          "chunk_remote": 8}, 1),
-             (gen.power_law(30000, seed=17), 4, 2, 18, {}, 2),           # y_R in packed tiles
+             (gen.power_law(30000, seed=17), 4, 2, 18, {}, 2),           # long remote rows
              (gen.power_law(30000, seed=17), 4, 2, 18, {"form": 1}, 2),  # 32-bit y_L columns
+             (gen.power_law(30000, seed=17), 4, 2, 18, {"lanes_remote": 2}, 2),
+             (long_pl, 4, 1, 26, {"form": 1, "lanes_remote": 1}, 2),      # y_R rows beyond a window
+             # the whole step in y_L's launch: packed y_L (32-bit, 16-bit
+             # columns) or 16-bit sliced y_L, with packed y_R (rounded
+             # products) or sliced y_R (fma chains) of at most 4 entries
+             (gen.banded_uniform(90000, 4, 30000, seed=2), 4, 1, 27, {"form": 3}, 3),
+             (gen.laplacian_3d7(24), 4, 1, 20, {"form": 4}, 3),
+             (gen.banded_uniform(60000, 3, 2000, seed=3), 4, 2, 28, {"form": 3}, 3),
+             (_two_remote_per_row(), 2, 0, 29, {}, 3),
+             (_two_remote_per_row(uneven_local=True), 2, 0, 30, {}, 3),
+             (gen.banded_uniform(90000, 6, 2000, seed=3), 4, 2, 28, {"form": 3}, 2),  # 6 entries
              (_dense_remote_rows(), 2, 1, 23, {"form": 5}, 0),            # nothing to send
              (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5, "fuse_unpack": 2}, 2),
              (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5, "rows_remote": 2}, 2),
              (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5, "kernel_local": 1}, 0),
              (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5, "chunk_local": 8,
                                                          "chunk_remote": 4}, 2),
-             (gen.laplacian_3d7(24), 4, 1, 20, {}, 2),                   # 16-bit sliced y_L
+             (gen.laplacian_3d7(24), 4, 1, 20, {}, 3),                   # 16-bit sliced y_L
+             (gen.stencil_3d27(30, seed=5), 4, 2, 24, {}, 2),          # 12 remote entries
              (gen.stencil_3d27(20, seed=3), 4, 1, 25, {"form": 2}, 0),   # 32-bit sliced y_L
-             (gen.laplacian_2d5(40), 1, 0, 21, {"form": 1}, 0)]          # no send list
+             (gen.laplacian_2d5(40), 1, 0, 21, {"form": 1}, 0)]          # one rank
     for A, P, r, seed, tune, grouped in cases:
         tune = {**tune, "flags": flags}
         log(f"exec_resident {mode} n={A.n_rows} P={P} r={r} {tune}")
