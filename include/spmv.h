@@ -231,9 +231,10 @@ typedef struct {
     int32_t fine;          /* 1 while a fine-grained order is in force       */
     int32_t device;        /* HIP device of the plan's memory (-1 host-only) */
     int32_t resident_grouped; /* launches of spmv_exec_resident: 1 = the two
-                              grouped launches, 2 = Pack as extra blocks of
-                              y_L's launch, then y_R, 0 = one per op (see
-                              spmv_exec_resident)                           */
+                              grouped launches, 3 = one launch (y_L's, with
+                              Pack and the remote sums), 2 = Pack as extra
+                              blocks of y_L's launch, then y_R, 0 = one per
+                              op (see spmv_exec_resident)                   */
 } spmv_info_t;
 
 /* Integer metadata selectors for spmv_plan_get_i32. */
@@ -378,8 +379,13 @@ int spmv_exec(spmv_plan_t *plan, const double *x_local, double *y_local, void *s
  *      width, Unpack fused: two grouped launches, Pack, y_L and the slab
  *      tiles (none reads what another writes) as the work items of one,
  *      then the slab sums adding into y;
- *   2  y_L in packed tiles or the 16-bit sliced form: Pack as extra blocks
- *      of y_L's launch, then Unpack (unless fused) and y_R;
+ *   3  y_L in packed tiles or the 16-bit sliced form, Unpack fused, y_R
+ *      sliced or in packed tiles with one summing lane, no remote row
+ *      longer than 4 entries: the whole step in y_L's launch, Pack as extra
+ *      blocks and each row's remote sum (computed as y_R's kernel computes
+ *      it) added where the row's local sum is stored;
+ *   2  otherwise, with y_L in packed tiles or the 16-bit sliced form: Pack
+ *      as extra blocks of y_L's launch, then Unpack (unless fused) and y_R;
  *   0  otherwise, and always with SPMV_F_RESIDENT_SEQUENTIAL: one launch
  *      per op in the DAG's order.
  * y has the bits spmv_exec gives for the same halo in every case.  x_local, y_local as in spmv_exec.  The Sec. III-A
