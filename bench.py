@@ -918,9 +918,13 @@ def measure_share(sp, torch, gen, key: str, args, sweep: bool = True,
                    "fused_combine": info["fused_combine"], "replicas": R,
                    "step": {1: "Pack, y_L and y_R's column-slab tiles as one grouped launch, "
                                    "then the slab sums into y",
+                            3: "one launch: y_L, Pack as extra blocks, each remote row's "
+                               "sum added where its local sum is stored",
+                            4: "y_L, Pack and y_R's tiles as blocks of one launch, then the "
+                               "combine into y",
                             2: "y_L with Pack as extra blocks of its launch, then y_R into y",
-                            0: "Pack, y_L, Unpack, y_R, one launch each"}[
-                                info["resident_grouped"]] +
+                            0: "Pack, y_L, Unpack, y_R, one launch each"}.get(
+                                info["resident_grouped"], "see spmv_exec_resident") +
                            ", on one stream, halo resident in HBM (spmv_exec_resident)",
                    "resident_grouped": info["resident_grouped"],
                    "step_device_bytes": dev_bytes, "exec_device_bytes": B["total"],
