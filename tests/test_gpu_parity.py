@@ -914,6 +914,9 @@ def test_exec_resident_matches_exec(mode):
              (gen.power_law(30000, seed=17), 4, 2, 18, {}, 2),           # long remote rows
              (gen.power_law(30000, seed=17), 4, 2, 18, {"form": 1}, 2),  # 32-bit y_L columns
              (gen.power_law(30000, seed=17), 4, 2, 18, {"lanes_remote": 2}, 2),
+             (gen.power_law(30000, seed=17), 4, 2, 18, {"lanes_remote": 4}, 2),
+             (gen.power_law(30000, seed=17), 4, 2, 18, {"form": 1, "chunk_local": 8,
+                                                       "chunk_remote": 4}, 2),
              (long_pl, 4, 1, 26, {"form": 1, "lanes_remote": 1}, 2),      # y_R rows beyond a window
              # the whole step in y_L's launch: packed y_L (32-bit, 16-bit
              # columns) or 16-bit sliced y_L, with packed y_R (rounded
