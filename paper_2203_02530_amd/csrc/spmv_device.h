@@ -8,16 +8,21 @@ namespace spmv {
 
 constexpr int kXcds = 8;   // MI355X: 8 XCDs, workgroups dispatched round-robin
 
-// Block b of nb is dispatched to XCD b % 8.  With remap, XCD x processes the
-// contiguous tile range [x*per + min(x, rem), ...) instead of every 8th tile,
-// so x entries shared by neighbouring tiles stay in that XCD's L2.
-// Bijective for any nb.
+// Block b of nb is dispatched to XCD b % 8.  With remap 1, XCD x processes
+// the contiguous tile range [x*per + min(x, rem), ...) instead of every 8th
+// tile, so x entries shared by neighbouring tiles stay in that XCD's L2.
+// Remap 3 is remap 1 with the last XCD's range taken from its end, so that
+// the last tiles, which hold a contiguous row block's high boundary rows,
+// start first on their XCD rather than close the launch.  Bijective for
+// any nb (the last XCD's range has per tiles).
 __device__ __forceinline__ int tile_of_block(int b, int nb, int remap)
 {
-    if (remap != 1) return b;
+    if (remap != 1 && remap != 3) return b;
     const int xcd = b % kXcds, local = b / kXcds;
     const int per = nb / kXcds, rem = nb % kXcds;
-    return xcd * per + min(xcd, rem) + local;
+    const int first = xcd * per + min(xcd, rem);
+    if (remap == 3 && xcd == kXcds - 1) return first + per - 1 - local;
+    return first + local;
 }
 
 template <int CTRL>

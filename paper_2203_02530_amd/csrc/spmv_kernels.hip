@@ -457,6 +457,8 @@ hipError_t launch_stream_t(const CsrDev &A, const double *x, double *out, double
     const unsigned grid = unsigned(nt + nb);
     if (grid == 0) return hipSuccess;
     const bool tl = nb > 0 || rem.mask;   // the resident step's instance
+    // remote sums lengthen the boundary tiles: start the last of them first
+    if (rem.mask && remap == 1) remap = 3;
     if (A.col16 && tl)
         hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, true, true>), dim3(grid), dim3(kBlock), 0, s,
                            a, remap, nt, tail, rem);
@@ -578,7 +580,8 @@ hipError_t launch_sell16(const CsrDev &A, const double *x, double *out, int xcd_
     a.n_x = uint32_t(A.n_x);
     const int nb = pack_blocks<64>(tail);
     const unsigned grid = unsigned(A.n_slices + nb);
-    const int remap = xcd_remap == 2 ? 0 : 1;
+    // remote sums lengthen the boundary slices: start the last of them first
+    const int remap = xcd_remap == 2 ? 0 : rem.mask ? 3 : 1;
     switch (A.sell_u * 2 + (nb > 0 || rem.mask ? 1 : 0)) {
         case 16: hipLaunchKernelGGL((k_sell16<1, false>), dim3(grid), dim3(64), 0, s, a, remap, tail, rem); break;
         case 17: hipLaunchKernelGGL((k_sell16<1, true>), dim3(grid), dim3(64), 0, s, a, remap, tail, rem); break;

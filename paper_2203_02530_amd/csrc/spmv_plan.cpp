@@ -97,8 +97,10 @@ bool packs_with_yl(const spmv_plan *p)
 // sit in its first and last tiles, which the XCD-contiguous tile order
 // puts on two XCDs, and one lane of each row walks its remote entries;
 // with one entry per remote row (7-point share) the step took 10.6 us
-// against 12.9 with y_R in a launch of its own, with nine (27-point) 30.2
-// against 26.8.
+// against 12.9 with y_R in a launch of its own (9.9 us once the last XCD
+// takes its tiles from the end), with nine (27-point) 30.2 against 26.8,
+// and 26.5-27.6 with the tiles split among the XCDs by a cost that counts
+// a remote entry three times.
 constexpr int kFuseMaxRemote = 4;
 
 bool fuses_remote(const spmv_plan *p)
