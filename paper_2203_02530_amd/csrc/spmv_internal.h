@@ -218,12 +218,20 @@ struct PackTail {
 // and the products added left to right from zero (packed tiles with one
 // summing lane), so that local + remote has the bits of spmv_exec.
 // mask == nullptr: no remote part.
+// tj, te (packed-tile y_L with rounded products): tile t's rows hold the
+// compressed rows [tj[t], tj[t + 1]) and their entries [te[t], te[t + 1]),
+// at most one window's worth (kTileRemoteCap and the tile's window); its
+// block loads them beside its own entries instead of each row's storing
+// lane walking them after the local sum.
 struct RemoteFuse {
     const uint64_t *mask = nullptr;
     const int32_t *j0 = nullptr, *rp = nullptr, *col = nullptr;
     const double *val = nullptr, *xh = nullptr;
     int32_t fma_chain = 0;
+    const int32_t *tj = nullptr, *te = nullptr;
+    int32_t tile_cap = 0;   // the bound the plan checked te[t + 1] - te[t] against
 };
+constexpr int kTileRemoteCap = 1024;   // remote entries per tile, 4 per thread
 constexpr int kPackPerThread = 4;
 // Longest send list a PackTail takes (its block and entry indices are int;
 // a longer one runs Pack as a kernel of its own).
@@ -418,6 +426,7 @@ struct spmv_plan {
     uint64_t *d_rf_mask = nullptr;
     int32_t *d_rf_j0 = nullptr, *d_rf_rp = nullptr, *d_rf_col = nullptr;
     double *d_rf_val = nullptr;
+    int32_t *d_rf_tj = nullptr, *d_rf_te = nullptr;
     int32_t *d_tile_row[2] = {}, *d_tile_k[2] = {};
     int32_t *d_sell_ptr[2] = {};
 

@@ -204,8 +204,9 @@ int pack_blocks(const PackTail &P)
 
 // Single-share stream-CSR product: one block per tile (see spmv_stream.h);
 // with TAIL the n_tiles blocks are followed by the PackTail's blocks (the
-// instances without it are the plain product).
-template <int NPT, int VW, int SL, bool C16, bool TAIL>
+// instances without it are the plain product), and with COOP each tile's
+// block also loads and sums the remote part of its rows (F.tj, F.te).
+template <int NPT, int VW, int SL, bool C16, bool TAIL, bool COOP = false>
 __global__ __launch_bounds__(kBlock) void k_csr_stream(StreamArgs A, int remap, int n_tiles,
                                                        PackTail P, RemoteFuse F)
 {
@@ -216,8 +217,8 @@ __global__ __launch_bounds__(kBlock) void k_csr_stream(StreamArgs A, int remap, 
             pack_block<kBlock>(P, int(blockIdx.x) - n_tiles);
             return;
         }
-        stream_tile<NPT, VW, SL, C16>(A, tile_of_block(int(blockIdx.x), n_tiles, remap), s_p,
-                                      s_rp, &F);
+        stream_tile<NPT, VW, SL, C16, COOP>(A, tile_of_block(int(blockIdx.x), n_tiles, remap),
+                                            s_p, s_rp, &F);
     } else {
         stream_tile<NPT, VW, SL, C16>(A, tile_of_block(int(blockIdx.x), int(gridDim.x), remap),
                                       s_p, s_rp);
@@ -459,7 +460,16 @@ hipError_t launch_stream_t(const CsrDev &A, const double *x, double *out, double
     const bool tl = nb > 0 || rem.mask;   // the resident step's instance
     // remote sums lengthen the boundary tiles: start the last of them first
     if (rem.mask && remap == 1) remap = 3;
-    if (A.col16 && tl)
+    // a tile's remote products go where its window's products were
+    if (rem.mask && rem.tj && (rem.tile_cap > NPT * kBlock || rem.tile_cap > kTileRemoteCap))
+        return hipErrorInvalidValue;
+    if (A.col16 && rem.mask && rem.tj)
+        hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, true, true, true>), dim3(grid), dim3(kBlock),
+                           0, s, a, remap, nt, tail, rem);
+    else if (rem.mask && rem.tj)
+        hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, false, true, true>), dim3(grid),
+                           dim3(kBlock), 0, s, a, remap, nt, tail, rem);
+    else if (A.col16 && tl)
         hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, true, true>), dim3(grid), dim3(kBlock), 0, s,
                            a, remap, nt, tail, rem);
     else if (A.col16)

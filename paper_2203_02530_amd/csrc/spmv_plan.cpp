@@ -89,19 +89,29 @@ bool packs_with_yl(const spmv_plan *p)
 }
 
 // y_R can be added where y_L stores its rows (the resident step in one
-// launch): y_L's kernel takes the extra work, the Unpack is fused, every
-// remote row is short, and y_R's kernel sums a row the way remote_add
-// does: the sliced form (an fma chain), or packed tiles with one summing
-// lane and no row longer than a window (those a block sums with fma
-// chains and a tree).  Short: the remote rows of a contiguous row block
-// sit in its first and last tiles, which the XCD-contiguous tile order
-// puts on two XCDs, and one lane of each row walks its remote entries;
-// with one entry per remote row (7-point share) the step took 10.6 us
-// against 12.9 with y_R in a launch of its own (9.9 us once the last XCD
-// takes its tiles from the end), with nine (27-point) 30.2 against 26.8,
-// and 26.5-27.6 with the tiles split among the XCDs by a cost that counts
-// a remote entry three times.
+// launch): y_L's kernel takes the extra work, the Unpack is fused, and
+// y_R's kernel sums a row the way the fused sum does: the sliced form (an
+// fma chain), or packed tiles with one summing lane and no row longer than
+// a window (those a block sums with fma chains and a tree).  With y_L in
+// packed tiles and y_R's rounded products, each tile's block loads its
+// rows' remote entries beside its own (at most tile_remote_cap per tile)
+// and the rows' storing lanes add them up from LDS; otherwise each row's
+// storing lane walks its remote entries after its local sum, so the rows
+// must be short: the remote rows of a contiguous row block sit in its
+// first and last tiles, on two XCDs.  Measured steps: 7-point share (one
+// entry per remote row, sliced y_L) 10.6 us against 12.9 with y_R in a
+// launch of its own, 10.1 once the last XCD takes its tiles from the end;
+// 27-point share (nine) 30.2 us with the rows walked against 26.3-27.2,
+// 26.5-27.6 with the tiles split among the XCDs by a cost that counts a
+// remote entry three times, 24.9-26.7 with the tiles' blocks loading them.
 constexpr int kFuseMaxRemote = 4;
+
+int tile_remote_cap(const spmv_plan *p)
+{
+    return std::min(kTileRemoteCap, stream_cap(p->cfg[0].chunk));
+}
+
+bool remote_by_tile(const spmv_plan *p) { return p->cfg[0].form != 3 && p->cfg[1].form == 1; }
 
 bool fuses_remote(const spmv_plan *p)
 {
@@ -109,15 +119,30 @@ bool fuses_remote(const spmv_plan *p)
     const CsrCfg &c = p->cfg[1];
     if (!packs_with_yl(p) || !p->fuse_unpack || S.R_rows.empty()) return false;
     if (int64_t(S.send_idx.size()) > kPackTailMax || c.kernel != SPMV_KERNEL_STREAM) return false;
-    for (size_t j = 0; j + 1 < S.R_ptr.size(); ++j)
-        if (S.R_ptr[j + 1] - S.R_ptr[j] > kFuseMaxRemote) return false;
-    if (c.form == 2) return true;
-    if (c.form != 1 || c.lanes != 1) return false;
-    const int cap = stream_cap(c.chunk);
-    for (size_t t = 0; t + 1 < c.tile_row.size(); ++t)
-        if (c.tile_row[t + 1] - c.tile_row[t] == 1 &&
-            c.tile_k[t + 1] - (c.tile_k[t] & ~(c.width - 1)) > cap)
-            return false;
+    if (c.form == 1) {
+        if (c.lanes != 1) return false;
+        const int cap = stream_cap(c.chunk);
+        for (size_t t = 0; t + 1 < c.tile_row.size(); ++t)
+            if (c.tile_row[t + 1] - c.tile_row[t] == 1 &&
+                c.tile_k[t + 1] - (c.tile_k[t] & ~(c.width - 1)) > cap)
+                return false;
+    } else if (c.form != 2) {
+        return false;
+    }
+    if (remote_by_tile(p)) {
+        const std::vector<int32_t> &tr = p->cfg[0].tile_row;
+        const int cap = tile_remote_cap(p);
+        size_t j = 0;
+        int32_t e_prev = 0;
+        for (size_t t = 1; t < tr.size(); ++t) {
+            while (j < S.R_rows.size() && S.R_rows[j] < tr[t]) ++j;
+            if (S.R_ptr[j] - e_prev > cap) return false;
+            e_prev = S.R_ptr[j];
+        }
+    } else {
+        for (size_t j = 0; j + 1 < S.R_ptr.size(); ++j)
+            if (S.R_ptr[j + 1] - S.R_ptr[j] > kFuseMaxRemote) return false;
+    }
     return true;
 }
 
@@ -162,7 +187,18 @@ int allocate_and_upload(spmv_plan *p)
     const bool rf = fuses_remote(p);
     const bool rf_copy = rf && p->cfg[1].form != 1;
     std::vector<uint64_t> rf_mask;
-    std::vector<int32_t> rf_j0;
+    std::vector<int32_t> rf_j0, rf_tj, rf_te;
+    if (rf && remote_by_tile(p)) {   // each tile's compressed rows and entries
+        const std::vector<int32_t> &tr = p->cfg[0].tile_row;
+        rf_tj.resize(tr.size());
+        rf_te.resize(tr.size());
+        size_t j = 0;
+        for (size_t t = 0; t < tr.size(); ++t) {
+            while (j < n_rr && S.R_rows[j] < tr[t]) ++j;
+            rf_tj[t] = int32_t(j);
+            rf_te[t] = S.R_ptr[j];
+        }
+    }
     if (rf) {
         const int64_t ng = (S.n_loc + 63) / 64;
         rf_mask.assign(size_t(ng), 0);
@@ -227,6 +263,8 @@ int allocate_and_upload(spmv_plan *p)
         {(void **)&p->d_rf_rp, rf_copy ? S.R_ptr.size() * 4 : 0, S.R_ptr.data(), 0},
         {(void **)&p->d_rf_col, rf_copy ? S.R_col.size() * 4 : 0, S.R_col.data(), 0},
         {(void **)&p->d_rf_val, rf_copy ? S.R_val.size() * 8 : 0, S.R_val.data(), 0},
+        {(void **)&p->d_rf_tj, rf_tj.size() * 4, rf_tj.data(), 0},
+        {(void **)&p->d_rf_te, rf_te.size() * 4, rf_te.data(), 0},
     };
     size_t total = 0;
     for (const Item &it : items) total += align_up(std::max<size_t>(it.bytes + it.pad, 1));
@@ -269,6 +307,11 @@ int allocate_and_upload(spmv_plan *p)
         p->rf.val = rf_copy ? p->d_rf_val : p->dR_val;
         p->rf.xh = p->d_recvbuf;
         p->rf.fma_chain = p->cfg[1].form == 2 ? 1 : 0;
+        if (!rf_tj.empty()) {
+            p->rf.tj = p->d_rf_tj;
+            p->rf.te = p->d_rf_te;
+            p->rf.tile_cap = tile_remote_cap(p);
+        }
     }
     if (int rc = resident_build(p)) return rc;
     SPMV_HIP(hipDeviceSynchronize());

@@ -170,6 +170,66 @@ __device__ __forceinline__ double remote_add(const RemoteFuse &F, int r, double 
     return s + t;
 }
 
+// The remote part of one packed tile (RemoteFuse tj/te), loaded by the
+// whole block beside the tile's own loads: entries [ea, ea + ne) of the
+// compressed remote rows [ja, ja + nj), up to NQ per thread, each product
+// rounded as soon as its x value is in; the storing lane of each row keeps
+// its row group's mask word and first compressed row.
+struct RemoteTile {
+    static constexpr int NQ = kTileRemoteCap / kBlock;
+    int ja, nj, ea, ne;
+    int32_t qc[NQ];
+    double qa[NQ], qp[NQ];
+    int32_t qr;   // rp[ja + tid] - ea, tid < nj
+    uint64_t m;
+    int32_t j0;
+};
+
+template <int SL>
+__device__ __forceinline__ void rtile_load(const RemoteFuse &F, int t, int r0, int nr,
+                                           RemoteTile &R)
+{
+    const int tid = int(threadIdx.x);
+    R.ja = F.tj[t];
+    R.nj = F.tj[t + 1] - R.ja;
+    R.ea = F.te[t];
+    R.ne = F.te[t + 1] - R.ea;
+    R.qr = 0;
+    R.m = 0;
+    R.j0 = 0;
+    if (R.nj == 0) return;   // block-uniform: no remote rows in this tile
+#pragma unroll
+    for (int u = 0; u < R.NQ; ++u) {
+        const int k = u * kBlock + tid;
+        const bool in = k < R.ne;
+        R.qc[u] = in ? F.col[R.ea + k] : 0;
+        R.qa[u] = in ? F.val[R.ea + k] : 0.0;
+    }
+    if (tid < R.nj) R.qr = F.rp[R.ja + tid] - R.ea;
+    const int g = tid / SL;
+    if (tid % SL == SL - 1 && g < nr) {
+        R.m = F.mask[(r0 + g) >> 6];
+        R.j0 = F.j0[(r0 + g) >> 6];
+    }
+}
+
+__device__ __forceinline__ double product_rn(double a, double b)
+{
+#pragma clang fp contract(off)
+    return a * b;
+}
+
+__device__ __forceinline__ void rtile_gather(const RemoteFuse &F, RemoteTile &R)
+{
+    if (R.nj == 0) return;
+    const int tid = int(threadIdx.x);
+    double xq[RemoteTile::NQ];
+#pragma unroll
+    for (int u = 0; u < R.NQ; ++u) xq[u] = u * kBlock + tid < R.ne ? F.xh[R.qc[u]] : 0.0;
+#pragma unroll
+    for (int u = 0; u < R.NQ; ++u) R.qp[u] = product_rn(R.qa[u], xq[u]);
+}
+
 // Operands of one stream-CSR product.  out[r] = row sum (acc == nullptr) or
 // acc[rows[r]] += row sum.  nnz_alloc = entries incl. padding, n_x = |x|.
 // With 16-bit columns (C16), col holds int16 offsets of each entry's column
@@ -246,12 +306,15 @@ __device__ __forceinline__ void tile_gather(__amdgpu_buffer_rsrc_t r_x, TileRegs
 }
 
 // Stage 3: products into LDS, row sums by SL lanes per row in a fixed
-// order, results stored.  Contains one barrier; the caller separates
-// consecutive tiles with another (LDS is reused).
-template <int NPT, int VW, int SL>
+// order, results stored.  Contains one barrier (three with a remote part
+// R, whose products and row pointers then take the place of the local
+// ones in LDS: s_p must hold its ne <= kBlock * NPT entries); the caller
+// separates consecutive tiles with another (LDS is reused).
+template <int NPT, int VW, int SL, bool COOP = false>
 __device__ __forceinline__ void tile_reduce(const StreamArgs &A, const TileRegs<NPT, VW> &T,
                                             double *s_p, int32_t *s_rp,
-                                            const RemoteFuse *F = nullptr)
+                                            const RemoteFuse *F = nullptr,
+                                            const RemoteTile *R = nullptr)
 {
     const int tid = int(threadIdx.x);
 #pragma unroll
@@ -279,8 +342,31 @@ __device__ __forceinline__ void tile_reduce(const StreamArgs &A, const TileRegs<
         for (; k < e; k += SL) s += s_p[k];
     }
     s = group_sum<SL>(s);
+    if constexpr (COOP) {
+        if (R->nj > 0) {   // block-uniform
+            __syncthreads();   // every row has read s_p and s_rp
+#pragma unroll
+            for (int u = 0; u < R->NQ; ++u) {
+                const int k = u * kBlock + tid;
+                if (k < R->ne) s_p[k] = R->qp[u];
+            }
+            if (tid < R->nj) s_rp[tid] = R->qr;
+            if (tid == 0) s_rp[R->nj] = R->ne;
+            __syncthreads();
+            const int l = (T.r0 + g) & 63;
+            if (lane == SL - 1 && g < T.nr && ((R->m >> l) & 1ull)) {
+                // y_R's sum of the row: rounded products, left to right from 0
+                const int jr = R->j0 + __popcll(R->m & ((1ull << l) - 1ull)) - R->ja;
+                const int qb = s_rp[jr], qe = s_rp[jr + 1];
+                double q = 0.0;
+                for (int k = qb; k < qe; ++k) q += s_p[k];
+                s = s + q;
+            }
+        }
+    } else {
+        if (lane == SL - 1 && g < T.nr && F && F->mask) s = remote_add(*F, T.r0 + g, s);
+    }
     if (lane == SL - 1 && g < T.nr) {
-        if (F && F->mask) s = remote_add(*F, T.r0 + g, s);
         if (A.acc)
             A.acc[A.rows[T.r0 + g]] += s;
         else
@@ -338,8 +424,9 @@ __device__ __forceinline__ void long_row_tile(const StreamArgs &A, __amdgpu_buff
 
 // One tile.  s_p: LDS[kBlock * NPT] doubles, s_rp: LDS[kBlock / SL + 1] ints.
 // Block-uniform control flow; the caller separates consecutive tiles with a
-// barrier (LDS is reused).
-template <int NPT, int VW, int SL, bool C16 = false>
+// barrier (LDS is reused).  COOP: F has tj/te, and the tile's remote part
+// is loaded by the block (RemoteTile).
+template <int NPT, int VW, int SL, bool C16 = false, bool COOP = false>
 __device__ __forceinline__ void stream_tile(const StreamArgs &A, int t, double *s_p, int32_t *s_rp,
                                             const RemoteFuse *F = nullptr)
 {
@@ -359,8 +446,16 @@ __device__ __forceinline__ void stream_tile(const StreamArgs &A, int t, double *
 
     TileRegs<NPT, VW> T;
     tile_load<NPT, VW, C16>(A, r_col, r_val, t, T);
-    tile_gather<NPT, VW>(r_x, T);
-    tile_reduce<NPT, VW, SL>(A, T, s_p, s_rp, F);
+    if constexpr (COOP) {
+        RemoteTile R;
+        rtile_load<SL>(*F, t, T.r0, T.nr, R);
+        tile_gather<NPT, VW>(r_x, T);
+        rtile_gather(*F, R);
+        tile_reduce<NPT, VW, SL, true>(A, T, s_p, s_rp, F, &R);
+    } else {
+        tile_gather<NPT, VW>(r_x, T);
+        tile_reduce<NPT, VW, SL>(A, T, s_p, s_rp, F);
+    }
 }
 
 // Wide tile: up to RPT * kBlock short rows whose entries fit one window of

@@ -723,7 +723,7 @@ def test_full_stencil27_150_p8_rank3():
         info = res["info"]
         assert info["n_loc"] == 421875 and info["n_halo"] == 45151
         assert_share_parity(res, ref)
-        _resident_bits(res, x, 2)
+        _resident_bits(res, x, 3)
     finally:
         sp.spmv_plan_destroy(res["plan"])
 
@@ -887,6 +887,32 @@ def _two_remote_per_row(n_half=4096, seed=0, uneven_local=False):
                    rng.standard_normal(col.size))
 
 
+def _long_local_rows(n_half=6000, seed=0):
+    """Two ranks; rank 0's rows hold a local band of three, a few of them
+    3,000 or more local entries (longer than a packed window), and every
+    seventh row and the long rows 5 and 5,999 one to five entries in rank
+    1's block; rank 1's rows their diagonal.  So y_R is in packed tiles
+    with one summing lane, and some of y_L's single-row tiles have remote
+    entries."""
+    rng = np.random.default_rng(seed)
+    long_rows = {5, 700, 2999, 5990, n_half - 1}
+    ptr, cols = [0], []
+    for i in range(2 * n_half):
+        c = {i}
+        if i < n_half:
+            c |= {max(i - 1, 0), min(i + 1, n_half - 1)}
+            if i in long_rows:
+                c |= set(range(0, 3000 + i % 7))
+            if i % 7 == 3 or i in (5, n_half - 1):
+                c |= {n_half + int(v) for v in rng.integers(0, n_half, 1 + i % 5)}
+        c = sorted(c)
+        cols.append(np.asarray(c, np.int32))
+        ptr.append(ptr[-1] + len(c))
+    col = np.concatenate(cols)
+    return gen.CSR(2 * n_half, 2 * n_half, np.asarray(ptr, np.int32), col,
+                   rng.standard_normal(col.size))
+
+
 @pytest.mark.parametrize("mode", ["grouped", "sequential"])
 def test_exec_resident_matches_exec(mode):
     """The device work alone (halo already in the receive buffer): the bits
@@ -900,8 +926,10 @@ def test_exec_resident_matches_exec(mode):
     step in y_L's launch, Pack as extra blocks and each row's remote sum
     added where its local sum is stored, when y_R is sliced (an fma chain,
     one or two entries per row) or packed with one summing lane and no row
-    longer than a window (mode 3), or Pack alone in y_L's launch and y_R
-    after it (mode 2); otherwise, or with the flag, the ops one by one."""
+    longer than a window (mode 3; with both in packed tiles each tile's
+    block loads its rows' remote entries, at most a window's worth), or
+    Pack alone in y_L's launch and y_R after it (mode 2); otherwise, or
+    with the flag, the ops one by one."""
     import torch
     flags = {"grouped": 0, "sequential": sp.SPMV_F_RESIDENT_SEQUENTIAL}[mode]
     long_pl = gen.power_law(40000, mean_len=200.0, sigma=1.2, max_len=10000, seed=44)
@@ -934,7 +962,12 @@ def test_exec_resident_matches_exec(mode):
              (gen.power_law(30000, seed=17), 16, 5, 19, {"form": 5, "chunk_local": 8,
                                                          "chunk_remote": 4}, 2),
              (gen.laplacian_3d7(24), 4, 1, 20, {}, 3),                   # 16-bit sliced y_L
-             (gen.stencil_3d27(30, seed=5), 4, 2, 24, {}, 2),          # 12 remote entries
+             (gen.stencil_3d27(30, seed=5), 4, 2, 24, {}, 3),          # 12 remote entries
+             # packed y_L (16-bit, 32-bit, two summing lanes) whose rows
+             # longer than a window sum their remote part one by one
+             (_long_local_rows(), 2, 0, 31, {}, 3),
+             (_long_local_rows(seed=1), 2, 0, 32, {"form": 1}, 3),
+             (_long_local_rows(seed=2), 2, 0, 33, {"lanes_local": 2}, 3),
              (gen.stencil_3d27(20, seed=3), 4, 1, 25, {"form": 2}, 0),   # 32-bit sliced y_L
              (gen.laplacian_2d5(40), 1, 0, 21, {"form": 1}, 0)]          # one rank
     for A, P, r, seed, tune, grouped in cases:
