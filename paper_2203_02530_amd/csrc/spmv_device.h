@@ -25,6 +25,23 @@ __device__ __forceinline__ int tile_of_block(int b, int nb, int remap)
     return first + local;
 }
 
+// Block b of 8 * (longest range) blocks, for tiles given to the XCDs in
+// contiguous ranges: XCD x runs [xr[x], xr[x + 1]), the last XCD from the
+// end of its range as with remap 3; -1 for a block past its XCD's range.
+__device__ __forceinline__ int tile_of_range(int b, const int32_t *xr)
+{
+    const int xcd = b % kXcds, local = b / kXcds;
+    int lo = 0, hi = 0;
+#pragma unroll
+    for (int k = 0; k < kXcds; ++k)   // selects: xcd is uniform, no indexed kernarg
+        if (k == xcd) {
+            lo = xr[k];
+            hi = xr[k + 1];
+        }
+    if (local >= hi - lo) return -1;
+    return xcd == kXcds - 1 ? hi - 1 - local : lo + local;
+}
+
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v)
 {

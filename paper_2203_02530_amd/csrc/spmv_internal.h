@@ -230,6 +230,12 @@ struct RemoteFuse {
     int32_t fma_chain = 0;
     const int32_t *tj = nullptr, *te = nullptr;
     int32_t tile_cap = 0;   // the bound the plan checked te[t + 1] - te[t] against
+    // With n_grid > 0 the tiles go to the XCDs in contiguous ranges of
+    // equal cost: XCD x runs tiles [xr[x], xr[x + 1]) (the last XCD from
+    // the end of its range) in the first n_grid = 8 * (longest range)
+    // blocks; a block past its XCD's range exits.
+    int32_t n_grid = 0;
+    int32_t xr[9] = {};
 };
 constexpr int kTileRemoteCap = 1024;   // remote entries per tile, 4 per thread
 constexpr int kPackPerThread = 4;

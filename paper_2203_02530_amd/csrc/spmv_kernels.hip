@@ -217,8 +217,10 @@ __global__ __launch_bounds__(kBlock) void k_csr_stream(StreamArgs A, int remap, 
             pack_block<kBlock>(P, int(blockIdx.x) - n_tiles);
             return;
         }
-        stream_tile<NPT, VW, SL, C16, COOP>(A, tile_of_block(int(blockIdx.x), n_tiles, remap),
-                                            s_p, s_rp, &F);
+        const int t = (COOP && F.n_grid) ? tile_of_range(int(blockIdx.x), F.xr)
+                                         : tile_of_block(int(blockIdx.x), n_tiles, remap);
+        if (t < 0) return;   // whole block, before any barrier
+        stream_tile<NPT, VW, SL, C16, COOP>(A, t, s_p, s_rp, &F);
     } else {
         stream_tile<NPT, VW, SL, C16>(A, tile_of_block(int(blockIdx.x), int(gridDim.x), remap),
                                       s_p, s_rp);
@@ -454,19 +456,24 @@ hipError_t launch_stream_t(const CsrDev &A, const double *x, double *out, double
     a.acc = acc;
     a.nnz_alloc = uint32_t(A.nnz_alloc);
     a.n_x = uint32_t(A.n_x);
-    const int nt = std::max(A.n_tiles, 0), nb = pack_blocks<kBlock>(tail);
+    static_assert(sizeof(RemoteFuse::xr) / sizeof(int32_t) == kXcds + 1, "one range per XCD");
+    const bool coop = rem.mask && rem.tj;
+    // with XCD ranges the product's blocks are n_grid, the Pack blocks after them
+    const int nt = coop && rem.n_grid ? rem.n_grid : std::max(A.n_tiles, 0);
+    const int nb = pack_blocks<kBlock>(tail);
     const unsigned grid = unsigned(nt + nb);
     if (grid == 0) return hipSuccess;
     const bool tl = nb > 0 || rem.mask;   // the resident step's instance
     // remote sums lengthen the boundary tiles: start the last of them first
     if (rem.mask && remap == 1) remap = 3;
     // a tile's remote products go where its window's products were
-    if (rem.mask && rem.tj && (rem.tile_cap > NPT * kBlock || rem.tile_cap > kTileRemoteCap))
+    if (coop && (rem.tile_cap > NPT * kBlock || rem.tile_cap > kTileRemoteCap ||
+                 (rem.n_grid && rem.xr[kXcds] != A.n_tiles)))
         return hipErrorInvalidValue;
-    if (A.col16 && rem.mask && rem.tj)
+    if (A.col16 && coop)
         hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, true, true, true>), dim3(grid), dim3(kBlock),
                            0, s, a, remap, nt, tail, rem);
-    else if (rem.mask && rem.tj)
+    else if (coop)
         hipLaunchKernelGGL((k_csr_stream<NPT, VW, SL, false, true, true>), dim3(grid),
                            dim3(kBlock), 0, s, a, remap, nt, tail, rem);
     else if (A.col16 && tl)

@@ -15,6 +15,7 @@
 #include <map>
 #include <mutex>
 
+#include "spmv_device.h"
 #include "spmv_internal.h"
 
 namespace spmv {
@@ -112,6 +113,34 @@ int tile_remote_cap(const spmv_plan *p)
 }
 
 bool remote_by_tile(const spmv_plan *p) { return p->cfg[0].form != 3 && p->cfg[1].form == 1; }
+
+// The tiles of a one-launch step whose tiles load their rows' remote
+// entries go to the XCDs in contiguous ranges (neighbouring tiles share x
+// lines in one L2) of equal cost, a remote entry counted twice a local
+// one: the remote rows of a contiguous row block sit in its first and
+// last tiles, which equal ranges put on two XCDs (27-point share: 24.0-25.4
+// us against 25.0-26.2 with equal ranges; weights 1, 3, 4 and 6 measured
+// 23.9-25.2, 24.5-25.5, 24.7-25.6 and 25.8-27.2).
+constexpr double kRemoteEntryCost = 2.0;
+
+void xcd_ranges(const CsrCfg &c, const std::vector<int32_t> &te, RemoteFuse &rf)
+{
+    const int64_t nt = int64_t(c.tile_row.size()) - 1;
+    std::vector<double> pre(size_t(nt + 1), 0.0);
+    for (int64_t t = 0; t < nt; ++t)
+        pre[size_t(t + 1)] = pre[size_t(t)] + double(c.tile_k[size_t(t + 1)] - c.tile_k[size_t(t)]) +
+                             kRemoteEntryCost * double(te[size_t(t + 1)] - te[size_t(t)]);
+    int64_t t = 0, longest = 0;
+    rf.xr[0] = 0;
+    for (int x = 1; x < kXcds; ++x) {
+        const double target = pre[size_t(nt)] * x / kXcds;
+        while (t < nt && pre[size_t(t + 1)] <= target) ++t;
+        rf.xr[x] = int32_t(t);
+    }
+    rf.xr[kXcds] = int32_t(nt);
+    for (int x = 0; x < kXcds; ++x) longest = std::max<int64_t>(longest, rf.xr[x + 1] - rf.xr[x]);
+    rf.n_grid = int32_t(kXcds * longest);
+}
 
 bool fuses_remote(const spmv_plan *p)
 {
@@ -311,6 +340,7 @@ int allocate_and_upload(spmv_plan *p)
             p->rf.tj = p->d_rf_tj;
             p->rf.te = p->d_rf_te;
             p->rf.tile_cap = tile_remote_cap(p);
+            if (p->xcd_remap == 1) xcd_ranges(p->cfg[0], rf_te, p->rf);
         }
     }
     if (int rc = resident_build(p)) return rc;
