@@ -380,10 +380,12 @@ int spmv_exec(spmv_plan_t *plan, const double *x_local, double *y_local, void *s
  *      tiles (none reads what another writes) as the work items of one,
  *      then the slab sums adding into y;
  *   3  y_L in packed tiles or the 16-bit sliced form, Unpack fused, y_R
- *      sliced or in packed tiles with one summing lane, no remote row
- *      longer than 4 entries: the whole step in y_L's launch, Pack as extra
- *      blocks and each row's remote sum (computed as y_R's kernel computes
- *      it) added where the row's local sum is stored;
+ *      sliced or in packed tiles with one summing lane, and either both in
+ *      packed tiles with at most one window (and at most 1,024) of remote
+ *      entries in the rows of each y_L tile, or no remote row longer than 4
+ *      entries: the whole step in y_L's launch, Pack as extra blocks and
+ *      each row's remote sum (computed as y_R's kernel computes it) added
+ *      where the row's local sum is stored;
  *   2  otherwise, with y_L in packed tiles or the 16-bit sliced form: Pack
  *      as extra blocks of y_L's launch, then Unpack (unless fused) and y_R;
  *   0  otherwise, and always with SPMV_F_RESIDENT_SEQUENTIAL: one launch
