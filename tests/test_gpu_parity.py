@@ -913,6 +913,28 @@ def _long_local_rows(n_half=6000, seed=0):
                    rng.standard_normal(col.size))
 
 
+def _remote_per_row(n_remote, n_half=4096, seed=0):
+    """Two ranks; rank 0's rows hold 4 local entries and n_remote in rank
+    1's block, rank 1's rows their diagonal and one entry in rank 0's block
+    (so rank 0 has a send list): in packed tiles of 1,024 entries (256
+    rows) a tile's rows hold 256 * n_remote remote entries, exactly a
+    window's worth with 4."""
+    rng = np.random.default_rng(seed)
+    ptr, cols = [0], []
+    for i in range(2 * n_half):
+        if i < n_half:
+            c = [(i + k) % n_half for k in range(4)]
+            c += [n_half + (i * 13 + k * 1031) % n_half for k in range(n_remote)]
+        else:
+            c = [i - n_half, i]
+        c = sorted(set(c))
+        cols.append(np.asarray(c, np.int32))
+        ptr.append(ptr[-1] + len(c))
+    col = np.concatenate(cols)
+    return gen.CSR(2 * n_half, 2 * n_half, np.asarray(ptr, np.int32), col,
+                   rng.standard_normal(col.size))
+
+
 @pytest.mark.parametrize("mode", ["grouped", "sequential"])
 def test_exec_resident_matches_exec(mode):
     """The device work alone (halo already in the receive buffer): the bits
@@ -968,6 +990,9 @@ def test_exec_resident_matches_exec(mode):
              (_long_local_rows(), 2, 0, 31, {}, 3),
              (_long_local_rows(seed=1), 2, 0, 32, {"form": 1}, 3),
              (_long_local_rows(seed=2), 2, 0, 33, {"lanes_local": 2}, 3),
+             # a tile's remote entries at the window's 1,024, and past it
+             (_remote_per_row(4), 2, 0, 34, {"form": 1}, 3),
+             (_remote_per_row(5), 2, 0, 35, {"form": 1}, 2),
              (gen.stencil_3d27(20, seed=3), 4, 1, 25, {"form": 2}, 0),   # 32-bit sliced y_L
              (gen.laplacian_2d5(40), 1, 0, 21, {"form": 1}, 0)]          # one rank
     for A, P, r, seed, tune, grouped in cases:
