@@ -990,6 +990,9 @@ def test_exec_resident_matches_exec(mode):
              (_long_local_rows(), 2, 0, 31, {}, 3),
              (_long_local_rows(seed=1), 2, 0, 32, {"form": 1}, 3),
              (_long_local_rows(seed=2), 2, 0, 33, {"lanes_local": 2}, 3),
+             (_long_local_rows(seed=3), 2, 0, 36, {"lanes_local": 4}, 3),
+             (_long_local_rows(seed=4), 2, 0, 37, {"chunk_local": 8, "chunk_remote": 8}, 3),
+             (_long_local_rows(seed=5), 2, 0, 38, {"xcd_remap": 2}, 3),   # no XCD ranges
              # a tile's remote entries at the window's 1,024, and past it
              (_remote_per_row(4), 2, 0, 34, {"form": 1}, 3),
              (_remote_per_row(5), 2, 0, 35, {"form": 1}, 2),
