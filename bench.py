@@ -57,7 +57,7 @@ MEASURED_TRAFFIC = {
     ("powerlaw_4m_p16r5", "k_csr_slabs<4,2,1>+k_slab_sum"):
         (111_144_633, "profiles/yr_slabs_powerlaw_4m_p16r5.md"),
     ("powerlaw_4m_p16r5", "k_resident<4,2>"):
-        (140_786_503, "profiles/resident_grouped_powerlaw_4m_p16r5.md"),
+        (140_957_582, "profiles/resident_grouped_powerlaw_4m_p16r5.md"),
     ("laplace3d_128_p4r1", "k_sell16<1>"):
         (47_998_920, "profiles/sliced16_laplace3d_128_p4r1.md"),
     ("stencil27_150_p8r3", "k_csr_stream<4,2,2,true>"):

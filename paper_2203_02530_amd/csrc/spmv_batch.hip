@@ -1058,9 +1058,11 @@ int resident_build(spmv_plan *p)
     const int gather_len = kBlock * cl.chunk;
     // y_L tiles, then Pack ranges, go to the XCDs by contiguous ranges (item
     // i of n on XCD 8 i / n), as the single-share kernels order their
-    // blocks, and run before the XCD's slab tiles (the other order of y_L
-    // and Pack measured 0.6 us slower per step, Pack spread evenly among
-    // the slab tiles 2.7 us slower); the slab sums likewise
+    // blocks, and run after the XCD's slab tiles, filling the slab tiles'
+    // ragged end: 42.6-42.9 us per step against 43.7-44.2 with y_L and Pack
+    // first (y_L, slab tiles, Pack: 42.9-43.6; slab tiles, Pack, y_L:
+    // 43.9-44.4; Pack spread evenly among the slab tiles, y_L and Pack
+    // first: 2.7 us slower); the slab sums likewise
     auto xcd_of = [](int64_t i, int64_t n) { return int(i * kXcds / std::max<int64_t>(n, 1)); };
     std::vector<Item> a1[kXcds], a2[kXcds], b1[kXcds], none[kXcds];
     const int64_t n_lt = int64_t(cl.tile_k.size()) - 1;
@@ -1082,7 +1084,7 @@ int resident_build(spmv_plan *p)
         const int64_t a = j * kBlock;
         b1[xcd_of(j, n_sum)].push_back({kSlabSum, 0, int32_t(a), int32_t(std::min<int64_t>(kBlock, n_rr - a))});
     }
-    const std::vector<Item> a_items = place_items(a1, a2);
+    const std::vector<Item> a_items = place_items(a2, a1);
     const std::vector<Item> b_items = place_items(b1, none);
     auto *r = new (std::nothrow) ResidentProg();
     if (!r) return set_error(SPMV_ENOMEM, "resident program");
