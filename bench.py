@@ -916,12 +916,10 @@ def measure_share(sp, torch, gen, key: str, args, sweep: bool = True,
                    "n_tiles_local": info["n_tiles_local"], "n_tiles_remote": info["n_tiles_remote"],
                    "xcd_remap": info["xcd_remap"], "fuse_unpack": info["fuse_unpack"],
                    "fused_combine": info["fused_combine"], "replicas": R,
-                   "step": {1: "Pack, y_L and y_R's column-slab tiles as one grouped launch, "
-                                   "then the slab sums into y",
+                   "step": {1: "y_R's column-slab tiles, then y_L and Pack, as one grouped "
+                                   "launch, then the slab sums into y",
                             3: "one launch: y_L, Pack as extra blocks, each remote row's "
                                "sum added where its local sum is stored",
-                            4: "y_L, Pack and y_R's tiles as blocks of one launch, then the "
-                               "combine into y",
                             2: "y_L with Pack as extra blocks of its launch, then y_R into y",
                             0: "Pack, y_L, Unpack, y_R, one launch each"}.get(
                                 info["resident_grouped"], "see spmv_exec_resident") +
